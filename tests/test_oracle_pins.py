@@ -1,0 +1,440 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Brute-force enumerations on graphs of at most 16 nodes, closed forms
+(cliques, stars, K_2, U = 1), a hand-worked example, invariants the paper
+states (Section 3.1: clusters within U; contraction keeps cut and balance),
+and the paper's sequential SCLaP as a quality reference.
+"""
+import json
+import math
+import os
+import random
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tinygraphs import clique, family, from_edges, path, star
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def nbrs(g):
+    ew = g.edge_weights()
+    return [[(int(g.col[e]), int(ew[e])) for e in range(g.row_ptr[v], g.row_ptr[v + 1])] for v in range(g.n)]
+
+
+# ---------------------------------------------------------------- brute force
+
+
+def brute_rate(g, lab, W, cap, rnd, dir_rule, refine, nlabels):
+    """Enumerate every label t in [0, nlabels) for every node."""
+    c = g.node_weights()
+    N = nbrs(g)
+    out = []
+    for v in range(g.n):
+        own = int(lab[v])
+        best_key, best_t = None, own
+        for t in range(nlabels):
+            conn = sum(w for u, w in N[v] if lab[u] == t)
+            if t != own and not any(lab[u] == t for u, _ in N[v]):
+                continue
+            if t == own:
+                if refine and W[own] > cap:
+                    continue
+            else:
+                if dir_rule and rnd % 2 == 1 and t > own:
+                    continue
+                if dir_rule and rnd % 2 == 0 and t < own:
+                    continue
+                if W[t] + c[v] > cap:
+                    continue
+            key = (conn, -t)
+            if best_key is None or key > best_key:
+                best_key, best_t = key, t
+        out.append(best_t)
+    return np.array(out, np.int32)
+
+
+def brute_admit(g, desire, lab, W, cap):
+    """Group movers by target, sort each group by node id, admit by prefix."""
+    c = g.node_weights()
+    adm = np.zeros(g.n, bool)
+    for t in sorted(set(int(x) for x in desire)):
+        movers = sorted(v for v in range(g.n) if desire[v] == t and lab[v] != t)
+        pre = 0
+        for v in movers:
+            pre += int(c[v])
+            adm[v] = W[t] + pre <= cap
+    new = np.where(adm, desire, lab).astype(np.int32)
+    return new, adm
+
+
+def random_state(g, rng, nlabels, refine):
+    c = g.node_weights()
+    if refine:
+        lab = np.array([rng.randrange(nlabels) for _ in range(g.n)], np.int32)
+    else:
+        lab = np.array([rng.randrange(g.n) for _ in range(g.n)], np.int32) if g.n else np.zeros(0, np.int32)
+    W = np.zeros(nlabels, np.int64)
+    for v in range(g.n):
+        W[lab[v]] += c[v]
+    return lab, W
+
+
+@pytest.mark.parametrize("refine", [0, 1])
+def test_rate_matches_brute_force(refine):
+    rng = random.Random(11 + refine)
+    checked = 0
+    for name, g in family(seed=3):
+        if g.n == 0:
+            continue
+        for trial in range(3):
+            nlabels = rng.choice((2, 3, 4)) if refine else g.n
+            lab, W = random_state(g, rng, nlabels, refine)
+            total = int(W.sum())
+            cap = rng.choice((max(1, total // 4), max(1, total // 2), total + 1, 1, int(W.max())))
+            for rnd in (1, 2, 3):
+                for dr in (0, 1):
+                    want = brute_rate(g, lab, W, cap, rnd, dr, refine, nlabels)
+                    got = oracle.rate(g, lab, W, cap, rnd, dr, refine)
+                    assert np.array_equal(got, want), (name, trial, rnd, dr, cap)
+                    checked += 1
+    assert checked > 500
+
+
+def test_admission_matches_brute_force():
+    rng = random.Random(5)
+    for name, g in family(seed=9):
+        if g.n == 0:
+            continue
+        for trial in range(4):
+            lab, W = random_state(g, rng, g.n, 0)
+            desire = np.array([rng.randrange(g.n) for _ in range(g.n)], np.int32)
+            cap = rng.choice((1, 2, 3, int(W.sum()), int(W.max()) + 2))
+            new, Wn, adm, moved = oracle.admit_apply(g, desire, lab, W, cap)
+            want_new, want_adm = brute_admit(g, desire, lab, W, cap)
+            assert np.array_equal(adm, want_adm), name
+            assert np.array_equal(new, want_new), name
+            assert moved == int(want_adm.sum())
+            c = g.node_weights()
+            want_W = np.zeros(g.n, np.int64)
+            np.add.at(want_W, new, c)
+            assert np.array_equal(Wn, want_W)
+
+
+def test_contract_matches_pair_sums():
+    rng = random.Random(21)
+    for name, g in family(seed=13):
+        if g.n == 0:
+            continue
+        lab = np.array([rng.randrange(max(1, g.n // 2)) for _ in range(g.n)], np.int32)
+        co = oracle.contract(g, lab)
+        used = sorted(set(int(x) for x in lab))
+        rank = {t: i for i, t in enumerate(used)}
+        assert co.n == len(used)
+        assert np.array_equal(co.coarse_of, np.array([rank[int(t)] for t in lab], np.int32))
+        c = g.node_weights()
+        want_nw = np.zeros(len(used), np.int64)
+        for v in range(g.n):
+            want_nw[rank[int(lab[v])]] += c[v]
+        assert np.array_equal(co.nw, want_nw)
+        pairs = {}
+        for v in range(g.n):
+            for u, w in nbrs(g)[v]:
+                x, y = rank[int(lab[v])], rank[int(lab[u])]
+                if x != y:
+                    pairs[(x, y)] = pairs.get((x, y), 0) + w
+        got = {}
+        for x in range(co.n):
+            row = co.col[co.row_ptr[x]:co.row_ptr[x + 1]]
+            assert np.all(np.diff(row) > 0), "rows ascending, no duplicates"
+            for e in range(co.row_ptr[x], co.row_ptr[x + 1]):
+                got[(x, int(co.col[e]))] = int(co.ew[e])
+        assert got == pairs, name
+
+
+def test_contract_drop_isolated():
+    g = from_edges(6, [(1, 2), (2, 4)])
+    lab = np.array([0, 1, 1, 3, 4, 5], np.int32)
+    co = oracle.contract(g, lab, drop_isolated=1)
+    assert list(co.coarse_of) == [-1, 0, 0, -1, 1, -1]
+    assert list(co.nw) == [2, 1]
+    assert list(co.col) == [1, 0] and list(co.ew) == [1, 1]
+
+
+# ---------------------------------------------------------------- closed forms
+
+
+def test_bounds_golden():
+    gold = json.load(open(os.path.join(GOLDEN, "bounds.json")))
+    for case in gold["cases"]:
+        lmax, W, U = oracle.bounds(case["total_w"], case["max_w"], case["k"], 3, 100, 14)
+        assert (lmax, W, U) == (case["lmax"], case["W"], case["U"]), case["name"]
+
+
+def test_threshold_paper_rule():
+    g = graphgen.config1_graph()
+    _, st = oracle.partition(g, 2)
+    assert st["threshold"] == 136
+    assert st["U"] == 602 and st["lmax"] == 8437
+
+
+def test_hand_worked_two_triangles():
+    gold = json.load(open(os.path.join(GOLDEN, "two_triangles.json")))
+    g = from_edges(gold["graph"]["n"], [tuple(e) for e in gold["graph"]["edges"]])
+    U = gold["U"]
+    lab = np.arange(g.n, dtype=np.int32)
+    W = np.ones(g.n, np.int64)
+    for rd in gold["rounds"]:
+        desire = oracle.rate(g, lab, W, U, rd["round"], gold["direction_rule"], 0)
+        assert list(desire) == rd["desire"], rd["round"]
+        lab, W, _, moved = oracle.admit_apply(g, desire, lab, W, U)
+        assert list(lab) == rd["labels_after"], rd["round"]
+        assert moved == rd["moved"]
+    res = oracle.cluster(g, U, max_rounds=4, stop_rule=0)
+    assert list(res.labels) == gold["rounds"][-1]["labels_after"]
+    assert res.moved == [r["moved"] for r in gold["rounds"]]
+    # 5% rule over the last two rounds: after round 3, 20 * (0 + 1) >= 6 keeps
+    # going; after round 4, 20 * (0 + 0) < 6 stops
+    res = oracle.cluster(g, U, max_rounds=10, stop_rule=1)
+    assert res.rounds == 4 and res.moved == [5, 1, 0, 0]
+    co = oracle.contract(g, res.labels)
+    want = gold["contracted"]
+    assert list(co.coarse_of) == want["coarse_of"]
+    assert list(co.row_ptr) == want["row_ptr"] and list(co.col) == want["col"]
+    assert list(co.ew) == want["ew"] and list(co.nw) == want["nw"]
+
+
+def test_u1_only_singletons():
+    """U = 1 on an unweighted graph: singletons are the only feasible
+    clustering (Section 2.1), so nothing ever moves."""
+    for name, g in family(seed=1, count=30):
+        if g.nw is not None or g.n == 0:
+            continue
+        res = oracle.cluster(g, 1, max_rounds=6)
+        assert np.array_equal(res.labels, np.arange(g.n)), name
+        assert sum(res.moved) == 0
+
+
+def test_disjoint_cliques_converge_to_min_id():
+    rng = random.Random(4)
+    for trial in range(20):
+        n = 16
+        ids = list(range(n))
+        rng.shuffle(ids)
+        sizes, i = [], 0
+        while i < n:
+            s = min(rng.randint(1, 6), n - i)
+            sizes.append(ids[i:i + s])
+            i += s
+        edges = [e for grp in sizes for e in clique(grp)]
+        g = from_edges(n, edges)
+        U = max(len(grp) for grp in sizes) + rng.randint(0, 2)
+        res = oracle.cluster(g, U, max_rounds=5)
+        want = np.empty(n, np.int32)
+        for grp in sizes:
+            want[grp] = min(grp)
+        assert np.array_equal(res.labels, want)
+        assert res.moved[0] == n - len(sizes) and sum(res.moved[1:]) == 0
+
+
+def test_star_joins_centre():
+    for L in (1, 3, 7, 15):
+        g = from_edges(L + 1, star(L + 1))
+        res = oracle.cluster(g, L + 1, max_rounds=3)
+        assert np.all(res.labels == 0) and res.moved[0] == L
+        # cap below L + 1: the smallest ids are admitted first
+        U = max(1, (L + 1) // 2)
+        res = oracle.cluster(g, U, max_rounds=3)
+        assert list(np.nonzero(res.labels == 0)[0]) == list(range(U))
+
+
+def test_k2_direction_rule():
+    g = from_edges(2, [(0, 1)])
+    res = oracle.cluster(g, 2, max_rounds=4)
+    assert list(res.labels) == [0, 0] and res.moved == [1, 0, 0, 0]
+    # without the direction rule the synchronous rule swaps forever
+    res = oracle.cluster(g, 2, max_rounds=4, dir_rule=0)
+    assert res.moved == [2, 2, 2, 2] and list(res.labels) == [0, 1]
+
+
+def test_isolated_nodes_never_move():
+    g = from_edges(5, [(1, 3)])
+    res = oracle.cluster(g, 5, max_rounds=4)
+    assert list(res.labels) == [0, 1, 2, 1, 4]
+
+
+def test_initial_partition_closed_forms():
+    # path 0-1-...-(n-1): BFS order is the id order, block = floor(k v / n)
+    for n, k in ((16, 2), (16, 3), (10, 4), (7, 7)):
+        g = from_edges(n, path(n))
+        part = oracle.initial_partition(g, k)
+        assert list(part) == [min(k - 1, (k * v) // n) for v in range(n)]
+    # star with centre 5 and shuffled rows: centre first would only happen if
+    # it were the smallest id; BFS from 0 reaches 5, then 1..4, 6..
+    rng = random.Random(1)
+    g = from_edges(8, star(8, centre=5), rng=rng, shuffle_rows=True)
+    part = oracle.initial_partition(g, 8)
+    order = [0, 5, 1, 2, 3, 4, 6, 7]
+    assert [part[v] for v in order] == list(range(8))
+    # disjoint components are visited by their smallest id
+    g = from_edges(6, [(3, 4), (1, 5)])
+    part = oracle.initial_partition(g, 6)
+    order = [0, 1, 5, 2, 3, 4]
+    assert [part[v] for v in order] == list(range(6))
+
+
+def test_place_isolated():
+    # fills the lightest blocks up to a common level, lower block ids first
+    B = np.array([5, 7], np.int64)
+    iso = np.array([1, 1, 1], np.uint8)
+    part = oracle.place_isolated(None, iso, 2, B)
+    assert list(part) == [0, 0, 0]
+    B = np.array([5, 5], np.int64)
+    part = oracle.place_isolated(None, np.array([1, 0, 1], np.uint8), 2, B)
+    assert list(part) == [0, -1, 1]
+    B = np.array([3, 0, 3, 1], np.int64)
+    part = oracle.place_isolated(np.array([1, 1, 1, 1, 0], np.int64), np.ones(5, np.uint8), 4, B)
+    # C_I = 4: D(2) = 3 < 4, D(3) = 5 -> lambda = 3, deficits (0, 3, 0, 2),
+    # intervals [0,3) block 1 and [3,5) block 3; the zero-weight node has P = 4
+    assert list(part) == [1, 1, 1, 3, 3]
+
+
+# ---------------------------------------------------------------- invariants
+
+
+def check_csr(rp, col, ew):
+    n = rp.shape[0] - 1
+    ent = {}
+    for x in range(n):
+        row = col[rp[x]:rp[x + 1]]
+        assert np.all(np.diff(row) > 0)
+        assert not np.any(row == x)
+        for e in range(rp[x], rp[x + 1]):
+            ent[(x, int(col[e]))] = int(ew[e])
+    for (x, y), w in ent.items():
+        assert ent.get((y, x)) == w
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_round_invariants_rmat(seed):
+    g = graphgen.rmat(11, 8, seed=seed)
+    c = g.node_weights()
+    U = 40
+    lab = np.arange(g.n, dtype=np.int32)
+    W = c.copy()
+    for rnd in range(1, 9):
+        desire = oracle.rate(g, lab, W, U, rnd)
+        lab, W, adm, moved = oracle.admit_apply(g, desire, lab, W, U)
+        assert W.max() <= U
+        assert W.sum() == c.sum()
+        if rnd % 2 == 1:
+            assert np.all(lab[adm] < np.arange(g.n)[adm] + g.n)  # moves recorded
+    co = oracle.contract(g, lab)
+    assert co.nw.sum() == c.sum() and co.nw.max() <= U
+    check_csr(co.row_ptr, co.col, co.ew)
+    intra = sum(1 for v in range(g.n) for e in range(g.row_ptr[v], g.row_ptr[v + 1]) if lab[g.col[e]] == lab[v])
+    assert co.ew.sum() == g.m - intra
+    # a partition of the coarse graph has the same cut and balance when
+    # projected (Section 3.1)
+    k = 4
+    part_c = oracle.initial_partition(oracle.OGraph(co.row_ptr, co.col, co.ew, co.nw), k)
+    cut_c, bw_c = oracle.cut(oracle.OGraph(co.row_ptr, co.col, co.ew, co.nw), part_c, k)
+    part_f = part_c[co.coarse_of]
+    cut_f, bw_f = oracle.cut(g, part_f, k)
+    assert cut_c == cut_f and np.array_equal(bw_c, bw_f)
+
+
+def test_cut_equals_contracted_by_partition():
+    rng = random.Random(2)
+    for name, g in family(seed=17, count=40):
+        if g.n == 0:
+            continue
+        k = rng.randint(1, min(4, g.n))
+        part = np.array([rng.randrange(k) for _ in range(g.n)], np.int32)
+        cut, bw = oracle.cut(g, part, k)
+        co = oracle.contract(g, part)
+        assert cut == int(co.ew.sum()) // 2
+        used = sorted(set(int(x) for x in part))
+        assert list(co.nw) == [int(bw[b]) for b in used]
+
+
+def test_refine_caps_and_overload():
+    rng = random.Random(8)
+    for seed in range(1, 6):
+        g = graphgen.rmat(10, 8, seed=seed)
+        n = g.n
+        k = rng.choice((2, 4, 8))
+        lmax = math.floor(1.03 * math.ceil(n / k))
+        part = np.array([rng.randrange(k) for _ in range(n)], np.int32)
+        _, bw0 = oracle.cut(g, part, k)
+        out, rounds, moved, visits = oracle.refine(g, part, k, lmax, max_rounds=10)
+        _, bw1 = oracle.cut(g, out, k)
+        for b in range(k):
+            if bw0[b] <= lmax:
+                assert bw1[b] <= lmax
+            else:
+                assert bw1[b] <= bw0[b]
+        assert visits >= g.m  # round 1 rates every node
+
+
+def opt_bisection(g, lmax):
+    best = None
+    c = g.node_weights()
+    N = nbrs(g)
+    for mask in range(1 << g.n):
+        w1 = sum(int(c[v]) for v in range(g.n) if mask >> v & 1)
+        if w1 > lmax or int(c.sum()) - w1 > lmax:
+            continue
+        cut = sum(w for v in range(g.n) for u, w in N[v] if (mask >> v & 1) != (mask >> u & 1)) // 2
+        best = cut if best is None else min(best, cut)
+    return best
+
+
+def test_partition_feasible_and_above_optimum():
+    rng = random.Random(3)
+    cnt = 0
+    for name, g in family(seed=23, count=40):
+        if g.n < 4 or g.n > 14 or g.nw is not None:
+            continue
+        part, st = oracle.partition(g, 2)
+        assert set(int(x) for x in part) <= {0, 1}
+        opt = opt_bisection(g, st["lmax"])
+        if st["max_block"] <= st["lmax"]:
+            assert st["cut"] >= opt
+        cnt += 1
+    assert cnt > 10
+
+
+def test_row_order_invariance():
+    rng = random.Random(12)
+    g = graphgen.rmat(10, 8, seed=4)
+    perm_col = g.col.copy()
+    for v in range(g.n):
+        seg = perm_col[g.row_ptr[v]:g.row_ptr[v + 1]]
+        rng.shuffle(seg)
+    g2 = graphgen.Graph(g.row_ptr, perm_col)
+    p1, s1 = oracle.partition(g, 4)
+    p2, s2 = oracle.partition(g2, 4)
+    assert np.array_equal(p1, p2) and s1 == s2
+
+
+# ---------------------------------------------------------------- quality
+
+
+def test_quality_gate_vs_sequential_sclap():
+    """The synchronous reading must not cut much worse than the paper's
+    sequential SCLaP (increasing-degree order, Section 4) with the same
+    hierarchy driver, initial partition and refinement cap."""
+    ratios = []
+    for seed in range(1, 8):
+        graphs = [graphgen.rmat(11, 4 + 4 * (seed % 3), seed=seed), graphgen.rgg(3000 + 500 * seed, 8.0, seed=seed)]
+        for g in graphs:
+            for k in (2, 4, 16):
+                _, s_sync = oracle.partition(g, k)
+                _, s_seq = oracle.seq_partition(g, k)
+                ratios.append(max(1, s_sync["cut"]) / max(1, s_seq["cut"]))
+    gm = math.exp(sum(math.log(r) for r in ratios) / len(ratios))
+    assert gm <= 1.10, gm
