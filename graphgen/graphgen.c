@@ -78,10 +78,11 @@ static void sort_row(int32_t* row, int64_t d) {
 static int build_sym_csr(int64_t n, int64_t ns, const int32_t* su, const int32_t* sv, gg_csr* out) {
   int64_t* cnt = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   if (!cnt) return -1;
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < ns; ++i) {
     if (su[i] == sv[i]) continue;
-    cnt[su[i] + 1]++;
-    cnt[sv[i] + 1]++;
+    __atomic_fetch_add(&cnt[su[i] + 1], 1, __ATOMIC_RELAXED);
+    __atomic_fetch_add(&cnt[sv[i] + 1], 1, __ATOMIC_RELAXED);
   }
   for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
   int64_t tot = cnt[n];
@@ -89,11 +90,13 @@ static int build_sym_csr(int64_t n, int64_t ns, const int32_t* su, const int32_t
   int64_t* pos = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
   if (!tmp || !pos) { free(cnt); free(tmp); free(pos); return -1; }
   memcpy(pos, cnt, (size_t)n * sizeof(int64_t));
+  /* order inside a row is arbitrary here; rows are sorted below */
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < ns; ++i) {
     int32_t a = su[i], b = sv[i];
     if (a == b) continue;
-    tmp[pos[a]++] = b;
-    tmp[pos[b]++] = a;
+    tmp[__atomic_fetch_add(&pos[a], 1, __ATOMIC_RELAXED)] = b;
+    tmp[__atomic_fetch_add(&pos[b], 1, __ATOMIC_RELAXED)] = a;
   }
   free(pos);
   int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));

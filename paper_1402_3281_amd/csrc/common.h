@@ -1,0 +1,135 @@
+// common.h -- internal declarations shared by the device library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/sclap.h"
+
+namespace sclap {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Errors: every internal function returns an int status; the message of the
+// last failure is kept per thread.
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define SCLAP_HIP(expr)                                                                        \
+  do {                                                                                         \
+    hipError_t _e = (expr);                                                                    \
+    if (_e != hipSuccess)                                                                      \
+      return ::sclap::fail(_e == hipErrorOutOfMemory ? SCLAP_ENOMEM : SCLAP_EHIP,              \
+                           std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+  } while (0)
+
+#define SCLAP_TRY(expr)      \
+  do {                       \
+    int _rc = (expr);        \
+    if (_rc != SCLAP_OK) return _rc; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// One graph taking part in a fused label-propagation round.  Nodes of all
+// slots of a round form one global id space: slot s owns [nbase, nbase + n).
+// Labels of slot s live in [0, nlabels) and form the global target range
+// [lbase, lbase + nlabels) used to key contended admissions.
+// ---------------------------------------------------------------------------
+enum : int32_t { MODE_CLUSTER = 0, MODE_REFINE = 1 };
+
+struct DevSlot {
+  const int64_t* rp;
+  const int32_t* col;
+  const int32_t* ew;      // nullptr: unit edge weights
+  const int64_t* nw;      // never null
+  int32_t* lab;           // n: cluster label / block id (-1: takes no part)
+  int32_t* desire;        // n
+  uint8_t* adm;           // n: admitted flag of the current round
+  int64_t* W;             // nlabels: label weights before the round
+  int64_t* inc;           // nlabels: incoming mover weight (kept zero between rounds)
+  uint8_t* flag_cur;      // refine: rated set of this round (use_flags)
+  uint8_t* flag_next;     // refine: rated set of the next round
+  int64_t* ctr;           // device counters of this slot, see CTR_*
+  int64_t n;
+  int64_t nbase;
+  int64_t nlabels;
+  int64_t lbase;
+  int64_t cap;
+  int32_t round;          // 1-based round number; 0: slot idle this step
+  int32_t mode;           // MODE_CLUSTER / MODE_REFINE
+  int32_t dir_rule;
+  int32_t use_flags;      // rate only nodes with flag_cur set
+  int32_t hub_off_valid;  // unused padding for alignment
+  int32_t pad;
+};
+
+enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_N = 4 };
+
+// Degree bins of the rating kernels.
+constexpr int kBins = 4;
+constexpr int64_t kBinG8 = 8;        // degree 1..8: 8 lanes per node
+constexpr int64_t kBinG64 = 64;      // degree 9..64: one wave per node
+constexpr int64_t kBinBlock = 4096;  // degree 65..4096: one workgroup per node, LDS table
+// above kBinBlock: several workgroups per node, global table
+
+constexpr int kHubChunk = 4096;      // entries per workgroup in the multi-workgroup path
+
+__device__ __forceinline__ int slot_of(const DevSlot* __restrict__ S, int ns, int64_t u) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (S[mid].nbase <= u) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Candidate key: larger connection wins, then smaller label.  0 = none.
+__device__ __forceinline__ uint64_t pack_key(int64_t conn, int32_t t) {
+  return ((uint64_t)conn << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)t);
+}
+__device__ __forceinline__ int32_t key_label(uint64_t key) {
+  return (int32_t)(0xFFFFFFFFu - (uint32_t)(key & 0xFFFFFFFFu));
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352dU;
+  x ^= x >> 15;
+  x *= 0x846ca68bU;
+  x ^= x >> 16;
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory: stream-ordered allocations from the device's default pool.
+// ---------------------------------------------------------------------------
+struct Ctx;
+
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+int dalloc(void** p, size_t bytes, hipStream_t st);
+void dfree(void* p, hipStream_t st);
+
+template <class T>
+int dalloc_t(T** p, size_t count, hipStream_t st) {
+  return dalloc(reinterpret_cast<void**>(p), count * sizeof(T), st);
+}
+
+// Growable scratch buffer owned by the context.
+struct Scratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need, hipStream_t st);
+  void release(hipStream_t st);
+};
+
+}  // namespace sclap

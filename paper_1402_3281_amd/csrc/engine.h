@@ -1,0 +1,125 @@
+// engine.h -- host-side executor of the multilevel scheme over a set of jobs.
+//
+// A job is one graph's partition (or a single clustering / refinement run).
+// The executor advances all jobs step by step; every step fuses the work of
+// all jobs that are at that step into one set of launches:
+//   LP round   (clustering rounds and refinement rounds together)
+//   contract   (jobs whose clustering of a level finished)
+//   initial    (jobs that reached their coarsest level)
+//   finish     (jobs whose finest level is refined)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.h"
+#include "lp.h"
+#include "misc.h"
+
+namespace sclap {
+
+struct Level {
+  int64_t n = 0, m = 0;
+  const int64_t* rp = nullptr;
+  const int32_t* col = nullptr;
+  const int32_t* ew = nullptr;
+  const int64_t* nw = nullptr;
+  // owned storage (coarse levels; widened node weights of the input)
+  int64_t* own_rp = nullptr;
+  int32_t* own_col = nullptr;
+  int32_t* own_ew = nullptr;
+  int64_t* own_nw = nullptr;
+  int32_t* coarse_of = nullptr;  // n: map to the next coarser level
+  int rows_sorted = 0;
+  int64_t n_active = 0;          // nodes of degree > 0
+  int64_t hub_c = 0;             // global hub table entries when clustering this level
+  int64_t hub_r = 0;             // ... when refining it
+};
+
+enum Stage : int { ST_COARSEN, ST_CONTRACT, ST_IP, ST_REFINE, ST_FINISH, ST_DONE, ST_ERROR };
+enum Kind : int { JOB_PARTITION, JOB_CLUSTER, JOB_REFINE };
+
+struct Job {
+  Kind kind = JOB_PARTITION;
+  Stage stage = ST_COARSEN;
+  int status = SCLAP_OK;
+  // parameters
+  int32_t k = 2;
+  int64_t lmax = 0, U = 0, W = 0, threshold = 0;
+  int32_t lp_rounds = 10, ref_rounds = 10, dir_rule = 1, stop_rule = 1;
+  int64_t total_w = 0;
+  std::vector<Level> lv;
+  int cur = 0;
+  // LP state of the current stage
+  int32_t round = 0;
+  int64_t moved_prev = 0;
+  int32_t zero_streak = 0;
+  int64_t n_stop = 0;              // node count of the 5% rule
+  int32_t* lab = nullptr;          // labels (cluster) or blocks (refine)
+  bool lab_owned = false;
+  int32_t* desire = nullptr;
+  uint8_t* adm = nullptr;
+  int64_t* Wt = nullptr;
+  int64_t* inc = nullptr;
+  uint8_t* fcur = nullptr;
+  uint8_t* fnext = nullptr;
+  int64_t nlabels = 0;
+  // outputs
+  int32_t* part_out = nullptr;     // caller buffer (level-0 blocks / labels)
+  sclap_stats st{};
+  sclap_round_stats rst{};         // single clustering / refinement runs
+  double t_start = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  int cu_count = 256;
+  // scratch reused by every step
+  Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
+  Scratch step_ctr, small, slots_dev, ip_slots;
+  int64_t hub_cap = 0;             // entries of the global hub table (kept -1/0)
+  // pinned host staging
+  int64_t* pin = nullptr;
+  size_t pin_bytes = 0;
+  DevSlot* pin_slots = nullptr;
+  size_t pin_slots_cap = 0;
+  // optional per-kernel timing of the rating step
+  bool profile = false;
+  hipEvent_t ev[8];
+  double prof_rate_ms = 0;         // sum over launches of the rating step
+  int64_t prof_rate_launches = 0;
+  int64_t prof_rate_visits = 0;
+  int64_t prof_rate_nodes = 0;
+  double prof_round_ms = 0;        // whole LP rounds
+  int64_t prof_rounds = 0;
+};
+
+int ctx_ensure_pin(Ctx* c, size_t bytes);
+int ctx_ensure_slots(Ctx* c, size_t count);
+
+// Prepare a job's level 0 from the caller's CSR (widens node weights).
+int job_set_input(Ctx* c, Job* j, const sclap_csr* g, hipStream_t st);
+// Compute per-level totals (n_active, hub table needs); returns via sync.
+int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipStream_t st);
+// Start clustering on level cur (labels = node ids).
+int job_begin_cluster(Ctx* c, Job* j, hipStream_t st);
+// Start refinement on level cur with blocks in `part` (owned by the job).
+int job_begin_refine(Ctx* c, Job* j, int32_t* part, bool owned, hipStream_t st);
+void job_release_lp(Job* j, hipStream_t st, bool keep_lab);
+void job_release_levels(Job* j, hipStream_t st);
+
+// One fused LP round over the given jobs (all in ST_COARSEN or ST_REFINE).
+int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st);
+// Contract level cur of a job into level cur + 1.
+int contract_level(Ctx* c, Job* j, int i, int drop_isolated, hipStream_t st);
+// Fused initial partition of the jobs' current (coarsest) levels.
+int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipStream_t st);
+
+// Run jobs to completion (the executor).
+int run_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st);
+
+double now_ms();
+int bits_for(int64_t count);
+
+}  // namespace sclap

@@ -1,0 +1,691 @@
+// engine.hip -- host executor of the multilevel scheme (Section 1, Figure 1;
+// Section 3.1): coarsening by size-constrained label propagation and cluster
+// contraction, initial partition of the coarsest level, projection and label
+// propagation local search on every level.  Every step fuses all jobs that are
+// at that step into one set of launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <string>
+
+#include "engine.h"
+
+namespace sclap {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+const char* last_error_cstr() { return g_err.c_str(); }
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int bits_for(int64_t count) {
+  if (count <= 2) return 1;
+  return 64 - __builtin_clzll((unsigned long long)(count - 1));
+}
+
+int dalloc(void** p, size_t bytes, hipStream_t st) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMallocAsync(p, bytes, st);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? SCLAP_ENOMEM : SCLAP_EHIP,
+                std::string("device allocation of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+  }
+  return SCLAP_OK;
+}
+
+void dfree(void* p, hipStream_t st) {
+  if (p) (void)hipFreeAsync(p, st);
+}
+
+int Scratch::ensure(size_t need, hipStream_t st) {
+  if (need <= bytes && p) return SCLAP_OK;
+  release(st);
+  size_t nb = need + need / 4 + 4096;
+  SCLAP_TRY(dalloc(&p, nb, st));
+  bytes = nb;
+  return SCLAP_OK;
+}
+
+void Scratch::release(hipStream_t st) {
+  dfree(p, st);
+  p = nullptr;
+  bytes = 0;
+}
+
+int ctx_ensure_pin(Ctx* c, size_t bytes) {
+  if (bytes <= c->pin_bytes) return SCLAP_OK;
+  if (c->pin) (void)hipHostFree(c->pin);
+  c->pin = nullptr;
+  size_t nb = std::max<size_t>(bytes, 1 << 16);
+  SCLAP_HIP(hipHostMalloc((void**)&c->pin, nb, hipHostMallocDefault));
+  c->pin_bytes = nb;
+  return SCLAP_OK;
+}
+
+int ctx_ensure_slots(Ctx* c, size_t count) {
+  if (count <= c->pin_slots_cap) return SCLAP_OK;
+  if (c->pin_slots) (void)hipHostFree(c->pin_slots);
+  c->pin_slots = nullptr;
+  size_t nc = std::max<size_t>(count, 64);
+  SCLAP_HIP(hipHostMalloc((void**)&c->pin_slots, nc * sizeof(DevSlot), hipHostMallocDefault));
+  c->pin_slots_cap = nc;
+  return SCLAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Levels and jobs.
+// ---------------------------------------------------------------------------
+int job_set_input(Ctx* c, Job* j, const sclap_csr* g, hipStream_t st) {
+  (void)c;
+  j->lv.clear();
+  j->lv.emplace_back();
+  Level& L = j->lv[0];
+  L.n = g->n;
+  L.m = g->m;
+  L.rp = g->row_ptr;
+  L.col = g->col;
+  L.ew = g->ew;
+  L.rows_sorted = g->rows_sorted;
+  SCLAP_TRY(dalloc_t(&L.own_nw, (size_t)std::max<int64_t>(g->n, 1), st));
+  SCLAP_TRY(widen_nw(g->nw, g->nw_bytes, g->n, L.own_nw, st));
+  L.nw = L.own_nw;
+  return SCLAP_OK;
+}
+
+int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipStream_t st) {
+  SCLAP_TRY(c->small.ensure(256, st));
+  unsigned long long* d = (unsigned long long*)c->small.p;
+  SCLAP_TRY(graph_totals(L->rp, L->nw, L->n, L->n, d, st));
+  SCLAP_TRY(ctx_ensure_pin(c, 64));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, d, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  if (sum_w) *sum_w = c->pin[0];
+  if (max_w) *max_w = c->pin[1];
+  L->n_active = c->pin[2];
+  L->hub_c = c->pin[3];
+  const int64_t hubs = c->pin[4];
+  int64_t t = 64;
+  const int64_t kk = std::max<int64_t>(j->k, 1);
+  while (t < 2 * kk) t <<= 1;
+  L->hub_r = hubs * t;
+  return SCLAP_OK;
+}
+
+void job_release_lp(Job* j, hipStream_t st, bool keep_lab) {
+  if (!keep_lab && j->lab_owned) dfree(j->lab, st);
+  if (!keep_lab) j->lab = nullptr;
+  j->lab_owned = false;
+  dfree(j->desire, st);
+  dfree(j->adm, st);
+  dfree(j->Wt, st);
+  dfree(j->inc, st);
+  dfree(j->fcur, st);
+  dfree(j->fnext, st);
+  j->desire = nullptr;
+  j->adm = nullptr;
+  j->Wt = nullptr;
+  j->inc = nullptr;
+  j->fcur = nullptr;
+  j->fnext = nullptr;
+}
+
+static void level_free(Level& L, hipStream_t st) {
+  dfree(L.own_rp, st);
+  dfree(L.own_col, st);
+  dfree(L.own_ew, st);
+  dfree(L.own_nw, st);
+  dfree(L.coarse_of, st);
+  L.own_rp = nullptr;
+  L.own_col = nullptr;
+  L.own_ew = nullptr;
+  L.own_nw = nullptr;
+  L.coarse_of = nullptr;
+}
+
+void job_release_levels(Job* j, hipStream_t st) {
+  for (auto& L : j->lv) level_free(L, st);
+}
+
+int job_begin_cluster(Ctx* c, Job* j, hipStream_t st) {
+  (void)c;
+  Level& L = j->lv[j->cur];
+  const int64_t n = L.n;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  if (j->kind == JOB_CLUSTER) {
+    j->lab = j->part_out;
+    j->lab_owned = false;
+  } else {
+    SCLAP_TRY(dalloc_t(&j->lab, nn, st));
+    j->lab_owned = true;
+  }
+  SCLAP_TRY(dalloc_t(&j->desire, nn, st));
+  SCLAP_TRY(dalloc_t(&j->adm, nn, st));
+  SCLAP_TRY(dalloc_t(&j->Wt, nn, st));
+  SCLAP_TRY(dalloc_t(&j->inc, nn, st));
+  SCLAP_TRY(fill_i64(j->inc, n, 0, st));
+  SCLAP_TRY(init_cluster(j->lab, j->desire, j->Wt, L.nw, n, st));
+  j->nlabels = n;
+  j->round = 1;
+  j->moved_prev = 0;
+  j->n_stop = (j->cur == 0 && j->kind == JOB_PARTITION) ? L.n_active : L.n;
+  j->stage = ST_COARSEN;
+  return SCLAP_OK;
+}
+
+int job_begin_refine(Ctx* c, Job* j, int32_t* part, bool owned, hipStream_t st) {
+  (void)c;
+  Level& L = j->lv[j->cur];
+  const int64_t n = L.n;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  const size_t kk = (size_t)std::max<int32_t>(j->k, 1);
+  j->lab = part;
+  j->lab_owned = owned;
+  SCLAP_TRY(dalloc_t(&j->desire, nn, st));
+  SCLAP_TRY(dalloc_t(&j->adm, nn, st));
+  SCLAP_TRY(dalloc_t(&j->Wt, kk, st));
+  SCLAP_TRY(dalloc_t(&j->inc, kk, st));
+  SCLAP_TRY(dalloc_t(&j->fcur, nn, st));
+  SCLAP_TRY(dalloc_t(&j->fnext, nn, st));
+  SCLAP_TRY(fill_i64(j->inc, j->k, 0, st));
+  SCLAP_TRY(fill_u8(j->fnext, n, 0, st));
+  SCLAP_TRY(fill_u8(j->fcur, n, 0, st));
+  SCLAP_TRY(copy_i32(part, j->desire, n, st));
+  SCLAP_TRY(block_weights(part, L.nw, n, j->k, j->Wt, st));
+  j->nlabels = j->k;
+  j->round = 1;
+  j->zero_streak = 0;
+  j->stage = ST_REFINE;
+  return SCLAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One fused LP round.
+// ---------------------------------------------------------------------------
+int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
+  const int ns = (int)jobs.size();
+  if (ns == 0) return SCLAP_OK;
+  SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
+  int64_t N = 0, Lt = 0, hub_need = 0;
+  SCLAP_TRY(c->step_ctr.ensure((size_t)ns * CTR_N * sizeof(int64_t), st));
+  int64_t* ctr = (int64_t*)c->step_ctr.p;
+  for (int s = 0; s < ns; ++s) {
+    Job* j = jobs[s];
+    const Level& L = j->lv[j->cur];
+    DevSlot& d = c->pin_slots[s];
+    std::memset(&d, 0, sizeof(d));
+    d.rp = L.rp;
+    d.col = L.col;
+    d.ew = L.ew;
+    d.nw = L.nw;
+    d.lab = j->lab;
+    d.desire = j->desire;
+    d.adm = j->adm;
+    d.W = j->Wt;
+    d.inc = j->inc;
+    d.flag_cur = j->fcur;
+    d.flag_next = j->fnext;
+    d.ctr = ctr + (size_t)s * CTR_N;
+    d.n = L.n;
+    d.nbase = N;
+    d.nlabels = j->nlabels;
+    d.lbase = Lt;
+    const bool refine = j->stage == ST_REFINE;
+    d.cap = refine ? j->lmax : j->U;
+    d.round = j->round;
+    d.mode = refine ? MODE_REFINE : MODE_CLUSTER;
+    d.dir_rule = j->dir_rule;
+    d.use_flags = refine && j->round > 1;
+    N += L.n;
+    Lt += j->nlabels;
+    hub_need += refine ? L.hub_r : L.hub_c;
+  }
+  if (N >= ((int64_t)1 << 31) || Lt >= ((int64_t)1 << 32))
+    return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
+  const size_t Nz = (size_t)std::max<int64_t>(N, 1);
+  SCLAP_TRY(c->bins.ensure(4 * Nz * sizeof(int32_t), st));
+  SCLAP_TRY(c->small.ensure(256, st));
+  SCLAP_TRY(c->hub_chunk.ensure((Nz + 1) * sizeof(uint32_t), st));
+  SCLAP_TRY(c->hub_tab.ensure(Nz * sizeof(int64_t), st));
+  if (c->hub_own.bytes < Nz * sizeof(int64_t)) {
+    SCLAP_TRY(c->hub_own.ensure(Nz * sizeof(int64_t), st));
+    SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
+  }
+  if (c->hub_cap < hub_need || !c->hub_gkeys.p) {
+    const int64_t cap = std::max<int64_t>(hub_need, 1024);
+    SCLAP_TRY(c->hub_gkeys.ensure((size_t)cap * 4, st));
+    SCLAP_TRY(c->hub_gvals.ensure((size_t)cap * 4, st));
+    c->hub_cap = (int64_t)std::min(c->hub_gkeys.bytes, c->hub_gvals.bytes) / 4;
+    SCLAP_TRY(fill_i32((int32_t*)c->hub_gkeys.p, c->hub_cap, -1, st));
+    SCLAP_TRY(fill_i32((int32_t*)c->hub_gvals.p, c->hub_cap, 0, st));
+  }
+  SCLAP_TRY(c->ckeys.ensure(Nz * 8, st));
+  SCLAP_TRY(c->slots_dev.ensure((size_t)ns * sizeof(DevSlot), st));
+  DevSlot* S = (DevSlot*)c->slots_dev.p;
+  SCLAP_HIP(hipMemcpyAsync(S, c->pin_slots, (size_t)ns * sizeof(DevSlot), hipMemcpyHostToDevice, st));
+  SCLAP_TRY(fill_i64(ctr, (int64_t)ns * CTR_N, 0, st));
+  uint32_t* small = (uint32_t*)c->small.p;  // [0..3] bin counts, [4] contended, [5] overflow, [6] hub chunks
+  SCLAP_TRY(fill_u32(small, 16, 0, st));
+  int32_t* bins = (int32_t*)c->bins.p;
+  const int64_t bin_cap = (int64_t)Nz;
+
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[0], st));
+  SCLAP_TRY(launch_bin(S, ns, N, bins, bin_cap, small, st));
+  RateHubScratch hub;
+  hub.chunk_off = (uint32_t*)c->hub_chunk.p;
+  hub.tab_off = (int64_t*)c->hub_tab.p;
+  hub.totals = small + 6;
+  hub.gkeys = (int32_t*)c->hub_gkeys.p;
+  hub.gvals = (int32_t*)c->hub_gvals.p;
+  hub.own = (int64_t*)c->hub_own.p;
+  hub.overflow = small + 5;
+  hub.tab_cap = c->hub_cap;
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[1], st));
+  SCLAP_TRY(launch_rate(S, ns, bins, bin_cap, small, hub, st));
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[2], st));
+  const int node_bits = bits_for(N);
+  const int lab_bits = bits_for(Lt);
+  SCLAP_TRY(launch_incoming_decide(S, ns, N, (uint64_t*)c->ckeys.p, small + 4, node_bits, st));
+  SCLAP_TRY(ctx_ensure_pin(c, 64));
+  uint32_t* hs = (uint32_t*)c->pin;
+  SCLAP_HIP(hipMemcpyAsync(hs, small, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  if (hs[5]) return fail(SCLAP_EHIP, "hub rating table too small");
+  const uint32_t cc = hs[4];
+  if (c->profile) {
+    c->prof_rate_visits += 0;  // filled from the slot counters below
+    c->prof_rate_nodes += (int64_t)hs[0] + hs[1] + hs[2] + hs[3];
+  }
+  if (cc > 0) {
+    SCLAP_TRY(c->ckeys2.ensure((size_t)cc * 8, st));
+    SCLAP_TRY(c->tkey.ensure((size_t)cc * 4, st));
+    SCLAP_TRY(c->wv.ensure((size_t)cc * 8, st));
+    SCLAP_TRY(c->prefix.ensure((size_t)cc * 8, st));
+    const size_t tb = std::max(prim_sort_keys_bytes(cc), prim_scan_by_key_bytes(cc));
+    SCLAP_TRY(c->prim.ensure(tb, st));
+    SCLAP_TRY(prim_sort_keys(c->prim.p, tb, (const uint64_t*)c->ckeys.p, (uint64_t*)c->ckeys2.p, cc,
+                             node_bits + lab_bits, st));
+    SCLAP_TRY(launch_contended_split(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits, (uint32_t*)c->tkey.p,
+                                     (int64_t*)c->wv.p, st));
+    SCLAP_TRY(prim_scan_by_key(c->prim.p, tb, (const uint32_t*)c->tkey.p, (const int64_t*)c->wv.p,
+                               (int64_t*)c->prefix.p, cc, st));
+    SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
+                                    (const int64_t*)c->prefix.p, st));
+  }
+  SCLAP_TRY(launch_apply(S, ns, N, st));
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[3], st));
+  SCLAP_TRY(ctx_ensure_pin(c, (size_t)ns * CTR_N * sizeof(int64_t)));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, ctr, (size_t)ns * CTR_N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  if (c->profile) {
+    float a = 0, b = 0;
+    SCLAP_HIP(hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
+    SCLAP_HIP(hipEventElapsedTime(&b, c->ev[0], c->ev[3]));
+    c->prof_rate_ms += a;
+    c->prof_round_ms += b;
+    c->prof_rate_launches += 1;
+    c->prof_rounds += 1;
+    for (int s = 0; s < ns; ++s) c->prof_rate_visits += c->pin[(size_t)s * CTR_N + CTR_VISITS];
+  }
+  return SCLAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Contraction of level i into level i + 1 (Section 3.1, Figure 2).
+// ---------------------------------------------------------------------------
+int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
+  Level& F = j->lv[i];
+  const int64_t n = F.n;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  int32_t *used = nullptr, *cid = nullptr;
+  SCLAP_TRY(dalloc_t(&used, nn, st));
+  SCLAP_TRY(dalloc_t(&cid, nn, st));
+  SCLAP_TRY(contract_flag(j->lab, F.rp, n, drop, used, st));
+  const size_t sb = prim_exscan_i32_bytes(nn);
+  SCLAP_TRY(c->prim.ensure(sb, st));
+  SCLAP_TRY(prim_exscan_i32(c->prim.p, sb, used, cid, (size_t)n, st));
+  SCLAP_TRY(ctx_ensure_pin(c, 64));
+  int64_t nc = 0;
+  if (n > 0) {
+    int32_t* h = (int32_t*)c->pin;
+    SCLAP_HIP(hipMemcpyAsync(h, cid + n - 1, 4, hipMemcpyDeviceToHost, st));
+    SCLAP_HIP(hipMemcpyAsync(h + 1, used + n - 1, 4, hipMemcpyDeviceToHost, st));
+    SCLAP_HIP(hipStreamSynchronize(st));
+    nc = (int64_t)h[0] + h[1];
+  }
+  Level C;
+  C.n = nc;
+  C.rows_sorted = 1;
+  SCLAP_TRY(dalloc_t(&F.coarse_of, nn, st));
+  SCLAP_TRY(dalloc_t(&C.own_nw, (size_t)std::max<int64_t>(nc, 1), st));
+  SCLAP_TRY(contract_coarse_of(j->lab, F.rp, F.nw, n, drop, cid, F.coarse_of, C.own_nw, nc, st));
+  dfree(used, st);
+  dfree(cid, st);
+  const int bits = bits_for(nc);
+  SCLAP_TRY(c->small.ensure(256, st));
+  unsigned long long* cnt = (unsigned long long*)c->small.p;
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, bits, 0, cnt, nullptr, nullptr, st));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, cnt, 8, hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  const int64_t mx = c->pin[0];
+  const size_t mz = (size_t)std::max<int64_t>(mx, 1);
+  uint64_t *k1 = nullptr, *k2 = nullptr;
+  int32_t *v1 = nullptr, *v2 = nullptr;
+  SCLAP_TRY(dalloc_t(&k1, mz, st));
+  SCLAP_TRY(dalloc_t(&k2, mz, st));
+  SCLAP_TRY(dalloc_t(&v1, mz, st));
+  SCLAP_TRY(dalloc_t(&v2, mz, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, bits, 1, cnt, k1, v1, st));
+  const size_t tb = std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
+  SCLAP_TRY(c->prim.ensure(tb, st));
+  SCLAP_TRY(prim_sort_pairs(c->prim.p, tb, k1, k2, v1, v2, (size_t)mx, 2 * bits, st));
+  // reduce equal (x, y) keys: unique keys into k1, sums into an int64 buffer
+  int64_t* aggs = nullptr;
+  SCLAP_TRY(dalloc_t(&aggs, mz, st));
+  uint32_t* ucount = (uint32_t*)((char*)c->small.p + 64);
+  SCLAP_TRY(fill_u32(ucount, 2, 0, st));
+  if (mx > 0) SCLAP_TRY(prim_reduce_by_key(c->prim.p, tb, k2, v2, k1, aggs, ucount, (size_t)mx, st));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, ucount, 4, hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  const int64_t mc = (int64_t)((uint32_t*)c->pin)[0];
+  C.m = mc;
+  SCLAP_TRY(dalloc_t(&C.own_rp, (size_t)nc + 1, st));
+  SCLAP_TRY(dalloc_t(&C.own_col, (size_t)std::max<int64_t>(mc, 1), st));
+  SCLAP_TRY(dalloc_t(&C.own_ew, (size_t)std::max<int64_t>(mc, 1), st));
+  unsigned* ovf = (unsigned*)ucount + 1;
+  SCLAP_TRY(contract_finish(k1, aggs, mc, bits, nc, C.own_rp, C.own_col, C.own_ew, ovf, st));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, ovf, 4, hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  const unsigned overflow = ((uint32_t*)c->pin)[0];
+  dfree(k1, st);
+  dfree(k2, st);
+  dfree(v1, st);
+  dfree(v2, st);
+  dfree(aggs, st);
+  C.rp = C.own_rp;
+  C.col = C.own_col;
+  C.ew = C.own_ew;
+  C.nw = C.own_nw;
+  j->lv.push_back(C);
+  if (overflow) return fail(SCLAP_EOVERFLOW, "coarse edge weight exceeds int32");
+  return SCLAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fused initial partition: one workgroup per job.
+// ---------------------------------------------------------------------------
+int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipStream_t st) {
+  const int cnt = (int)jobs.size();
+  if (cnt == 0) return SCLAP_OK;
+  std::vector<IpSlot> hs(cnt);
+  std::vector<int32_t*> scratch(cnt, nullptr);
+  for (int s = 0; s < cnt; ++s) {
+    Job* j = jobs[s];
+    const Level& L = j->lv[j->cur];
+    const int64_t n = L.n;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    SCLAP_TRY(dalloc_t(&scratch[s], 4 * nn, st));
+    IpSlot& x = hs[s];
+    x.rp = L.rp;
+    x.col = L.col;
+    x.nw = L.nw;
+    x.n = n;
+    x.k = j->k;
+    x.skip_isolated = (j->cur == 0 && j->kind == JOB_PARTITION) ? 1 : 0;
+    x.rows_sorted = L.rows_sorted;
+    x.part = parts[s];
+    x.order = scratch[s];
+    x.pos = scratch[s] + nn;
+    x.claim = scratch[s] + 2 * nn;
+    x.cnt = scratch[s] + 3 * nn;
+    SCLAP_TRY(fill_i32(x.part, n, -1, st));
+    SCLAP_TRY(fill_i32(x.pos, n, -1, st));
+    SCLAP_TRY(fill_i32(x.claim, n, INT32_MAX, st));
+  }
+  SCLAP_TRY(c->ip_slots.ensure((size_t)cnt * sizeof(IpSlot), st));
+  SCLAP_TRY(ctx_ensure_pin(c, (size_t)cnt * sizeof(IpSlot)));
+  std::memcpy(c->pin, hs.data(), (size_t)cnt * sizeof(IpSlot));
+  SCLAP_HIP(hipMemcpyAsync(c->ip_slots.p, c->pin, (size_t)cnt * sizeof(IpSlot), hipMemcpyHostToDevice, st));
+  SCLAP_TRY(initial_partition((const IpSlot*)c->ip_slots.p, cnt, st));
+  SCLAP_HIP(hipStreamSynchronize(st));  // pinned staging is reused right after
+  for (int s = 0; s < cnt; ++s) dfree(scratch[s], st);
+  return SCLAP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Executor.
+// ---------------------------------------------------------------------------
+static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, hipStream_t st) {
+  if (c->small.ensure(256, st) != SCLAP_OK) return -1;
+  unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
+  if (cut_twice(L.rp, L.col, L.ew, part, L.n, d, st) != SCLAP_OK) return -1;
+  if (ctx_ensure_pin(c, 64) != SCLAP_OK) return -1;
+  if (hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
+  if (hipStreamSynchronize(st) != hipSuccess) return -1;
+  return c->pin[0] / 2;
+}
+
+// Allocate the block array of level i (level 0 writes the caller's buffer).
+static int alloc_part(Job* j, int i, int32_t** out, bool* owned, hipStream_t st) {
+  if (i == 0 && j->part_out) {
+    *out = j->part_out;
+    *owned = false;
+    return SCLAP_OK;
+  }
+  *owned = true;
+  return dalloc_t(out, (size_t)std::max<int64_t>(j->lv[i].n, 1), st);
+}
+
+static int finish_partition(Ctx* c, Job* j, hipStream_t st) {
+  Level& L = j->lv[0];
+  int32_t* part = j->part_out;
+  const int64_t k = j->k;
+  int64_t* B = nullptr;
+  SCLAP_TRY(dalloc_t(&B, (size_t)k, st));
+  if (j->st.n_isolated > 0) {
+    SCLAP_TRY(block_weights(part, L.nw, L.n, j->k, B, st));
+    int64_t *tw = nullptr, *tp = nullptr, *ends = nullptr;
+    int32_t* last = nullptr;
+    SCLAP_TRY(dalloc_t(&tw, (size_t)L.n, st));
+    SCLAP_TRY(dalloc_t(&tp, (size_t)L.n, st));
+    SCLAP_TRY(dalloc_t(&ends, (size_t)k, st));
+    SCLAP_TRY(dalloc_t(&last, 1, st));
+    const size_t sb = prim_exscan_i64_bytes((size_t)L.n);
+    SCLAP_TRY(c->prim.ensure(sb, st));
+    SCLAP_TRY(place_isolated(L.rp, L.nw, L.n, B, j->k, part, tw, tp, ends, last, c->prim.p, sb, st));
+    dfree(tw, st);
+    dfree(tp, st);
+    dfree(ends, st);
+    dfree(last, st);
+  }
+  SCLAP_TRY(block_weights(part, L.nw, L.n, j->k, B, st));
+  const int64_t cut = read_cut(c, L, part, st);
+  if (cut < 0) return fail(SCLAP_EHIP, "cut");
+  SCLAP_TRY(ctx_ensure_pin(c, (size_t)k * 8));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, B, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  int64_t mb = 0;
+  for (int64_t b = 0; b < k; ++b) mb = std::max(mb, c->pin[b]);
+  dfree(B, st);
+  j->st.cut = cut;
+  j->st.max_block = mb;
+  return SCLAP_OK;
+}
+
+// After the refinement of level cur: project to the next finer level or
+// finish.
+static int after_refine_level(Ctx* c, Job* j, hipStream_t st) {
+  if (j->kind == JOB_REFINE) {
+    job_release_lp(j, st, true);
+    j->stage = ST_DONE;
+    return SCLAP_OK;
+  }
+  if (j->cur == 0) {
+    job_release_lp(j, st, true);
+    j->stage = ST_FINISH;
+    return SCLAP_OK;
+  }
+  const int fine = j->cur - 1;
+  int32_t* pf = nullptr;
+  bool owned = false;
+  SCLAP_TRY(alloc_part(j, fine, &pf, &owned, st));
+  SCLAP_TRY(project(j->lv[fine].coarse_of, j->lab, j->lv[fine].n, pf, st));
+  job_release_lp(j, st, false);
+  // the coarse level is no longer needed
+  level_free(j->lv[j->cur], st);
+  j->cur = fine;
+  if (j->ref_rounds <= 0) {
+    j->lab = pf;
+    j->lab_owned = owned;
+    return after_refine_level(c, j, st);
+  }
+  return job_begin_refine(c, j, pf, owned, st);
+}
+
+static int start_ip_or_refine(Ctx* c, Job* j, std::vector<Job*>& ipq) {
+  (void)c;
+  j->stage = ST_IP;
+  ipq.push_back(j);
+  return SCLAP_OK;
+}
+
+static int after_contract(Ctx* c, Job* j, std::vector<Job*>& ipq, hipStream_t st) {
+  // level cur was just contracted into cur + 1
+  const int64_t n_prev = j->cur == 0 ? j->lv[0].n_active : j->lv[j->cur].n;
+  job_release_lp(j, st, false);
+  j->cur += 1;
+  Level& L = j->lv[j->cur];
+  SCLAP_TRY(level_totals(c, j, &L, nullptr, nullptr, st));
+  j->st.levels = j->cur + 1;
+  j->st.n_level[j->cur] = L.n;
+  j->st.m_level[j->cur] = L.m;
+  const bool stall = 20 * (n_prev - L.n) < n_prev;
+  if (L.n > j->threshold && !stall && j->cur + 1 < SCLAP_MAX_LEVELS) return job_begin_cluster(c, j, st);
+  return start_ip_or_refine(c, j, ipq);
+}
+
+int run_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
+  std::vector<Job*> ipq;
+  for (Job* j : jobs) {
+    if (j->stage == ST_IP) ipq.push_back(j);
+  }
+  for (;;) {
+    // 1. LP rounds
+    std::vector<Job*> lp;
+    for (Job* j : jobs)
+      if (j->stage == ST_COARSEN || j->stage == ST_REFINE) lp.push_back(j);
+    if (!lp.empty()) {
+      const double t0 = now_ms();
+      SCLAP_TRY(lp_round(c, lp, st));
+      const double dt = now_ms() - t0;
+      for (size_t s = 0; s < lp.size(); ++s) {
+        Job* j = lp[s];
+        const int64_t moved = c->pin[s * CTR_N + CTR_MOVED];
+        const int64_t visits = c->pin[s * CTR_N + CTR_VISITS];
+        const int r = j->round;
+        if (j->stage == ST_COARSEN) {
+          j->st.ms_cluster += dt;
+          j->st.moved_c[j->cur][r - 1] = moved;
+          j->st.visits_c[j->cur] += visits;
+          j->rst.moved[r - 1] = moved;
+          j->rst.visits += visits;
+          j->rst.ms += dt;
+          bool done = r >= j->lp_rounds;
+          if (j->stop_rule == 1 && r >= 2 && 20 * (moved + j->moved_prev) < j->n_stop) done = true;
+          j->moved_prev = moved;
+          if (done) {
+            j->st.rounds_c[j->cur] = r;
+            j->rst.rounds = r;
+            j->stage = j->kind == JOB_CLUSTER ? ST_DONE : ST_CONTRACT;
+            if (j->kind == JOB_CLUSTER) job_release_lp(j, st, true);
+          } else {
+            j->round = r + 1;
+          }
+        } else {
+          j->st.ms_refine += dt;
+          j->st.moved_r[j->cur][r - 1] = moved;
+          j->st.visits_r[j->cur] += visits;
+          j->rst.moved[r - 1] = moved;
+          j->rst.visits += visits;
+          j->rst.ms += dt;
+          j->zero_streak = moved == 0 ? j->zero_streak + 1 : 0;
+          const bool done = r >= j->ref_rounds || j->zero_streak >= 2;
+          if (done) {
+            j->st.rounds_r[j->cur] = r;
+            j->rst.rounds = r;
+            SCLAP_TRY(after_refine_level(c, j, st));
+          } else {
+            std::swap(j->fcur, j->fnext);
+            SCLAP_TRY(fill_u8(j->fnext, j->lv[j->cur].n, 0, st));
+            j->round = r + 1;
+          }
+        }
+      }
+    }
+    // 2. contractions
+    for (Job* j : jobs) {
+      if (j->stage != ST_CONTRACT) continue;
+      const double t0 = now_ms();
+      int rc = contract_level(c, j, j->cur, j->cur == 0 ? 1 : 0, st);
+      if (rc == SCLAP_EOVERFLOW) {
+        j->status = rc;
+        j->stage = ST_ERROR;
+        job_release_lp(j, st, false);
+        continue;
+      }
+      SCLAP_TRY(rc);
+      SCLAP_TRY(after_contract(c, j, ipq, st));
+      j->st.ms_contract += now_ms() - t0;
+    }
+    // 3. initial partitions
+    if (!ipq.empty()) {
+      const double t0 = now_ms();
+      std::vector<int32_t*> parts(ipq.size());
+      std::vector<bool> owned(ipq.size());
+      for (size_t s = 0; s < ipq.size(); ++s) {
+        bool o = false;
+        SCLAP_TRY(alloc_part(ipq[s], ipq[s]->cur, &parts[s], &o, st));
+        owned[s] = o;
+      }
+      SCLAP_TRY(ip_jobs(c, ipq, parts, st));
+      const double dt = now_ms() - t0;
+      for (size_t s = 0; s < ipq.size(); ++s) {
+        Job* j = ipq[s];
+        j->st.ms_initial += dt;
+        j->st.ip_cut = read_cut(c, j->lv[j->cur], parts[s], st);
+        if (j->ref_rounds > 0) {
+          SCLAP_TRY(job_begin_refine(c, j, parts[s], owned[s], st));
+        } else {
+          j->lab = parts[s];
+          j->lab_owned = owned[s];
+          SCLAP_TRY(after_refine_level(c, j, st));
+        }
+      }
+      ipq.clear();
+    }
+    // 4. finish
+    bool all_done = true;
+    for (Job* j : jobs) {
+      if (j->stage == ST_FINISH) {
+        SCLAP_TRY(finish_partition(c, j, st));
+        j->stage = ST_DONE;
+      }
+      if (j->stage == ST_DONE && j->st.ms_total == 0) j->st.ms_total = now_ms() - j->t_start;
+      if (j->stage != ST_DONE && j->stage != ST_ERROR) all_done = false;
+    }
+    if (all_done) break;
+  }
+  return SCLAP_OK;
+}
+
+}  // namespace sclap

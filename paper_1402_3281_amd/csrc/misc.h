@@ -1,0 +1,61 @@
+// misc.h -- launchers of the contraction, initial-partition, projection, cut,
+// block-weight, placement and validation kernels.
+#pragma once
+
+#include "common.h"
+
+namespace sclap {
+
+int fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
+int fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
+int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+
+// out4 (device, 5 entries): [sum c, max c, #nodes of degree > 0, hub table entries, #hubs]
+int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t nlabels, unsigned long long* out4,
+                 hipStream_t st);
+int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st);
+int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);
+int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st);
+int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, int64_t* W, hipStream_t st);
+int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n,
+              unsigned long long* out, hipStream_t st);
+
+int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st);
+int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw, int64_t n, int drop,
+                       const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, hipStream_t st);
+int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
+                   int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals, hipStream_t st);
+int contract_finish(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int64_t nc, int64_t* rp,
+                    int32_t* col, int32_t* ew, unsigned* overflow, hipStream_t st);
+int project(const int32_t* cof, const int32_t* pc, int64_t n, int32_t* pf, hipStream_t st);
+
+// One graph of a fused initial-partition launch.
+struct IpSlot {
+  const int64_t* rp;
+  const int32_t* col;
+  const int64_t* nw;
+  int64_t n;
+  int32_t k;
+  int32_t skip_isolated;
+  int32_t rows_sorted;
+  int32_t pad;
+  int32_t* part;   // n, pre-filled with -1
+  int32_t* order;  // n scratch
+  int32_t* pos;    // n scratch, pre-filled with -1
+  int32_t* claim;  // n scratch, pre-filled with INT32_MAX
+  int32_t* cnt;    // n scratch
+};
+int initial_partition(const IpSlot* dev_slots, int count, hipStream_t st);
+
+int place_isolated(const int64_t* rp, const int64_t* nw, int64_t n, const int64_t* B, int32_t k, int32_t* part,
+                   int64_t* tmp_w, int64_t* tmp_pre, int64_t* ends, int32_t* last, void* scan_tmp, size_t scan_bytes,
+                   hipStream_t st);
+
+int validate_keys(const int64_t* rp, const int32_t* col, const int32_t* ew, int64_t n, int64_t m, int bits,
+                  uint64_t* fk, uint64_t* rk, int32_t* fw, unsigned* bad, hipStream_t st);
+int validate_cmp(const uint64_t* fk, const uint64_t* rk, const int32_t* fw, const int32_t* rw, int64_t m,
+                 unsigned* bad, hipStream_t st);
+int validate_nw(const void* nw, int bytes, int64_t n, unsigned* bad, hipStream_t st);
+
+}  // namespace sclap

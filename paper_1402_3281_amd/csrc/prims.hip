@@ -1,0 +1,103 @@
+// prims.hip -- thin wrappers over rocPRIM device-wide primitives (radix sort,
+// scans, reduce-by-key), kept in one translation unit.  All of them operate
+// on integers, so their results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include <rocprim/rocprim.hpp>
+
+#include "lp.h"
+
+namespace sclap {
+
+#define PRIM_CALL(expr)                                                              \
+  do {                                                                               \
+    hipError_t _e = (expr);                                                          \
+    if (_e != hipSuccess) return fail(SCLAP_EHIP, std::string("rocprim: ") + hipGetErrorString(_e)); \
+  } while (0)
+
+size_t prim_sort_keys_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::radix_sort_keys(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr, n, 0, 64);
+  return b;
+}
+
+int prim_sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, size_t n, int end_bit,
+                   hipStream_t st) {
+  if (n == 0) return SCLAP_OK;
+  PRIM_CALL(rocprim::radix_sort_keys(tmp, tmp_bytes, in, out, n, 0, (unsigned)end_bit, st));
+  return SCLAP_OK;
+}
+
+size_t prim_sort_pairs_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, b, (const uint64_t*)nullptr, (uint64_t*)nullptr, (const int32_t*)nullptr,
+                            (int32_t*)nullptr, n, 0, 64);
+  return b;
+}
+
+int prim_sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
+                    int32_t* vout, size_t n, int end_bit, hipStream_t st) {
+  if (n == 0) return SCLAP_OK;
+  PRIM_CALL(rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, n, 0, (unsigned)end_bit, st));
+  return SCLAP_OK;
+}
+
+size_t prim_scan_by_key_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::inclusive_scan_by_key(nullptr, b, (const uint32_t*)nullptr, (const int64_t*)nullptr, (int64_t*)nullptr,
+                                 n, rocprim::plus<int64_t>());
+  return b;
+}
+
+int prim_scan_by_key(void* tmp, size_t tmp_bytes, const uint32_t* keys, const int64_t* in, int64_t* out, size_t n,
+                     hipStream_t st) {
+  if (n == 0) return SCLAP_OK;
+  PRIM_CALL(rocprim::inclusive_scan_by_key(tmp, tmp_bytes, keys, in, out, n, rocprim::plus<int64_t>(),
+                                           rocprim::equal_to<uint32_t>(), st));
+  return SCLAP_OK;
+}
+
+size_t prim_exscan_i32_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::exclusive_scan(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr, (int32_t)0, n,
+                          rocprim::plus<int32_t>());
+  return b;
+}
+
+int prim_exscan_i32(void* tmp, size_t tmp_bytes, const int32_t* in, int32_t* out, size_t n, hipStream_t st) {
+  if (n == 0) return SCLAP_OK;
+  PRIM_CALL(rocprim::exclusive_scan(tmp, tmp_bytes, in, out, (int32_t)0, n, rocprim::plus<int32_t>(), st));
+  return SCLAP_OK;
+}
+
+size_t prim_exscan_i64_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::exclusive_scan(nullptr, b, (const int64_t*)nullptr, (int64_t*)nullptr, (int64_t)0, n,
+                          rocprim::plus<int64_t>());
+  return b;
+}
+
+int prim_exscan_i64(void* tmp, size_t tmp_bytes, const int64_t* in, int64_t* out, size_t n, hipStream_t st) {
+  if (n == 0) return SCLAP_OK;
+  PRIM_CALL(rocprim::exclusive_scan(tmp, tmp_bytes, in, out, (int64_t)0, n, rocprim::plus<int64_t>(), st));
+  return SCLAP_OK;
+}
+
+size_t prim_reduce_by_key_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::reduce_by_key(nullptr, b, (const uint64_t*)nullptr, (const int32_t*)nullptr, n, (uint64_t*)nullptr,
+                         (int64_t*)nullptr, (uint32_t*)nullptr, rocprim::plus<int64_t>());
+  return b;
+}
+
+int prim_reduce_by_key(void* tmp, size_t tmp_bytes, const uint64_t* keys, const int32_t* vals, uint64_t* ukeys,
+                       int64_t* aggs, uint32_t* count, size_t n, hipStream_t st) {
+  PRIM_CALL(rocprim::reduce_by_key(tmp, tmp_bytes, keys, vals, n, ukeys, aggs, count, rocprim::plus<int64_t>(),
+                                   rocprim::equal_to<uint64_t>(), st));
+  return SCLAP_OK;
+}
+
+}  // namespace sclap
