@@ -89,14 +89,20 @@ def main() -> int:
     ms_per_step = elapsed * 1000.0 / args.steps
     value = visits / elapsed
 
-    # rating step roofline: algorithmic bytes per launch / mean launch time
-    rate_bytes = prof["rate_bytes"] if "rate_bytes" in prof else None
-    launches = max(prof["rate_launches"], 1)
-    avg_ms = prof["rate_ms"] / launches
-    if rate_bytes is None:
-        rate_bytes = 8 * prof["visits"] + 32 * prof["nodes"]
-    bytes_per_launch = rate_bytes / launches
+    # roofline of the dominant rating kernel: algorithmic bytes per launch
+    # (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge
+    # visit, 32 B per rated node) / mean launch duration (HIP events)
+    names = ["k_rate_group<8>", "k_rate_group<16>", "k_rate_group<32>", "k_rate_group<64>", "k_rate_wave<256>",
+             "k_rate_wave<1024>", "k_rate_block<2048, 256>", "k_rate_block<8192, 512>", "hub path (4 kernels)"]
+    launches = max(prof["kernel_launches"], 1)
+    dom = max(range(8), key=lambda b: prof["kernels"][b]["ms"])
+    kd = prof["kernels"][dom]
+    avg_ms = kd["ms"] / launches
+    bytes_per_launch = kd["bytes"] / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    step_kernels = [{"kernel": names[b], "ms_per_round": prof["kernels"][b]["ms"] / launches,
+                     "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
+                     if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(9)]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -136,9 +142,10 @@ def main() -> int:
             "levels": [s["n_level"] for s in sts],
         },
         "sclap_round_visits_per_s": (prof["visits"] / (prof["round_ms"] * 1e-3)) if prof["round_ms"] > 0 else None,
+        "rating_kernels": step_kernels,
         "roofline": {
             "bound": "hbm",
-            "kernel": "rating step (degree-binned rate kernels of one LP round)",
+            "kernel": names[dom],
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -146,7 +153,7 @@ def main() -> int:
             "traffic": None,
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms,
-            "launches": prof["rate_launches"],
+            "launches": launches,
         },
         "cpu_baseline": cpu,
     }

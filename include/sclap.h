@@ -267,6 +267,13 @@ int sclap_profile_enable(sclap_ctx* ctx, int32_t on);
  * visits and nodes rated, whole-round device ms and rounds. */
 int sclap_profile_read(sclap_ctx* ctx, double* rate_ms, int64_t* rate_launches, int64_t* visits, int64_t* nodes,
                        double* round_ms, int64_t* rounds);
+/* Per rating kernel (degree bins 0..6: 8, 16, 32 and 64 lanes per node, one
+ * wave with an LDS table, one workgroup with an LDS table, the multi-
+ * workgroup hub path): device ms, algorithmic bytes (4 B neighbour id + 4 B
+ * neighbour label [+ 4 B edge weight] per visit, 32 B per rated node), edge
+ * visits and nodes, summed over rounds; *launches = rounds profiled. */
+int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
+                          int64_t* launches);
 
 #ifdef __cplusplus
 }

@@ -132,6 +132,8 @@ SIGNATURES = {
     "sclap_profile_enable": (ctypes.c_int, [_vp, _i32]),
     "sclap_profile_read": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(_i64), _P(_i64), _P(_i64),
                                           _P(ctypes.c_double), _P(_i64)]),
+    "sclap_profile_kernels": (ctypes.c_int, [_vp, _i32, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i64),
+                                             _P(_i64), _P(_i64)]),
 }
 
 _lib = None
@@ -198,8 +200,17 @@ class Context:
         la, vis, nodes, rounds = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self.lib.sclap_profile_read(self.h, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(vis),
                                            ctypes.byref(nodes), ctypes.byref(rnd_ms), ctypes.byref(rounds)))
-        return {"rate_ms": ms.value, "rate_launches": la.value, "visits": vis.value, "nodes": nodes.value,
-                "round_ms": rnd_ms.value, "rounds": rounds.value}
+        out = {"rate_ms": ms.value, "rate_launches": la.value, "visits": vis.value, "nodes": nodes.value,
+               "round_ms": rnd_ms.value, "rounds": rounds.value}
+        K = 9
+        kms, kb = (ctypes.c_double * K)(), (ctypes.c_double * K)()
+        kv, kn = (ctypes.c_int64 * K)(), (ctypes.c_int64 * K)()
+        kl = ctypes.c_int64()
+        _check(self.lib.sclap_profile_kernels(self.h, K, kms, kb, kv, kn, ctypes.byref(kl)))
+        out["kernels"] = [{"bin": i, "ms": kms[i], "bytes": kb[i], "visits": kv[i], "nodes": kn[i]}
+                          for i in range(K)]
+        out["kernel_launches"] = kl.value
+        return out
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:

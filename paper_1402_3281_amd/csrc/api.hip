@@ -164,7 +164,7 @@ int sclap_destroy(sclap_ctx* ctx) {
   (void)hipDeviceSynchronize();
   Scratch* all[] = {&c.bins, &c.ckeys, &c.ckeys2, &c.tkey, &c.wv, &c.prefix, &c.prim, &c.hub_chunk,
                     &c.hub_tab, &c.hub_own, &c.hub_gkeys, &c.hub_gvals, &c.step_ctr, &c.small,
-                    &c.slots_dev, &c.ip_slots};
+                    &c.slots_dev, &c.ip_slots, &c.hub_slice, &c.hub_best, &c.movers};
   for (Scratch* s : all) s->release(nullptr);
   (void)hipDeviceSynchronize();
   if (c.pin) (void)hipHostFree(c.pin);
@@ -412,7 +412,7 @@ int sclap_cut(sclap_ctx* ctx, const sclap_csr* g, const int32_t* part, int32_t k
   hipStream_t st = as_stream(stream);
   SCLAP_TRY(c->small.ensure(256, st));
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
-  SCLAP_TRY(cut_twice(g->row_ptr, g->col, g->ew, part, g->n, d, st));
+  SCLAP_TRY(cut_twice(g->row_ptr, g->col, g->ew, part, g->n, g->m, d, st));
   SCLAP_TRY(ctx_ensure_pin(c, 64 + (size_t)k * 8));
   SCLAP_HIP(hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
@@ -485,6 +485,27 @@ int sclap_profile_enable(sclap_ctx* ctx, int32_t on) {
   ctx->c.prof_rate_nodes = 0;
   ctx->c.prof_round_ms = 0;
   ctx->c.prof_rounds = 0;
+  ctx->c.prof_k_launches = 0;
+  for (int b = 0; b < kBins; ++b) {
+    ctx->c.prof_k_ms[b] = 0;
+    ctx->c.prof_k_bytes[b] = 0;
+    ctx->c.prof_k_visits[b] = 0;
+    ctx->c.prof_k_nodes[b] = 0;
+  }
+  return SCLAP_OK;
+}
+
+int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
+                          int64_t* launches) {
+  if (!ctx || count < 0) return fail(SCLAP_EINVAL, "bad argument");
+  const Ctx& c = ctx->c;
+  for (int b = 0; b < count && b < kBins; ++b) {
+    if (ms) ms[b] = c.prof_k_ms[b];
+    if (bytes) bytes[b] = c.prof_k_bytes[b];
+    if (visits) visits[b] = c.prof_k_visits[b];
+    if (nodes) nodes[b] = c.prof_k_nodes[b];
+  }
+  if (launches) *launches = c.prof_k_launches;
   return SCLAP_OK;
 }
 

@@ -69,12 +69,14 @@ struct DevSlot {
 
 enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_N = 4 };
 
-// Degree bins of the rating kernels.
-constexpr int kBins = 4;
-constexpr int64_t kBinG8 = 8;        // degree 1..8: 8 lanes per node
-constexpr int64_t kBinG64 = 64;      // degree 9..64: one wave per node
-constexpr int64_t kBinBlock = 4096;  // degree 65..4096: one workgroup per node, LDS table
-// above kBinBlock: several workgroups per node, global table
+// Degree bins of the rating kernels:
+//   0: 1..8       8 lanes per node        5: 129..512    one wave, 1024-entry LDS table
+//   1: 9..16      16 lanes per node       6: 513..1024   one workgroup, 2048-entry LDS table
+//   2: 17..32     32 lanes per node       7: 1025..4096  one workgroup, 8192-entry LDS table
+//   3: 33..64     one wave per node       8: > 4096      several workgroups, global table
+//   4: 65..128    one wave, 256-entry LDS table
+constexpr int kBins = 9;
+constexpr int64_t kBinBlock = 4096;
 
 constexpr int kHubChunk = 4096;      // entries per workgroup in the multi-workgroup path
 

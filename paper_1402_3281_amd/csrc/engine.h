@@ -77,22 +77,27 @@ struct Ctx {
   int cu_count = 256;
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
-  Scratch step_ctr, small, slots_dev, ip_slots;
+  Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers;
   int64_t hub_cap = 0;             // entries of the global hub table (kept -1/0)
   // pinned host staging
   int64_t* pin = nullptr;
   size_t pin_bytes = 0;
   DevSlot* pin_slots = nullptr;
   size_t pin_slots_cap = 0;
-  // optional per-kernel timing of the rating step
+  // optional timing of the rating kernels (per degree bin) and LP rounds
   bool profile = false;
-  hipEvent_t ev[8];
-  double prof_rate_ms = 0;         // sum over launches of the rating step
+  hipEvent_t ev[kBins + 3];       // [0..kBins] rating kernels, [kBins+1], [kBins+2] whole round
+  double prof_rate_ms = 0;         // sum over rounds of the whole rating step
   int64_t prof_rate_launches = 0;
   int64_t prof_rate_visits = 0;
   int64_t prof_rate_nodes = 0;
   double prof_round_ms = 0;        // whole LP rounds
   int64_t prof_rounds = 0;
+  double prof_k_ms[kBins] = {};    // per rating kernel (last bin: the four hub kernels)
+  double prof_k_bytes[kBins] = {}; // algorithmic bytes moved by that kernel
+  int64_t prof_k_visits[kBins] = {};
+  int64_t prof_k_nodes[kBins] = {};
+  int64_t prof_k_launches = 0;
 };
 
 int ctx_ensure_pin(Ctx* c, size_t bytes);

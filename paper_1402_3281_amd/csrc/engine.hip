@@ -253,14 +253,20 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (N >= ((int64_t)1 << 31) || Lt >= ((int64_t)1 << 32))
     return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
   const size_t Nz = (size_t)std::max<int64_t>(N, 1);
-  SCLAP_TRY(c->bins.ensure(4 * Nz * sizeof(int32_t), st));
-  SCLAP_TRY(c->small.ensure(256, st));
+  SCLAP_TRY(c->bins.ensure(kBins * Nz * sizeof(int32_t), st));
+  SCLAP_TRY(c->small.ensure(1024, st));
   SCLAP_TRY(c->hub_chunk.ensure((Nz + 1) * sizeof(uint32_t), st));
   SCLAP_TRY(c->hub_tab.ensure(Nz * sizeof(int64_t), st));
+  SCLAP_TRY(c->hub_slice.ensure((Nz + 1) * sizeof(uint32_t), st));
   if (c->hub_own.bytes < Nz * sizeof(int64_t)) {
     SCLAP_TRY(c->hub_own.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
   }
+  if (c->hub_best.bytes < Nz * sizeof(int64_t)) {
+    SCLAP_TRY(c->hub_best.ensure(Nz * sizeof(int64_t), st));
+    SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
+  }
+  SCLAP_TRY(c->movers.ensure(Nz * sizeof(int32_t), st));
   if (c->hub_cap < hub_need || !c->hub_gkeys.p) {
     const int64_t cap = std::max<int64_t>(hub_need, 1024);
     SCLAP_TRY(c->hub_gkeys.ensure((size_t)cap * 4, st));
@@ -274,37 +280,55 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   DevSlot* S = (DevSlot*)c->slots_dev.p;
   SCLAP_HIP(hipMemcpyAsync(S, c->pin_slots, (size_t)ns * sizeof(DevSlot), hipMemcpyHostToDevice, st));
   SCLAP_TRY(fill_i64(ctr, (int64_t)ns * CTR_N, 0, st));
-  uint32_t* small = (uint32_t*)c->small.p;  // [0..3] bin counts, [4] contended, [5] overflow, [6] hub chunks
-  SCLAP_TRY(fill_u32(small, 16, 0, st));
+  // lp counters: u32 [0..8] bin counts, [9] contended, [10] overflow, [11..12] hub
+  // chunks and slices, [13] refinement movers; u64 at byte 64: visits per bin
+  uint32_t* small = (uint32_t*)((char*)c->small.p + 256);
+  unsigned long long* bin_vis = (unsigned long long*)((char*)small + 64);
+  SCLAP_TRY(fill_u32(small, 64, 0, st));
   int32_t* bins = (int32_t*)c->bins.p;
   const int64_t bin_cap = (int64_t)Nz;
 
-  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[0], st));
-  SCLAP_TRY(launch_bin(S, ns, N, bins, bin_cap, small, st));
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kBins + 1], st));
+  SCLAP_TRY(launch_bin(S, ns, N, bins, bin_cap, small, bin_vis, st));
   RateHubScratch hub;
   hub.chunk_off = (uint32_t*)c->hub_chunk.p;
   hub.tab_off = (int64_t*)c->hub_tab.p;
-  hub.totals = small + 6;
+  hub.totals = small + 11;
+  hub.slice_off = (uint32_t*)c->hub_slice.p;
+  hub.best = (unsigned long long*)c->hub_best.p;
   hub.gkeys = (int32_t*)c->hub_gkeys.p;
   hub.gvals = (int32_t*)c->hub_gvals.p;
   hub.own = (int64_t*)c->hub_own.p;
-  hub.overflow = small + 5;
+  hub.overflow = small + 10;
   hub.tab_cap = c->hub_cap;
-  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[1], st));
-  SCLAP_TRY(launch_rate(S, ns, bins, bin_cap, small, hub, st));
-  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[2], st));
+  SCLAP_TRY(launch_rate(S, ns, bins, bin_cap, small, hub, N, st, c->profile ? c->ev : nullptr));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
-  SCLAP_TRY(launch_incoming_decide(S, ns, N, (uint64_t*)c->ckeys.p, small + 4, node_bits, st));
-  SCLAP_TRY(ctx_ensure_pin(c, 64));
+  SCLAP_TRY(launch_incoming_decide(S, ns, N, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
+  SCLAP_TRY(ctx_ensure_pin(c, 256));
   uint32_t* hs = (uint32_t*)c->pin;
-  SCLAP_HIP(hipMemcpyAsync(hs, small, 16 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipMemcpyAsync(hs, small, 160, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
-  if (hs[5]) return fail(SCLAP_EHIP, "hub rating table too small");
-  const uint32_t cc = hs[4];
+  if (hs[10]) return fail(SCLAP_EHIP, "hub rating table too small");
+  const uint32_t cc = hs[9];
   if (c->profile) {
-    c->prof_rate_visits += 0;  // filled from the slot counters below
-    c->prof_rate_nodes += (int64_t)hs[0] + hs[1] + hs[2] + hs[3];
+    const unsigned long long* hv = (const unsigned long long*)((char*)hs + 64);
+    bool weighted = false;
+    for (int s = 0; s < ns; ++s) weighted = weighted || c->pin_slots[s].ew != nullptr;
+    for (int b = 0; b < kBins; ++b) {
+      float ms = 0;
+      SCLAP_HIP(hipEventElapsedTime(&ms, c->ev[b], c->ev[b + 1]));
+      c->prof_k_ms[b] += ms;
+      c->prof_k_visits[b] += (int64_t)hv[b];
+      c->prof_k_nodes[b] += hs[b];
+      c->prof_k_bytes[b] += (double)hv[b] * (weighted ? 12.0 : 8.0) + (double)hs[b] * 32.0;
+      c->prof_rate_nodes += hs[b];
+    }
+    float a = 0;
+    SCLAP_HIP(hipEventElapsedTime(&a, c->ev[0], c->ev[kBins]));
+    c->prof_rate_ms += a;
+    c->prof_rate_launches += 1;
+    c->prof_k_launches += 1;
   }
   if (cc > 0) {
     SCLAP_TRY(c->ckeys2.ensure((size_t)cc * 8, st));
@@ -322,18 +346,17 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                     (const int64_t*)c->prefix.p, st));
   }
-  SCLAP_TRY(launch_apply(S, ns, N, st));
-  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[3], st));
+  bool any_refine = false;
+  for (int s = 0; s < ns; ++s) any_refine = any_refine || c->pin_slots[s].mode == MODE_REFINE;
+  SCLAP_TRY(launch_apply(S, ns, N, (int32_t*)c->movers.p, small + 13, any_refine, st));
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kBins + 2], st));
   SCLAP_TRY(ctx_ensure_pin(c, (size_t)ns * CTR_N * sizeof(int64_t)));
   SCLAP_HIP(hipMemcpyAsync(c->pin, ctr, (size_t)ns * CTR_N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   if (c->profile) {
-    float a = 0, b = 0;
-    SCLAP_HIP(hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
-    SCLAP_HIP(hipEventElapsedTime(&b, c->ev[0], c->ev[3]));
-    c->prof_rate_ms += a;
+    float b = 0;
+    SCLAP_HIP(hipEventElapsedTime(&b, c->ev[kBins + 1], c->ev[kBins + 2]));
     c->prof_round_ms += b;
-    c->prof_rate_launches += 1;
     c->prof_rounds += 1;
     for (int s = 0; s < ns; ++s) c->prof_rate_visits += c->pin[(size_t)s * CTR_N + CTR_VISITS];
   }
@@ -374,7 +397,7 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   const int bits = bits_for(nc);
   SCLAP_TRY(c->small.ensure(256, st));
   unsigned long long* cnt = (unsigned long long*)c->small.p;
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, bits, 0, cnt, nullptr, nullptr, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, cnt, nullptr, nullptr, st));
   SCLAP_HIP(hipMemcpyAsync(c->pin, cnt, 8, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   const int64_t mx = c->pin[0];
@@ -385,7 +408,7 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&k2, mz, st));
   SCLAP_TRY(dalloc_t(&v1, mz, st));
   SCLAP_TRY(dalloc_t(&v2, mz, st));
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, bits, 1, cnt, k1, v1, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, cnt, k1, v1, st));
   const size_t tb = std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
   SCLAP_TRY(c->prim.ensure(tb, st));
   SCLAP_TRY(prim_sort_pairs(c->prim.p, tb, k1, k2, v1, v2, (size_t)mx, 2 * bits, st));
@@ -424,11 +447,72 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Fused initial partition: one workgroup per job.
 // ---------------------------------------------------------------------------
+constexpr int64_t kIpBigLevel = 1 << 18;  // entries of a BFS level expanded grid-wide
+
+// Expand yielded BFS levels of one slot with grid-wide kernels until the
+// workgroup kernel finishes.
+static int ip_single_loop(Ctx* c, IpSlot* dslot, int64_t* dstate, hipStream_t st) {
+  int64_t *deg = nullptr, *dpre = nullptr;
+  int32_t *flags = nullptr, *fpos = nullptr;
+  SCLAP_TRY(ctx_ensure_pin(c, 256));
+  for (int iter = 0;; ++iter) {
+    SCLAP_TRY(initial_partition(dslot, 1, 1, kIpBigLevel, st));
+    SCLAP_HIP(hipMemcpyAsync(c->pin, dstate, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SCLAP_HIP(hipStreamSynchronize(st));
+    if (c->pin[3] == 0) break;
+    const int64_t head = c->pin[0], tail = c->pin[1], next = c->pin[2];
+    const int64_t F = tail - head;
+    // frontier degrees -> exclusive prefix (F + 1 entries, the last = E)
+    SCLAP_TRY(dalloc_t(&deg, (size_t)F + 1, st));
+    SCLAP_TRY(dalloc_t(&dpre, (size_t)F + 1, st));
+    SCLAP_TRY(ip_level_deg(dslot, head, F, deg, st));
+    size_t sb = prim_exscan_i64_bytes((size_t)F + 1);
+    SCLAP_TRY(c->prim.ensure(sb, st));
+    SCLAP_TRY(prim_exscan_i64(c->prim.p, sb, deg, dpre, (size_t)F + 1, st));
+    SCLAP_HIP(hipMemcpyAsync(c->pin, dpre + F, 8, hipMemcpyDeviceToHost, st));
+    SCLAP_HIP(hipStreamSynchronize(st));
+    const int64_t E = c->pin[0];
+    SCLAP_TRY(dalloc_t(&flags, (size_t)std::max<int64_t>(E, 1), st));
+    SCLAP_TRY(dalloc_t(&fpos, (size_t)std::max<int64_t>(E, 1), st));
+    SCLAP_TRY(ip_level_entries(dslot, head, F, dpre, E, 0, nullptr, st));
+    SCLAP_TRY(ip_level_entries(dslot, head, F, dpre, E, 1, flags, st));
+    sb = prim_exscan_i32_bytes((size_t)std::max<int64_t>(E, 1));
+    SCLAP_TRY(c->prim.ensure(sb, st));
+    SCLAP_TRY(prim_exscan_i32(c->prim.p, sb, flags, fpos, (size_t)E, st));
+    int64_t T = 0;
+    if (E > 0) {
+      int32_t* h = (int32_t*)c->pin;
+      SCLAP_HIP(hipMemcpyAsync(h, fpos + E - 1, 4, hipMemcpyDeviceToHost, st));
+      SCLAP_HIP(hipMemcpyAsync(h + 1, flags + E - 1, 4, hipMemcpyDeviceToHost, st));
+      SCLAP_HIP(hipStreamSynchronize(st));
+      T = (int64_t)h[0] + h[1];
+    }
+    SCLAP_TRY(ip_level_emit(dslot, head, tail, F, dpre, E, flags, fpos, T, st));
+    dfree(deg, st);
+    dfree(dpre, st);
+    dfree(flags, st);
+    dfree(fpos, st);
+    deg = nullptr;
+    dpre = nullptr;
+    flags = fpos = nullptr;
+    c->pin[0] = tail;
+    c->pin[1] = tail + T;
+    c->pin[2] = next;
+    c->pin[3] = 0;
+    SCLAP_HIP(hipMemcpyAsync(dstate, c->pin, 4 * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    SCLAP_HIP(hipStreamSynchronize(st));
+  }
+  return SCLAP_OK;
+}
+
 int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipStream_t st) {
   const int cnt = (int)jobs.size();
   if (cnt == 0) return SCLAP_OK;
   std::vector<IpSlot> hs(cnt);
   std::vector<int32_t*> scratch(cnt, nullptr);
+  int64_t* states = nullptr;
+  SCLAP_TRY(dalloc_t(&states, (size_t)cnt * 4, st));
+  SCLAP_TRY(fill_i64(states, (int64_t)cnt * 4, 0, st));
   for (int s = 0; s < cnt; ++s) {
     Job* j = jobs[s];
     const Level& L = j->lv[j->cur];
@@ -448,6 +532,7 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
     x.pos = scratch[s] + nn;
     x.claim = scratch[s] + 2 * nn;
     x.cnt = scratch[s] + 3 * nn;
+    x.state = states + 4 * s;
     SCLAP_TRY(fill_i32(x.part, n, -1, st));
     SCLAP_TRY(fill_i32(x.pos, n, -1, st));
     SCLAP_TRY(fill_i32(x.claim, n, INT32_MAX, st));
@@ -456,9 +541,15 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
   SCLAP_TRY(ctx_ensure_pin(c, (size_t)cnt * sizeof(IpSlot)));
   std::memcpy(c->pin, hs.data(), (size_t)cnt * sizeof(IpSlot));
   SCLAP_HIP(hipMemcpyAsync(c->ip_slots.p, c->pin, (size_t)cnt * sizeof(IpSlot), hipMemcpyHostToDevice, st));
-  SCLAP_TRY(initial_partition((const IpSlot*)c->ip_slots.p, cnt, st));
   SCLAP_HIP(hipStreamSynchronize(st));  // pinned staging is reused right after
+  const Level& L0 = jobs[0]->lv[jobs[0]->cur];
+  if (cnt == 1 && L0.rows_sorted && L0.m > kIpBigLevel) {
+    SCLAP_TRY(ip_single_loop(c, (IpSlot*)c->ip_slots.p, states, st));
+  } else {
+    SCLAP_TRY(initial_partition((const IpSlot*)c->ip_slots.p, cnt, 0, 0, st));
+  }
   for (int s = 0; s < cnt; ++s) dfree(scratch[s], st);
+  dfree(states, st);
   return SCLAP_OK;
 }
 
@@ -468,7 +559,7 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
 static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, hipStream_t st) {
   if (c->small.ensure(256, st) != SCLAP_OK) return -1;
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
-  if (cut_twice(L.rp, L.col, L.ew, part, L.n, d, st) != SCLAP_OK) return -1;
+  if (cut_twice(L.rp, L.col, L.ew, part, L.n, L.m, d, st) != SCLAP_OK) return -1;
   if (ctx_ensure_pin(c, 64) != SCLAP_OK) return -1;
   if (hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
   if (hipStreamSynchronize(st) != hipSuccess) return -1;

@@ -7,8 +7,10 @@ namespace sclap {
 
 struct RateHubScratch {
   uint32_t* chunk_off;  // bin capacity + 1
+  uint32_t* slice_off;  // bin capacity + 1
+  unsigned long long* best;  // bin capacity, kept at 0 between rounds
   int64_t* tab_off;     // bin capacity
-  uint32_t* totals;     // 1
+  uint32_t* totals;     // 2: chunks, slices
   int32_t* gkeys;       // tab_cap, kept at -1 between rounds
   int32_t* gvals;       // tab_cap, kept at 0 between rounds
   int64_t* own;         // bin capacity, kept at 0 between rounds
@@ -17,16 +19,19 @@ struct RateHubScratch {
 };
 
 int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, int64_t bin_cap, uint32_t* bin_cnt,
-               hipStream_t st);
+               unsigned long long* bin_visits, hipStream_t st);
+// evs (may be NULL): kBins + 1 events recorded between the per-bin kernels.
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_cap, const uint32_t* bin_cnt,
-                const RateHubScratch& hub, hipStream_t st);
+                const RateHubScratch& hub, int64_t n_hint, hipStream_t st, hipEvent_t* evs);
 int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, uint64_t* ckeys, uint32_t* ccnt, int node_bits,
                            hipStream_t st);
 int launch_contended_split(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
                            uint32_t* tkey, int64_t* wv, hipStream_t st);
 int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
                           const int64_t* prefix, hipStream_t st);
-int launch_apply(const DevSlot* S, int ns, int64_t N, hipStream_t st);
+// movers (N entries) and mcnt (zeroed) collect the moved nodes of refinement slots.
+int launch_apply(const DevSlot* S, int ns, int64_t N, int32_t* movers, uint32_t* mcnt, bool any_refine,
+                 hipStream_t st);
 
 // Library primitives (rocPRIM) used as steps: sorts, scans, reductions.
 size_t prim_sort_keys_bytes(size_t n);

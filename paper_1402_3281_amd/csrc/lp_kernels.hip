@@ -1,24 +1,22 @@
 // lp_kernels.hip -- one synchronous size-constrained label propagation round
 // (Section 3.1) over a set of graphs ("slots"), as gfx950 kernels:
 //
-//   bin      nodes to rate -> four degree bins, edge visits per slot
+//   bin      nodes to rate -> seven degree bins, edge visits per slot
 //   rate     per-node neighbour-cluster rating: conn(v, t) = sum of w(v, u)
 //            over neighbours u with label t; candidates = own label and
 //            neighbour labels in the allowed direction; eligible if
 //            W(t) + c(v) <= cap; argmax with ties to the smallest label.
-//              8 lanes per node (deg <= 8), one wave per node (deg <= 64),
-//              one workgroup with an LDS hash table (deg <= 4096), several
-//              workgroups with a global hash table (hubs).
 //   admit    movers into a target are admitted in increasing node id while
 //            W(t) + inclusive prefix of their weights <= cap: targets whose
 //            total incoming weight fits admit everyone; the others sort
 //            their movers by (target, node) and scan.
-//   apply    labels, label weights (integer atomics), moved counts, and in
-//            refinement the rated set of the next round.
+//   apply    labels, label weights, moved counts, and in refinement the
+//            rated set of the next round.
 //
 // Every result is a pure function of the previous round's state: integer
 // atomics only ever sum or take maxima, so the order of execution does not
-// change any value.
+// change any value.  Sums that many threads add to the same address are
+// first combined per workgroup in LDS.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -28,43 +26,66 @@ namespace sclap {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-// Wave-aggregated append: returns this lane's slot (valid if pred).
-__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
-  const uint64_t mask = __ballot(pred);
-  if (mask == 0) return 0;
-  const int leader = __ffsll((unsigned long long)mask) - 1;
-  uint32_t base = 0;
-  if ((int)lane_id() == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-  base = __shfl(base, leader);
-  return base + (uint32_t)__popcll(mask & ((1ull << lane_id()) - 1ull));
-}
-
-// Add `val` to S[s].ctr[which], aggregated over the wave when the slot is
-// the same for all lanes.
-__device__ __forceinline__ void wave_count(const DevSlot* __restrict__ S, int s, int which, int64_t val) {
-  const int s0 = __shfl(s, 0);
-  if (__all(s == s0)) {
-    int64_t sum = val;
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-    if (lane_id() == 0 && sum != 0) atomicAdd((unsigned long long*)&S[s0].ctr[which], (unsigned long long)sum);
-  } else if (val != 0) {
-    atomicAdd((unsigned long long*)&S[s].ctr[which], (unsigned long long)val);
-  }
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
 }
 
 __device__ __forceinline__ int bin_of(int64_t d) {
-  return d <= kBinG8 ? 0 : d <= kBinG64 ? 1 : d <= kBinBlock ? 2 : 3;
+  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : d <= 512 ? 5 : d <= 1024 ? 6
+       : d <= kBinBlock ? 7 : 8;
+}
+
+// Per-workgroup sum of `val` per slot, flushed with one atomic per wave run
+// of equal slots.  All threads of the block must call it.
+__device__ __forceinline__ void block_slot_add(const DevSlot* __restrict__ S, int s, int which, int64_t val,
+                                               int* s_slot, int64_t* s_sum) {
+  const int w = threadIdx.x / kWave;
+  const int s0 = __shfl(s, 0);
+  const bool uni = __all(s == s0);
+  int64_t sum = val;
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (!uni && val != 0) atomicAdd((unsigned long long*)&S[s].ctr[which], (unsigned long long)val);
+  if (lane_id() == 0) {
+    s_slot[w] = uni ? s0 : -1;
+    s_sum[w] = uni ? sum : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    int cur = -1;
+    int64_t acc = 0;
+    for (int i = 0; i < nw; ++i) {
+      if (s_slot[i] != cur) {
+        if (cur >= 0 && acc) atomicAdd((unsigned long long*)&S[cur].ctr[which], (unsigned long long)acc);
+        cur = s_slot[i];
+        acc = 0;
+      }
+      acc += s_sum[i];
+    }
+    if (cur >= 0 && acc) atomicAdd((unsigned long long*)&S[cur].ctr[which], (unsigned long long)acc);
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // Binning: every node of an active slot with degree > 0 (and, in refinement
-// after round 1, in the rated set) is appended to its degree bin.
+// after round 1, in the rated set) is appended to its degree bin.  Positions
+// are reserved with one atomic per bin per workgroup.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int ns, int64_t N,
                                              int32_t* __restrict__ bins, int64_t bin_cap,
-                                             uint32_t* __restrict__ bin_cnt) {
+                                             uint32_t* __restrict__ bin_cnt,
+                                             unsigned long long* __restrict__ bin_visits) {
+  __shared__ uint32_t s_w[4 * kBins];  // 4 waves x bins
+  __shared__ uint32_t s_base[kBins];
+  __shared__ unsigned long long s_vis[kBins];
+  __shared__ int s_slot[4];
+  __shared__ int64_t s_sum[4];
+  const int w = threadIdx.x / kWave;
+  const uint64_t lt = (1ull << lane_id()) - 1ull;
+  if (threadIdx.x < kBins) s_vis[threadIdx.x] = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // all lanes iterate the same number of times (convergent wave_append)
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += stride) {
     const int64_t u = base + threadIdx.x;
     bool take = false;
@@ -81,17 +102,57 @@ __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int 
         b = bin_of(d);
       }
     }
-    wave_count(S, s, CTR_VISITS, take ? d : 0);
+    uint32_t rank = 0;
 #pragma unroll
     for (int j = 0; j < kBins; ++j) {
-      const uint32_t pos = wave_append(&bin_cnt[j], take && b == j);
-      if (take && b == j) bins[j * bin_cap + pos] = (int32_t)u;
+      const uint64_t m = __ballot(take && b == j);
+      if (take && b == j) rank = (uint32_t)__popcll(m & lt);
+      if (lane_id() == 0) s_w[w * kBins + j] = (uint32_t)__popcll(m);
     }
+    if (take) atomicAdd(&s_vis[b], (unsigned long long)d);
+    __syncthreads();
+    if (threadIdx.x < kBins) {
+      const int j = threadIdx.x;
+      uint32_t tot = 0;
+      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+        const uint32_t c = s_w[i * kBins + j];
+        s_w[i * kBins + j] = tot;
+        tot += c;
+      }
+      s_base[j] = tot ? atomicAdd(&bin_cnt[j], tot) : 0;
+    }
+    __syncthreads();
+    if (take) bins[b * bin_cap + s_base[b] + s_w[w * kBins + b] + rank] = (int32_t)u;
+    block_slot_add(S, s, CTR_VISITS, take ? d : 0, s_slot, s_sum);
   }
+  __syncthreads();
+  if (threadIdx.x < kBins && s_vis[threadIdx.x]) atomicAdd(&bin_visits[threadIdx.x], s_vis[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
-// Rating, G lanes per node (degree <= G).
+// Choice of a node from its aggregated candidates.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool own_allowed(const DevSlot& sl, int32_t own) {
+  return !(sl.mode == MODE_REFINE && sl.W[own] > sl.cap);
+}
+
+// Foreign candidate t with connection c: its key if it can win and is
+// eligible (W(t) + c(v) <= cap), else 0.  A candidate that cannot beat the
+// own label is not looked up (the own label is always in the set then).
+__device__ __forceinline__ uint64_t cand_key(const DevSlot& sl, bool own_ok, int64_t conn_own, int32_t own,
+                                             int64_t cv, int32_t t, int64_t c) {
+  const bool beats = !own_ok || c > conn_own || (c == conn_own && t < own);
+  if (beats && sl.W[t] + cv <= sl.cap) return pack_key(c, t);
+  return 0;
+}
+
+__device__ __forceinline__ bool dir_blocked(const DevSlot& sl, int32_t t, int32_t own) {
+  return sl.dir_rule && ((sl.round & 1) ? t > own : t < own);
+}
+
+// ---------------------------------------------------------------------------
+// Rating, G lanes per node (degree <= G).  The pairwise loop runs over the
+// wave's largest degree only.
 // ---------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(256) k_rate_group(const DevSlot* __restrict__ S, int ns,
@@ -117,6 +178,12 @@ __global__ void __launch_bounds__(256) k_rate_group(const DevSlot* __restrict__ 
       d = (int)(sl.rp[v + 1] - e0);
       own = sl.lab[v];
     }
+    int dm = d;
+    for (int off = 32; off > 0; off >>= 1) {
+      const int o = __shfl_xor(dm, off);
+      dm = o > dm ? o : dm;
+    }
+    const int dlim = dm < G ? dm : G;
     int32_t t = -1, w = 0;
     if (gl < d) {
       t = sl.lab[sl.col[e0 + gl]];
@@ -125,17 +192,18 @@ __global__ void __launch_bounds__(256) k_rate_group(const DevSlot* __restrict__ 
     const bool foreign = t >= 0 && t != own;
     const uint64_t fmask = __ballot(foreign);
     const bool boundary = ((fmask >> gbase) & (G == 64 ? ~0ull : ((1ull << G) - 1ull))) != 0;
-    int32_t te = t;
-    if (foreign && sl.dir_rule) {
-      const bool odd = sl.round & 1;
-      if (odd ? t > own : t < own) te = -1;
-    }
+    const int32_t te = (foreign && dir_blocked(sl, t, own)) ? -1 : t;
     int64_t conn = 0, conn_own = 0;
     bool leader = te >= 0;
-#pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const int32_t tj = __shfl(te, gbase + j);
-      const int32_t wj = __shfl(w, gbase + j);
+    for (int j = 0; j < dlim; ++j) {
+      int32_t tj, wj;
+      if (G == 64) {
+        tj = __builtin_amdgcn_readlane(te, j);
+        wj = __builtin_amdgcn_readlane(w, j);
+      } else {
+        tj = __shfl(te, gbase + j);
+        wj = __shfl(w, gbase + j);
+      }
       if (tj == te) {
         conn += wj;
         if (j < gl) leader = false;
@@ -143,17 +211,10 @@ __global__ void __launch_bounds__(256) k_rate_group(const DevSlot* __restrict__ 
       if (tj == own) conn_own += wj;
     }
     uint64_t key = 0;
+    bool own_ok = true;
     if (valid) {
-      const int64_t cv = sl.nw[v];
-      const bool own_ok = !(sl.mode == MODE_REFINE && sl.W[own] > sl.cap);
-      if (leader && te != own) {
-        const bool beats = !own_ok || conn > conn_own || (conn == conn_own && te < own);
-        if (beats && sl.W[te] + cv <= sl.cap) key = pack_key(conn, te);
-      }
-      if (own_ok) {
-        const uint64_t ok = pack_key(conn_own, own);
-        key = key > ok ? key : ok;
-      }
+      own_ok = own_allowed(sl, own);
+      if (leader && te != own) key = cand_key(sl, own_ok, conn_own, own, sl.nw[v], te, conn);
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) {
@@ -161,13 +222,105 @@ __global__ void __launch_bounds__(256) k_rate_group(const DevSlot* __restrict__ 
       key = key > o ? key : o;
     }
     if (valid && gl == 0) {
+      if (own_ok) {
+        const uint64_t ok = pack_key(conn_own, own);
+        key = key > ok ? key : ok;
+      }
       sl.desire[v] = key ? key_label(key) : own;
       if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
     }
   }
 }
 
-// Block-wide reductions for 256 threads.
+// Insert (t, w) into an open-addressing table (keys -1 = empty).
+__device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t mask, int32_t t, int32_t w) {
+  uint32_t h = hash32((uint32_t)t) & mask;
+  for (;;) {
+    const int32_t prev = atomicCAS(&keys[h], -1, t);
+    if (prev == -1 || prev == t) {
+      atomicAdd(&vals[h], w);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ uint32_t table_size(int64_t d, int64_t nlabels) {
+  const int64_t distinct = d < nlabels ? d : nlabels;
+  uint32_t tsz = 64;
+  while (tsz < 2 * distinct) tsz <<= 1;
+  return tsz;
+}
+
+// ---------------------------------------------------------------------------
+// Rating, one wave per node (degree <= TS / 2), wave-private LDS table.
+// ---------------------------------------------------------------------------
+template <int TS>
+__global__ void __launch_bounds__(256) k_rate_wave(const DevSlot* __restrict__ S, int ns,
+                                                   const int32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ cnt_ptr) {
+  __shared__ int32_t keys_all[4][TS];
+  __shared__ int32_t vals_all[4][TS];
+  const int w = threadIdx.x / kWave;
+  int32_t* keys = keys_all[w];
+  int32_t* vals = vals_all[w];
+  const uint32_t cnt = *cnt_ptr;
+  const int lane = (int)lane_id();
+  for (uint32_t i = blockIdx.x * 4 + w; i < cnt; i += gridDim.x * 4) {
+    const int64_t u = list[i];
+    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const int64_t v = u - sl.nbase;
+    const int64_t e0 = sl.rp[v];
+    const int d = (int)(sl.rp[v + 1] - e0);
+    const int32_t own = sl.lab[v];
+    const uint32_t tsz = table_size(d, sl.nlabels);
+    for (uint32_t j = lane; j < tsz; j += kWave) {
+      keys[j] = -1;
+      vals[j] = 0;
+    }
+    wave_sync();
+    int64_t my_own = 0;
+    bool foreign = false;
+    for (int e = lane; e < d; e += kWave) {
+      const int32_t t = sl.lab[sl.col[e0 + e]];
+      const int32_t wt = sl.ew ? sl.ew[e0 + e] : 1;
+      if (t == own) {
+        my_own += wt;
+        continue;
+      }
+      foreign = true;
+      if (dir_blocked(sl, t, own)) continue;
+      table_add(keys, vals, tsz - 1, t, wt);
+    }
+    for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
+    const bool boundary = __ballot(foreign) != 0;
+    wave_sync();
+    const int64_t cv = sl.nw[v];
+    const bool own_ok = own_allowed(sl, own);
+    uint64_t best = 0;
+    for (uint32_t j = lane; j < tsz; j += kWave) {
+      const int32_t t = keys[j];
+      if (t < 0) continue;
+      const uint64_t k = cand_key(sl, own_ok, my_own, own, cv, t, vals[j]);
+      best = best > k ? best : k;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_xor(best, off);
+      best = best > o ? best : o;
+    }
+    if (lane == 0) {
+      if (own_ok) {
+        const uint64_t ok = pack_key(my_own, own);
+        best = best > ok ? best : ok;
+      }
+      sl.desire[v] = best ? key_label(best) : own;
+      if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+    }
+    wave_sync();
+  }
+}
+
+// Block-wide reductions (up to 8 waves; sh has 8 entries).
 template <class T, class Op>
 __device__ __forceinline__ T block_reduce(T x, T* sh, Op op) {
   for (int off = 32; off > 0; off >>= 1) x = op(x, __shfl_xor(x, off));
@@ -190,54 +343,36 @@ struct OpOr {
   __device__ int operator()(int a, int b) const { return a | b; }
 };
 
-// Insert (t, w) into an open-addressing table (keys -1 = empty).
-__device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t mask, int32_t t, int32_t w) {
-  uint32_t h = hash32((uint32_t)t) & mask;
-  for (;;) {
-    const int32_t prev = atomicCAS(&keys[h], -1, t);
-    if (prev == -1 || prev == t) {
-      atomicAdd(&vals[h], w);
-      return;
-    }
-    h = (h + 1) & mask;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// Rating, one workgroup per node (degree <= kBinBlock), LDS hash table.
+// Rating, one workgroup per node (degree <= TS / 2), LDS hash table.
 // ---------------------------------------------------------------------------
-constexpr int kBlockTable = 2 * kBinBlock;
-
-__global__ void __launch_bounds__(256) k_rate_block(const DevSlot* __restrict__ S, int ns,
-                                                    const int32_t* __restrict__ list,
-                                                    const uint32_t* __restrict__ cnt_ptr) {
-  __shared__ int32_t keys[kBlockTable];
-  __shared__ int32_t vals[kBlockTable];
-  __shared__ uint64_t red64[4];
-  __shared__ int64_t redi[4];
-  __shared__ int redo[4];
+template <int TS, int NT>
+__global__ void __launch_bounds__(NT) k_rate_block(const DevSlot* __restrict__ S, int ns,
+                                                   const int32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ cnt_ptr) {
+  __shared__ int32_t keys[TS];
+  __shared__ int32_t vals[TS];
+  __shared__ uint64_t red64[8];
+  __shared__ int64_t redi[8];
+  __shared__ int redo[8];
   const uint32_t cnt = *cnt_ptr;
   for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
     const int64_t u = list[i];
-    const int s = slot_of(S, ns, u);
-    const DevSlot& sl = S[s];
+    const DevSlot& sl = S[slot_of(S, ns, u)];
     const int64_t v = u - sl.nbase;
     const int64_t e0 = sl.rp[v];
     const int d = (int)(sl.rp[v + 1] - e0);
     const int32_t own = sl.lab[v];
-    int64_t distinct = d < sl.nlabels ? d : sl.nlabels;
-    uint32_t tsz = 64;
-    while (tsz < 2 * distinct) tsz <<= 1;
+    const uint32_t tsz = table_size(d, sl.nlabels);
     const uint32_t mask = tsz - 1;
-    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+    for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
       keys[j] = -1;
       vals[j] = 0;
     }
     __syncthreads();
-    const bool odd = sl.round & 1;
     int64_t my_own = 0;
     int foreign = 0;
-    for (int e = threadIdx.x; e < d; e += blockDim.x) {
+    for (int e = threadIdx.x; e < d; e += NT) {
       const int32_t t = sl.lab[sl.col[e0 + e]];
       const int32_t w = sl.ew ? sl.ew[e0 + e] : 1;
       if (t == own) {
@@ -245,23 +380,19 @@ __global__ void __launch_bounds__(256) k_rate_block(const DevSlot* __restrict__ 
         continue;
       }
       foreign = 1;
-      if (sl.dir_rule && (odd ? t > own : t < own)) continue;
+      if (dir_blocked(sl, t, own)) continue;
       table_add(keys, vals, mask, t, w);
     }
     const int64_t conn_own = block_reduce(my_own, redi, OpAdd64());
     const int boundary = block_reduce(foreign, redo, OpOr());
     const int64_t cv = sl.nw[v];
-    const bool own_ok = !(sl.mode == MODE_REFINE && sl.W[own] > sl.cap);
+    const bool own_ok = own_allowed(sl, own);
     uint64_t best = 0;
-    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+    for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
       const int32_t t = keys[j];
       if (t < 0) continue;
-      const int64_t c = vals[j];
-      const bool beats = !own_ok || c > conn_own || (c == conn_own && t < own);
-      if (beats && sl.W[t] + cv <= sl.cap) {
-        const uint64_t k = pack_key(c, t);
-        best = best > k ? best : k;
-      }
+      const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, vals[j]);
+      best = best > k ? best : k;
     }
     best = block_reduce(best, red64, OpMax64());
     if (threadIdx.x == 0) {
@@ -280,33 +411,32 @@ __global__ void __launch_bounds__(256) k_rate_block(const DevSlot* __restrict__ 
 // Rating of hubs (degree > kBinBlock): chunks of kHubChunk entries per
 // workgroup, aggregated in LDS and flushed into a per-hub global table.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t hub_table_size(int64_t d, int64_t nlabels) {
-  const int64_t distinct = d < nlabels ? d : nlabels;
-  uint32_t tsz = 64;
-  while (tsz < 2 * distinct) tsz <<= 1;
-  return tsz;
-}
 
 // One workgroup: exclusive offsets of chunk counts and table sizes.
+constexpr int kHubSlice = 4096;  // table entries scanned per workgroup in the final pass
+
 __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ cnt_ptr,
                                                    uint32_t* __restrict__ chunk_off, int64_t* __restrict__ tab_off,
+                                                   uint32_t* __restrict__ slice_off,
                                                    uint32_t* __restrict__ totals, int64_t tab_cap,
                                                    uint32_t* __restrict__ overflow) {
   __shared__ uint32_t sc[1024];
+  __shared__ uint32_t ss[1024];
   __shared__ int64_t st[1024];
-  __shared__ uint32_t carry_c;
+  __shared__ uint32_t carry_c, carry_s;
   __shared__ int64_t carry_t;
   const uint32_t cnt = *cnt_ptr;
   if (threadIdx.x == 0) {
     carry_c = 0;
+    carry_s = 0;
     carry_t = 0;
   }
   __syncthreads();
   for (uint32_t base = 0; base < cnt; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
-    uint32_t nc = 0;
+    uint32_t nc = 0, ns2 = 0;
     int64_t tz = 0;
     if (i < cnt) {
       const int64_t u = list[i];
@@ -314,33 +444,41 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
       const int64_t v = u - sl.nbase;
       const int64_t d = sl.rp[v + 1] - sl.rp[v];
       nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
-      tz = hub_table_size(d, sl.nlabels);
+      tz = table_size(d, sl.nlabels);
+      ns2 = (uint32_t)((tz + kHubSlice - 1) / kHubSlice);
     }
     sc[threadIdx.x] = nc;
+    ss[threadIdx.x] = ns2;
     st[threadIdx.x] = tz;
     __syncthreads();
     for (uint32_t off = 1; off < blockDim.x; off <<= 1) {  // inclusive Hillis-Steele
       uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+      uint32_t a2 = threadIdx.x >= off ? ss[threadIdx.x - off] : 0;
       int64_t b = threadIdx.x >= off ? st[threadIdx.x - off] : 0;
       __syncthreads();
       sc[threadIdx.x] += a;
+      ss[threadIdx.x] += a2;
       st[threadIdx.x] += b;
       __syncthreads();
     }
     if (i < cnt) {
       chunk_off[i] = carry_c + sc[threadIdx.x] - nc;
+      slice_off[i] = carry_s + ss[threadIdx.x] - ns2;
       tab_off[i] = carry_t + st[threadIdx.x] - tz;
     }
     __syncthreads();
     if (threadIdx.x == blockDim.x - 1) {
       carry_c += sc[threadIdx.x];
+      carry_s += ss[threadIdx.x];
       carry_t += st[threadIdx.x];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     totals[0] = carry_c;
+    totals[1] = carry_s;
     chunk_off[cnt] = carry_c;
+    slice_off[cnt] = carry_s;
     if (carry_t > tab_cap) *overflow = 1;
   }
 }
@@ -385,7 +523,6 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
       vals[j] = 0;
     }
     __syncthreads();
-    const bool odd = sl.round & 1;
     int64_t my_own = 0;
     int foreign = 0;
     for (int64_t e = e_begin + threadIdx.x; e < e_end; e += blockDim.x) {
@@ -396,7 +533,7 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
         continue;
       }
       foreign = 1;
-      if (sl.dir_rule && (odd ? t > own : t < own)) continue;
+      if (dir_blocked(sl, t, own)) continue;
       table_add(keys, vals, kHubLds - 1, t, w);
     }
     const int64_t co = block_reduce(my_own, redi, OpAdd64());
@@ -405,7 +542,7 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
       if (co) atomicAdd((unsigned long long*)&hub_own[i], (unsigned long long)co);
       if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
     }
-    const uint32_t gmask = hub_table_size(d, sl.nlabels) - 1;
+    const uint32_t gmask = table_size(d, sl.nlabels) - 1;
     int32_t* gk = gkeys + tab_off[i];
     int32_t* gv = gvals + tab_off[i];
     for (int j = threadIdx.x; j < kHubLds; j += blockDim.x) {
@@ -416,17 +553,30 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
   }
 }
 
-__global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S, int ns,
-                                                   const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr,
-                                                   const int64_t* __restrict__ tab_off,
-                                                   int32_t* __restrict__ gkeys, int32_t* __restrict__ gvals,
-                                                   int64_t* __restrict__ hub_own,
-                                                   const uint32_t* __restrict__ overflow) {
-  __shared__ uint64_t red64[4];
+// Slices of the hub tables: best eligible candidate per slice, combined per
+// hub with an integer maximum; the slice is reset for the next round.
+__global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ list,
+                                                  const uint32_t* __restrict__ cnt_ptr,
+                                                  const int64_t* __restrict__ tab_off,
+                                                  const uint32_t* __restrict__ slice_off,
+                                                  const uint32_t* __restrict__ totals,
+                                                  int32_t* __restrict__ gkeys, int32_t* __restrict__ gvals,
+                                                  const int64_t* __restrict__ hub_own,
+                                                  unsigned long long* __restrict__ hub_best,
+                                                  const uint32_t* __restrict__ overflow) {
+  __shared__ uint64_t red64[8];
   if (*overflow) return;
   const uint32_t cnt = *cnt_ptr;
-  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+  const uint32_t nslices = totals[1];
+  for (uint32_t c = blockIdx.x; c < nslices; c += gridDim.x) {
+    uint32_t lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (slice_off[mid] <= c) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t i = lo;
     const int64_t u = list[i];
     const DevSlot& sl = S[slot_of(S, ns, u)];
     const int64_t v = u - sl.nbase;
@@ -434,33 +584,50 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
     const int32_t own = sl.lab[v];
     const int64_t conn_own = hub_own[i];
     const int64_t cv = sl.nw[v];
-    const bool own_ok = !(sl.mode == MODE_REFINE && sl.W[own] > sl.cap);
-    const uint32_t tsz = hub_table_size(d, sl.nlabels);
+    const bool own_ok = own_allowed(sl, own);
+    const uint32_t tsz = table_size(d, sl.nlabels);
+    const uint32_t j0 = (c - slice_off[i]) * kHubSlice;
+    const uint32_t j1 = j0 + kHubSlice < tsz ? j0 + kHubSlice : tsz;
     int32_t* gk = gkeys + tab_off[i];
     int32_t* gv = gvals + tab_off[i];
     uint64_t best = 0;
-    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
       const int32_t t = gk[j];
       if (t < 0) continue;
-      const int64_t c = gv[j];
+      const int64_t cn = gv[j];
       gk[j] = -1;
       gv[j] = 0;
-      const bool beats = !own_ok || c > conn_own || (c == conn_own && t < own);
-      if (beats && sl.W[t] + cv <= sl.cap) {
-        const uint64_t k = pack_key(c, t);
-        best = best > k ? best : k;
-      }
+      const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, cn);
+      best = best > k ? best : k;
     }
     best = block_reduce(best, red64, OpMax64());
-    if (threadIdx.x == 0) {
-      if (own_ok) {
-        const uint64_t ok = pack_key(conn_own, own);
-        best = best > ok ? best : ok;
-      }
-      sl.desire[v] = best ? key_label(best) : own;
-      hub_own[i] = 0;
-    }
+    if (threadIdx.x == 0 && best) atomicMax(&hub_best[i], (unsigned long long)best);
     __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S, int ns,
+                                                   const int32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ cnt_ptr,
+                                                   int64_t* __restrict__ hub_own,
+                                                   unsigned long long* __restrict__ hub_best,
+                                                   const uint32_t* __restrict__ overflow) {
+  if (*overflow) return;
+  const uint32_t cnt = *cnt_ptr;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+    const int64_t u = list[i];
+    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const int64_t v = u - sl.nbase;
+    const int32_t own = sl.lab[v];
+    uint64_t best = hub_best[i];
+    if (own_allowed(sl, own)) {
+      const uint64_t ok = pack_key(hub_own[i], own);
+      best = best > ok ? best : ok;
+    }
+    sl.desire[v] = best ? key_label(best) : own;
+    hub_own[i] = 0;
+    hub_best[i] = 0;
   }
 }
 
@@ -468,16 +635,54 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
 // Admission.
 // ---------------------------------------------------------------------------
 
+// LDS table combining int64 additions to (slot, label) keys within a workgroup.
+constexpr unsigned long long kEmpty = ~0ull;
+constexpr uint32_t kCountLabel = 0xFFFFFFFFu;  // key label used for per-slot counters
+
+__device__ __forceinline__ void agg_add(unsigned long long* hk, long long* hv, uint32_t mask, unsigned long long key,
+                                        long long val) {
+  uint32_t h = hash32((uint32_t)key ^ (uint32_t)(key >> 32) * 0x9E3779B1u) & mask;
+  for (;;) {
+    const unsigned long long prev = atomicCAS(&hk[h], kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      atomicAdd((unsigned long long*)&hv[h], (unsigned long long)val);
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+constexpr int kAggNodes = 512;    // nodes per workgroup iteration
+constexpr int kIncTable = 1024;   // >= 2 x distinct keys of one iteration
+constexpr int kApplyTable = 2048;
+
 // inc(t) += c(v) for every mover v -> t.
 __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S, int ns, int64_t N) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += stride) {
-    const int s = slot_of(S, ns, u);
-    const DevSlot& sl = S[s];
-    if (sl.round == 0) continue;
-    const int64_t v = u - sl.nbase;
-    const int32_t t = sl.desire[v];
-    if (t != sl.lab[v]) atomicAdd((unsigned long long*)&sl.inc[t], (unsigned long long)sl.nw[v]);
+  __shared__ unsigned long long hk[kIncTable];
+  __shared__ long long hv[kIncTable];
+  for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
+    for (int j = threadIdx.x; j < kIncTable; j += blockDim.x) {
+      hk[j] = kEmpty;
+      hv[j] = 0;
+    }
+    __syncthreads();
+    for (int it = 0; it < kAggNodes / 256; ++it) {
+      const int64_t u = base + it * 256 + threadIdx.x;
+      if (u >= N) continue;
+      const int s = slot_of(S, ns, u);
+      const DevSlot& sl = S[s];
+      if (sl.round == 0) continue;
+      const int64_t v = u - sl.nbase;
+      const int32_t t = sl.desire[v];
+      if (t != sl.lab[v]) agg_add(hk, hv, kIncTable - 1, ((unsigned long long)s << 32) | (uint32_t)t, sl.nw[v]);
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < kIncTable; j += blockDim.x) {
+      const unsigned long long k = hk[j];
+      if (k == kEmpty || hv[j] == 0) continue;
+      atomicAdd((unsigned long long*)&S[k >> 32].inc[(uint32_t)k], (unsigned long long)hv[j]);
+    }
+    __syncthreads();
   }
 }
 
@@ -486,21 +691,22 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
 __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, int ns, int64_t N,
                                                 uint64_t* __restrict__ ckeys, uint32_t* __restrict__ ccnt,
                                                 int node_bits) {
+  __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_base;
+  const int w = threadIdx.x / kWave;
+  const uint64_t lt = (1ull << lane_id()) - 1ull;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += stride) {
     const int64_t u = base + threadIdx.x;
     bool contended = false;
     uint64_t key = 0;
-    int s = 0;
-    bool mover = false;
     if (u < N) {
-      s = slot_of(S, ns, u);
+      const int s = slot_of(S, ns, u);
       const DevSlot& sl = S[s];
       if (sl.round > 0) {
         const int64_t v = u - sl.nbase;
         const int32_t t = sl.desire[v];
         if (t != sl.lab[v]) {
-          mover = true;
           if (sl.W[t] + sl.inc[t] <= sl.cap) {
             sl.adm[v] = 1;
           } else {
@@ -511,9 +717,21 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
         }
       }
     }
-    wave_count(S, s, CTR_MOVERS, mover ? 1 : 0);
-    const uint32_t pos = wave_append(ccnt, contended);
-    if (contended) ckeys[pos] = key;
+    const uint64_t m = __ballot(contended);
+    if (lane_id() == 0) s_w[w] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+        const uint32_t c = s_w[i];
+        s_w[i] = tot;
+        tot += c;
+      }
+      s_base = tot ? atomicAdd(ccnt, tot) : 0;
+    }
+    __syncthreads();
+    if (contended) ckeys[s_base + s_w[w] + (uint32_t)__popcll(m & lt)] = key;
+    __syncthreads();
   }
 }
 
@@ -547,37 +765,90 @@ __global__ void __launch_bounds__(256) k_contended_mark(const DevSlot* __restric
 
 // Apply admitted moves; reset rejected desires and the incoming sums; in
 // refinement add the neighbours of moved nodes to the next rated set.
-__global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, int ns, int64_t N) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += stride) {
-    const int64_t u = base + threadIdx.x;
-    int s = 0;
-    bool moved = false;
-    if (u < N) {
-      s = slot_of(S, ns, u);
+__global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, int ns, int64_t N,
+                                               int32_t* __restrict__ movers, uint32_t* __restrict__ mcnt) {
+  __shared__ unsigned long long hk[kApplyTable];
+  __shared__ long long hv[kApplyTable];
+  __shared__ int32_t s_mov[kAggNodes];
+  __shared__ uint32_t s_mcnt, s_mbase;
+  for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
+    for (int j = threadIdx.x; j < kApplyTable; j += blockDim.x) {
+      hk[j] = kEmpty;
+      hv[j] = 0;
+    }
+    if (threadIdx.x == 0) s_mcnt = 0;
+    __syncthreads();
+    for (int it = 0; it < kAggNodes / 256; ++it) {
+      const int64_t u = base + it * 256 + threadIdx.x;
+      if (u >= N) continue;
+      const int s = slot_of(S, ns, u);
       const DevSlot& sl = S[s];
-      if (sl.round > 0) {
-        const int64_t v = u - sl.nbase;
-        const int32_t t = sl.desire[v];
-        const int32_t own = sl.lab[v];
-        if (t != own) {
-          sl.inc[t] = 0;
-          if (sl.adm[v]) {
-            const int64_t cv = sl.nw[v];
-            sl.lab[v] = t;
-            atomicAdd((unsigned long long*)&sl.W[t], (unsigned long long)cv);
-            atomicAdd((unsigned long long*)&sl.W[own], (unsigned long long)(-cv));
-            moved = true;
-            if (sl.mode == MODE_REFINE) {
-              for (int64_t e = sl.rp[v]; e < sl.rp[v + 1]; ++e) sl.flag_next[sl.col[e]] = 1;
-            }
-          } else {
-            sl.desire[v] = own;
-          }
+      if (sl.round == 0) continue;
+      const int64_t v = u - sl.nbase;
+      const int32_t t = sl.desire[v];
+      const int32_t own = sl.lab[v];
+      if (t == own) continue;
+      sl.inc[t] = 0;
+      if (sl.adm[v]) {
+        const int64_t cv = sl.nw[v];
+        sl.lab[v] = t;
+        const unsigned long long ks = (unsigned long long)s << 32;
+        if (cv) {
+          agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
+          agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
         }
+        agg_add(hk, hv, kApplyTable - 1, ks | kCountLabel, 1);
+        if (sl.mode == MODE_REFINE) s_mov[atomicAdd(&s_mcnt, 1u)] = (int32_t)u;
+      } else {
+        sl.desire[v] = own;
       }
     }
-    wave_count(S, s, CTR_MOVED, moved ? 1 : 0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < kApplyTable; j += blockDim.x) {
+      const unsigned long long k = hk[j];
+      if (k == kEmpty || hv[j] == 0) continue;
+      const DevSlot& sl = S[k >> 32];
+      const uint32_t lab = (uint32_t)k;
+      if (lab == kCountLabel) atomicAdd((unsigned long long*)&sl.ctr[CTR_MOVED], (unsigned long long)hv[j]);
+      else atomicAdd((unsigned long long*)&sl.W[lab], (unsigned long long)hv[j]);
+    }
+    if (threadIdx.x == 0) s_mbase = s_mcnt ? atomicAdd(mcnt, s_mcnt) : 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < s_mcnt; j += blockDim.x) movers[s_mbase + j] = s_mov[j];
+    __syncthreads();
+  }
+}
+
+// Refinement: the neighbours of moved nodes join the next rated set.  Each
+// wave takes 64 movers; short rows are walked by their lane, long rows by
+// the whole wave.
+__global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int ns,
+                                              const int32_t* __restrict__ movers, const uint32_t* __restrict__ mcnt) {
+  const uint32_t cnt = *mcnt;
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  for (uint32_t base = wid * kWave; base < cnt; base += waves * kWave) {
+    const uint32_t i = base + lane_id();
+    const DevSlot* sl = nullptr;
+    int64_t e0 = 0, d = 0;
+    if (i < cnt) {
+      const int64_t u = movers[i];
+      sl = &S[slot_of(S, ns, u)];
+      const int64_t v = u - sl->nbase;
+      e0 = sl->rp[v];
+      d = sl->rp[v + 1] - e0;
+    }
+    if (d <= kWave)
+      for (int64_t e = e0; e < e0 + d; ++e) sl->flag_next[sl->col[e]] = 1;
+    uint64_t big = __ballot(d > kWave);
+    while (big) {
+      const int l = __ffsll((unsigned long long)big) - 1;
+      big &= big - 1;
+      const int64_t be0 = __shfl(e0, l), bd = __shfl(d, l);
+      const int64_t bu = movers[base + l];
+      const DevSlot& bs = S[slot_of(S, ns, bu)];
+      for (int64_t e = be0 + lane_id(); e < be0 + bd; e += kWave) bs.flag_next[bs.col[e]] = 1;
+    }
   }
 }
 
@@ -591,33 +862,55 @@ static inline unsigned grid_for(int64_t items, int per_block, unsigned cap) {
 }
 
 int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, int64_t bin_cap, uint32_t* bin_cnt,
-               hipStream_t st) {
-  hipLaunchKernelGGL(k_bin, dim3(grid_for(N, 256, 8192)), dim3(256), 0, st, S, ns, N, bins, bin_cap, bin_cnt);
+               unsigned long long* bin_visits, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin, dim3(grid_for(N, 256, 4096)), dim3(256), 0, st, S, ns, N, bins, bin_cap, bin_cnt,
+                     bin_visits);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_cap, const uint32_t* bin_cnt,
-                const RateHubScratch& hub, hipStream_t st) {
-  const unsigned G = 2048;
-  hipLaunchKernelGGL(k_rate_group<8>, dim3(G), dim3(256), 0, st, S, ns, bins, bin_cnt);
-  hipLaunchKernelGGL(k_rate_group<64>, dim3(G), dim3(256), 0, st, S, ns, bins + bin_cap, bin_cnt + 1);
-  hipLaunchKernelGGL(k_rate_block, dim3(G), dim3(256), 0, st, S, ns, bins + 2 * bin_cap, bin_cnt + 2);
-  hipLaunchKernelGGL(k_hub_prep, dim3(1), dim3(1024), 0, st, S, ns, bins + 3 * bin_cap, bin_cnt + 3,
-                     hub.chunk_off, hub.tab_off, hub.totals, hub.tab_cap, hub.overflow);
-  hipLaunchKernelGGL(k_hub_chunk, dim3(G), dim3(256), 0, st, S, ns, bins + 3 * bin_cap, bin_cnt + 3,
-                     hub.chunk_off, hub.tab_off, hub.totals, hub.gkeys, hub.gvals, hub.own, hub.overflow);
-  hipLaunchKernelGGL(k_hub_final, dim3(G), dim3(256), 0, st, S, ns, bins + 3 * bin_cap, bin_cnt + 3,
-                     hub.tab_off, hub.gkeys, hub.gvals, hub.own, hub.overflow);
+                const RateHubScratch& hub, int64_t n_hint, hipStream_t st, hipEvent_t* evs) {
+  const unsigned G = grid_for(n_hint, 32, 4096);
+  auto rec = [&](int i) {
+    if (evs) (void)hipEventRecord(evs[i], st);
+  };
+  const int32_t* b = bins;
+  rec(0);
+  hipLaunchKernelGGL(k_rate_group<8>, dim3(G), dim3(256), 0, st, S, ns, b, bin_cnt);
+  rec(1);
+  hipLaunchKernelGGL(k_rate_group<16>, dim3(G), dim3(256), 0, st, S, ns, b + bin_cap, bin_cnt + 1);
+  rec(2);
+  hipLaunchKernelGGL(k_rate_group<32>, dim3(G), dim3(256), 0, st, S, ns, b + 2 * bin_cap, bin_cnt + 2);
+  rec(3);
+  hipLaunchKernelGGL(k_rate_group<64>, dim3(G), dim3(256), 0, st, S, ns, b + 3 * bin_cap, bin_cnt + 3);
+  rec(4);
+  hipLaunchKernelGGL(k_rate_wave<256>, dim3(G), dim3(256), 0, st, S, ns, b + 4 * bin_cap, bin_cnt + 4);
+  rec(5);
+  hipLaunchKernelGGL(k_rate_wave<1024>, dim3(G), dim3(256), 0, st, S, ns, b + 5 * bin_cap, bin_cnt + 5);
+  rec(6);
+  hipLaunchKernelGGL((k_rate_block<2048, 256>), dim3(G), dim3(256), 0, st, S, ns, b + 6 * bin_cap, bin_cnt + 6);
+  rec(7);
+  hipLaunchKernelGGL((k_rate_block<8192, 512>), dim3(G), dim3(512), 0, st, S, ns, b + 7 * bin_cap, bin_cnt + 7);
+  rec(8);
+  const int32_t* hb = b + 8 * bin_cap;
+  const uint32_t* hc = bin_cnt + 8;
+  hipLaunchKernelGGL(k_hub_prep, dim3(1), dim3(1024), 0, st, S, ns, hb, hc, hub.chunk_off, hub.tab_off,
+                     hub.slice_off, hub.totals, hub.tab_cap, hub.overflow);
+  hipLaunchKernelGGL(k_hub_chunk, dim3(G), dim3(256), 0, st, S, ns, hb, hc, hub.chunk_off, hub.tab_off, hub.totals,
+                     hub.gkeys, hub.gvals, hub.own, hub.overflow);
+  hipLaunchKernelGGL(k_hub_scan, dim3(G), dim3(256), 0, st, S, ns, hb, hc, hub.tab_off, hub.slice_off, hub.totals,
+                     hub.gkeys, hub.gvals, hub.own, hub.best, hub.overflow);
+  hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(256), 0, st, S, ns, hb, hc, hub.own, hub.best, hub.overflow);
+  rec(9);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
 
 int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, uint64_t* ckeys, uint32_t* ccnt, int node_bits,
                            hipStream_t st) {
-  const unsigned g = grid_for(N, 256, 8192);
-  hipLaunchKernelGGL(k_incoming, dim3(g), dim3(256), 0, st, S, ns, N);
-  hipLaunchKernelGGL(k_decide, dim3(g), dim3(256), 0, st, S, ns, N, ckeys, ccnt, node_bits);
+  hipLaunchKernelGGL(k_incoming, dim3(grid_for(N, kAggNodes, 4096)), dim3(256), 0, st, S, ns, N);
+  hipLaunchKernelGGL(k_decide, dim3(grid_for(N, 256, 4096)), dim3(256), 0, st, S, ns, N, ckeys, ccnt, node_bits);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -640,8 +933,11 @@ int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32
   return SCLAP_OK;
 }
 
-int launch_apply(const DevSlot* S, int ns, int64_t N, hipStream_t st) {
-  hipLaunchKernelGGL(k_apply, dim3(grid_for(N, 256, 8192)), dim3(256), 0, st, S, ns, N);
+int launch_apply(const DevSlot* S, int ns, int64_t N, int32_t* movers, uint32_t* mcnt, bool any_refine,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_apply, dim3(grid_for(N, kAggNodes, 4096)), dim3(256), 0, st, S, ns, N, movers, mcnt);
+  if (any_refine)
+    hipLaunchKernelGGL(k_mark, dim3(grid_for(N, 256 * kWave / 4, 2048)), dim3(256), 0, st, S, ns, movers, mcnt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -18,14 +18,15 @@ int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st
 int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);
 int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st);
 int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, int64_t* W, hipStream_t st);
-int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n,
+int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
               unsigned long long* out, hipStream_t st);
 
 int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st);
 int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw, int64_t n, int drop,
                        const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, hipStream_t st);
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
-                   int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals, hipStream_t st);
+                   int64_t m, int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals,
+                   hipStream_t st);
 int contract_finish(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int64_t nc, int64_t* rp,
                     int32_t* col, int32_t* ew, unsigned* overflow, hipStream_t st);
 int project(const int32_t* cof, const int32_t* pc, int64_t n, int32_t* pf, hipStream_t st);
@@ -45,8 +46,16 @@ struct IpSlot {
   int32_t* pos;    // n scratch, pre-filled with -1
   int32_t* claim;  // n scratch, pre-filled with INT32_MAX
   int32_t* cnt;    // n scratch
+  int64_t* state;  // 4: head, tail, next seed, yielded (zero before the first launch)
 };
-int initial_partition(const IpSlot* dev_slots, int count, hipStream_t st);
+// One workgroup per slot; see k_ip_bfs for allow_yield / big_entries.
+int initial_partition(const IpSlot* dev_slots, int count, int allow_yield, int64_t big_entries, hipStream_t st);
+// Grid-wide expansion of one level of the BFS of a single slot.
+int ip_level_deg(const IpSlot* slot, int64_t head, int64_t F, int64_t* deg, hipStream_t st);
+int ip_level_entries(const IpSlot* slot, int64_t head, int64_t F, const int64_t* dpre, int64_t E, int mode,
+                     int32_t* flags, hipStream_t st);
+int ip_level_emit(const IpSlot* slot, int64_t head, int64_t tail, int64_t F, const int64_t* dpre, int64_t E,
+                  const int32_t* flags, const int32_t* fpos, int64_t T, hipStream_t st);
 
 int place_isolated(const int64_t* rp, const int64_t* nw, int64_t n, const int64_t* B, int32_t k, int32_t* part,
                    int64_t* tmp_w, int64_t* tmp_pre, int64_t* ends, int32_t* last, void* scan_tmp, size_t scan_bytes,

@@ -168,51 +168,101 @@ int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, 
 }
 
 // ---------------------------------------------------------------------------
-// Wave-cooperative row traversal: each wave takes 64 consecutive nodes; a
-// lane walks its own row when it has at most kShort entries, longer rows are
-// walked by the whole wave, one after the other.
+// Edge-centric traversal: a workgroup takes kEpb consecutive stored entries;
+// the rows they belong to are found by binary search over an LDS copy of
+// the row offsets of that range, so neighbour ids are read coalesced.
 // ---------------------------------------------------------------------------
-constexpr int kShort = 32;
+constexpr int kItems = 8;
+constexpr int kEpb = 256 * kItems;
+constexpr int kRpLds = kEpb + 1;
+
+// largest u in [lo, hi] with rp[u] <= e (the row holding entry e)
+__device__ __forceinline__ int64_t row_search(const int64_t* __restrict__ rp, int64_t lo, int64_t hi, int64_t e) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (rp[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct EdgeRange {
+  int64_t e0, e1, ulo, uhi;
+  bool lds;
+};
+
+// All threads: set up the entry range [E0, E0 + kEpb) of this workgroup.
+__device__ __forceinline__ EdgeRange edge_range(const int64_t* __restrict__ rp, int64_t n, int64_t m, int64_t E0,
+                                                int64_t* s_rp, int64_t* s_bounds) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int64_t E1 = E0 + kEpb < m ? E0 + kEpb : m;
+    const int64_t ulo = row_search(rp, 0, n - 1, E0);
+    const int64_t uhi = row_search(rp, ulo, n - 1, E1 - 1);
+    s_bounds[0] = E1;
+    s_bounds[1] = ulo;
+    s_bounds[2] = uhi;
+  }
+  __syncthreads();
+  EdgeRange r;
+  r.e0 = E0;
+  r.e1 = s_bounds[0];
+  r.ulo = s_bounds[1];
+  r.uhi = s_bounds[2];
+  r.lds = r.uhi - r.ulo + 2 <= kRpLds;
+  if (r.lds)
+    for (int64_t i = threadIdx.x; i <= r.uhi - r.ulo + 1; i += blockDim.x) s_rp[i] = rp[r.ulo + i];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int64_t edge_row(const int64_t* __restrict__ rp, const EdgeRange& r,
+                                            const int64_t* s_rp, int64_t e) {
+  if (r.lds) {
+    int64_t lo = 0, hi = r.uhi - r.ulo;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (s_rp[mid] <= e) lo = mid;
+      else hi = mid - 1;
+    }
+    return r.ulo + lo;
+  }
+  return row_search(rp, r.ulo, r.uhi, e);
+}
 
 // Cut: sum of w(u, v) over stored entries with part(u) != part(v), halved on
 // the host.  Nodes with part -1 have no entries.
 __global__ void __launch_bounds__(256) k_cut(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                              const int32_t* __restrict__ ew, const int32_t* __restrict__ part,
-                                             int64_t n, unsigned long long* __restrict__ out) {
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+                                             int64_t n, int64_t m, unsigned long long* __restrict__ out) {
+  __shared__ int64_t s_rp[kRpLds];
+  __shared__ int64_t s_bounds[3];
   int64_t acc = 0;
-  for (int64_t base = wid * kWave; base < n; base += waves * kWave) {
-    const int64_t v = base + lane();
-    int64_t e0 = 0, d = 0;
-    int32_t pv = 0;
-    if (v < n) {
-      e0 = rp[v];
-      d = rp[v + 1] - e0;
-      pv = part[v];
-    }
-    if (d <= kShort)
-      for (int64_t e = e0; e < e0 + d; ++e)
-        if (part[col[e]] != pv) acc += ew ? ew[e] : 1;
-    uint64_t big = __ballot(d > kShort);
-    while (big) {
-      const int l = __ffsll((unsigned long long)big) - 1;
-      big &= big - 1;
-      const int64_t be0 = __shfl(e0, l), bd = __shfl(d, l);
-      const int32_t bp = __shfl(pv, l);
-      for (int64_t e = be0 + lane(); e < be0 + bd; e += kWave)
-        if (part[col[e]] != bp) acc += ew ? ew[e] : 1;
+  for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < m; E0 += (int64_t)gridDim.x * kEpb) {
+    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      if (e >= r.e1) continue;
+      const int64_t u = edge_row(rp, r, s_rp, e);
+      if (part[u] != part[col[e]]) acc += ew ? ew[e] : 1;
     }
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
 }
 
-int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n,
+static inline unsigned grid_edges(int64_t m) {
+  int64_t g = (m + kEpb - 1) / kEpb;
+  if (g < 1) g = 1;
+  return (unsigned)(g < 8192 ? g : 8192);
+}
+
+int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
               unsigned long long* out, hipStream_t st) {
   SCLAP_TRY(fill_t((uint64_t*)out, 1, (uint64_t)0, st));
-  if (n <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_cut, dim3(grid1((n + 63) / 64 * 64 / 4, 4096)), dim3(256), 0, st, rp, col, ew, part, n, out);
+  if (n <= 0 || m <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_cut, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, part, n, m, out);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -252,75 +302,63 @@ __global__ void __launch_bounds__(256) k_coarse_of(const int32_t* __restrict__ l
 // nodes, as keys x * 2^b + y with their weights.
 __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const int32_t* __restrict__ ew, const int32_t* __restrict__ cof,
-                                               int64_t n, int bits, int mode, unsigned long long* __restrict__ cnt,
-                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+                                               int64_t n, int64_t m, int bits, int mode,
+                                               unsigned long long* __restrict__ cnt, uint64_t* __restrict__ keys,
+                                               int32_t* __restrict__ vals) {
+  __shared__ int64_t s_rp[kRpLds];
+  __shared__ int64_t s_bounds[3];
+  __shared__ int64_t s_w[4];
+  __shared__ unsigned long long s_base;
   int64_t total = 0;
-  for (int64_t base = wid * kWave; base < n; base += waves * kWave) {
-    const int64_t v = base + lane();
-    int64_t e0 = 0, d = 0;
-    int32_t x = -1;
-    if (v < n) {
-      e0 = rp[v];
-      d = rp[v + 1] - e0;
-      x = cof[v];
+  for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < m; E0 += (int64_t)gridDim.x * kEpb) {
+    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
+    int32_t xs[kItems], ys[kItems];
+    int mine = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      xs[j] = -1;
+      ys[j] = -1;
+      if (e >= r.e1) continue;
+      const int32_t x = cof[edge_row(rp, r, s_rp, e)];
+      const int32_t y = cof[col[e]];
+      if (x != y) {
+        xs[j] = x;
+        ys[j] = y;
+        ++mine;
+      }
     }
-    // short rows: count own entries, then claim a range with one atomic
-    int64_t mine = 0;
-    if (d <= kShort)
-      for (int64_t e = e0; e < e0 + d; ++e) mine += cof[col[e]] != x;
     if (mode == 0) {
       total += mine;
-    } else {
-      int64_t incl = mine;
-      for (int off = 1; off < kWave; off <<= 1) {
-        const int64_t o = __shfl_up(incl, off);
-        if ((int)lane() >= off) incl += o;
-      }
-      const int64_t wsum = __shfl(incl, kWave - 1);
-      unsigned long long base_pos = 0;
-      if (lane() == kWave - 1 && wsum) base_pos = atomicAdd(cnt, (unsigned long long)wsum);
-      base_pos = __shfl(base_pos, kWave - 1);
-      int64_t p = (int64_t)base_pos + incl - mine;
-      if (d <= kShort)
-        for (int64_t e = e0; e < e0 + d; ++e) {
-          const int32_t y = cof[col[e]];
-          if (y != x) {
-            keys[p] = ((uint64_t)(uint32_t)x << bits) | (uint64_t)(uint32_t)y;
-            vals[p] = ew ? ew[e] : 1;
-            ++p;
-          }
-        }
+      continue;
     }
-    uint64_t big = __ballot(d > kShort);
-    while (big) {
-      const int l = __ffsll((unsigned long long)big) - 1;
-      big &= big - 1;
-      const int64_t be0 = __shfl(e0, l), bd = __shfl(d, l);
-      const int32_t bx = __shfl(x, l);
-      for (int64_t eb = be0; eb < be0 + bd; eb += kWave) {
-        const int64_t e = eb + lane();
-        bool c = false;
-        int32_t y = 0;
-        if (e < be0 + bd) {
-          y = cof[col[e]];
-          c = y != bx;
-        }
-        const uint64_t m = __ballot(c);
-        if (mode == 0) {
-          total += c ? 1 : 0;
-        } else if (m) {
-          unsigned long long bp = 0;
-          if (lane() == 0) bp = atomicAdd(cnt, (unsigned long long)__popcll(m));
-          bp = __shfl(bp, 0);
-          if (c) {
-            const int64_t p = (int64_t)bp + __popcll(m & ((1ull << lane()) - 1ull));
-            keys[p] = ((uint64_t)(uint32_t)bx << bits) | (uint64_t)(uint32_t)y;
-            vals[p] = ew ? ew[e] : 1;
-          }
-        }
+    // block exclusive scan of `mine`, one atomic per block
+    int64_t incl = mine;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int64_t o = __shfl_up(incl, off);
+      if ((int)lane() >= off) incl += o;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane() == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+      for (int i = 0; i < 4; ++i) {
+        const int64_t c = s_w[i];
+        s_w[i] = t;
+        t += c;
       }
+      s_base = t ? atomicAdd(cnt, (unsigned long long)t) : 0;
+    }
+    __syncthreads();
+    int64_t p = (int64_t)s_base + s_w[w] + incl - mine;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      if (xs[j] < 0) continue;
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      keys[p] = ((uint64_t)(uint32_t)xs[j] << bits) | (uint64_t)(uint32_t)ys[j];
+      vals[p] = ew ? ew[e] : 1;
+      ++p;
     }
   }
   if (mode == 0) {
@@ -377,11 +415,12 @@ int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw,
 }
 
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
-                   int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals, hipStream_t st) {
+                   int64_t m, int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals,
+                   hipStream_t st) {
   SCLAP_TRY(fill_t((uint64_t*)cnt, 1, (uint64_t)0, st));
-  if (n <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_cross, dim3(grid1((n + 3) / 4, 4096)), dim3(256), 0, st, rp, col, ew, cof, n, bits, mode,
-                     cnt, keys, vals);
+  if (n <= 0 || m <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, cnt, keys,
+                     vals);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -469,16 +508,34 @@ __device__ int64_t block_min64(int64_t x, int64_t* sh) {
   return r;
 }
 
-__global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict__ slots) {
+// largest l in [0, cnt) with pre[l] <= x (LDS)
+__device__ __forceinline__ int lds_upper(const int64_t* pre, int cnt, int64_t x) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// state[0..3] = head, tail, next seed, yielded flag.  With allow_yield the
+// kernel stops before a level whose frontier has more than big_entries
+// stored entries (rows ascending only); the host expands that level with
+// grid-wide kernels and relaunches.
+__global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict__ slots, int allow_yield,
+                                                      int64_t big_entries) {
   const IpSlot sl = slots[blockIdx.x];
   __shared__ int64_t sh[kIpWaves];
   __shared__ int64_t s_head, s_tail, s_next;
+  __shared__ int64_t s_pre[kIpThreads];
+  __shared__ int64_t s_e0[kIpThreads];
   const int64_t n = sl.n;
   const int wv = threadIdx.x / kWave;
   if (threadIdx.x == 0) {
-    s_head = 0;
-    s_tail = 0;
-    s_next = 0;
+    s_head = sl.state[0];
+    s_tail = sl.state[1];
+    s_next = sl.state[2];
   }
   __syncthreads();
   for (;;) {
@@ -518,62 +575,115 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       continue;
     }
     const int64_t F = tail - head;
-    // pass 1: claims
-    for (int64_t fi = wv; fi < F; fi += kIpWaves) {
-      const int32_t f = ld_acq(&sl.order[head + fi]);
-      const int64_t e0 = sl.rp[f], e1 = sl.rp[f + 1];
-      for (int64_t e = e0 + lane(); e < e1; e += kWave) {
-        const int32_t u = sl.col[e];
-        if (ld_acq(&sl.pos[u]) == -1) atomicMin(&sl.claim[u], (int32_t)fi);
+    if (allow_yield && sl.rows_sorted) {
+      int64_t E = 0;
+      for (int64_t fc = 0; fc < F; fc += kIpThreads) {
+        const int64_t fi = fc + threadIdx.x;
+        int64_t d = 0;
+        if (fi < F) {
+          const int32_t f = ld_acq(&sl.order[head + fi]);
+          d = sl.rp[f + 1] - sl.rp[f];
+        }
+        int64_t ex;
+        E += block_exscan(d, &ex, sh);
+        __syncthreads();
+      }
+      if (E > big_entries) {
+        if (threadIdx.x == 0) {
+          sl.state[0] = head;
+          sl.state[1] = tail;
+          sl.state[2] = next;
+          sl.state[3] = 1;
+        }
+        return;
       }
     }
-    __syncthreads();
-    // pass 2: children per frontier node
-    for (int64_t fi = wv; fi < F; fi += kIpWaves) {
-      const int32_t f = ld_acq(&sl.order[head + fi]);
-      const int64_t e0 = sl.rp[f], e1 = sl.rp[f + 1];
-      int64_t c = 0;
-      for (int64_t e = e0 + lane(); e < e1; e += kWave) {
-        const int32_t u = sl.col[e];
-        c += (ld_acq(&sl.claim[u]) == (int32_t)fi && ld_acq(&sl.pos[u]) == -1) ? 1 : 0;
+    // pass A: every unvisited neighbour takes the smallest frontier position
+    for (int64_t fc = 0; fc < F; fc += kIpThreads) {
+      const int64_t fi = fc + threadIdx.x;
+      int64_t d = 0, e0 = 0;
+      if (fi < F) {
+        const int32_t f = ld_acq(&sl.order[head + fi]);
+        e0 = sl.rp[f];
+        d = sl.rp[f + 1] - e0;
       }
-      for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-      if (lane() == 0) st_rel(&sl.cnt[fi], (int32_t)c);
-    }
-    __syncthreads();
-    // pass 3: exclusive offsets of the child counts
-    int64_t carry = 0;
-    for (int64_t b = 0; b < F; b += kIpThreads) {
-      const int64_t fi = b + threadIdx.x;
-      const int64_t c = fi < F ? ld_acq(&sl.cnt[fi]) : 0;
       int64_t ex;
-      const int64_t tot = block_exscan(c, &ex, sh);
-      if (fi < F) st_rel(&sl.cnt[fi], (int32_t)(carry + ex));
-      carry += tot;
+      const int64_t Tc = block_exscan(d, &ex, sh);
+      s_pre[threadIdx.x] = ex;
+      s_e0[threadIdx.x] = e0;
+      __syncthreads();
+      const int nf = (int)(F - fc < kIpThreads ? F - fc : kIpThreads);
+      for (int64_t idx = threadIdx.x; idx < Tc; idx += kIpThreads) {
+        const int l = lds_upper(s_pre, nf, idx);
+        const int32_t u = sl.col[s_e0[l] + idx - s_pre[l]];
+        if (ld_acq(&sl.pos[u]) == -1) atomicMin(&sl.claim[u], (int32_t)(fc + l));
+      }
       __syncthreads();
     }
-    const int64_t T = carry;
     __syncthreads();
-    // pass 4: children in ascending id
-    for (int64_t fi = wv; fi < F; fi += kIpWaves) {
-      const int32_t f = ld_acq(&sl.order[head + fi]);
-      const int64_t e0 = sl.rp[f], e1 = sl.rp[f + 1];
-      const int64_t off = tail + ld_acq(&sl.cnt[fi]);
-      if (sl.rows_sorted) {
-        int64_t run = 0;
-        for (int64_t eb = e0; eb < e1; eb += kWave) {
-          const int64_t e = eb + lane();
-          int32_t u = 0;
-          bool ch = false;
-          if (e < e1) {
-            u = sl.col[e];
-            ch = ld_acq(&sl.claim[u]) == (int32_t)fi && ld_acq(&sl.pos[u]) == -1;
-          }
-          const uint64_t m = __ballot(ch);
-          if (ch) st_rel(&sl.order[off + run + __popcll(m & ((1ull << lane()) - 1ull))], u);
-          run += __popcll(m);
+    int64_t T = 0;
+    if (sl.rows_sorted) {
+      // pass B: children in frontier order, each frontier node's children in
+      // row order = ascending id
+      for (int64_t fc = 0; fc < F; fc += kIpThreads) {
+        const int64_t fi = fc + threadIdx.x;
+        int64_t d = 0, e0 = 0;
+        if (fi < F) {
+          const int32_t f = ld_acq(&sl.order[head + fi]);
+          e0 = sl.rp[f];
+          d = sl.rp[f + 1] - e0;
         }
-      } else {
+        int64_t ex;
+        const int64_t Tc = block_exscan(d, &ex, sh);
+        s_pre[threadIdx.x] = ex;
+        s_e0[threadIdx.x] = e0;
+        __syncthreads();
+        const int nf = (int)(F - fc < kIpThreads ? F - fc : kIpThreads);
+        for (int64_t ib = 0; ib < Tc; ib += kIpThreads) {
+          const int64_t idx = ib + threadIdx.x;
+          bool ch = false;
+          int32_t u = 0;
+          if (idx < Tc) {
+            const int l = lds_upper(s_pre, nf, idx);
+            u = sl.col[s_e0[l] + idx - s_pre[l]];
+            ch = ld_acq(&sl.claim[u]) == (int32_t)(fc + l) && ld_acq(&sl.pos[u]) == -1;
+          }
+          int64_t cx;
+          const int64_t ct = block_exscan(ch ? 1 : 0, &cx, sh);
+          if (ch) st_rel(&sl.order[tail + T + cx], u);
+          T += ct;
+          __syncthreads();
+        }
+      }
+    } else {
+      // rows in any order: per frontier node, count children, offsets, and
+      // place each child by its rank among the node's children
+      for (int64_t fi = wv; fi < F; fi += kIpWaves) {
+        const int32_t f = ld_acq(&sl.order[head + fi]);
+        const int64_t e0 = sl.rp[f], e1 = sl.rp[f + 1];
+        int64_t c = 0;
+        for (int64_t e = e0 + lane(); e < e1; e += kWave) {
+          const int32_t u = sl.col[e];
+          c += (ld_acq(&sl.claim[u]) == (int32_t)fi && ld_acq(&sl.pos[u]) == -1) ? 1 : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if (lane() == 0) st_rel(&sl.cnt[fi], (int32_t)c);
+      }
+      __syncthreads();
+      for (int64_t b = 0; b < F; b += kIpThreads) {
+        const int64_t fi = b + threadIdx.x;
+        const int64_t c = fi < F ? ld_acq(&sl.cnt[fi]) : 0;
+        int64_t ex;
+        const int64_t tot = block_exscan(c, &ex, sh);
+        if (fi < F) st_rel(&sl.cnt[fi], (int32_t)(T + ex));
+        T += tot;
+        __syncthreads();
+      }
+      __syncthreads();
+      for (int64_t fi = wv; fi < F; fi += kIpWaves) {
+        const int32_t f = ld_acq(&sl.order[head + fi]);
+        const int64_t e0 = sl.rp[f], e1 = sl.rp[f + 1];
+        const int64_t off = tail + ld_acq(&sl.cnt[fi]);
         for (int64_t e = e0 + lane(); e < e1; e += kWave) {
           const int32_t u = sl.col[e];
           if (!(ld_acq(&sl.claim[u]) == (int32_t)fi && ld_acq(&sl.pos[u]) == -1)) continue;
@@ -587,7 +697,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       }
     }
     __syncthreads();
-    // pass 5: positions of the new nodes
+    // pass C: positions of the new nodes
     for (int64_t i = threadIdx.x; i < T; i += kIpThreads) {
       const int32_t u = ld_acq(&sl.order[tail + i]);
       st_rel(&sl.pos[u], (int32_t)(tail + i));
@@ -599,6 +709,12 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
     }
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    sl.state[0] = s_head;
+    sl.state[1] = s_tail;
+    sl.state[2] = s_next;
+    sl.state[3] = 0;
+  }
   // chunks of the BFS order: block(v) = min(k-1, floor(k P(v) / C))
   const int64_t placed = s_tail;
   int64_t C = 0;
@@ -631,9 +747,100 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
   }
 }
 
-int initial_partition(const IpSlot* dev_slots, int count, hipStream_t st) {
+// ---- grid-wide expansion of one large BFS level (rows ascending) ----------
+
+// dpre[fi] = degree of frontier node fi (scanned on the host side)
+__global__ void __launch_bounds__(256) k_lvl_deg(const IpSlot* __restrict__ slp, int64_t head, int64_t F,
+                                                 int64_t* __restrict__ deg) {
+  const IpSlot sl = *slp;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t fi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; fi <= F; fi += stride) {
+    if (fi == F) {
+      deg[fi] = 0;
+      continue;
+    }
+    const int32_t f = sl.order[head + fi];
+    deg[fi] = sl.rp[f + 1] - sl.rp[f];
+  }
+}
+
+// mode 0: claims; mode 1: child flags (1 = child) per flattened entry
+__global__ void __launch_bounds__(256) k_lvl_entries(const IpSlot* __restrict__ slp, int64_t head, int64_t F,
+                                                     const int64_t* __restrict__ dpre, int64_t E, int mode,
+                                                     int32_t* __restrict__ flags) {
+  const IpSlot sl = *slp;
+  __shared__ int64_t s_rp[kRpLds];
+  __shared__ int64_t s_bounds[3];
+  for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < E; E0 += (int64_t)gridDim.x * kEpb) {
+    const EdgeRange r = edge_range(dpre, F, E, E0, s_rp, s_bounds);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t idx = E0 + j * 256 + threadIdx.x;
+      if (idx >= r.e1) continue;
+      const int64_t fi = edge_row(dpre, r, s_rp, idx);
+      const int32_t f = sl.order[head + fi];
+      const int32_t u = sl.col[sl.rp[f] + idx - dpre[fi]];
+      if (mode == 0) {
+        if (sl.pos[u] == -1) atomicMin(&sl.claim[u], (int32_t)fi);
+      } else {
+        flags[idx] = (sl.claim[u] == (int32_t)fi && sl.pos[u] == -1) ? 1 : 0;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_lvl_emit(const IpSlot* __restrict__ slp, int64_t head, int64_t tail,
+                                                  int64_t F, const int64_t* __restrict__ dpre, int64_t E,
+                                                  const int32_t* __restrict__ flags, const int32_t* __restrict__ fpos) {
+  const IpSlot sl = *slp;
+  __shared__ int64_t s_rp[kRpLds];
+  __shared__ int64_t s_bounds[3];
+  for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < E; E0 += (int64_t)gridDim.x * kEpb) {
+    const EdgeRange r = edge_range(dpre, F, E, E0, s_rp, s_bounds);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t idx = E0 + j * 256 + threadIdx.x;
+      if (idx >= r.e1 || !flags[idx]) continue;
+      const int64_t fi = edge_row(dpre, r, s_rp, idx);
+      const int32_t f = sl.order[head + fi];
+      sl.order[tail + fpos[idx]] = sl.col[sl.rp[f] + idx - dpre[fi]];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_lvl_pos(const IpSlot* __restrict__ slp, int64_t tail, int64_t T) {
+  const IpSlot sl = *slp;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T; i += stride)
+    sl.pos[sl.order[tail + i]] = (int32_t)(tail + i);
+}
+
+int initial_partition(const IpSlot* dev_slots, int count, int allow_yield, int64_t big_entries, hipStream_t st) {
   if (count <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_ip_bfs, dim3(count), dim3(kIpThreads), 0, st, dev_slots);
+  hipLaunchKernelGGL(k_ip_bfs, dim3(count), dim3(kIpThreads), 0, st, dev_slots, allow_yield, big_entries);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int ip_level_deg(const IpSlot* slot, int64_t head, int64_t F, int64_t* deg, hipStream_t st) {
+  hipLaunchKernelGGL(k_lvl_deg, dim3(grid1(F + 1)), dim3(256), 0, st, slot, head, F, deg);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int ip_level_entries(const IpSlot* slot, int64_t head, int64_t F, const int64_t* dpre, int64_t E, int mode,
+                     int32_t* flags, hipStream_t st) {
+  if (E <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_lvl_entries, dim3(grid_edges(E)), dim3(256), 0, st, slot, head, F, dpre, E, mode, flags);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int ip_level_emit(const IpSlot* slot, int64_t head, int64_t tail, int64_t F, const int64_t* dpre, int64_t E,
+                  const int32_t* flags, const int32_t* fpos, int64_t T, hipStream_t st) {
+  if (E > 0)
+    hipLaunchKernelGGL(k_lvl_emit, dim3(grid_edges(E)), dim3(256), 0, st, slot, head, tail, F, dpre, E, flags, fpos);
+  if (T > 0) hipLaunchKernelGGL(k_lvl_pos, dim3(grid1(T)), dim3(256), 0, st, slot, tail, T);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
