@@ -248,13 +248,20 @@ typedef struct sclap_job_result {
  * jobs together step by step, so that jobs admitted while others run share
  * their launches.  A job's result equals sclap_partition on it alone. */
 int sclap_server_create(sclap_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_active, sclap_server** out);
+/* Copies job->graph (device memory that must be complete: the caller has
+ * synchronised the stream that wrote it) and queues the job.  SCLAP_EBUDGET
+ * if the job's footprint alone exceeds the budget.  part_out stays owned by
+ * the caller and must stay allocated until the job's result was taken. */
 int sclap_server_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticket);
-/* SCLAP_OK with *res filled once done; SCLAP_EAGAIN while pending. */
+/* SCLAP_OK with *res filled once done (part_out is then complete on the
+ * device), after which the ticket is forgotten; SCLAP_EAGAIN while pending;
+ * SCLAP_ENOTFOUND for an unknown or already taken ticket. */
 int sclap_server_poll(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
 int sclap_server_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
 /* Latency percentiles over completed jobs and throughput since creation. */
 int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double* jobs_per_s,
                        int64_t* completed, int64_t* peak_bytes);
+/* Finishes every queued and running job, then frees the server. */
 int sclap_server_destroy(sclap_server* srv);
 
 /* ---- measurement ------------------------------------------------------------ */

@@ -202,7 +202,7 @@ class Context:
                                            ctypes.byref(nodes), ctypes.byref(rnd_ms), ctypes.byref(rounds)))
         out = {"rate_ms": ms.value, "rate_launches": la.value, "visits": vis.value, "nodes": nodes.value,
                "round_ms": rnd_ms.value, "rounds": rounds.value}
-        K = 9
+        K = 4
         kms, kb = (ctypes.c_double * K)(), (ctypes.c_double * K)()
         kv, kn = (ctypes.c_int64 * K)(), (ctypes.c_int64 * K)()
         kl = ctypes.c_int64()
@@ -424,6 +424,8 @@ class Server:
                threshold: int = 0) -> int:
         job = Job(g.csr(), k, 0, eps[0], eps[1], ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold),
                   _ptr(part_out))
+        # the server copies the graph on a stream of its own
+        torch.cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
         _check(self.ctx.lib.sclap_server_submit(self.h, ctypes.byref(job), ctypes.byref(t)))
         self._keep[t.value] = part_out

@@ -84,8 +84,10 @@ static int check_edge_total(Ctx* c, const sclap_csr* g, hipStream_t st) {
   return SCLAP_OK;
 }
 
+namespace sclap {
+
 // Set up a partition job: bounds from the whole input, level 0, first stage.
-static int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t eps_num, int64_t eps_den,
+int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t eps_num, int64_t eps_den,
                                const sclap_ml_params* p, int32_t* part_out, hipStream_t st) {
   SCLAP_TRY(check_csr(g));
   if (!p) return fail(SCLAP_EINVAL, "params are NULL");
@@ -131,6 +133,8 @@ static int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, in
   return SCLAP_OK;
 }
 
+}  // namespace sclap
+
 extern "C" {
 
 const char* sclap_last_error(void) { return last_error_cstr(); }
@@ -162,14 +166,7 @@ int sclap_destroy(sclap_ctx* ctx) {
   Ctx& c = ctx->c;
   (void)hipSetDevice(c.device);
   (void)hipDeviceSynchronize();
-  Scratch* all[] = {&c.bins, &c.ckeys, &c.ckeys2, &c.tkey, &c.wv, &c.prefix, &c.prim, &c.hub_chunk,
-                    &c.hub_tab, &c.hub_own, &c.hub_gkeys, &c.hub_gvals, &c.step_ctr, &c.small,
-                    &c.slots_dev, &c.ip_slots, &c.hub_slice, &c.hub_best, &c.movers};
-  for (Scratch* s : all) s->release(nullptr);
-  (void)hipDeviceSynchronize();
-  if (c.pin) (void)hipHostFree(c.pin);
-  if (c.pin_slots) (void)hipHostFree(c.pin_slots);
-  for (auto& e : c.ev) (void)hipEventDestroy(e);
+  ctx_release(&c, nullptr);
   delete ctx;
   return SCLAP_OK;
 }

@@ -77,7 +77,11 @@ struct Ctx {
   int cu_count = 256;
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
-  Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers;
+  Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
+  // jobs and levels whose nodes the current bins hold (clustering rounds only)
+  std::vector<std::pair<const void*, int>> bin_sig;
+  bool bin_sig_valid = false;
+  int64_t bin_cap_used = 0;
   int64_t hub_cap = 0;             // entries of the global hub table (kept -1/0)
   // pinned host staging
   int64_t* pin = nullptr;
@@ -93,7 +97,7 @@ struct Ctx {
   int64_t prof_rate_nodes = 0;
   double prof_round_ms = 0;        // whole LP rounds
   int64_t prof_rounds = 0;
-  double prof_k_ms[kBins] = {};    // per rating kernel (last bin: the four hub kernels)
+  double prof_k_ms[kBins] = {};    // per rating launch group (kRateGroups used)
   double prof_k_bytes[kBins] = {}; // algorithmic bytes moved by that kernel
   int64_t prof_k_visits[kBins] = {};
   int64_t prof_k_nodes[kBins] = {};
@@ -101,6 +105,8 @@ struct Ctx {
 };
 
 int ctx_ensure_pin(Ctx* c, size_t bytes);
+// Frees every scratch buffer, the pinned staging and the events of c.
+void ctx_release(Ctx* c, hipStream_t st);
 int ctx_ensure_slots(Ctx* c, size_t count);
 
 // Prepare a job's level 0 from the caller's CSR (widens node weights).
@@ -121,7 +127,8 @@ int contract_level(Ctx* c, Job* j, int i, int drop_isolated, hipStream_t st);
 // Fused initial partition of the jobs' current (coarsest) levels.
 int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipStream_t st);
 
-// Run jobs to completion (the executor).
+// One executor step over the jobs (see engine.hip); run_jobs loops it.
+int step_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st, bool* all_done);
 int run_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st);
 
 double now_ms();

@@ -73,6 +73,21 @@ int ctx_ensure_pin(Ctx* c, size_t bytes) {
   return SCLAP_OK;
 }
 
+void ctx_release(Ctx* c, hipStream_t st) {
+  Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
+                    &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
+                    &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
+                    &c->hub_maps, &c->binmeta};
+  for (Scratch* s : all) s->release(st);
+  (void)hipStreamSynchronize(st);
+  if (c->pin) (void)hipHostFree(c->pin);
+  if (c->pin_slots) (void)hipHostFree(c->pin_slots);
+  c->pin = nullptr;
+  c->pin_slots = nullptr;
+  c->pin_bytes = c->pin_slots_cap = 0;
+  for (auto& ev : c->ev) (void)hipEventDestroy(ev);
+}
+
 int ctx_ensure_slots(Ctx* c, size_t count) {
   if (count <= c->pin_slots_cap) return SCLAP_OK;
   if (c->pin_slots) (void)hipHostFree(c->pin_slots);
@@ -217,8 +232,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (ns == 0) return SCLAP_OK;
   SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
   int64_t N = 0, Lt = 0, hub_need = 0;
-  SCLAP_TRY(c->step_ctr.ensure((size_t)ns * CTR_N * sizeof(int64_t), st));
-  int64_t* ctr = (int64_t*)c->step_ctr.p;
+  SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
+  int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
   for (int s = 0; s < ns; ++s) {
     Job* j = jobs[s];
     const Level& L = j->lv[j->cur];
@@ -254,10 +269,12 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
   const size_t Nz = (size_t)std::max<int64_t>(N, 1);
   SCLAP_TRY(c->bins.ensure(kBins * Nz * sizeof(int32_t), st));
-  SCLAP_TRY(c->small.ensure(1024, st));
+  SCLAP_TRY(c->binfo.ensure(kBins * Nz * sizeof(uint64_t), st));
   SCLAP_TRY(c->hub_chunk.ensure((Nz + 1) * sizeof(uint32_t), st));
   SCLAP_TRY(c->hub_tab.ensure(Nz * sizeof(int64_t), st));
   SCLAP_TRY(c->hub_slice.ensure((Nz + 1) * sizeof(uint32_t), st));
+  const size_t map_cap = Nz + (size_t)std::max<int64_t>(hub_need, 0) / 4096 + 64;
+  SCLAP_TRY(c->hub_maps.ensure(2 * map_cap * sizeof(uint32_t), st));
   if (c->hub_own.bytes < Nz * sizeof(int64_t)) {
     SCLAP_TRY(c->hub_own.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
@@ -266,7 +283,10 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_best.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
   }
-  SCLAP_TRY(c->movers.ensure(Nz * sizeof(int32_t), st));
+  SCLAP_TRY(c->movers.ensure(3 * Nz * sizeof(int32_t), st));  // rated list, movers, big movers
+  int32_t* rated = (int32_t*)c->movers.p;
+  int32_t* movers = rated + Nz;
+  int32_t* bigm = movers + Nz;
   if (c->hub_cap < hub_need || !c->hub_gkeys.p) {
     const int64_t cap = std::max<int64_t>(hub_need, 1024);
     SCLAP_TRY(c->hub_gkeys.ensure((size_t)cap * 4, st));
@@ -279,58 +299,69 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_TRY(c->slots_dev.ensure((size_t)ns * sizeof(DevSlot), st));
   DevSlot* S = (DevSlot*)c->slots_dev.p;
   SCLAP_HIP(hipMemcpyAsync(S, c->pin_slots, (size_t)ns * sizeof(DevSlot), hipMemcpyHostToDevice, st));
-  SCLAP_TRY(fill_i64(ctr, (int64_t)ns * CTR_N, 0, st));
-  // lp counters: u32 [0..8] bin counts, [9] contended, [10] overflow, [11..12] hub
-  // chunks and slices, [13] refinement movers; u64 at byte 64: visits per bin
+  // Per-round counters (zeroed together with the slot counters after them):
+  // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and slices,
+  // [13] refinement movers, [15] big movers, [16] contended set too large
+  // for the one-workgroup path.  The binning results live in c->binmeta:
+  // u32 [0..8] bin counts, [14] rated; u64 at byte 128: visits per bin.
+  // Clustering rounds of the same jobs on the same levels rate the same
+  // nodes, so their bins are reused.
   uint32_t* small = (uint32_t*)((char*)c->small.p + 256);
-  unsigned long long* bin_vis = (unsigned long long*)((char*)small + 64);
-  SCLAP_TRY(fill_u32(small, 64, 0, st));
+  SCLAP_TRY(c->binmeta.ensure(256, st));
+  uint32_t* meta = (uint32_t*)c->binmeta.p;
+  unsigned long long* bin_vis = (unsigned long long*)((char*)meta + 128);
+  SCLAP_TRY(fill_u32(small, 64 + (int64_t)ns * CTR_N * 2, 0, st));
   int32_t* bins = (int32_t*)c->bins.p;
   const int64_t bin_cap = (int64_t)Nz;
+  std::vector<std::pair<const void*, int>> sig;
+  bool all_cluster = true;
+  for (int s = 0; s < ns; ++s) {
+    sig.emplace_back(jobs[s], jobs[s]->cur);
+    all_cluster = all_cluster && jobs[s]->stage == ST_COARSEN;
+  }
+  const bool reuse_bins = all_cluster && c->bin_sig_valid && sig == c->bin_sig && c->bin_cap_used == bin_cap;
 
-  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kBins + 1], st));
-  SCLAP_TRY(launch_bin(S, ns, N, bins, bin_cap, small, bin_vis, st));
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kRateGroups + 1], st));
+  uint64_t* binfo = (uint64_t*)c->binfo.p;
+  if (!reuse_bins) {
+    SCLAP_TRY(fill_u32(meta, 64, 0, st));
+    SCLAP_TRY(launch_bin(S, ns, N, bins, binfo, bin_cap, meta, bin_vis, rated, meta + 14, st));
+    c->bin_sig = sig;
+    c->bin_sig_valid = all_cluster;
+    c->bin_cap_used = bin_cap;
+  }
   RateHubScratch hub;
   hub.chunk_off = (uint32_t*)c->hub_chunk.p;
   hub.tab_off = (int64_t*)c->hub_tab.p;
   hub.totals = small + 11;
   hub.slice_off = (uint32_t*)c->hub_slice.p;
+  hub.chunk_hub = (uint32_t*)c->hub_maps.p;
+  hub.slice_hub = hub.chunk_hub + map_cap;
+  hub.map_cap = (uint32_t)map_cap;
   hub.best = (unsigned long long*)c->hub_best.p;
   hub.gkeys = (int32_t*)c->hub_gkeys.p;
   hub.gvals = (int32_t*)c->hub_gvals.p;
   hub.own = (int64_t*)c->hub_own.p;
   hub.overflow = small + 10;
   hub.tab_cap = c->hub_cap;
-  SCLAP_TRY(launch_rate(S, ns, bins, bin_cap, small, hub, N, st, c->profile ? c->ev : nullptr));
+  SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hub_need > 0, st, c->profile ? c->ev : nullptr));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
-  SCLAP_TRY(launch_incoming_decide(S, ns, N, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
-  SCLAP_TRY(ctx_ensure_pin(c, 256));
-  uint32_t* hs = (uint32_t*)c->pin;
-  SCLAP_HIP(hipMemcpyAsync(hs, small, 160, hipMemcpyDeviceToHost, st));
+  SCLAP_TRY(launch_incoming_decide(S, ns, N, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
+  SCLAP_TRY(launch_contended_small(S, ns, (const uint64_t*)c->ckeys.p, small + 9, node_bits, small + 16, st));
+  bool any_refine = false;
+  for (int s = 0; s < ns; ++s) any_refine = any_refine || c->pin_slots[s].mode == MODE_REFINE;
+  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, small + 13, bigm, small + 15, any_refine, small + 16, st));
+  const size_t rd = 256 + (size_t)ns * CTR_N * sizeof(int64_t);
+  SCLAP_TRY(ctx_ensure_pin(c, rd + 512));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
+  const uint32_t* hs = (const uint32_t*)c->pin;
   if (hs[10]) return fail(SCLAP_EHIP, "hub rating table too small");
-  const uint32_t cc = hs[9];
-  if (c->profile) {
-    const unsigned long long* hv = (const unsigned long long*)((char*)hs + 64);
-    bool weighted = false;
-    for (int s = 0; s < ns; ++s) weighted = weighted || c->pin_slots[s].ew != nullptr;
-    for (int b = 0; b < kBins; ++b) {
-      float ms = 0;
-      SCLAP_HIP(hipEventElapsedTime(&ms, c->ev[b], c->ev[b + 1]));
-      c->prof_k_ms[b] += ms;
-      c->prof_k_visits[b] += (int64_t)hv[b];
-      c->prof_k_nodes[b] += hs[b];
-      c->prof_k_bytes[b] += (double)hv[b] * (weighted ? 12.0 : 8.0) + (double)hs[b] * 32.0;
-      c->prof_rate_nodes += hs[b];
-    }
-    float a = 0;
-    SCLAP_HIP(hipEventElapsedTime(&a, c->ev[0], c->ev[kBins]));
-    c->prof_rate_ms += a;
-    c->prof_rate_launches += 1;
-    c->prof_k_launches += 1;
-  }
-  if (cc > 0) {
+  if (hs[16]) {
+    // contended set too large for one workgroup: device-wide sort and scan,
+    // then the apply step that was skipped
+    const uint32_t cc = hs[9];
     SCLAP_TRY(c->ckeys2.ensure((size_t)cc * 8, st));
     SCLAP_TRY(c->tkey.ensure((size_t)cc * 4, st));
     SCLAP_TRY(c->wv.ensure((size_t)cc * 8, st));
@@ -345,21 +376,49 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                (int64_t*)c->prefix.p, cc, st));
     SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                     (const int64_t*)c->prefix.p, st));
+    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, small + 13, bigm, small + 15, any_refine, nullptr, st));
+    SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
+    SCLAP_HIP(hipStreamSynchronize(st));
   }
-  bool any_refine = false;
-  for (int s = 0; s < ns; ++s) any_refine = any_refine || c->pin_slots[s].mode == MODE_REFINE;
-  SCLAP_TRY(launch_apply(S, ns, N, (int32_t*)c->movers.p, small + 13, any_refine, st));
-  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kBins + 2], st));
-  SCLAP_TRY(ctx_ensure_pin(c, (size_t)ns * CTR_N * sizeof(int64_t)));
-  SCLAP_HIP(hipMemcpyAsync(c->pin, ctr, (size_t)ns * CTR_N * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  SCLAP_HIP(hipStreamSynchronize(st));
+  if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kRateGroups + 2], st));
+  // slot counters follow the lp counters: expose them at c->pin for the caller
+  const int64_t* sctr = (const int64_t*)((const char*)c->pin + 256);
   if (c->profile) {
-    float b = 0;
-    SCLAP_HIP(hipEventElapsedTime(&b, c->ev[kBins + 1], c->ev[kBins + 2]));
-    c->prof_round_ms += b;
+    SCLAP_HIP(hipStreamSynchronize(st));
+    uint32_t* hm = (uint32_t*)((char*)c->pin + rd);
+    SCLAP_HIP(hipMemcpyAsync(hm, meta, 256, hipMemcpyDeviceToHost, st));
+    SCLAP_HIP(hipStreamSynchronize(st));
+    const unsigned long long* hv = (const unsigned long long*)((const char*)hm + 128);
+    bool weighted = false;
+    for (int s = 0; s < ns; ++s) weighted = weighted || c->pin_slots[s].ew != nullptr;
+    const int group_of[kBins] = {0, 0, 0, 0, 0, 1, 1, 2, 3};
+    for (int g = 0; g < kRateGroups; ++g) {
+      float ms = 0;
+      SCLAP_HIP(hipEventElapsedTime(&ms, c->ev[g], c->ev[g + 1]));
+      c->prof_k_ms[g] += ms;
+    }
+    for (int b = 0; b < kBins; ++b) {
+      const int g = group_of[b];
+      c->prof_k_visits[g] += (int64_t)hv[b];
+      c->prof_k_nodes[g] += hm[b];
+      c->prof_k_bytes[g] += (double)hv[b] * (weighted ? 12.0 : 8.0) + (double)hm[b] * 32.0;
+      c->prof_rate_nodes += hm[b];
+    }
+    float a = 0, b2 = 0;
+    SCLAP_HIP(hipEventElapsedTime(&a, c->ev[0], c->ev[kRateGroups]));
+    SCLAP_HIP(hipEventElapsedTime(&b2, c->ev[kRateGroups + 1], c->ev[kRateGroups + 2]));
+    c->prof_rate_ms += a;
+    c->prof_rate_launches += 1;
+    c->prof_k_launches += 1;
+    c->prof_round_ms += b2;
     c->prof_rounds += 1;
-    for (int s = 0; s < ns; ++s) c->prof_rate_visits += c->pin[(size_t)s * CTR_N + CTR_VISITS];
+    for (int s = 0; s < ns; ++s) c->prof_rate_visits += sctr[(size_t)s * CTR_N + CTR_VISITS];
   }
+  // move the slot counters to the front of the staging buffer; a clustering
+  // round rates every node of degree > 0, so its edge visits are the level's m
+  std::memmove(c->pin, sctr, (size_t)ns * CTR_N * sizeof(int64_t));
+  for (int s = 0; s < ns; ++s)
+    if (jobs[s]->stage == ST_COARSEN) c->pin[(size_t)s * CTR_N + CTR_VISITS] = jobs[s]->lv[jobs[s]->cur].m;
   return SCLAP_OK;
 }
 
@@ -665,117 +724,129 @@ static int after_contract(Ctx* c, Job* j, std::vector<Job*>& ipq, hipStream_t st
   return start_ip_or_refine(c, j, ipq);
 }
 
-int run_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
+// One step of the executor: one fused LP round over every job at an LP
+// stage, then contractions, initial partitions and finishing.  Jobs whose
+// stage is ST_IP on entry are partitioned in this step.  *all_done is set
+// when every job is done or failed.
+int step_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st, bool* all_done_out) {
   std::vector<Job*> ipq;
-  for (Job* j : jobs) {
+  for (Job* j : jobs)
     if (j->stage == ST_IP) ipq.push_back(j);
-  }
-  for (;;) {
-    // 1. LP rounds
-    std::vector<Job*> lp;
-    for (Job* j : jobs)
-      if (j->stage == ST_COARSEN || j->stage == ST_REFINE) lp.push_back(j);
-    if (!lp.empty()) {
-      const double t0 = now_ms();
-      SCLAP_TRY(lp_round(c, lp, st));
-      const double dt = now_ms() - t0;
-      for (size_t s = 0; s < lp.size(); ++s) {
-        Job* j = lp[s];
-        const int64_t moved = c->pin[s * CTR_N + CTR_MOVED];
-        const int64_t visits = c->pin[s * CTR_N + CTR_VISITS];
-        const int r = j->round;
-        if (j->stage == ST_COARSEN) {
-          j->st.ms_cluster += dt;
-          j->st.moved_c[j->cur][r - 1] = moved;
-          j->st.visits_c[j->cur] += visits;
-          j->rst.moved[r - 1] = moved;
-          j->rst.visits += visits;
-          j->rst.ms += dt;
-          bool done = r >= j->lp_rounds;
-          if (j->stop_rule == 1 && r >= 2 && 20 * (moved + j->moved_prev) < j->n_stop) done = true;
-          j->moved_prev = moved;
-          if (done) {
-            j->st.rounds_c[j->cur] = r;
-            j->rst.rounds = r;
-            j->stage = j->kind == JOB_CLUSTER ? ST_DONE : ST_CONTRACT;
-            if (j->kind == JOB_CLUSTER) job_release_lp(j, st, true);
-          } else {
-            j->round = r + 1;
-          }
+  // 1. LP rounds
+  std::vector<Job*> lp;
+  for (Job* j : jobs)
+    if (j->stage == ST_COARSEN || j->stage == ST_REFINE) lp.push_back(j);
+  if (!lp.empty()) {
+    const double t0 = now_ms();
+    SCLAP_TRY(lp_round(c, lp, st));
+    const double dt = now_ms() - t0;
+    for (size_t s = 0; s < lp.size(); ++s) {
+      Job* j = lp[s];
+      const int64_t moved = c->pin[s * CTR_N + CTR_MOVED];
+      const int64_t visits = c->pin[s * CTR_N + CTR_VISITS];
+      const int r = j->round;
+      if (j->stage == ST_COARSEN) {
+        j->st.ms_cluster += dt;
+        j->st.moved_c[j->cur][r - 1] = moved;
+        j->st.visits_c[j->cur] += visits;
+        j->rst.moved[r - 1] = moved;
+        j->rst.visits += visits;
+        j->rst.ms += dt;
+        bool done = r >= j->lp_rounds;
+        if (j->stop_rule == 1 && r >= 2 && 20 * (moved + j->moved_prev) < j->n_stop) done = true;
+        j->moved_prev = moved;
+        if (done) {
+          j->st.rounds_c[j->cur] = r;
+          j->rst.rounds = r;
+          j->stage = j->kind == JOB_CLUSTER ? ST_DONE : ST_CONTRACT;
+          if (j->kind == JOB_CLUSTER) job_release_lp(j, st, true);
         } else {
-          j->st.ms_refine += dt;
-          j->st.moved_r[j->cur][r - 1] = moved;
-          j->st.visits_r[j->cur] += visits;
-          j->rst.moved[r - 1] = moved;
-          j->rst.visits += visits;
-          j->rst.ms += dt;
-          j->zero_streak = moved == 0 ? j->zero_streak + 1 : 0;
-          const bool done = r >= j->ref_rounds || j->zero_streak >= 2;
-          if (done) {
-            j->st.rounds_r[j->cur] = r;
-            j->rst.rounds = r;
-            SCLAP_TRY(after_refine_level(c, j, st));
-          } else {
-            std::swap(j->fcur, j->fnext);
-            SCLAP_TRY(fill_u8(j->fnext, j->lv[j->cur].n, 0, st));
-            j->round = r + 1;
-          }
+          j->round = r + 1;
         }
-      }
-    }
-    // 2. contractions
-    for (Job* j : jobs) {
-      if (j->stage != ST_CONTRACT) continue;
-      const double t0 = now_ms();
-      int rc = contract_level(c, j, j->cur, j->cur == 0 ? 1 : 0, st);
-      if (rc == SCLAP_EOVERFLOW) {
-        j->status = rc;
-        j->stage = ST_ERROR;
-        job_release_lp(j, st, false);
-        continue;
-      }
-      SCLAP_TRY(rc);
-      SCLAP_TRY(after_contract(c, j, ipq, st));
-      j->st.ms_contract += now_ms() - t0;
-    }
-    // 3. initial partitions
-    if (!ipq.empty()) {
-      const double t0 = now_ms();
-      std::vector<int32_t*> parts(ipq.size());
-      std::vector<bool> owned(ipq.size());
-      for (size_t s = 0; s < ipq.size(); ++s) {
-        bool o = false;
-        SCLAP_TRY(alloc_part(ipq[s], ipq[s]->cur, &parts[s], &o, st));
-        owned[s] = o;
-      }
-      SCLAP_TRY(ip_jobs(c, ipq, parts, st));
-      const double dt = now_ms() - t0;
-      for (size_t s = 0; s < ipq.size(); ++s) {
-        Job* j = ipq[s];
-        j->st.ms_initial += dt;
-        j->st.ip_cut = read_cut(c, j->lv[j->cur], parts[s], st);
-        if (j->ref_rounds > 0) {
-          SCLAP_TRY(job_begin_refine(c, j, parts[s], owned[s], st));
-        } else {
-          j->lab = parts[s];
-          j->lab_owned = owned[s];
+      } else {
+        j->st.ms_refine += dt;
+        j->st.moved_r[j->cur][r - 1] = moved;
+        j->st.visits_r[j->cur] += visits;
+        j->rst.moved[r - 1] = moved;
+        j->rst.visits += visits;
+        j->rst.ms += dt;
+        j->zero_streak = moved == 0 ? j->zero_streak + 1 : 0;
+        const bool done = r >= j->ref_rounds || j->zero_streak >= 2;
+        if (done) {
+          j->st.rounds_r[j->cur] = r;
+          j->rst.rounds = r;
           SCLAP_TRY(after_refine_level(c, j, st));
+        } else {
+          std::swap(j->fcur, j->fnext);  // the binning kernel clears the new fnext
+          j->round = r + 1;
         }
       }
-      ipq.clear();
     }
-    // 4. finish
-    bool all_done = true;
-    for (Job* j : jobs) {
-      if (j->stage == ST_FINISH) {
-        SCLAP_TRY(finish_partition(c, j, st));
-        j->stage = ST_DONE;
-      }
-      if (j->stage == ST_DONE && j->st.ms_total == 0) j->st.ms_total = now_ms() - j->t_start;
-      if (j->stage != ST_DONE && j->stage != ST_ERROR) all_done = false;
-    }
-    if (all_done) break;
   }
+  // 2. contractions
+  for (Job* j : jobs) {
+    if (j->stage != ST_CONTRACT) continue;
+    const double t0 = now_ms();
+    int rc = contract_level(c, j, j->cur, j->cur == 0 ? 1 : 0, st);
+    if (rc == SCLAP_EOVERFLOW) {
+      j->status = rc;
+      j->stage = ST_ERROR;
+      job_release_lp(j, st, false);
+      continue;
+    }
+    SCLAP_TRY(rc);
+    SCLAP_TRY(after_contract(c, j, ipq, st));
+    j->st.ms_contract += now_ms() - t0;
+  }
+  // 3. initial partitions
+  if (!ipq.empty()) {
+    const double t0 = now_ms();
+    std::vector<int32_t*> parts(ipq.size());
+    std::vector<bool> owned(ipq.size());
+    for (size_t s = 0; s < ipq.size(); ++s) {
+      bool o = false;
+      SCLAP_TRY(alloc_part(ipq[s], ipq[s]->cur, &parts[s], &o, st));
+      owned[s] = o;
+    }
+    SCLAP_TRY(ip_jobs(c, ipq, parts, st));
+    const double dt = now_ms() - t0;
+    for (size_t s = 0; s < ipq.size(); ++s) {
+      Job* j = ipq[s];
+      j->st.ms_initial += dt;
+      j->st.ip_cut = read_cut(c, j->lv[j->cur], parts[s], st);
+      if (j->ref_rounds > 0) {
+        SCLAP_TRY(job_begin_refine(c, j, parts[s], owned[s], st));
+      } else {
+        j->lab = parts[s];
+        j->lab_owned = owned[s];
+        SCLAP_TRY(after_refine_level(c, j, st));
+      }
+    }
+    ipq.clear();
+  }
+  // 4. finish
+  bool all_done = true;
+  for (Job* j : jobs) {
+    if (j->stage == ST_FINISH) {
+      SCLAP_TRY(finish_partition(c, j, st));
+      j->stage = ST_DONE;
+    }
+    if (j->stage == ST_DONE && j->st.ms_total == 0) j->st.ms_total = now_ms() - j->t_start;
+    if (j->stage != ST_DONE && j->stage != ST_ERROR) all_done = false;
+  }
+  *all_done_out = all_done;
+  return SCLAP_OK;
+}
+
+int run_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
+  // cached bins are keyed by job addresses, which other calls may reuse
+  c->bin_sig_valid = false;
+  for (;;) {
+    bool done = false;
+    SCLAP_TRY(step_jobs(c, jobs, st, &done));
+    if (done) break;
+  }
+  c->bin_sig_valid = false;
   return SCLAP_OK;
 }
 

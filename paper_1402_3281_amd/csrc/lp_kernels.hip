@@ -26,6 +26,10 @@ namespace sclap {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// Slot of global node u.  Kernels are instantiated for a single slot (ONE),
+// where the descriptor address is uniform and its fields use scalar loads.
+#define SLOT(u) (ONE ? 0 : slot_of(S, ns, (u)))
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -73,12 +77,15 @@ __device__ __forceinline__ void block_slot_add(const DevSlot* __restrict__ S, in
 // after round 1, in the rated set) is appended to its degree bin.  Positions
 // are reserved with one atomic per bin per workgroup.
 // ---------------------------------------------------------------------------
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int ns, int64_t N,
-                                             int32_t* __restrict__ bins, int64_t bin_cap,
+                                             int32_t* __restrict__ bins, uint64_t* __restrict__ binfo,
+                                             int64_t bin_cap,
                                              uint32_t* __restrict__ bin_cnt,
-                                             unsigned long long* __restrict__ bin_visits) {
-  __shared__ uint32_t s_w[4 * kBins];  // 4 waves x bins
-  __shared__ uint32_t s_base[kBins];
+                                             unsigned long long* __restrict__ bin_visits,
+                                             int32_t* __restrict__ rated, uint32_t* __restrict__ rated_cnt) {
+  __shared__ uint32_t s_w[4 * (kBins + 1)];  // 4 waves x (bins + rated list)
+  __shared__ uint32_t s_base[kBins + 1];
   __shared__ unsigned long long s_vis[kBins];
   __shared__ int s_slot[4];
   __shared__ int64_t s_sum[4];
@@ -91,38 +98,52 @@ __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int 
     bool take = false;
     int b = 0;
     int s = 0;
-    int64_t d = 0;
+    int64_t d = 0, e0 = 0;
     if (u < N) {
-      s = slot_of(S, ns, u);
+      s = SLOT(u);
       const DevSlot& sl = S[s];
       const int64_t v = u - sl.nbase;
       if (sl.round > 0 && (!sl.use_flags || sl.flag_cur[v])) {
-        d = sl.rp[v + 1] - sl.rp[v];
+        e0 = sl.rp[v];
+        d = sl.rp[v + 1] - e0;
         take = d > 0;
         b = bin_of(d);
       }
+      // the rated set of the next round is rebuilt from scratch
+      if (sl.round > 0 && sl.mode == MODE_REFINE) sl.flag_next[v] = 0;
     }
-    uint32_t rank = 0;
+    constexpr int NB = kBins + 1;
+    uint32_t rank = 0, rrank = 0;
 #pragma unroll
     for (int j = 0; j < kBins; ++j) {
       const uint64_t m = __ballot(take && b == j);
       if (take && b == j) rank = (uint32_t)__popcll(m & lt);
-      if (lane_id() == 0) s_w[w * kBins + j] = (uint32_t)__popcll(m);
+      if (lane_id() == 0) s_w[w * NB + j] = (uint32_t)__popcll(m);
+    }
+    {
+      const uint64_t m = __ballot(take);
+      rrank = (uint32_t)__popcll(m & lt);
+      if (lane_id() == 0) s_w[w * NB + kBins] = (uint32_t)__popcll(m);
     }
     if (take) atomicAdd(&s_vis[b], (unsigned long long)d);
     __syncthreads();
-    if (threadIdx.x < kBins) {
+    if (threadIdx.x < NB) {
       const int j = threadIdx.x;
       uint32_t tot = 0;
       for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-        const uint32_t c = s_w[i * kBins + j];
-        s_w[i * kBins + j] = tot;
+        const uint32_t c = s_w[i * NB + j];
+        s_w[i * NB + j] = tot;
         tot += c;
       }
-      s_base[j] = tot ? atomicAdd(&bin_cnt[j], tot) : 0;
+      s_base[j] = tot ? atomicAdd(j < kBins ? &bin_cnt[j] : rated_cnt, tot) : 0;
     }
     __syncthreads();
-    if (take) bins[b * bin_cap + s_base[b] + s_w[w * kBins + b] + rank] = (int32_t)u;
+    if (take) {
+      const int64_t pos = b * bin_cap + s_base[b] + s_w[w * NB + b] + rank;
+      bins[pos] = (int32_t)u;
+      if (b < kBins - 1) binfo[pos] = (uint64_t)e0 | ((uint64_t)d << 40);
+      rated[s_base[kBins] + s_w[w * NB + kBins] + rrank] = (int32_t)u;
+    }
     block_slot_add(S, s, CTR_VISITS, take ? d : 0, s_slot, s_sum);
   }
   __syncthreads();
@@ -150,84 +171,100 @@ __device__ __forceinline__ bool dir_blocked(const DevSlot& sl, int32_t t, int32_
   return sl.dir_rule && ((sl.round & 1) ? t > own : t < own);
 }
 
+// Row of a binned node: first entry | degree << 40.
+__device__ __forceinline__ int64_t info_e0(uint64_t x) { return (int64_t)(x & ((1ull << 40) - 1ull)); }
+__device__ __forceinline__ int info_d(uint64_t x) { return (int)(x >> 40); }
+
 // ---------------------------------------------------------------------------
-// Rating, G lanes per node (degree <= G).  The pairwise loop runs over the
+// Rating, G lanes per node (degree <= G).  Each iteration handles two sets of
+// nodes whose loads are issued together; the pairwise loop runs over the
 // wave's largest degree only.
 // ---------------------------------------------------------------------------
-template <int G>
-__global__ void __launch_bounds__(256) k_rate_group(const DevSlot* __restrict__ S, int ns,
-                                                    const int32_t* __restrict__ list,
-                                                    const uint32_t* __restrict__ cnt_ptr) {
-  const uint32_t cnt = *cnt_ptr;
+template <int G, bool ONE>
+__device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
+                                                const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
+                                                uint32_t nblk) {
+  constexpr int R = 2;
   const int lane = (int)lane_id();
   const int gl = lane & (G - 1);
   const int gbase = lane & ~(G - 1);
   const uint32_t per_block = blockDim.x / G;
-  for (uint32_t base = blockIdx.x * per_block; base < cnt; base += gridDim.x * per_block) {
-    const uint32_t i = base + threadIdx.x / G;
-    const bool valid = i < cnt;
-    const int64_t u = valid ? list[i] : 0;
-    const int s = slot_of(S, ns, u);
-    const DevSlot& sl = S[s];
-    const int64_t v = u - sl.nbase;
-    int64_t e0 = 0;
-    int d = 0;
-    int32_t own = -1;
-    if (valid) {
-      e0 = sl.rp[v];
-      d = (int)(sl.rp[v + 1] - e0);
-      own = sl.lab[v];
-    }
-    int dm = d;
-    for (int off = 32; off > 0; off >>= 1) {
-      const int o = __shfl_xor(dm, off);
-      dm = o > dm ? o : dm;
-    }
-    const int dlim = dm < G ? dm : G;
-    int32_t t = -1, w = 0;
-    if (gl < d) {
-      t = sl.lab[sl.col[e0 + gl]];
-      w = sl.ew ? sl.ew[e0 + gl] : 1;
-    }
-    const bool foreign = t >= 0 && t != own;
-    const uint64_t fmask = __ballot(foreign);
-    const bool boundary = ((fmask >> gbase) & (G == 64 ? ~0ull : ((1ull << G) - 1ull))) != 0;
-    const int32_t te = (foreign && dir_blocked(sl, t, own)) ? -1 : t;
-    int64_t conn = 0, conn_own = 0;
-    bool leader = te >= 0;
-    for (int j = 0; j < dlim; ++j) {
-      int32_t tj, wj;
-      if (G == 64) {
-        tj = __builtin_amdgcn_readlane(te, j);
-        wj = __builtin_amdgcn_readlane(w, j);
-      } else {
-        tj = __shfl(te, gbase + j);
-        wj = __shfl(w, gbase + j);
-      }
-      if (tj == te) {
-        conn += wj;
-        if (j < gl) leader = false;
-      }
-      if (tj == own) conn_own += wj;
-    }
-    uint64_t key = 0;
-    bool own_ok = true;
-    if (valid) {
-      own_ok = own_allowed(sl, own);
-      if (leader && te != own) key = cand_key(sl, own_ok, conn_own, own, sl.nw[v], te, conn);
+  for (uint32_t base = bid * per_block * R; base < cnt; base += nblk * per_block * R) {
+    bool valid[R];
+    int64_t u[R], e0[R];
+    int d[R];
+    int32_t own[R], nb[R], w[R], t[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t i = base + r * per_block + threadIdx.x / G;
+      valid[r] = i < cnt;
+      u[r] = valid[r] ? list[i] : 0;
+      const uint64_t x = valid[r] ? info[i] : 0;
+      e0[r] = info_e0(x);
+      d[r] = info_d(x);
     }
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-      const uint64_t o = __shfl_xor(key, off);
-      key = key > o ? key : o;
+    for (int r = 0; r < R; ++r) {
+      const DevSlot& sl = S[SLOT(u[r])];
+      own[r] = valid[r] ? sl.lab[u[r] - sl.nbase] : -1;
+      nb[r] = gl < d[r] ? sl.col[e0[r] + gl] : 0;
+      w[r] = gl < d[r] ? (sl.ew ? sl.ew[e0[r] + gl] : 1) : 0;
     }
-    if (valid && gl == 0) {
-      if (own_ok) {
-        const uint64_t ok = pack_key(conn_own, own);
-        key = key > ok ? key : ok;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const DevSlot& sl = S[SLOT(u[r])];
+      t[r] = gl < d[r] ? sl.lab[nb[r]] : -1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const DevSlot& sl = S[SLOT(u[r])];
+      const int64_t v = u[r] - sl.nbase;
+      int dm = d[r];
+      for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(dm, off);
+        dm = o > dm ? o : dm;
       }
-      sl.desire[v] = key ? key_label(key) : own;
-      if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+      const int dlim = dm < G ? dm : G;
+      const bool foreign = t[r] >= 0 && t[r] != own[r];
+      const uint64_t fmask = __ballot(foreign);
+      const bool boundary = ((fmask >> gbase) & (G == 64 ? ~0ull : ((1ull << G) - 1ull))) != 0;
+      const int32_t te = (foreign && dir_blocked(sl, t[r], own[r])) ? -1 : t[r];
+      int64_t conn = 0, conn_own = 0;
+      bool leader = te >= 0;
+      for (int j = 0; j < dlim; ++j) {
+        int32_t tj, wj;
+        if (G == 64) {
+          tj = __builtin_amdgcn_readlane(te, j);
+          wj = __builtin_amdgcn_readlane(w[r], j);
+        } else {
+          tj = __shfl(te, gbase + j);
+          wj = __shfl(w[r], gbase + j);
+        }
+        if (tj == te) {
+          conn += wj;
+          if (j < gl) leader = false;
+        }
+        if (tj == own[r]) conn_own += wj;
+      }
+      uint64_t key = 0;
+      bool own_ok = true;
+      if (valid[r]) {
+        own_ok = own_allowed(sl, own[r]);
+        if (leader && te != own[r]) key = cand_key(sl, own_ok, conn_own, own[r], sl.nw[v], te, conn);
+      }
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(key, off);
+        key = key > o ? key : o;
+      }
+      if (valid[r] && gl == 0) {
+        if (own_ok) {
+          const uint64_t ok = pack_key(conn_own, own[r]);
+          key = key > ok ? key : ok;
+        }
+        sl.desire[v] = key ? key_label(key) : own[r];
+        if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+      }
     }
   }
 }
@@ -252,26 +289,56 @@ __device__ __forceinline__ uint32_t table_size(int64_t d, int64_t nlabels) {
   return tsz;
 }
 
+// Walk entries [lo, hi) of a row with stride `step` starting at `first`,
+// loading B entries (ids, then labels) before inserting them; accumulates
+// the own label's connection and whether a foreign label was seen.
+template <int B>
+__device__ __forceinline__ void table_fill(const DevSlot& sl, int64_t row0, int64_t first, int64_t hi, int step,
+                                           int32_t own, int32_t* keys, int32_t* vals, uint32_t mask,
+                                           int64_t& my_own, bool& foreign) {
+  for (int64_t e = first; e < hi; e += (int64_t)step * B) {
+    int32_t nb[B], wt[B], tt[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int64_t ee = e + (int64_t)q * step;
+      nb[q] = ee < hi ? sl.col[row0 + ee] : -1;
+      wt[q] = ee < hi ? (sl.ew ? sl.ew[row0 + ee] : 1) : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) tt[q] = nb[q] >= 0 ? sl.lab[nb[q]] : -1;
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const int32_t tq = tt[q];
+      if (nb[q] < 0) continue;
+      if (tq == own) {
+        my_own += wt[q];
+        continue;
+      }
+      foreign = true;
+      if (dir_blocked(sl, tq, own)) continue;
+      table_add(keys, vals, mask, tq, wt[q]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Rating, one wave per node (degree <= TS / 2), wave-private LDS table.
 // ---------------------------------------------------------------------------
-template <int TS>
-__global__ void __launch_bounds__(256) k_rate_wave(const DevSlot* __restrict__ S, int ns,
-                                                   const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr) {
-  __shared__ int32_t keys_all[4][TS];
-  __shared__ int32_t vals_all[4][TS];
+template <int TS, bool ONE>
+__device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
+                                               const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
+                                               uint32_t nblk, int32_t* lds) {
   const int w = threadIdx.x / kWave;
-  int32_t* keys = keys_all[w];
-  int32_t* vals = vals_all[w];
-  const uint32_t cnt = *cnt_ptr;
+  int32_t* keys = lds + w * TS;
+  int32_t* vals = lds + 4 * TS + w * TS;
   const int lane = (int)lane_id();
-  for (uint32_t i = blockIdx.x * 4 + w; i < cnt; i += gridDim.x * 4) {
+  for (uint32_t i = bid * 4 + w; i < cnt; i += nblk * 4) {
     const int64_t u = list[i];
-    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const uint64_t x = info[i];
+    const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t e0 = sl.rp[v];
-    const int d = (int)(sl.rp[v + 1] - e0);
+    const int64_t e0 = info_e0(x);
+    const int d = info_d(x);
     const int32_t own = sl.lab[v];
     const uint32_t tsz = table_size(d, sl.nlabels);
     for (uint32_t j = lane; j < tsz; j += kWave) {
@@ -281,17 +348,7 @@ __global__ void __launch_bounds__(256) k_rate_wave(const DevSlot* __restrict__ S
     wave_sync();
     int64_t my_own = 0;
     bool foreign = false;
-    for (int e = lane; e < d; e += kWave) {
-      const int32_t t = sl.lab[sl.col[e0 + e]];
-      const int32_t wt = sl.ew ? sl.ew[e0 + e] : 1;
-      if (t == own) {
-        my_own += wt;
-        continue;
-      }
-      foreign = true;
-      if (dir_blocked(sl, t, own)) continue;
-      table_add(keys, vals, tsz - 1, t, wt);
-    }
+    table_fill<4>(sl, e0, lane, d, kWave, own, keys, vals, tsz - 1, my_own, foreign);
     for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
     const bool boundary = __ballot(foreign) != 0;
     wave_sync();
@@ -346,22 +403,22 @@ struct OpOr {
 // ---------------------------------------------------------------------------
 // Rating, one workgroup per node (degree <= TS / 2), LDS hash table.
 // ---------------------------------------------------------------------------
-template <int TS, int NT>
-__global__ void __launch_bounds__(NT) k_rate_block(const DevSlot* __restrict__ S, int ns,
-                                                   const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr) {
-  __shared__ int32_t keys[TS];
-  __shared__ int32_t vals[TS];
+template <int TS, int NT, bool ONE>
+__device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
+                                                const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
+                                                uint32_t nblk, int32_t* lds) {
+  int32_t* keys = lds;
+  int32_t* vals = lds + TS;
   __shared__ uint64_t red64[8];
   __shared__ int64_t redi[8];
   __shared__ int redo[8];
-  const uint32_t cnt = *cnt_ptr;
-  for (uint32_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+  for (uint32_t i = bid; i < cnt; i += nblk) {
     const int64_t u = list[i];
-    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const uint64_t x = info[i];
+    const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t e0 = sl.rp[v];
-    const int d = (int)(sl.rp[v + 1] - e0);
+    const int64_t e0 = info_e0(x);
+    const int d = info_d(x);
     const int32_t own = sl.lab[v];
     const uint32_t tsz = table_size(d, sl.nlabels);
     const uint32_t mask = tsz - 1;
@@ -371,20 +428,10 @@ __global__ void __launch_bounds__(NT) k_rate_block(const DevSlot* __restrict__ S
     }
     __syncthreads();
     int64_t my_own = 0;
-    int foreign = 0;
-    for (int e = threadIdx.x; e < d; e += NT) {
-      const int32_t t = sl.lab[sl.col[e0 + e]];
-      const int32_t w = sl.ew ? sl.ew[e0 + e] : 1;
-      if (t == own) {
-        my_own += w;
-        continue;
-      }
-      foreign = 1;
-      if (dir_blocked(sl, t, own)) continue;
-      table_add(keys, vals, mask, t, w);
-    }
+    bool foreign = false;
+    table_fill<4>(sl, e0, threadIdx.x, d, NT, own, keys, vals, mask, my_own, foreign);
     const int64_t conn_own = block_reduce(my_own, redi, OpAdd64());
-    const int boundary = block_reduce(foreign, redo, OpOr());
+    const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
     const int64_t cv = sl.nw[v];
     const bool own_ok = own_allowed(sl, own);
     uint64_t best = 0;
@@ -408,6 +455,51 @@ __global__ void __launch_bounds__(NT) k_rate_block(const DevSlot* __restrict__ S
 }
 
 // ---------------------------------------------------------------------------
+// Fused launches: blocks [b * nblk, (b + 1) * nblk) serve bin `first + b`.
+// ---------------------------------------------------------------------------
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_rate_small(const DevSlot* __restrict__ S, int ns,
+                                                    const int32_t* __restrict__ bins,
+                                                    const uint64_t* __restrict__ binfo, int64_t bin_cap,
+                                                    const uint32_t* __restrict__ bin_cnt, uint32_t nblk) {
+  __shared__ int32_t lds[8 * 256];
+  const uint32_t b = blockIdx.x / nblk, bid = blockIdx.x % nblk;
+  const int32_t* list = bins + b * bin_cap;
+  const uint64_t* info = binfo + b * bin_cap;
+  const uint32_t cnt = bin_cnt[b];
+  switch (b) {
+    case 0: rate_group_body<8, ONE>(S, ns, list, info, cnt, bid, nblk); break;
+    case 1: rate_group_body<16, ONE>(S, ns, list, info, cnt, bid, nblk); break;
+    case 2: rate_group_body<32, ONE>(S, ns, list, info, cnt, bid, nblk); break;
+    case 3: rate_group_body<64, ONE>(S, ns, list, info, cnt, bid, nblk); break;
+    default: rate_wave_body<256, ONE>(S, ns, list, info, cnt, bid, nblk, lds); break;
+  }
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_rate_mid(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ bins,
+                                                  const uint64_t* __restrict__ binfo, int64_t bin_cap,
+                                                  const uint32_t* __restrict__ bin_cnt, uint32_t nblk) {
+  __shared__ int32_t lds[8 * 1024];
+  const uint32_t b = 5 + blockIdx.x / nblk, bid = blockIdx.x % nblk;
+  const int32_t* list = bins + b * bin_cap;
+  const uint64_t* info = binfo + b * bin_cap;
+  const uint32_t cnt = bin_cnt[b];
+  if (b == 5) rate_wave_body<1024, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
+  else rate_block_body<2048, 256, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(512) k_rate_large(const DevSlot* __restrict__ S, int ns,
+                                                    const int32_t* __restrict__ list,
+                                                    const uint64_t* __restrict__ info,
+                                                    const uint32_t* __restrict__ cnt_ptr) {
+  __shared__ int32_t lds[2 * 8192];
+  rate_block_body<8192, 512, ONE>(S, ns, list, info, *cnt_ptr, blockIdx.x, gridDim.x, lds);
+}
+
+// ---------------------------------------------------------------------------
 // Rating of hubs (degree > kBinBlock): chunks of kHubChunk entries per
 // workgroup, aggregated in LDS and flushed into a per-hub global table.
 // ---------------------------------------------------------------------------
@@ -415,12 +507,14 @@ __global__ void __launch_bounds__(NT) k_rate_block(const DevSlot* __restrict__ S
 // One workgroup: exclusive offsets of chunk counts and table sizes.
 constexpr int kHubSlice = 4096;  // table entries scanned per workgroup in the final pass
 
+template <bool ONE>
 __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ cnt_ptr,
                                                    uint32_t* __restrict__ chunk_off, int64_t* __restrict__ tab_off,
                                                    uint32_t* __restrict__ slice_off,
-                                                   uint32_t* __restrict__ totals, int64_t tab_cap,
+                                                   uint32_t* __restrict__ chunk_hub, uint32_t* __restrict__ slice_hub,
+                                                   uint32_t map_cap, uint32_t* __restrict__ totals, int64_t tab_cap,
                                                    uint32_t* __restrict__ overflow) {
   __shared__ uint32_t sc[1024];
   __shared__ uint32_t ss[1024];
@@ -440,7 +534,7 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
     int64_t tz = 0;
     if (i < cnt) {
       const int64_t u = list[i];
-      const DevSlot& sl = S[slot_of(S, ns, u)];
+      const DevSlot& sl = S[SLOT(u)];
       const int64_t v = u - sl.nbase;
       const int64_t d = sl.rp[v + 1] - sl.rp[v];
       nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
@@ -462,9 +556,16 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
       __syncthreads();
     }
     if (i < cnt) {
-      chunk_off[i] = carry_c + sc[threadIdx.x] - nc;
-      slice_off[i] = carry_s + ss[threadIdx.x] - ns2;
+      const uint32_t c0 = carry_c + sc[threadIdx.x] - nc, s0 = carry_s + ss[threadIdx.x] - ns2;
+      chunk_off[i] = c0;
+      slice_off[i] = s0;
       tab_off[i] = carry_t + st[threadIdx.x] - tz;
+      if (c0 + nc <= map_cap && s0 + ns2 <= map_cap) {
+        for (uint32_t c = 0; c < nc; ++c) chunk_hub[c0 + c] = i;
+        for (uint32_t c = 0; c < ns2; ++c) slice_hub[s0 + c] = i;
+      } else {
+        *overflow = 1;
+      }
     }
     __syncthreads();
     if (threadIdx.x == blockDim.x - 1) {
@@ -485,11 +586,13 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
 
 constexpr int kHubLds = 2 * kHubChunk;
 
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ cnt_ptr,
                                                    const uint32_t* __restrict__ chunk_off,
                                                    const int64_t* __restrict__ tab_off,
+                                                   const uint32_t* __restrict__ chunk_hub,
                                                    const uint32_t* __restrict__ totals,
                                                    int32_t* __restrict__ gkeys, int32_t* __restrict__ gvals,
                                                    int64_t* __restrict__ hub_own,
@@ -502,16 +605,9 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
   const uint32_t cnt = *cnt_ptr;
   const uint32_t nchunks = totals[0];
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    // hub i with chunk_off[i] <= c < chunk_off[i + 1]
-    uint32_t lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (chunk_off[mid] <= c) lo = mid;
-      else hi = mid - 1;
-    }
-    const uint32_t i = lo;
+    const uint32_t i = chunk_hub[c];
     const int64_t u = list[i];
-    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int64_t row0 = sl.rp[v];
     const int64_t d = sl.rp[v + 1] - row0;
@@ -524,20 +620,10 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
     }
     __syncthreads();
     int64_t my_own = 0;
-    int foreign = 0;
-    for (int64_t e = e_begin + threadIdx.x; e < e_end; e += blockDim.x) {
-      const int32_t t = sl.lab[sl.col[row0 + e]];
-      const int32_t w = sl.ew ? sl.ew[row0 + e] : 1;
-      if (t == own) {
-        my_own += w;
-        continue;
-      }
-      foreign = 1;
-      if (dir_blocked(sl, t, own)) continue;
-      table_add(keys, vals, kHubLds - 1, t, w);
-    }
+    bool foreign = false;
+    table_fill<8>(sl, row0, e_begin + threadIdx.x, e_end, blockDim.x, own, keys, vals, kHubLds - 1, my_own, foreign);
     const int64_t co = block_reduce(my_own, redi, OpAdd64());
-    const int boundary = block_reduce(foreign, redo, OpOr());
+    const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
     if (threadIdx.x == 0) {
       if (co) atomicAdd((unsigned long long*)&hub_own[i], (unsigned long long)co);
       if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
@@ -555,11 +641,13 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
 
 // Slices of the hub tables: best eligible candidate per slice, combined per
 // hub with an integer maximum; the slice is reset for the next round.
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S, int ns,
                                                   const int32_t* __restrict__ list,
                                                   const uint32_t* __restrict__ cnt_ptr,
                                                   const int64_t* __restrict__ tab_off,
                                                   const uint32_t* __restrict__ slice_off,
+                                                  const uint32_t* __restrict__ slice_hub,
                                                   const uint32_t* __restrict__ totals,
                                                   int32_t* __restrict__ gkeys, int32_t* __restrict__ gvals,
                                                   const int64_t* __restrict__ hub_own,
@@ -570,15 +658,9 @@ __global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S,
   const uint32_t cnt = *cnt_ptr;
   const uint32_t nslices = totals[1];
   for (uint32_t c = blockIdx.x; c < nslices; c += gridDim.x) {
-    uint32_t lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (slice_off[mid] <= c) lo = mid;
-      else hi = mid - 1;
-    }
-    const uint32_t i = lo;
+    const uint32_t i = slice_hub[c];
     const int64_t u = list[i];
-    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int64_t d = sl.rp[v + 1] - sl.rp[v];
     const int32_t own = sl.lab[v];
@@ -606,6 +688,7 @@ __global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S,
   }
 }
 
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
                                                    const uint32_t* __restrict__ cnt_ptr,
@@ -617,7 +700,7 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
     const int64_t u = list[i];
-    const DevSlot& sl = S[slot_of(S, ns, u)];
+    const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int32_t own = sl.lab[v];
     uint64_t best = hub_best[i];
@@ -656,10 +739,13 @@ constexpr int kAggNodes = 512;    // nodes per workgroup iteration
 constexpr int kIncTable = 1024;   // >= 2 x distinct keys of one iteration
 constexpr int kApplyTable = 2048;
 
-// inc(t) += c(v) for every mover v -> t.
-__global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S, int ns, int64_t N) {
+// inc(t) += c(v) for every mover v -> t (movers are rated nodes).
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt) {
   __shared__ unsigned long long hk[kIncTable];
   __shared__ long long hv[kIncTable];
+  const int64_t N = *rcnt;
   for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
     for (int j = threadIdx.x; j < kIncTable; j += blockDim.x) {
       hk[j] = kEmpty;
@@ -667,11 +753,11 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
     }
     __syncthreads();
     for (int it = 0; it < kAggNodes / 256; ++it) {
-      const int64_t u = base + it * 256 + threadIdx.x;
-      if (u >= N) continue;
-      const int s = slot_of(S, ns, u);
+      const int64_t i = base + it * 256 + threadIdx.x;
+      if (i >= N) continue;
+      const int64_t u = rated[i];
+      const int s = SLOT(u);
       const DevSlot& sl = S[s];
-      if (sl.round == 0) continue;
       const int64_t v = u - sl.nbase;
       const int32_t t = sl.desire[v];
       if (t != sl.lab[v]) agg_add(hk, hv, kIncTable - 1, ((unsigned long long)s << 32) | (uint32_t)t, sl.nw[v]);
@@ -688,22 +774,26 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
 
 // Movers into targets whose whole incoming weight fits are admitted; the
 // others are appended as (target, node) keys for the exact path.
-__global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, int ns, int64_t N,
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, int ns,
+                                                const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
                                                 uint64_t* __restrict__ ckeys, uint32_t* __restrict__ ccnt,
                                                 int node_bits) {
   __shared__ uint32_t s_w[4];
   __shared__ uint32_t s_base;
   const int w = threadIdx.x / kWave;
   const uint64_t lt = (1ull << lane_id()) - 1ull;
+  const int64_t N = *rcnt;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += stride) {
-    const int64_t u = base + threadIdx.x;
+    const int64_t i = base + threadIdx.x;
     bool contended = false;
     uint64_t key = 0;
-    if (u < N) {
-      const int s = slot_of(S, ns, u);
+    if (i < N) {
+      const int64_t u = rated[i];
+      const int s = SLOT(u);
       const DevSlot& sl = S[s];
-      if (sl.round > 0) {
+      {
         const int64_t v = u - sl.nbase;
         const int32_t t = sl.desire[v];
         if (t != sl.lab[v]) {
@@ -736,6 +826,7 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
 }
 
 // For sorted contended keys: segment key (target) and weight of each entry.
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_contended_split(const DevSlot* __restrict__ S, int ns,
                                                          const uint64_t* __restrict__ keys, uint32_t cnt,
                                                          int node_bits, uint32_t* __restrict__ tkey,
@@ -744,12 +835,13 @@ __global__ void __launch_bounds__(256) k_contended_split(const DevSlot* __restri
   if (i >= cnt) return;
   const uint64_t k = keys[i];
   const int64_t u = (int64_t)(k & ((1ull << node_bits) - 1ull));
-  const DevSlot& sl = S[slot_of(S, ns, u)];
+  const DevSlot& sl = S[SLOT(u)];
   tkey[i] = (uint32_t)(k >> node_bits);
   wv[i] = sl.nw[u - sl.nbase];
 }
 
 // Admit contended movers whose inclusive prefix fits.
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_contended_mark(const DevSlot* __restrict__ S, int ns,
                                                         const uint64_t* __restrict__ keys, uint32_t cnt,
                                                         int node_bits, const int64_t* __restrict__ prefix) {
@@ -757,20 +849,103 @@ __global__ void __launch_bounds__(256) k_contended_mark(const DevSlot* __restric
   if (i >= cnt) return;
   const uint64_t k = keys[i];
   const int64_t u = (int64_t)(k & ((1ull << node_bits) - 1ull));
-  const DevSlot& sl = S[slot_of(S, ns, u)];
+  const DevSlot& sl = S[SLOT(u)];
   const int64_t v = u - sl.nbase;
   const int32_t t = sl.desire[v];
   sl.adm[v] = sl.W[t] + prefix[i] <= sl.cap ? 1 : 0;
 }
 
+// Contended movers, when at most kSmallContended: one workgroup sorts the
+// (target, node) keys in LDS (bitonic), scans the weights per target and
+// admits the inclusive prefixes that fit.  Larger sets are left to the
+// device-wide path and flagged.
+constexpr int kSmallContended = 2048;
+
+template <bool ONE>
+__global__ void __launch_bounds__(1024) k_contended_small(const DevSlot* __restrict__ S, int ns,
+                                                          const uint64_t* __restrict__ keys,
+                                                          const uint32_t* __restrict__ ccnt, int node_bits,
+                                                          uint32_t* __restrict__ big_flag) {
+  __shared__ uint64_t k[kSmallContended];
+  __shared__ int64_t w[kSmallContended];
+  __shared__ int8_t head[kSmallContended];
+  const uint32_t cnt = *ccnt;
+  if (cnt == 0) return;
+  if (cnt > kSmallContended) {
+    if (threadIdx.x == 0) *big_flag = 1;
+    return;
+  }
+  uint32_t P = 1;
+  while (P < cnt) P <<= 1;
+  for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) k[i] = i < cnt ? keys[i] : ~0ull;
+  __syncthreads();
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) {
+        const uint32_t j = i ^ stride;
+        if (j > i) {
+          const bool up = (i & size) == 0;
+          const uint64_t a = k[i], b = k[j];
+          if ((a > b) == up) {
+            k[i] = b;
+            k[j] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const uint64_t nmask = (1ull << node_bits) - 1ull;
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t u = (int64_t)(k[i] & nmask);
+    const DevSlot& sl = S[SLOT(u)];
+    w[i] = sl.nw[u - sl.nbase];
+    head[i] = (i == 0 || (k[i] >> node_bits) != (k[i - 1] >> node_bits)) ? 1 : 0;
+  }
+  __syncthreads();
+  // inclusive segmented scan (Hillis-Steele on (value, head) pairs)
+  for (uint32_t off = 1; off < cnt; off <<= 1) {
+    int64_t nv[2];
+    int8_t nh[2];
+    int c = 0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x, ++c) {
+      nv[c] = w[i];
+      nh[c] = head[i];
+      if (i >= off && !head[i]) {
+        nv[c] += w[i - off];
+        nh[c] = head[i - off];
+      }
+    }
+    __syncthreads();
+    c = 0;
+    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x, ++c) {
+      w[i] = nv[c];
+      head[i] = nh[c];
+    }
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int64_t u = (int64_t)(k[i] & nmask);
+    const DevSlot& sl = S[SLOT(u)];
+    const int64_t v = u - sl.nbase;
+    const int32_t t = sl.desire[v];
+    sl.adm[v] = sl.W[t] + w[i] <= sl.cap ? 1 : 0;
+  }
+}
+
 // Apply admitted moves; reset rejected desires and the incoming sums; in
 // refinement add the neighbours of moved nodes to the next rated set.
-__global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, int ns, int64_t N,
-                                               int32_t* __restrict__ movers, uint32_t* __restrict__ mcnt) {
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, int ns,
+                                               const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
+                                               int32_t* __restrict__ movers, uint32_t* __restrict__ mcnt,
+                                               const uint32_t* __restrict__ skip) {
   __shared__ unsigned long long hk[kApplyTable];
   __shared__ long long hv[kApplyTable];
   __shared__ int32_t s_mov[kAggNodes];
   __shared__ uint32_t s_mcnt, s_mbase;
+  if (skip && *skip) return;  // the admission is completed on the host-driven path first
+  const int64_t N = *rcnt;
   for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
     for (int j = threadIdx.x; j < kApplyTable; j += blockDim.x) {
       hk[j] = kEmpty;
@@ -779,11 +954,11 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
     if (threadIdx.x == 0) s_mcnt = 0;
     __syncthreads();
     for (int it = 0; it < kAggNodes / 256; ++it) {
-      const int64_t u = base + it * 256 + threadIdx.x;
-      if (u >= N) continue;
-      const int s = slot_of(S, ns, u);
+      const int64_t i = base + it * 256 + threadIdx.x;
+      if (i >= N) continue;
+      const int64_t u = rated[i];
+      const int s = SLOT(u);
       const DevSlot& sl = S[s];
-      if (sl.round == 0) continue;
       const int64_t v = u - sl.nbase;
       const int32_t t = sl.desire[v];
       const int32_t own = sl.lab[v];
@@ -820,10 +995,17 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
 }
 
 // Refinement: the neighbours of moved nodes join the next rated set.  Each
-// wave takes 64 movers; short rows are walked by their lane, long rows by
-// the whole wave.
+// wave takes 64 movers; rows of up to 64 entries are walked by their lane,
+// rows of up to kMarkBig entries by the whole wave; longer rows are listed
+// and walked by all workgroups together (k_mark_big).
+constexpr int64_t kMarkBig = 4096;
+
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int ns,
-                                              const int32_t* __restrict__ movers, const uint32_t* __restrict__ mcnt) {
+                                              const int32_t* __restrict__ movers, const uint32_t* __restrict__ mcnt,
+                                              int32_t* __restrict__ big, uint32_t* __restrict__ big_cnt,
+                                              const uint32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const uint32_t cnt = *mcnt;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -831,24 +1013,43 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
     const uint32_t i = base + lane_id();
     const DevSlot* sl = nullptr;
     int64_t e0 = 0, d = 0;
+    int32_t u = 0;
     if (i < cnt) {
-      const int64_t u = movers[i];
-      sl = &S[slot_of(S, ns, u)];
+      u = movers[i];
+      sl = &S[SLOT(u)];
       const int64_t v = u - sl->nbase;
       e0 = sl->rp[v];
       d = sl->rp[v + 1] - e0;
     }
     if (d <= kWave)
       for (int64_t e = e0; e < e0 + d; ++e) sl->flag_next[sl->col[e]] = 1;
-    uint64_t big = __ballot(d > kWave);
-    while (big) {
-      const int l = __ffsll((unsigned long long)big) - 1;
-      big &= big - 1;
+    if (d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = u;
+    uint64_t mid = __ballot(d > kWave && d <= kMarkBig);
+    while (mid) {
+      const int l = __ffsll((unsigned long long)mid) - 1;
+      mid &= mid - 1;
       const int64_t be0 = __shfl(e0, l), bd = __shfl(d, l);
-      const int64_t bu = movers[base + l];
-      const DevSlot& bs = S[slot_of(S, ns, bu)];
+      const int32_t bu = __shfl(u, l);
+      const DevSlot& bs = S[SLOT(bu)];
       for (int64_t e = be0 + lane_id(); e < be0 + bd; e += kWave) bs.flag_next[bs.col[e]] = 1;
     }
+  }
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_mark_big(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ big, const uint32_t* __restrict__ big_cnt,
+                                                  const uint32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const uint32_t cnt = *big_cnt;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const int64_t u = big[i];
+    const DevSlot& sl = S[SLOT(u)];
+    const int64_t v = u - sl.nbase;
+    const int64_t e0 = sl.rp[v], e1 = sl.rp[v + 1];
+    for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride)
+      sl.flag_next[sl.col[e]] = 1;
   }
 }
 
@@ -861,56 +1062,55 @@ static inline unsigned grid_for(int64_t items, int per_block, unsigned cap) {
   return (unsigned)(g < cap ? g : cap);
 }
 
-int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, int64_t bin_cap, uint32_t* bin_cnt,
-               unsigned long long* bin_visits, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin, dim3(grid_for(N, 256, 4096)), dim3(256), 0, st, S, ns, N, bins, bin_cap, bin_cnt,
-                     bin_visits);
+// Launch the single-slot instantiation when one graph takes part.
+#define LAUNCH(kern, grid, block, ...)                                                     \
+  do {                                                                                     \
+    if (ns == 1) hipLaunchKernelGGL(kern<true>, dim3(grid), dim3(block), 0, st, __VA_ARGS__); \
+    else hipLaunchKernelGGL(kern<false>, dim3(grid), dim3(block), 0, st, __VA_ARGS__);       \
+  } while (0)
+
+int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, uint64_t* binfo, int64_t bin_cap,
+               uint32_t* bin_cnt, unsigned long long* bin_visits, int32_t* rated, uint32_t* rated_cnt,
+               hipStream_t st) {
+  LAUNCH(k_bin, grid_for(N, 256, 4096), 256, S, ns, N, bins, binfo, bin_cap, bin_cnt, bin_visits, rated, rated_cnt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
 
-int launch_rate(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_cap, const uint32_t* bin_cnt,
-                const RateHubScratch& hub, int64_t n_hint, hipStream_t st, hipEvent_t* evs) {
-  const unsigned G = grid_for(n_hint, 32, 4096);
+int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
+                const uint32_t* bin_cnt, const RateHubScratch& hub, int64_t n_hint, bool hubs, hipStream_t st,
+                hipEvent_t* evs) {
+  const unsigned G = grid_for(n_hint, 64, 2048);
   auto rec = [&](int i) {
     if (evs) (void)hipEventRecord(evs[i], st);
   };
-  const int32_t* b = bins;
   rec(0);
-  hipLaunchKernelGGL(k_rate_group<8>, dim3(G), dim3(256), 0, st, S, ns, b, bin_cnt);
+  LAUNCH(k_rate_small, 5 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(1);
-  hipLaunchKernelGGL(k_rate_group<16>, dim3(G), dim3(256), 0, st, S, ns, b + bin_cap, bin_cnt + 1);
+  LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(2);
-  hipLaunchKernelGGL(k_rate_group<32>, dim3(G), dim3(256), 0, st, S, ns, b + 2 * bin_cap, bin_cnt + 2);
+  LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
   rec(3);
-  hipLaunchKernelGGL(k_rate_group<64>, dim3(G), dim3(256), 0, st, S, ns, b + 3 * bin_cap, bin_cnt + 3);
+  if (hubs) {
+    const int32_t* hb = bins + 8 * bin_cap;
+    const uint32_t* hc = bin_cnt + 8;
+    LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub.chunk_off, hub.tab_off, hub.slice_off, hub.chunk_hub,
+           hub.slice_hub, hub.map_cap, hub.totals, hub.tab_cap, hub.overflow);
+    LAUNCH(k_hub_chunk, G, 256, S, ns, hb, hc, hub.chunk_off, hub.tab_off, hub.chunk_hub, hub.totals, hub.gkeys,
+           hub.gvals, hub.own, hub.overflow);
+    LAUNCH(k_hub_scan, G, 256, S, ns, hb, hc, hub.tab_off, hub.slice_off, hub.slice_hub, hub.totals, hub.gkeys,
+           hub.gvals, hub.own, hub.best, hub.overflow);
+    LAUNCH(k_hub_final, 64, 256, S, ns, hb, hc, hub.own, hub.best, hub.overflow);
+  }
   rec(4);
-  hipLaunchKernelGGL(k_rate_wave<256>, dim3(G), dim3(256), 0, st, S, ns, b + 4 * bin_cap, bin_cnt + 4);
-  rec(5);
-  hipLaunchKernelGGL(k_rate_wave<1024>, dim3(G), dim3(256), 0, st, S, ns, b + 5 * bin_cap, bin_cnt + 5);
-  rec(6);
-  hipLaunchKernelGGL((k_rate_block<2048, 256>), dim3(G), dim3(256), 0, st, S, ns, b + 6 * bin_cap, bin_cnt + 6);
-  rec(7);
-  hipLaunchKernelGGL((k_rate_block<8192, 512>), dim3(G), dim3(512), 0, st, S, ns, b + 7 * bin_cap, bin_cnt + 7);
-  rec(8);
-  const int32_t* hb = b + 8 * bin_cap;
-  const uint32_t* hc = bin_cnt + 8;
-  hipLaunchKernelGGL(k_hub_prep, dim3(1), dim3(1024), 0, st, S, ns, hb, hc, hub.chunk_off, hub.tab_off,
-                     hub.slice_off, hub.totals, hub.tab_cap, hub.overflow);
-  hipLaunchKernelGGL(k_hub_chunk, dim3(G), dim3(256), 0, st, S, ns, hb, hc, hub.chunk_off, hub.tab_off, hub.totals,
-                     hub.gkeys, hub.gvals, hub.own, hub.overflow);
-  hipLaunchKernelGGL(k_hub_scan, dim3(G), dim3(256), 0, st, S, ns, hb, hc, hub.tab_off, hub.slice_off, hub.totals,
-                     hub.gkeys, hub.gvals, hub.own, hub.best, hub.overflow);
-  hipLaunchKernelGGL(k_hub_final, dim3(64), dim3(256), 0, st, S, ns, hb, hc, hub.own, hub.best, hub.overflow);
-  rec(9);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
 
-int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, uint64_t* ckeys, uint32_t* ccnt, int node_bits,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_incoming, dim3(grid_for(N, kAggNodes, 4096)), dim3(256), 0, st, S, ns, N);
-  hipLaunchKernelGGL(k_decide, dim3(grid_for(N, 256, 4096)), dim3(256), 0, st, S, ns, N, ckeys, ccnt, node_bits);
+int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
+                           uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st) {
+  LAUNCH(k_incoming, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt);
+  LAUNCH(k_decide, grid_for(N, 256, 4096), 256, S, ns, rated, rcnt, ckeys, ccnt, node_bits);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -918,8 +1118,7 @@ int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, uint64_t* ckeys,
 int launch_contended_split(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
                            uint32_t* tkey, int64_t* wv, hipStream_t st) {
   if (cnt == 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_contended_split, dim3((cnt + 255) / 256), dim3(256), 0, st, S, ns, keys, cnt, node_bits,
-                     tkey, wv);
+  LAUNCH(k_contended_split, (cnt + 255) / 256, 256, S, ns, keys, cnt, node_bits, tkey, wv);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -927,17 +1126,26 @@ int launch_contended_split(const DevSlot* S, int ns, const uint64_t* keys, uint3
 int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
                           const int64_t* prefix, hipStream_t st) {
   if (cnt == 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_contended_mark, dim3((cnt + 255) / 256), dim3(256), 0, st, S, ns, keys, cnt, node_bits,
-                     prefix);
+  LAUNCH(k_contended_mark, (cnt + 255) / 256, 256, S, ns, keys, cnt, node_bits, prefix);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
 
-int launch_apply(const DevSlot* S, int ns, int64_t N, int32_t* movers, uint32_t* mcnt, bool any_refine,
+int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,
+                           uint32_t* big_flag, hipStream_t st) {
+  LAUNCH(k_contended_small, 1, 1024, S, ns, keys, ccnt, node_bits, big_flag);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* movers,
+                 uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine, const uint32_t* skip,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_apply, dim3(grid_for(N, kAggNodes, 4096)), dim3(256), 0, st, S, ns, N, movers, mcnt);
-  if (any_refine)
-    hipLaunchKernelGGL(k_mark, dim3(grid_for(N, 256 * kWave / 4, 2048)), dim3(256), 0, st, S, ns, movers, mcnt);
+  LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, movers, mcnt, skip);
+  if (any_refine) {
+    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, movers, mcnt, big, big_cnt, skip);
+    LAUNCH(k_mark_big, 1024, 256, S, ns, big, big_cnt, skip);
+  }
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
