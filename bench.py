@@ -1,17 +1,21 @@
-"""Benchmark: SCLaP edge visits/s of the full multilevel partitioner on one
-MI355X, with the rating step's HBM roofline fraction and the CPU oracle as a
-reported baseline.
+"""Benchmark of the SCLaP multilevel partitioner on one MI355X.
 
-Workload (one step): partition an R-MAT graph (scale 22, edge factor 16,
-a/b/c/d = .57/.19/.19/.05, 4.19M nodes) and a 2D random geometric graph
+Default workload (one step): partition an R-MAT graph (scale 22, edge factor
+16, a/b/c/d = .57/.19/.19/.05, 4.19M nodes) and a 2D random geometric graph
 (2^22 nodes, average degree 10) into k = 16 blocks, eps = 3/100, f = 14,
-coarsening to <= 5000 k = 80,000 nodes, 10 LP rounds per level, LP
-refinement on every level.  Inputs are generated on the host, copied to the
-device before timing, and stay resident.
+coarsening to <= 5000 k = 80,000 nodes, 10 LP rounds per level, LP refinement
+on every level.  Inputs are generated on the host, copied to the device before
+timing, and stay resident.  value = edge visits (clustering + refinement
+rounds, both graphs) per second of the whole step (contraction, initial
+partition and projection included).  The JSON line carries the HBM roofline
+of the dominant rating kernel and the CPU oracle as a reported baseline.
 
-value = edge visits (clustering + refinement rounds, both graphs) per
-second of the whole step (contraction, initial partition and projection
-included).
+Other workloads (`--workload`):
+  batch  512 mixed graphs, batched (every step fused over all graphs) versus
+         plain (one graph after the other); graphs/s.
+  serve  served Poisson stream of partition jobs under an HBM budget versus
+         plain; p50/p99 latency and jobs/s.
+  large  one R-MAT graph of scale 26, k = 32, with result properties checked.
 """
 from __future__ import annotations
 
@@ -25,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+RATE_KERNELS = ["k_rate_small (degree 1-128)", "k_rate_mid (degree 129-1024)", "k_rate_large (degree 1025-4096)",
+                "hub path (4 kernels, degree > 4096)"]
 
 
 def log(msg: str) -> None:
@@ -42,15 +48,15 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str):
-    """HBM bytes per launch of `kernel` from profiles/traffic.json (rocprofv3
-    FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
-    when the kernels changed since the counters were taken."""
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from profiles/traffic.json
+    (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the kernels changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if t.get("source_digest") != kernel_source_digest():
+    if t.get("source_digest") != kernel_source_digest() or t.get("workload", "two-graphs-s22") != workload:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -70,24 +76,55 @@ def copy_calibration(mbytes: int) -> int:
     return 0
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--scale", type=int, default=22, help="R-MAT scale (log2 of the node count of both graphs)")
-    ap.add_argument("--calib-copy-mb", type=int, default=0,
-                    help="only run a plain device copy of this many MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.calib_copy_mb:
-        return copy_calibration(args.calib_copy_mb)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the partitioner's multi-GPU path is "
-              "not built; see the sharding notes in DESIGN.md.", file=sys.stderr)
-        return 2
+def roofline(prof: dict, workload: str) -> tuple[dict, list]:
+    """Roofline of the dominant rating kernel: algorithmic bytes per launch
+    (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge visit,
+    32 B per rated node) / mean launch duration from HIP events."""
+    launches = max(prof["kernel_launches"], 1)
+    dom = max(range(3), key=lambda b: prof["kernels"][b]["ms"])
+    kd = prof["kernels"][dom]
+    avg_ms = kd["ms"] / launches
+    bpl = kd["bytes"] / launches
+    achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    per_kernel = [{"kernel": RATE_KERNELS[b], "ms_per_round": prof["kernels"][b]["ms"] / launches,
+                   "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
+                   if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(4)]
+    rl = {"bound": "hbm", "kernel": RATE_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(RATE_KERNELS[dom], workload),
+          "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": launches}
+    return rl, per_kernel
 
-    import numpy as np
+
+def profiled(ctx, fn):
+    """Run fn once more with HIP events around every rating launch."""
+    import torch
+
+    ctx.profile(True)
+    fn()
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    return prof
+
+
+def visits_of(st: dict) -> int:
+    return sum(st["visits_c"]) + sum(st["visits_r"])
+
+
+def round_rate(prof: dict):
+    return (prof["visits"] / (prof["round_ms"] * 1e-3)) if prof["round_ms"] > 0 else None
+
+
+def base_line(metric, value, unit, steps, warmup, ms_per_step, config, scaling="weak"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": scaling, "vs_baseline": None,
+            "dtype": "int32", "data": "synthetic", "config": config}
+
+
+# --------------------------------------------------------------------------
+# R-MAT s22 + RGG 2^22, k = 16 (default)
+
+def run_two_graphs(args) -> int:
     import torch
 
     import graphgen
@@ -116,39 +153,15 @@ def main() -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     visits = 0
-    visits_c = 0
     sts = []
     for i in range(args.steps):
         sts = step()
-        visits += sum(sum(s["visits_c"]) + sum(s["visits_r"]) for s in sts)
-        visits_c += sum(sum(s["visits_c"]) for s in sts)
+        visits += sum(visits_of(s) for s in sts)
         log(f"step {i} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_per_step = elapsed * 1000.0 / args.steps
-    value = visits / elapsed
-
-    # one more step, untimed, with HIP events around every rating launch
-    ctx.profile(True)
-    step()
-    torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-
-    # roofline of the dominant rating kernel: algorithmic bytes per launch
-    # (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge
-    # visit, 32 B per rated node) / mean launch duration (HIP events)
-    names = ["k_rate_small (degree 1-128)", "k_rate_mid (degree 129-1024)", "k_rate_large (degree 1025-4096)",
-             "hub path (4 kernels, degree > 4096)"]
-    launches = max(prof["kernel_launches"], 1)
-    dom = max(range(3), key=lambda b: prof["kernels"][b]["ms"])
-    kd = prof["kernels"][dom]
-    avg_ms = kd["ms"] / launches
-    bytes_per_launch = kd["bytes"] / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    step_kernels = [{"kernel": names[b], "ms_per_round": prof["kernels"][b]["ms"] / launches,
-                     "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
-                     if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(4)]
+    prof = profiled(ctx, step)
+    rl, per_kernel = roofline(prof, "two-graphs-s22")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -169,47 +182,365 @@ def main() -> int:
                "sample": "oracle level-0 clustering (up to 10 LP rounds with the coarsening stop rule) of both "
                          f"graphs, single thread, gcc -O2: {rounds} rounds, {cv} visits in {ct:.1f}s"}
 
-    line = {
-        "metric": "SCLaP edge visits/s (multilevel partition, clustering + refinement rounds)",
-        "value": value,
-        "unit": "edge visits/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"rmat-s{scale}-ef16 + rgg-2^{scale}-d10, k=16, eps=3/100, f=14, coarsen to <= {thr}, "
-                        "10 LP rounds per level, LP refinement on every level",
-            "k": k,
-            "graphs": [{"name": g.name, "n": g.n, "m": g.m} for g in graphs],
-            "cuts": [s["cut"] for s in sts],
-            "levels": [s["n_level"] for s in sts],
-        },
-        "sclap_round_visits_per_s": (prof["visits"] / (prof["round_ms"] * 1e-3)) if prof["round_ms"] > 0 else None,
+    line = base_line(
+        "SCLaP edge visits/s (multilevel partition, clustering + refinement rounds)", visits / elapsed,
+        "edge visits/s", args.steps, args.warmup, elapsed * 1000.0 / args.steps,
+        {"workload": f"rmat-s{scale}-ef16 + rgg-2^{scale}-d10, k=16, eps=3/100, f=14, coarsen to <= {thr}, "
+                     "10 LP rounds per level, LP refinement on every level",
+         "k": k, "graphs": [{"name": g.name, "n": g.n, "m": g.m} for g in graphs],
+         "cuts": [s["cut"] for s in sts], "levels": [s["n_level"] for s in sts]})
+    line.update({
+        "sclap_round_visits_per_s": round_rate(prof),
         "visits_per_step": visits // max(args.steps, 1),
-        "rating_kernels": step_kernels,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": names[dom],
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_for(names[dom]),
-            "bytes_per_launch": bytes_per_launch,
-            "avg_launch_ms": avg_ms,
-            "launches": launches,
-        },
+        "phase_ms": [dict(graph=g.name, **s["ms"]) for g, s in zip(graphs, sts)],
+        "rating_kernels": per_kernel,
+        "roofline": rl,
         "cpu_baseline": cpu,
-    }
+    })
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0
+
+
+# --------------------------------------------------------------------------
+# 512 mixed graphs: batched versus plain
+
+def run_batch(args) -> int:
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1402_3281_amd as sc
+
+    t0 = time.time()
+    specs = graphgen.batch_specs(count=args.graphs, seed=3)
+    graphs = [s.make() for s in specs]
+    ks = [s.k for s in specs]
+    log(f"generated {len(graphs)} graphs in {time.time() - t0:.1f}s: n={sum(g.n for g in graphs)} "
+        f"m={sum(g.m for g in graphs)}")
+    torch.cuda.set_device(0)
+    devs = [sc.DeviceGraph.from_host(g, rows_sorted=True) for g in graphs]
+    ctx = sc.Context(0)
+    stream = torch.cuda.current_stream()
+    plain_parts = [torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in graphs]
+    batch_parts = [torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in graphs]
+
+    def plain():
+        return [sc.partition(ctx, d, k, stream=stream, part_out=p)[1] for d, k, p in zip(devs, ks, plain_parts)]
+
+    def batched():
+        return sc.partition_batch(ctx, devs, ks, stream=stream, parts_out=batch_parts)[1]
+
+    def timed(fn, name):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = None
+        for _ in range(args.steps):
+            out = fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / args.steps
+        log(f"{name}: {dt * 1e3:.1f} ms per pass over the batch")
+        return dt, out
+
+    tp, sts_p = timed(plain, "plain")
+    tb, sts_b = timed(batched, "batched")
+    same = all(torch.equal(a[:g.n], b[:g.n]) for a, b, g in zip(plain_parts, batch_parts, graphs))
+    same = same and all(a["cut"] == b["cut"] for a, b in zip(sts_p, sts_b))
+    visits = sum(visits_of(s) for s in sts_b)
+    prof = profiled(ctx, batched)
+    rl, per_kernel = roofline(prof, "batch-512")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        done = 0
+        equal = True
+        while done < len(graphs) and time.perf_counter() - t1 < 15.0:
+            part, st = oracle.partition(graphs[done], ks[done])
+            equal = equal and st["cut"] == sts_b[done]["cut"] and np.array_equal(
+                part, batch_parts[done][:graphs[done].n].cpu().numpy())
+            done += 1
+        ct = time.perf_counter() - t1
+        cpu = {"value": done / ct, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle partition of the first {done} graphs of the batch, one after the other, single "
+                         f"thread; blocks equal to the batched GPU blocks: {equal}"}
+
+    line = base_line(
+        "graphs/s, mixed graphs partitioned batched (every executor step fused over all graphs)",
+        len(graphs) / tb, "graphs/s", args.steps, args.warmup, tb * 1000.0,
+        {"workload": f"{len(graphs)} graphs, n log-uniform in [2^8, 2^16], half R-MAT (edge factor 4-32), half "
+                     "RGG (degree 6-12), k in {2,4,8,16}, eps=3/100, f=14, coarsening threshold max(60k, n/(60k))",
+         "graphs": len(graphs), "n_total": sum(g.n for g in graphs), "m_total": sum(g.m for g in graphs)})
+    line.update({
+        "plain": {"graphs_per_s": len(graphs) / tp, "ms_per_pass": tp * 1e3,
+                  "visits_per_s": sum(visits_of(s) for s in sts_p) / tp},
+        "batched": {"graphs_per_s": len(graphs) / tb, "ms_per_pass": tb * 1e3, "visits_per_s": visits / tb},
+        "batched_over_plain": tp / tb,
+        "identical_results": bool(same),
+        "sclap_round_visits_per_s": round_rate(prof),
+        "rating_kernels": per_kernel,
+        "roofline": rl,
+        "cpu_baseline": cpu,
+    })
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0 if same else 1
+
+
+# --------------------------------------------------------------------------
+# served Poisson stream versus plain
+
+def run_serve(args) -> int:
+    import threading
+
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1402_3281_amd as sc
+
+    specs = graphgen.serve_specs(count=args.jobs, seed=4)
+    pool_n = min(args.pool, len(specs))
+    t0 = time.time()
+    pool = [specs[i].make() for i in range(pool_n)]
+    log(f"generated a pool of {pool_n} graphs in {time.time() - t0:.1f}s: n={sum(g.n for g in pool)} "
+        f"m={sum(g.m for g in pool)}")
+    torch.cuda.set_device(0)
+    devs = [sc.DeviceGraph.from_host(g, rows_sorted=True) for g in pool]
+    # job i partitions pool graph (i mod pool size) into its own k
+    jobs = [(i % pool_n, specs[i].k) for i in range(len(specs))]
+    ctx = sc.Context(0)
+    stream = torch.cuda.current_stream()
+    outs = [torch.empty(max(pool[g].n, 1), dtype=torch.int32, device="cuda") for g, _ in jobs]
+
+    # plain: one job after the other, on a prefix of the stream
+    n_plain = min(args.plain_jobs, len(jobs))
+    plain_parts = [torch.empty(max(pool[g].n, 1), dtype=torch.int32, device="cuda") for g, _ in jobs[:n_plain]]
+    for g, k in jobs[:min(4, n_plain)]:
+        sc.partition(ctx, devs[g], k, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain_cut = []
+    for (g, k), p in zip(jobs[:n_plain], plain_parts):
+        plain_cut.append(sc.partition(ctx, devs[g], k, stream=stream, part_out=p)[1]["cut"])
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    plain_jps = n_plain / tp
+    log(f"plain: {n_plain} jobs in {tp:.2f}s ({plain_jps:.1f} jobs/s)")
+
+    budget = args.budget_gb << 30
+
+    def serve(rate: float, count: int):
+        srv = sc.Server(ctx, hbm_budget_bytes=budget, max_active=args.max_active)
+        arrivals = graphgen.poisson_arrivals(count, rate, seed=5) if rate > 0 else np.zeros(count)
+        tickets = [None] * count
+        ready = threading.Semaphore(0)
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i in range(count):
+                dt = arrivals[i] - (time.perf_counter() - t_start)
+                if dt > 0:
+                    time.sleep(dt)
+                g, k = jobs[i]
+                tickets[i] = srv.submit(devs[g], k, outs[i])
+                ready.release()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        res = []
+        for i in range(count):
+            ready.acquire()
+            res.append(srv.wait(tickets[i]))
+            if (i + 1) % 1000 == 0:
+                log(f"  {i + 1} jobs done")
+        th.join()
+        wall = time.perf_counter() - t_start
+        st = srv.stats()
+        srv.close()
+        return res, st, wall
+
+    # capacity: every job of a prefix submitted at once
+    n_cap = min(args.capacity_jobs, len(jobs))
+    _, _, wall = serve(0.0, n_cap)
+    capacity = n_cap / wall
+    log(f"closed loop: {n_cap} jobs in {wall:.2f}s ({capacity:.1f} jobs/s)")
+    rate = args.rate if args.rate > 0 else 0.8 * capacity
+    res, st, wall = serve(rate, len(jobs))
+    log(f"Poisson stream at {rate:.1f} jobs/s: {len(jobs)} jobs in {wall:.2f}s, p50 {st['p50_ms']:.1f} ms "
+        f"p99 {st['p99_ms']:.1f} ms")
+    ok = all(r["status"] == sc.OK for r in res)
+    same = all(res[i]["cut"] == plain_cut[i] and torch.equal(outs[i][:pool[jobs[i][0]].n],
+                                                              plain_parts[i][:pool[jobs[i][0]].n])
+               for i in range(n_plain))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        done = 0
+        while done < len(jobs) and time.perf_counter() - t1 < 15.0:
+            g, k = jobs[done]
+            oracle.partition(pool[g], k)
+            done += 1
+        ct = time.perf_counter() - t1
+        cpu = {"value": done / ct, "unit": "jobs/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle partition of the first {done} jobs of the stream, one after the other, single thread"}
+
+    line = base_line(
+        "jobs/s, served Poisson stream of partition jobs (continuous batching under an HBM budget)",
+        st["jobs_per_s"], "jobs/s", 1, 0, wall * 1000.0,
+        {"workload": f"{len(jobs)} jobs, n log-uniform in [2^10, 2^20], R-MAT (edge factor 16) and RGG (degree 8) "
+                     f"1:1, k in 2..64, graphs from a pool of the first {pool_n} job graphs, Poisson arrivals at "
+                     f"{rate:.1f} jobs/s, HBM budget {args.budget_gb} GB",
+         "jobs": len(jobs), "pool": pool_n, "rate_per_s": rate, "budget_gb": args.budget_gb}, scaling="strong")
+    line.update({
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "completed": st["completed"], "peak_bytes": st["peak_bytes"],
+        "closed_loop_jobs_per_s": capacity, "plain_jobs_per_s": plain_jps, "plain_jobs": n_plain,
+        "served_over_plain": st["jobs_per_s"] / plain_jps, "all_ok": ok, "identical_to_plain": bool(same),
+        "cpu_baseline": cpu,
+    })
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0 if (ok and same) else 1
+
+
+# --------------------------------------------------------------------------
+# R-MAT scale 26, k = 32
+
+def run_large(args) -> int:
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_1402_3281_amd as sc
+
+    k, scale = 32, args.scale
+    t0 = time.time()
+    graphgen.set_progress(True)
+    g = graphgen.rmat(scale, 16, seed=1)
+    graphgen.set_progress(False)
+    log(f"generated {g.name} n={g.n} m={g.m} in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    dev = sc.DeviceGraph.from_host(g, rows_sorted=True)
+    part = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    ctx = sc.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return sc.partition(ctx, dev, k, stream=stream, part_out=part)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = None
+    visits = 0
+    for i in range(args.steps):
+        st = step()
+        visits += visits_of(st)
+        log(f"step {i} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    prof = profiled(ctx, step)
+    rl, per_kernel = roofline(prof, f"rmat-s{scale}")
+
+    # properties that hold at any size: the cut and block weights recomputed on
+    # the host from the returned blocks, every block within L_max
+    log("checking result properties on the host")
+    p = part.cpu().numpy()
+    lmax, _, _ = sc.bounds(g.n, 1, k, (3, 100), 14)
+    bw = np.bincount(p, minlength=k)
+    cut = 0
+    step_rows = 1 << 22
+    for lo in range(0, g.n, step_rows):
+        hi = min(g.n, lo + step_rows)
+        a, b = int(g.row_ptr[lo]), int(g.row_ptr[hi])
+        src = np.repeat(p[lo:hi], np.diff(g.row_ptr[lo:hi + 1]))
+        cut += int(np.count_nonzero(src != p[g.col[a:b]]))
+    cut //= 2
+    props = {"blocks_in_range": bool(p.min() >= 0 and p.max() < k), "max_block": int(bw.max()), "lmax": lmax,
+             "max_block_le_lmax": bool(bw.max() <= lmax), "max_block_matches": int(bw.max()) == st["max_block"],
+             "cut_recomputed": cut, "cut_matches": cut == st["cut"]}
+    ok = props["blocks_in_range"] and props["max_block_le_lmax"] and props["max_block_matches"] and \
+        props["cut_matches"]
+    log(f"properties: {props}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        log("timing the oracle")
+        t1 = time.perf_counter()
+        _, _, U = oracle.bounds(g.n, 1, k, 3, 100, 14)
+        r = oracle.cluster(oracle.OGraph.of(g), U, 1, 0, 1)
+        ct = time.perf_counter() - t1
+        cpu = {"value": r.visits / ct, "unit": "edge visits/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle clustering round 1 on level 0, single thread: {r.visits} visits in {ct:.1f}s"}
+
+    line = base_line(
+        "SCLaP edge visits/s (multilevel partition, clustering + refinement rounds)", visits / elapsed,
+        "edge visits/s", args.steps, args.warmup, elapsed * 1000.0 / args.steps,
+        {"workload": f"rmat-s{scale}-ef16, k={k}, eps=3/100, f=14, coarsening threshold max(60k, n/(60k)), "
+                     "10 LP rounds per level, LP refinement on every level",
+         "k": k, "graphs": [{"name": g.name, "n": g.n, "m": g.m}], "cut": st["cut"], "levels": st["n_level"]})
+    line.update({
+        "sclap_round_visits_per_s": round_rate(prof),
+        "phase_ms": st["ms"],
+        "properties": props,
+        "rating_kernels": per_kernel,
+        "roofline": rl,
+        "cpu_baseline": cpu,
+    })
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0 if ok else 1
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="two-graphs", choices=("two-graphs", "batch", "serve", "large"),
+                    help="two-graphs: R-MAT s22 + RGG 2^22, k=16 (default); batch: 512 mixed graphs batched vs "
+                         "plain; serve: Poisson stream of jobs; large: R-MAT s26, k=32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--scale", type=int, default=0, help="R-MAT scale (two-graphs: 22, large: 26)")
+    ap.add_argument("--graphs", type=int, default=512, help="batch size (batch)")
+    ap.add_argument("--jobs", type=int, default=10000, help="jobs in the served stream (serve)")
+    ap.add_argument("--pool", type=int, default=128, help="distinct graphs the served jobs draw from (serve)")
+    ap.add_argument("--plain-jobs", type=int, default=1000, help="jobs run one by one for comparison (serve)")
+    ap.add_argument("--capacity-jobs", type=int, default=2000, help="jobs of the closed-loop capacity run (serve)")
+    ap.add_argument("--rate", type=float, default=0.0, help="arrival rate in jobs/s (serve; default 0.8 x capacity)")
+    ap.add_argument("--budget-gb", type=int, default=200, help="HBM budget of the server (serve)")
+    ap.add_argument("--max-active", type=int, default=256, help="jobs on the device at once (serve)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.calib_copy_mb:
+        return copy_calibration(args.calib_copy_mb)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the partitioner's multi-GPU path is "
+              "not built; see the sharding notes in DESIGN.md.", file=sys.stderr)
+        return 2
+    if args.workload == "two-graphs":
+        args.scale = args.scale or 22
+        return run_two_graphs(args)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
+    args.scale = args.scale or 26
+    return run_large(args)
 
 
 if __name__ == "__main__":

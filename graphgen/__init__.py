@@ -63,6 +63,8 @@ def _load():
         lib.gg_rgg.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_uint64, ctypes.POINTER(_Csr)]
         lib.gg_free.restype = None
         lib.gg_free.argtypes = [ctypes.c_void_p]
+        lib.gg_set_progress.restype = None
+        lib.gg_set_progress.argtypes = [ctypes.c_int]
         lib.gg_draw_u64.restype = ctypes.c_uint64
         lib.gg_draw_u64.argtypes = [ctypes.c_uint64] * 4
         _lib = lib
@@ -144,6 +146,11 @@ def rgg(n: int, avg_degree: float, seed: int = 1) -> Graph:
         raise RuntimeError(f"gg_rgg failed ({rc})")
     rp, col = _take(out)
     return Graph(rp, col, name=f"rgg-n{n}-d{avg_degree}-seed{seed}")
+
+
+def set_progress(on: bool) -> None:
+    """Print a line to stderr after every phase of a generation."""
+    _load().gg_set_progress(1 if on else 0)
 
 
 def draw_u64(seed: int, tag: int, i: int, j: int) -> int:

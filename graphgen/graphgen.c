@@ -14,6 +14,7 @@
  * does not depend on the number of threads.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
@@ -41,6 +42,16 @@ typedef struct gg_csr {
 } gg_csr;
 
 void gg_free(void* p) { free(p); }
+
+/* When on, every finished phase of a generation prints a line to stderr. */
+static int gg_progress = 0;
+void gg_set_progress(int on) { gg_progress = on; }
+static void gg_phase(const char* what, int64_t count) {
+  if (gg_progress) {
+    fprintf(stderr, "graphgen: %s (%lld)\n", what, (long long)count);
+    fflush(stderr);
+  }
+}
 
 /* Exposed for tests: raw draw and stream key. */
 uint64_t gg_draw_u64(uint64_t seed, uint64_t tag, uint64_t i, uint64_t j) {
@@ -86,6 +97,7 @@ static int build_sym_csr(int64_t n, int64_t ns, const int32_t* su, const int32_t
   }
   for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
   int64_t tot = cnt[n];
+  gg_phase("degrees counted", tot);
   int32_t* tmp = (int32_t*)malloc((size_t)(tot > 0 ? tot : 1) * sizeof(int32_t));
   int64_t* pos = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
   if (!tmp || !pos) { free(cnt); free(tmp); free(pos); return -1; }
@@ -99,6 +111,7 @@ static int build_sym_csr(int64_t n, int64_t ns, const int32_t* su, const int32_t
     tmp[__atomic_fetch_add(&pos[b], 1, __ATOMIC_RELAXED)] = a;
   }
   free(pos);
+  gg_phase("entries scattered", tot);
   int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
   if (!deg) { free(cnt); free(tmp); return -1; }
 #pragma omp parallel for schedule(dynamic, 64)
@@ -113,6 +126,7 @@ static int build_sym_csr(int64_t n, int64_t ns, const int32_t* su, const int32_t
   }
   for (int64_t v = 0; v < n; ++v) deg[v + 1] += deg[v];
   int64_t m = deg[n];
+  gg_phase("rows sorted and deduplicated", m);
   int32_t* col = (int32_t*)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
   if (!col) { free(cnt); free(tmp); free(deg); return -1; }
 #pragma omp parallel for schedule(dynamic, 1024)
@@ -168,6 +182,7 @@ int gg_rmat(int32_t scale, int64_t n, int64_t nsamples, uint64_t seed,
     su[i] = (int32_t)u;
     sv[i] = (int32_t)v;
   }
+  gg_phase("R-MAT samples drawn", nsamples);
   int rc = build_sym_csr(n, nsamples, su, sv, out);
   free(su);
   free(sv);
