@@ -181,6 +181,7 @@ int sclap_validate(sclap_ctx* ctx, const sclap_csr* g, void* stream) {
   if (!ctx) return fail(SCLAP_EINVAL, "ctx is NULL");
   SCLAP_TRY(check_csr(g));
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   const int64_t n = g->n, m = g->m;
   const size_t mz = (size_t)std::max<int64_t>(m, 1);
@@ -221,6 +222,7 @@ int sclap_cluster(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_
   SCLAP_TRY(check_lp(p));
   if (g->n > 0 && !labels_out) return fail(SCLAP_EINVAL, "labels_out is NULL");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   SCLAP_TRY(check_edge_total(c, g, st));
   Job j;
@@ -277,6 +279,7 @@ int sclap_contract(sclap_ctx* ctx, const sclap_csr* g, const int32_t* labels, in
   SCLAP_TRY(check_csr(g));
   if (g->n > 0 && (!labels || !coarse_of_out)) return fail(SCLAP_EINVAL, "NULL labels or coarse_of_out");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   SCLAP_TRY(check_edge_total(c, g, st));
   Job j;
@@ -350,6 +353,7 @@ int sclap_initial_partition(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int32
   if (k < 1) return fail(SCLAP_EINVAL, "k must be >= 1");
   if (g->n > 0 && !part_out) return fail(SCLAP_EINVAL, "part_out is NULL");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   Job j;
   j.kind = skip_isolated ? JOB_PARTITION : JOB_REFINE;  // selects skip_isolated on level 0
@@ -376,6 +380,7 @@ int sclap_refine(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int64_t lmax, co
   if (k < 1) return fail(SCLAP_EINVAL, "k must be >= 1");
   if (g->n > 0 && !part_inout) return fail(SCLAP_EINVAL, "part_inout is NULL");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   SCLAP_TRY(check_edge_total(c, g, st));
   Job j;
@@ -406,6 +411,7 @@ int sclap_cut(sclap_ctx* ctx, const sclap_csr* g, const int32_t* part, int32_t k
   SCLAP_TRY(check_csr(g));
   if (k < 1) return fail(SCLAP_EINVAL, "k must be >= 1");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   SCLAP_TRY(c->small.ensure(256, st));
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
@@ -433,6 +439,7 @@ int sclap_partition(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int64_t eps_n
                     const sclap_ml_params* p, int32_t* part_out, sclap_stats* stats, void* stream) {
   if (!ctx) return fail(SCLAP_EINVAL, "ctx is NULL");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   Job j;
   int rc = setup_partition_job(c, &j, g, k, eps_num, eps_den, p, part_out, st);
@@ -453,6 +460,7 @@ int sclap_partition_batch(sclap_ctx* ctx, int32_t count, const sclap_csr* gs, co
                           void* stream) {
   if (!ctx || count < 0 || (count > 0 && (!gs || !ks || !parts_out))) return fail(SCLAP_EINVAL, "NULL argument");
   Ctx* c = &ctx->c;
+  CtxScope scope(c);
   hipStream_t st = as_stream(stream);
   std::vector<Job> jobs((size_t)count);
   std::vector<Job*> ptrs;

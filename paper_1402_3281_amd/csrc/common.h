@@ -80,6 +80,25 @@ constexpr int64_t kBinBlock = 4096;
 
 constexpr int kHubChunk = 4096;      // entries per workgroup in the multi-workgroup path
 
+// Loads and stores through the global address space: global_load /
+// global_store with an SGPR base, instead of the flat instructions that
+// pointers read from a descriptor would otherwise get (flat accesses also
+// count against the LDS/scalar wait counter and serialise with them).
+#define SCLAP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gld(const T* p, int64_t i) {
+  return ((const SCLAP_GLOBAL T*)p)[i];
+}
+template <class T>
+__device__ __forceinline__ void gst(T* p, int64_t i, T v) {
+  ((SCLAP_GLOBAL T*)p)[i] = v;
+}
+// Relaxed device-scope atomic sum on a global int64 element.
+__device__ __forceinline__ void gadd64(int64_t* p, int64_t i, int64_t v) {
+  __hip_atomic_fetch_add((SCLAP_GLOBAL unsigned long long*)(p + i), (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ int slot_of(const DevSlot* __restrict__ S, int ns, int64_t u) {
   int lo = 0, hi = ns - 1;
   while (lo < hi) {

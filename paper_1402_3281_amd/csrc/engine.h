@@ -72,9 +72,20 @@ struct Job {
   double t_start = 0;
 };
 
+// Device blocks that a context keeps for reuse instead of returning them to
+// the HIP memory pool (whose frees of large blocks take milliseconds).
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  hipStream_t st;
+};
+
 struct Ctx {
   int device = 0;
   int cu_count = 256;
+  // freed device blocks kept for later allocations on the same stream
+  std::vector<CachedBlock> cache;
+  size_t cache_bytes = 0;
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
@@ -105,6 +116,15 @@ struct Ctx {
 };
 
 int ctx_ensure_pin(Ctx* c, size_t bytes);
+// While a CtxScope for c is alive on a thread, dalloc and dfree on that
+// thread take blocks from and return blocks to c's cache.
+struct CtxScope {
+  Ctx* prev;
+  explicit CtxScope(Ctx* c);
+  ~CtxScope();
+};
+// Returns every cached block of c to HIP (synchronises the device first).
+void ctx_trim(Ctx* c);
 // Frees every scratch buffer, the pinned staging and the events of c.
 void ctx_release(Ctx* c, hipStream_t st);
 int ctx_ensure_slots(Ctx* c, size_t count);

@@ -11,6 +11,9 @@
 #include <cstring>
 #include <string>
 
+#include <mutex>
+#include <unordered_map>
+
 #include "engine.h"
 
 namespace sclap {
@@ -32,20 +35,105 @@ int bits_for(int64_t count) {
   return 64 - __builtin_clzll((unsigned long long)(count - 1));
 }
 
+namespace {
+thread_local Ctx* tls_ctx = nullptr;
+std::mutex g_size_mu;
+struct BlockInfo {
+  size_t bytes;
+  int device;
+};
+std::unordered_map<void*, BlockInfo> g_size;  // every live dalloc block
+
+// Allocation classes: powers of two up to 1 MiB, then eighths of an octave.
+size_t alloc_class(size_t bytes) {
+  if (bytes <= 256) return 256;
+  if (bytes <= (1u << 20)) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  const int lg = 63 - __builtin_clzll((unsigned long long)bytes);
+  const size_t step = (size_t)1 << (lg - 3);
+  return (bytes + step - 1) / step * step;
+}
+
+constexpr size_t kCacheLimit = (size_t)96 << 30;  // bytes a context keeps cached at most
+}  // namespace
+
+CtxScope::CtxScope(Ctx* c) : prev(tls_ctx) { tls_ctx = c; }
+CtxScope::~CtxScope() { tls_ctx = prev; }
+
+void ctx_trim(Ctx* c) {
+  if (c->cache.empty()) return;
+  // a cached block may still be read by work queued before its release
+  (void)hipDeviceSynchronize();
+  for (const CachedBlock& b : c->cache) {
+    (void)hipFree(b.p);
+    std::lock_guard<std::mutex> lk(g_size_mu);
+    g_size.erase(b.p);
+  }
+  c->cache.clear();
+  c->cache_bytes = 0;
+}
+
 int dalloc(void** p, size_t bytes, hipStream_t st) {
   *p = nullptr;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMallocAsync(p, bytes, st);
+  const size_t need = alloc_class(bytes == 0 ? 256 : bytes);
+  Ctx* c = tls_ctx;
+  if (c) {
+    // best fit among cached blocks of this stream, at most 1/4 larger
+    int best = -1;
+    for (int i = 0; i < (int)c->cache.size(); ++i) {
+      const CachedBlock& b = c->cache[i];
+      if (b.st == st && b.bytes >= need && b.bytes <= need + need / 4 &&
+          (best < 0 || b.bytes < c->cache[best].bytes))
+        best = i;
+    }
+    if (best >= 0) {
+      *p = c->cache[best].p;
+      c->cache_bytes -= c->cache[best].bytes;
+      c->cache[best] = c->cache.back();
+      c->cache.pop_back();
+      return SCLAP_OK;
+    }
+  }
+  hipError_t e = hipMallocAsync(p, need, st);
+  if (e == hipErrorOutOfMemory && c && !c->cache.empty()) {
+    (void)hipGetLastError();
+    ctx_trim(c);
+    e = hipMallocAsync(p, need, st);
+  }
   if (e != hipSuccess) {
     *p = nullptr;
     return fail(e == hipErrorOutOfMemory ? SCLAP_ENOMEM : SCLAP_EHIP,
                 std::string("device allocation of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
   }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_size_mu);
+  g_size[*p] = BlockInfo{need, dev};
   return SCLAP_OK;
 }
 
 void dfree(void* p, hipStream_t st) {
-  if (p) (void)hipFreeAsync(p, st);
+  if (!p) return;
+  Ctx* c = tls_ctx;
+  size_t bytes = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_size_mu);
+    auto it = g_size.find(p);
+    if (it != g_size.end()) {
+      bytes = it->second.bytes;
+      if (c && it->second.device != c->device) c = nullptr;
+      if (!c || c->cache_bytes + bytes > kCacheLimit) g_size.erase(it);
+    }
+  }
+  if (c && bytes && c->cache_bytes + bytes <= kCacheLimit) {
+    c->cache.push_back({p, bytes, st});
+    c->cache_bytes += bytes;
+    return;
+  }
+  (void)hipFreeAsync(p, st);
 }
 
 int Scratch::ensure(size_t need, hipStream_t st) {
@@ -74,6 +162,7 @@ int ctx_ensure_pin(Ctx* c, size_t bytes) {
 }
 
 void ctx_release(Ctx* c, hipStream_t st) {
+  ctx_trim(c);
   Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,

@@ -103,14 +103,14 @@ __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int 
       s = SLOT(u);
       const DevSlot& sl = S[s];
       const int64_t v = u - sl.nbase;
-      if (sl.round > 0 && (!sl.use_flags || sl.flag_cur[v])) {
-        e0 = sl.rp[v];
-        d = sl.rp[v + 1] - e0;
+      if (sl.round > 0 && (!sl.use_flags || gld(sl.flag_cur, v))) {
+        e0 = gld(sl.rp, v);
+        d = gld(sl.rp, v + 1) - e0;
         take = d > 0;
         b = bin_of(d);
       }
       // the rated set of the next round is rebuilt from scratch
-      if (sl.round > 0 && sl.mode == MODE_REFINE) sl.flag_next[v] = 0;
+      if (sl.round > 0 && sl.mode == MODE_REFINE) gst(sl.flag_next, v, (uint8_t)0);
     }
     constexpr int NB = kBins + 1;
     uint32_t rank = 0, rrank = 0;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int 
 // Choice of a node from its aggregated candidates.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool own_allowed(const DevSlot& sl, int32_t own) {
-  return !(sl.mode == MODE_REFINE && sl.W[own] > sl.cap);
+  return !(sl.mode == MODE_REFINE && gld(sl.W, own) > sl.cap);
 }
 
 // Foreign candidate t with connection c: its key if it can win and is
@@ -163,7 +163,7 @@ __device__ __forceinline__ bool own_allowed(const DevSlot& sl, int32_t own) {
 __device__ __forceinline__ uint64_t cand_key(const DevSlot& sl, bool own_ok, int64_t conn_own, int32_t own,
                                              int64_t cv, int32_t t, int64_t c) {
   const bool beats = !own_ok || c > conn_own || (c == conn_own && t < own);
-  if (beats && sl.W[t] + cv <= sl.cap) return pack_key(c, t);
+  if (beats && gld(sl.W, t) + cv <= sl.cap) return pack_key(c, t);
   return 0;
 }
 
@@ -190,39 +190,56 @@ __device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, i
   const int gbase = lane & ~(G - 1);
   const uint32_t per_block = blockDim.x / G;
   for (uint32_t base = bid * per_block * R; base < cnt; base += nblk * per_block * R) {
+    // Every load is issued from a clamped, always valid index and masked
+    // afterwards, so the loads of all R node sets are in flight at once.
     bool valid[R];
-    int64_t u[R], e0[R];
+    uint32_t ic[R];
+    uint64_t x[R];
+    int64_t u[R], e0[R], v[R], cv[R];
     int d[R];
     int32_t own[R], nb[R], w[R], t[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint32_t i = base + r * per_block + threadIdx.x / G;
       valid[r] = i < cnt;
-      u[r] = valid[r] ? list[i] : 0;
-      const uint64_t x = valid[r] ? info[i] : 0;
-      e0[r] = info_e0(x);
-      d[r] = info_d(x);
+      ic[r] = valid[r] ? i : cnt - 1;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = gld(list, ic[r]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = gld(info, ic[r]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      e0[r] = info_e0(x[r]);
+      d[r] = info_d(x[r]);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const DevSlot& sl = S[SLOT(u[r])];
-      own[r] = valid[r] ? sl.lab[u[r] - sl.nbase] : -1;
-      nb[r] = gl < d[r] ? sl.col[e0[r] + gl] : 0;
-      w[r] = gl < d[r] ? (sl.ew ? sl.ew[e0[r] + gl] : 1) : 0;
+      v[r] = u[r] - sl.nbase;
+      own[r] = gld(sl.lab, v[r]);
+      cv[r] = gld(sl.nw, v[r]);
+      const int64_t e = e0[r] + (gl < d[r] ? gl : d[r] - 1);
+      nb[r] = gld(sl.col, e);
+      w[r] = sl.ew ? gld(sl.ew, e) : 1;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const DevSlot& sl = S[SLOT(u[r])];
-      t[r] = gl < d[r] ? sl.lab[nb[r]] : -1;
+      const int32_t tl = gld(sl.lab, nb[r]);
+      t[r] = gl < d[r] ? tl : -1;
+      w[r] = gl < d[r] ? w[r] : 0;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const DevSlot& sl = S[SLOT(u[r])];
-      const int64_t v = u[r] - sl.nbase;
-      int dm = d[r];
-      for (int off = 32; off > 0; off >>= 1) {
-        const int o = __shfl_xor(dm, off);
-        dm = o > dm ? o : dm;
+      // largest degree in the wave (every degree here is at most G <= 64)
+      const int dv = valid[r] ? d[r] : 0;
+      int dm = 0;
+#pragma unroll
+      for (int b = 6; b >= 0; --b) {
+        const int c = dm | (1 << b);
+        if (__ballot(dv >= c)) dm = c;
       }
       const int dlim = dm < G ? dm : G;
       const bool foreign = t[r] >= 0 && t[r] != own[r];
@@ -250,7 +267,7 @@ __device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, i
       bool own_ok = true;
       if (valid[r]) {
         own_ok = own_allowed(sl, own[r]);
-        if (leader && te != own[r]) key = cand_key(sl, own_ok, conn_own, own[r], sl.nw[v], te, conn);
+        if (leader && te != own[r]) key = cand_key(sl, own_ok, conn_own, own[r], cv[r], te, conn);
       }
 #pragma unroll
       for (int off = G / 2; off > 0; off >>= 1) {
@@ -262,8 +279,8 @@ __device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, i
           const uint64_t ok = pack_key(conn_own, own[r]);
           key = key > ok ? key : ok;
         }
-        sl.desire[v] = key ? key_label(key) : own[r];
-        if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+        gst(sl.desire, v[r], key ? key_label(key) : own[r]);
+        if (sl.mode == MODE_REFINE && boundary) gst(sl.flag_next, v[r], (uint8_t)1);
       }
     }
   }
@@ -298,18 +315,21 @@ __device__ __forceinline__ void table_fill(const DevSlot& sl, int64_t row0, int6
                                            int64_t& my_own, bool& foreign) {
   for (int64_t e = first; e < hi; e += (int64_t)step * B) {
     int32_t nb[B], wt[B], tt[B];
+    bool ok[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int64_t ee = e + (int64_t)q * step;
-      nb[q] = ee < hi ? sl.col[row0 + ee] : -1;
-      wt[q] = ee < hi ? (sl.ew ? sl.ew[row0 + ee] : 1) : 0;
+      ok[q] = ee < hi;
+      const int64_t ec = row0 + (ok[q] ? ee : hi - 1);
+      nb[q] = gld(sl.col, ec);
+      wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
     }
 #pragma unroll
-    for (int q = 0; q < B; ++q) tt[q] = nb[q] >= 0 ? sl.lab[nb[q]] : -1;
+    for (int q = 0; q < B; ++q) tt[q] = gld(sl.lab, nb[q]);
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int32_t tq = tt[q];
-      if (nb[q] < 0) continue;
+      if (!ok[q]) continue;
       if (tq == own) {
         my_own += wt[q];
         continue;
@@ -332,14 +352,15 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
   int32_t* keys = lds + w * TS;
   int32_t* vals = lds + 4 * TS + w * TS;
   const int lane = (int)lane_id();
-  for (uint32_t i = bid * 4 + w; i < cnt; i += nblk * 4) {
-    const int64_t u = list[i];
-    const uint64_t x = info[i];
+  for (uint32_t i = __builtin_amdgcn_readfirstlane(bid * 4 + w); i < cnt; i += nblk * 4) {
+    const int64_t u = gld(list, i);
+    const uint64_t x = gld(info, i);
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int64_t e0 = info_e0(x);
     const int d = info_d(x);
-    const int32_t own = sl.lab[v];
+    const int32_t own = gld(sl.lab, v);
+    const int64_t cv = gld(sl.nw, v);
     const uint32_t tsz = table_size(d, sl.nlabels);
     for (uint32_t j = lane; j < tsz; j += kWave) {
       keys[j] = -1;
@@ -352,7 +373,6 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
     for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
     const bool boundary = __ballot(foreign) != 0;
     wave_sync();
-    const int64_t cv = sl.nw[v];
     const bool own_ok = own_allowed(sl, own);
     uint64_t best = 0;
     for (uint32_t j = lane; j < tsz; j += kWave) {
@@ -370,8 +390,8 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
         const uint64_t ok = pack_key(my_own, own);
         best = best > ok ? best : ok;
       }
-      sl.desire[v] = best ? key_label(best) : own;
-      if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+      gst(sl.desire, v, best ? key_label(best) : own);
+      if (sl.mode == MODE_REFINE && boundary) gst(sl.flag_next, v, (uint8_t)1);
     }
     wave_sync();
   }
@@ -413,13 +433,14 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
   __shared__ int64_t redi[8];
   __shared__ int redo[8];
   for (uint32_t i = bid; i < cnt; i += nblk) {
-    const int64_t u = list[i];
-    const uint64_t x = info[i];
+    const int64_t u = gld(list, i);
+    const uint64_t x = gld(info, i);
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int64_t e0 = info_e0(x);
     const int d = info_d(x);
-    const int32_t own = sl.lab[v];
+    const int32_t own = gld(sl.lab, v);
+    const int64_t cv = gld(sl.nw, v);
     const uint32_t tsz = table_size(d, sl.nlabels);
     const uint32_t mask = tsz - 1;
     for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
@@ -432,7 +453,6 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     table_fill<4>(sl, e0, threadIdx.x, d, NT, own, keys, vals, mask, my_own, foreign);
     const int64_t conn_own = block_reduce(my_own, redi, OpAdd64());
     const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
-    const int64_t cv = sl.nw[v];
     const bool own_ok = own_allowed(sl, own);
     uint64_t best = 0;
     for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
@@ -447,8 +467,8 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
         const uint64_t ok = pack_key(conn_own, own);
         best = best > ok ? best : ok;
       }
-      sl.desire[v] = best ? key_label(best) : own;
-      if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+      gst(sl.desire, v, best ? key_label(best) : own);
+      if (sl.mode == MODE_REFINE && boundary) gst(sl.flag_next, v, (uint8_t)1);
     }
     __syncthreads();
   }
@@ -609,11 +629,11 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
     const int64_t u = list[i];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t row0 = sl.rp[v];
-    const int64_t d = sl.rp[v + 1] - row0;
+    const int64_t row0 = gld(sl.rp, v);
+    const int64_t d = gld(sl.rp, v + 1) - row0;
     const int64_t e_begin = (int64_t)(c - chunk_off[i]) * kHubChunk;
     const int64_t e_end = e_begin + kHubChunk < d ? e_begin + kHubChunk : d;
-    const int32_t own = sl.lab[v];
+    const int32_t own = gld(sl.lab, v);
     for (int j = threadIdx.x; j < kHubLds; j += blockDim.x) {
       keys[j] = -1;
       vals[j] = 0;
@@ -626,7 +646,7 @@ __global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S
     const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
     if (threadIdx.x == 0) {
       if (co) atomicAdd((unsigned long long*)&hub_own[i], (unsigned long long)co);
-      if (sl.mode == MODE_REFINE && boundary) sl.flag_next[v] = 1;
+      if (sl.mode == MODE_REFINE && boundary) gst(sl.flag_next, v, (uint8_t)1);
     }
     const uint32_t gmask = table_size(d, sl.nlabels) - 1;
     int32_t* gk = gkeys + tab_off[i];
@@ -662,10 +682,10 @@ __global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S,
     const int64_t u = list[i];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t d = sl.rp[v + 1] - sl.rp[v];
-    const int32_t own = sl.lab[v];
+    const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
+    const int32_t own = gld(sl.lab, v);
     const int64_t conn_own = hub_own[i];
-    const int64_t cv = sl.nw[v];
+    const int64_t cv = gld(sl.nw, v);
     const bool own_ok = own_allowed(sl, own);
     const uint32_t tsz = table_size(d, sl.nlabels);
     const uint32_t j0 = (c - slice_off[i]) * kHubSlice;
@@ -702,13 +722,13 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
     const int64_t u = list[i];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int32_t own = sl.lab[v];
+    const int32_t own = gld(sl.lab, v);
     uint64_t best = hub_best[i];
     if (own_allowed(sl, own)) {
       const uint64_t ok = pack_key(hub_own[i], own);
       best = best > ok ? best : ok;
     }
-    sl.desire[v] = best ? key_label(best) : own;
+    gst(sl.desire, v, best ? key_label(best) : own);
     hub_own[i] = 0;
     hub_best[i] = 0;
   }
@@ -752,21 +772,35 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
       hv[j] = 0;
     }
     __syncthreads();
-    for (int it = 0; it < kAggNodes / 256; ++it) {
+    constexpr int IT = kAggNodes / 256;
+    int64_t u[IT], v[IT], cv[IT];
+    int sv[IT];
+    int32_t t[IT], own[IT];
+    bool ok[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
       const int64_t i = base + it * 256 + threadIdx.x;
-      if (i >= N) continue;
-      const int64_t u = rated[i];
-      const int s = SLOT(u);
-      const DevSlot& sl = S[s];
-      const int64_t v = u - sl.nbase;
-      const int32_t t = sl.desire[v];
-      if (t != sl.lab[v]) agg_add(hk, hv, kIncTable - 1, ((unsigned long long)s << 32) | (uint32_t)t, sl.nw[v]);
+      ok[it] = i < N;
+      u[it] = gld(rated, ok[it] ? i : N - 1);
     }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      sv[it] = SLOT(u[it]);
+      const DevSlot& sl = S[sv[it]];
+      v[it] = u[it] - sl.nbase;
+      t[it] = gld(sl.desire, v[it]);
+      own[it] = gld(sl.lab, v[it]);
+      cv[it] = gld(sl.nw, v[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it)
+      if (ok[it] && t[it] != own[it])
+        agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it]);
     __syncthreads();
     for (int j = threadIdx.x; j < kIncTable; j += blockDim.x) {
       const unsigned long long k = hk[j];
       if (k == kEmpty || hv[j] == 0) continue;
-      atomicAdd((unsigned long long*)&S[k >> 32].inc[(uint32_t)k], (unsigned long long)hv[j]);
+      gadd64(S[k >> 32].inc, (uint32_t)k, hv[j]);
     }
     __syncthreads();
   }
@@ -789,21 +823,20 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
     const int64_t i = base + threadIdx.x;
     bool contended = false;
     uint64_t key = 0;
-    if (i < N) {
-      const int64_t u = rated[i];
-      const int s = SLOT(u);
-      const DevSlot& sl = S[s];
-      {
-        const int64_t v = u - sl.nbase;
-        const int32_t t = sl.desire[v];
-        if (t != sl.lab[v]) {
-          if (sl.W[t] + sl.inc[t] <= sl.cap) {
-            sl.adm[v] = 1;
-          } else {
-            sl.adm[v] = 0;
-            contended = true;
-            key = ((uint64_t)(sl.lbase + t) << node_bits) | (uint64_t)u;
-          }
+    {
+      const bool ok = i < N;
+      const int64_t u = gld(rated, ok ? i : N - 1);
+      const DevSlot& sl = S[SLOT(u)];
+      const int64_t v = u - sl.nbase;
+      const int32_t t = gld(sl.desire, v);
+      const int32_t own = gld(sl.lab, v);
+      if (ok && t != own) {
+        if (gld(sl.W, t) + gld(sl.inc, t) <= sl.cap) {
+          gst(sl.adm, v, (uint8_t)1);
+        } else {
+          gst(sl.adm, v, (uint8_t)0);
+          contended = true;
+          key = ((uint64_t)(sl.lbase + t) << node_bits) | (uint64_t)u;
         }
       }
     }
@@ -953,20 +986,35 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
     }
     if (threadIdx.x == 0) s_mcnt = 0;
     __syncthreads();
-    for (int it = 0; it < kAggNodes / 256; ++it) {
+    constexpr int IT = kAggNodes / 256;
+    int64_t uu[IT];
+    bool ok[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
       const int64_t i = base + it * 256 + threadIdx.x;
-      if (i >= N) continue;
-      const int64_t u = rated[i];
+      ok[it] = i < N;
+      uu[it] = gld(rated, ok[it] ? i : N - 1);
+    }
+    int32_t tt[IT], oo[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const DevSlot& sl = S[SLOT(uu[it])];
+      tt[it] = gld(sl.desire, uu[it] - sl.nbase);
+      oo[it] = gld(sl.lab, uu[it] - sl.nbase);
+    }
+    for (int it = 0; it < IT; ++it) {
+      if (!ok[it]) continue;
+      const int64_t u = uu[it];
       const int s = SLOT(u);
       const DevSlot& sl = S[s];
       const int64_t v = u - sl.nbase;
-      const int32_t t = sl.desire[v];
-      const int32_t own = sl.lab[v];
+      const int32_t t = tt[it];
+      const int32_t own = oo[it];
       if (t == own) continue;
-      sl.inc[t] = 0;
-      if (sl.adm[v]) {
-        const int64_t cv = sl.nw[v];
-        sl.lab[v] = t;
+      gst(sl.inc, t, (int64_t)0);
+      if (gld(sl.adm, v)) {
+        const int64_t cv = gld(sl.nw, v);
+        gst(sl.lab, v, t);
         const unsigned long long ks = (unsigned long long)s << 32;
         if (cv) {
           agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
@@ -975,7 +1023,7 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
         agg_add(hk, hv, kApplyTable - 1, ks | kCountLabel, 1);
         if (sl.mode == MODE_REFINE) s_mov[atomicAdd(&s_mcnt, 1u)] = (int32_t)u;
       } else {
-        sl.desire[v] = own;
+        gst(sl.desire, v, own);
       }
     }
     __syncthreads();
@@ -984,8 +1032,8 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       if (k == kEmpty || hv[j] == 0) continue;
       const DevSlot& sl = S[k >> 32];
       const uint32_t lab = (uint32_t)k;
-      if (lab == kCountLabel) atomicAdd((unsigned long long*)&sl.ctr[CTR_MOVED], (unsigned long long)hv[j]);
-      else atomicAdd((unsigned long long*)&sl.W[lab], (unsigned long long)hv[j]);
+      if (lab == kCountLabel) gadd64(sl.ctr, CTR_MOVED, hv[j]);
+      else gadd64(sl.W, lab, hv[j]);
     }
     if (threadIdx.x == 0) s_mbase = s_mcnt ? atomicAdd(mcnt, s_mcnt) : 0;
     __syncthreads();
@@ -1018,11 +1066,11 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
       u = movers[i];
       sl = &S[SLOT(u)];
       const int64_t v = u - sl->nbase;
-      e0 = sl->rp[v];
-      d = sl->rp[v + 1] - e0;
+      e0 = gld(sl->rp, v);
+      d = gld(sl->rp, v + 1) - e0;
     }
     if (d <= kWave)
-      for (int64_t e = e0; e < e0 + d; ++e) sl->flag_next[sl->col[e]] = 1;
+      for (int64_t e = e0; e < e0 + d; ++e) gst(sl->flag_next, gld(sl->col, e), (uint8_t)1);
     if (d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = u;
     uint64_t mid = __ballot(d > kWave && d <= kMarkBig);
     while (mid) {
@@ -1031,7 +1079,7 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
       const int64_t be0 = __shfl(e0, l), bd = __shfl(d, l);
       const int32_t bu = __shfl(u, l);
       const DevSlot& bs = S[SLOT(bu)];
-      for (int64_t e = be0 + lane_id(); e < be0 + bd; e += kWave) bs.flag_next[bs.col[e]] = 1;
+      for (int64_t e = be0 + lane_id(); e < be0 + bd; e += kWave) gst(bs.flag_next, gld(bs.col, e), (uint8_t)1);
     }
   }
 }
@@ -1049,7 +1097,7 @@ __global__ void __launch_bounds__(256) k_mark_big(const DevSlot* __restrict__ S,
     const int64_t v = u - sl.nbase;
     const int64_t e0 = sl.rp[v], e1 = sl.rp[v + 1];
     for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride)
-      sl.flag_next[sl.col[e]] = 1;
+      gst(sl.flag_next, gld(sl.col, e), (uint8_t)1);
   }
 }
 

@@ -103,6 +103,7 @@ struct sclap_server {
 
 void sclap_server::run() {
   (void)hipSetDevice(device);
+  CtxScope scope(&ctx);
   for (;;) {
     std::vector<ServedJob*> admit;
     {
