@@ -29,8 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-RATE_KERNELS = ["k_rate_small (degree 1-128)", "k_rate_mid (degree 129-1024)", "k_rate_large (degree 1025-4096)",
-                "hub path (4 kernels, degree > 4096)"]
+RATE_KERNELS = ["k_rate_tiny (degree 1-32)", "k_rate_small (degree 33-128)", "k_rate_mid (degree 129-1024)",
+                "k_rate_large (degree 1025-4096)", "hub path (4 kernels, degree > 4096)"]
 
 
 def log(msg: str) -> None:
@@ -81,14 +81,14 @@ def roofline(prof: dict, workload: str) -> tuple[dict, list]:
     (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge visit,
     32 B per rated node) / mean launch duration from HIP events."""
     launches = max(prof["kernel_launches"], 1)
-    dom = max(range(3), key=lambda b: prof["kernels"][b]["ms"])
+    dom = max(range(4), key=lambda b: prof["kernels"][b]["ms"])
     kd = prof["kernels"][dom]
     avg_ms = kd["ms"] / launches
     bpl = kd["bytes"] / launches
     achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     per_kernel = [{"kernel": RATE_KERNELS[b], "ms_per_round": prof["kernels"][b]["ms"] / launches,
                    "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
-                   if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(4)]
+                   if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(5)]
     rl = {"bound": "hbm", "kernel": RATE_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(RATE_KERNELS[dom], workload),
           "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": launches}

@@ -55,6 +55,7 @@ struct DevSlot {
   uint8_t* flag_next;     // refine: rated set of the next round
   int64_t* ctr;           // device counters of this slot, see CTR_*
   int64_t n;
+  int64_t m;              // stored entries of the graph
   int64_t nbase;
   int64_t nlabels;
   int64_t lbase;

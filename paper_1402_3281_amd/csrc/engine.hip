@@ -341,6 +341,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.flag_next = j->fnext;
     d.ctr = ctr + (size_t)s * CTR_N;
     d.n = L.n;
+    d.m = L.m;
     d.nbase = N;
     d.nlabels = j->nlabels;
     d.lbase = Lt;
@@ -433,7 +434,10 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   hub.own = (int64_t*)c->hub_own.p;
   hub.overflow = small + 10;
   hub.tab_cap = c->hub_cap;
-  SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hub_need > 0, st, c->profile ? c->ev : nullptr));
+  bool unit_weights = true;
+  for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
+  SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hub_need > 0, unit_weights, st,
+                        c->profile ? c->ev : nullptr));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
   SCLAP_TRY(launch_incoming_decide(S, ns, N, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
@@ -480,7 +484,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     const unsigned long long* hv = (const unsigned long long*)((const char*)hm + 128);
     bool weighted = false;
     for (int s = 0; s < ns; ++s) weighted = weighted || c->pin_slots[s].ew != nullptr;
-    const int group_of[kBins] = {0, 0, 0, 0, 0, 1, 1, 2, 3};
+    const int group_of[kBins] = {0, 0, 0, 1, 1, 2, 2, 3, 4};
     for (int g = 0; g < kRateGroups; ++g) {
       float ms = 0;
       SCLAP_HIP(hipEventElapsedTime(&ms, c->ev[g], c->ev[g + 1]));

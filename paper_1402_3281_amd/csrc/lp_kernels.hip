@@ -19,6 +19,8 @@
 // first combined per workgroup in LDS.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "lp.h"
 
@@ -35,7 +37,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ int bin_of(int64_t d) {
+// Graphs with fewer stored entries than this rate their nodes of degree <= 32
+// in the 64-lane bin: the one-thread-per-node bins read a window of up to 32
+// entries from the row start.
+constexpr int64_t kThreadMinM = 32;
+
+__device__ __forceinline__ int bin_of(int64_t d, int64_t m) {
+  if (m < kThreadMinM && d <= 64) return 3;
   return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : d <= 512 ? 5 : d <= 1024 ? 6
        : d <= kBinBlock ? 7 : 8;
 }
@@ -107,7 +115,7 @@ __global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int 
         e0 = gld(sl.rp, v);
         d = gld(sl.rp, v + 1) - e0;
         take = d > 0;
-        b = bin_of(d);
+        b = bin_of(d, sl.m);
       }
       // the rated set of the next round is rebuilt from scratch
       if (sl.round > 0 && sl.mode == MODE_REFINE) gst(sl.flag_next, v, (uint8_t)0);
@@ -284,6 +292,161 @@ __device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, i
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Rating, one thread per node (degree <= D): the node's neighbour labels are
+// sorted in registers by a bitonic network, so that equal labels form runs
+// whose weight sums are the connections; the best run that beats the own
+// label and is eligible wins.  Nothing crosses lanes.
+// ---------------------------------------------------------------------------
+constexpr int32_t kNoLabel = 0x7FFFFFFF;  // sorts after every label
+// Word 3 of a raw 32-bit buffer resource on gfx9-family GPUs (data format 32).
+constexpr int kBufferConfig = 0x00020000;
+
+template <int D, bool WEIGHTED>
+__device__ __forceinline__ void sort_labels(int32_t (&t)[D], int32_t (&w)[D]) {
+#pragma unroll
+  for (int k = 2; k <= D; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const int32_t a = t[i], b = t[l];
+          if (WEIGHTED) {
+            const bool sw = up ? a > b : a < b;
+            const int32_t wa = w[i], wb = w[l];
+            t[i] = sw ? b : a;
+            t[l] = sw ? a : b;
+            w[i] = sw ? wb : wa;
+            w[l] = sw ? wa : wb;
+          } else {
+            t[i] = up ? min(a, b) : max(a, b);
+            t[l] = up ? max(a, b) : min(a, b);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Largest candidate key below `limit` among the runs of the sorted labels
+// that beat the own label (0 if none); branch-free over the unrolled runs.
+template <int D, bool WEIGHTED>
+__device__ __forceinline__ uint64_t best_run(const int32_t (&t)[D], const int32_t (&w)[D], bool own_ok,
+                                             int64_t conn_own, int32_t own, uint64_t limit) {
+  using Acc = typename std::conditional<WEIGHTED, int64_t, int32_t>::type;
+  uint64_t best = 0;
+  Acc acc = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    acc += WEIGHTED ? (Acc)w[q] : (Acc)1;
+    const int32_t tq = t[q];
+    const bool end = q == D - 1 || t[q + 1 < D ? q + 1 : q] != tq;
+    const bool beats = !own_ok || (int64_t)acc > conn_own || ((int64_t)acc == conn_own && tq < own);
+    const uint64_t k = pack_key((int64_t)acc, tq);
+    const bool take = end && tq != kNoLabel && beats && k < limit && k > best;
+    best = take ? k : best;
+    acc = end ? (Acc)0 : acc;
+  }
+  return best;
+}
+
+template <int D, bool ONE, bool WEIGHTED>
+__device__ __forceinline__ void rate_thread_body(const DevSlot* __restrict__ S, int ns,
+                                                 const int32_t* __restrict__ list, const uint64_t* __restrict__ info,
+                                                 uint32_t cnt, uint32_t bid, uint32_t nblk) {
+  for (uint32_t base = bid * blockDim.x; base < cnt; base += nblk * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const bool valid = i < cnt;
+    const uint32_t ic = valid ? i : cnt - 1;
+    const int64_t u = gld(list, ic);
+    const uint64_t x = gld(info, ic);
+    const int64_t e0 = info_e0(x);
+    const int d = info_d(x);
+    const DevSlot& sl = S[SLOT(u)];
+    const int64_t v = u - sl.nbase;
+    const int32_t own = gld(sl.lab, v);
+    const int64_t cv = gld(sl.nw, v);
+    // A window of D consecutive entries holding the row, so that every load
+    // has the same base and a constant offset: it starts at the row unless
+    // the row is among the last D entries of the graph (then it ends there;
+    // graphs with fewer than kThreadMinM entries are binned elsewhere).
+    int32_t t[D], w[D];
+    const int64_t eb = e0 + D <= sl.m ? e0 : sl.m - D;
+    const int sh = (int)(e0 - eb);
+    {
+      const int32_t* cb = sl.col + eb;
+      const int32_t* wb = WEIGHTED && sl.ew ? sl.ew + eb : nullptr;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        t[q] = gld(cb, q);
+        w[q] = wb ? gld(wb, q) : 1;
+      }
+    }
+    if (ONE && sl.n < ((int64_t)1 << 30)) {
+      // one slot: the label gathers go through a buffer resource (scalar
+      // base, 32-bit offsets, range-checked by the hardware)
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)sl.lab, (short)0, (int)(sl.n * 4), kBufferConfig);
+#pragma unroll
+      for (int q = 0; q < D; ++q) t[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, t[q] * 4, 0, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < D; ++q) t[q] = gld(sl.lab, t[q]);
+    }
+    // own connection, boundary flag, and the labels that may be chosen
+    // (direction rule: odd rounds only smaller labels, even rounds larger)
+    // as the interval [lo, hi] of labels that may be chosen
+    const bool down = sl.dir_rule && (sl.round & 1), up = sl.dir_rule && !(sl.round & 1);
+    const int32_t lo = up ? own + 1 : INT32_MIN, hi = down ? own - 1 : INT32_MAX;
+    int64_t conn_own = 0;
+    bool foreign = false;
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const bool in = q >= sh && q < sh + d;
+      const int32_t tq = t[q];
+      const bool mine = in && tq == own;
+      conn_own += mine ? (WEIGHTED ? (int64_t)w[q] : (int64_t)1) : (int64_t)0;
+      const bool f = in && tq != own;
+      foreign = foreign || f;
+      t[q] = (f && tq >= lo && tq <= hi) ? tq : kNoLabel;
+      if (WEIGHTED) w[q] = in ? w[q] : 0;
+    }
+    sort_labels<D, WEIGHTED>(t, w);
+    const bool own_ok = own_allowed(sl, own);
+    uint64_t limit = ~0ull, key = 0;
+    for (;;) {
+      const uint64_t k = best_run<D, WEIGHTED>(t, w, own_ok, conn_own, own, limit);
+      if (!k) break;
+      if (gld(sl.W, key_label(k)) + cv <= sl.cap) {
+        key = k;
+        break;
+      }
+      limit = k;  // ineligible: look for the next best run
+    }
+    if (valid) {
+      if (own_ok) {
+        const uint64_t ok = pack_key(conn_own, own);
+        key = key > ok ? key : ok;
+      }
+      gst(sl.desire, v, key ? key_label(key) : own);
+      if (sl.mode == MODE_REFINE && foreign) gst(sl.flag_next, v, (uint8_t)1);
+    }
+  }
+}
+
+// Degree <= D: one thread per node on unit-weight levels, D lanes per node
+// (rate_group_body) on weighted ones.
+template <int D, bool ONE>
+__device__ __forceinline__ void rate_upto(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
+                                          const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
+                                          uint32_t nblk, int unit_weights) {
+  if (unit_weights) rate_thread_body<D, ONE, false>(S, ns, list, info, cnt, bid, nblk);
+  else rate_group_body<D, ONE>(S, ns, list, info, cnt, bid, nblk);
 }
 
 // Insert (t, w) into an open-addressing table (keys -1 = empty).
@@ -478,22 +641,39 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
 // Fused launches: blocks [b * nblk, (b + 1) * nblk) serve bin `first + b`.
 // ---------------------------------------------------------------------------
 template <bool ONE>
+__global__ void __launch_bounds__(256) k_rate_tiny(const DevSlot* __restrict__ S, int ns,
+                                                   const int32_t* __restrict__ bins,
+                                                   const uint64_t* __restrict__ binfo, int64_t bin_cap,
+                                                   const uint32_t* __restrict__ bin_cnt, uint32_t nblk,
+                                                   int unit_weights) {
+  const uint32_t b = blockIdx.x / nblk, bid = blockIdx.x % nblk;
+  const int32_t* list = bins + b * bin_cap;
+  const uint64_t* info = binfo + b * bin_cap;
+  const uint32_t cnt = bin_cnt[b];
+  if (b == 0) rate_upto<8, ONE>(S, ns, list, info, cnt, bid, nblk, unit_weights);
+  else rate_upto<16, ONE>(S, ns, list, info, cnt, bid, nblk, unit_weights);
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_rate_b32(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ list,
+                                                  const uint64_t* __restrict__ info,
+                                                  const uint32_t* __restrict__ cnt_ptr, int unit_weights) {
+  rate_upto<32, ONE>(S, ns, list, info, *cnt_ptr, blockIdx.x, gridDim.x, unit_weights);
+}
+
+template <bool ONE>
 __global__ void __launch_bounds__(256) k_rate_small(const DevSlot* __restrict__ S, int ns,
                                                     const int32_t* __restrict__ bins,
                                                     const uint64_t* __restrict__ binfo, int64_t bin_cap,
                                                     const uint32_t* __restrict__ bin_cnt, uint32_t nblk) {
   __shared__ int32_t lds[8 * 256];
-  const uint32_t b = blockIdx.x / nblk, bid = blockIdx.x % nblk;
+  const uint32_t b = 3 + blockIdx.x / nblk, bid = blockIdx.x % nblk;
   const int32_t* list = bins + b * bin_cap;
   const uint64_t* info = binfo + b * bin_cap;
   const uint32_t cnt = bin_cnt[b];
-  switch (b) {
-    case 0: rate_group_body<8, ONE>(S, ns, list, info, cnt, bid, nblk); break;
-    case 1: rate_group_body<16, ONE>(S, ns, list, info, cnt, bid, nblk); break;
-    case 2: rate_group_body<32, ONE>(S, ns, list, info, cnt, bid, nblk); break;
-    case 3: rate_group_body<64, ONE>(S, ns, list, info, cnt, bid, nblk); break;
-    default: rate_wave_body<256, ONE>(S, ns, list, info, cnt, bid, nblk, lds); break;
-  }
+  if (b == 3) rate_group_body<64, ONE>(S, ns, list, info, cnt, bid, nblk);
+  else rate_wave_body<256, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
 }
 
 template <bool ONE>
@@ -1126,19 +1306,23 @@ int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, uint64_t* bin
 }
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
-                const uint32_t* bin_cnt, const RateHubScratch& hub, int64_t n_hint, bool hubs, hipStream_t st,
-                hipEvent_t* evs) {
+                const uint32_t* bin_cnt, const RateHubScratch& hub, int64_t n_hint, bool hubs, bool unit_weights,
+                hipStream_t st, hipEvent_t* evs) {
   const unsigned G = grid_for(n_hint, 64, 2048);
   auto rec = [&](int i) {
     if (evs) (void)hipEventRecord(evs[i], st);
   };
   rec(0);
-  LAUNCH(k_rate_small, 5 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
+  const int uw = unit_weights ? 1 : 0;
+  LAUNCH(k_rate_tiny, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G, uw);
+  LAUNCH(k_rate_b32, G, 256, S, ns, bins + 2 * bin_cap, binfo + 2 * bin_cap, bin_cnt + 2, uw);
   rec(1);
-  LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
+  LAUNCH(k_rate_small, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(2);
-  LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
+  LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(3);
+  LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
+  rec(4);
   if (hubs) {
     const int32_t* hb = bins + 8 * bin_cap;
     const uint32_t* hc = bin_cnt + 8;
@@ -1150,7 +1334,7 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
            hub.gvals, hub.own, hub.best, hub.overflow);
     LAUNCH(k_hub_final, 64, 256, S, ns, hb, hc, hub.own, hub.best, hub.overflow);
   }
-  rec(4);
+  rec(5);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
