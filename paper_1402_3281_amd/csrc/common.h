@@ -80,6 +80,17 @@ constexpr int kBins = 9;
 constexpr int64_t kBinBlock = 4096;
 
 constexpr int kHubChunk = 4096;      // entries per workgroup in the multi-workgroup path
+constexpr int kHubPartLabels = 2048; // target distinct labels per label part of a hub
+constexpr int kHubMaxParts = 2048;
+
+// Label parts of a hub of degree d: a power of two, about kHubPartLabels
+// distinct labels each.
+__host__ __device__ __forceinline__ uint32_t hub_parts(int64_t d, int64_t nlabels) {
+  const int64_t distinct = d < nlabels ? d : nlabels;
+  uint32_t P = 1;
+  while (P < (uint32_t)kHubMaxParts && (int64_t)P * kHubPartLabels < distinct) P <<= 1;
+  return P;
+}
 
 // Loads and stores through the global address space: global_load /
 // global_store with an SGPR base, instead of the flat instructions that

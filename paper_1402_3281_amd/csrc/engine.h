@@ -33,8 +33,11 @@ struct Level {
   int32_t* coarse_of = nullptr;  // n: map to the next coarser level
   int rows_sorted = 0;
   int64_t n_active = 0;          // nodes of degree > 0
-  int64_t hub_c = 0;             // global hub table entries when clustering this level
-  int64_t hub_r = 0;             // ... when refining it
+  // sizes of the hub rating path on this level (degree > kBinBlock)
+  int64_t hubs = 0;
+  int64_t hub_stage = 0;         // staged pair slots
+  int64_t hub_parts_c = 0, hub_mat_c = 0;  // label parts, matrix entries: clustering
+  int64_t hub_parts_r = 0, hub_mat_r = 0;  // ... refinement
 };
 
 enum Stage : int { ST_COARSEN, ST_CONTRACT, ST_IP, ST_REFINE, ST_FINISH, ST_DONE, ST_ERROR };
@@ -89,11 +92,12 @@ struct Ctx {
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
+  Scratch hub_P, hub_ptot, hub_pbase, hub_mat;
   // jobs and levels whose nodes the current bins hold (clustering rounds only)
   std::vector<std::pair<const void*, int>> bin_sig;
   bool bin_sig_valid = false;
   int64_t bin_cap_used = 0;
-  int64_t hub_cap = 0;             // entries of the global hub table (kept -1/0)
+  int64_t hub_parts_cap = 0;       // part counters allocated (kept 0 between rounds)
   // pinned host staging
   int64_t* pin = nullptr;
   size_t pin_bytes = 0;

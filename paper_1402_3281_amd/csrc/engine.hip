@@ -166,7 +166,8 @@ void ctx_release(Ctx* c, hipStream_t st) {
   Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
-                    &c->hub_maps, &c->binmeta};
+                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_pbase, &c->hub_mat};
+  c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
   (void)hipStreamSynchronize(st);
   if (c->pin) (void)hipHostFree(c->pin);
@@ -210,19 +211,19 @@ int job_set_input(Ctx* c, Job* j, const sclap_csr* g, hipStream_t st) {
 int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipStream_t st) {
   SCLAP_TRY(c->small.ensure(256, st));
   unsigned long long* d = (unsigned long long*)c->small.p;
-  SCLAP_TRY(graph_totals(L->rp, L->nw, L->n, L->n, d, st));
-  SCLAP_TRY(ctx_ensure_pin(c, 64));
-  SCLAP_HIP(hipMemcpyAsync(c->pin, d, 5 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SCLAP_TRY(graph_totals(L->rp, L->nw, L->n, std::max<int64_t>(j->k, 1), d, st));
+  SCLAP_TRY(ctx_ensure_pin(c, 128));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, d, kGraphTotals * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   if (sum_w) *sum_w = c->pin[0];
   if (max_w) *max_w = c->pin[1];
   L->n_active = c->pin[2];
-  L->hub_c = c->pin[3];
-  const int64_t hubs = c->pin[4];
-  int64_t t = 64;
-  const int64_t kk = std::max<int64_t>(j->k, 1);
-  while (t < 2 * kk) t <<= 1;
-  L->hub_r = hubs * t;
+  L->hub_stage = c->pin[3];
+  L->hubs = c->pin[4];
+  L->hub_parts_c = c->pin[5];
+  L->hub_mat_c = c->pin[6];
+  L->hub_parts_r = c->pin[7];
+  L->hub_mat_r = c->pin[8];
   return SCLAP_OK;
 }
 
@@ -320,7 +321,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   const int ns = (int)jobs.size();
   if (ns == 0) return SCLAP_OK;
   SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
-  int64_t N = 0, Lt = 0, hub_need = 0;
+  int64_t N = 0, Lt = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
   for (int s = 0; s < ns; ++s) {
@@ -353,18 +354,34 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.use_flags = refine && j->round > 1;
     N += L.n;
     Lt += j->nlabels;
-    hub_need += refine ? L.hub_r : L.hub_c;
+    hub_stage += L.hub_stage;
+    hub_parts += refine ? L.hub_parts_r : L.hub_parts_c;
+    hub_mat += refine ? L.hub_mat_r : L.hub_mat_c;
   }
   if (N >= ((int64_t)1 << 31) || Lt >= ((int64_t)1 << 32))
     return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
   const size_t Nz = (size_t)std::max<int64_t>(N, 1);
   SCLAP_TRY(c->bins.ensure(kBins * Nz * sizeof(int32_t), st));
   SCLAP_TRY(c->binfo.ensure(kBins * Nz * sizeof(uint64_t), st));
-  SCLAP_TRY(c->hub_chunk.ensure((Nz + 1) * sizeof(uint32_t), st));
-  SCLAP_TRY(c->hub_tab.ensure(Nz * sizeof(int64_t), st));
-  SCLAP_TRY(c->hub_slice.ensure((Nz + 1) * sizeof(uint32_t), st));
-  const size_t map_cap = Nz + (size_t)std::max<int64_t>(hub_need, 0) / 4096 + 64;
-  SCLAP_TRY(c->hub_maps.ensure(2 * map_cap * sizeof(uint32_t), st));
+  // hub rating path (see HubLayout): per hub, per chunk and per label part
+  const bool hubs = hub_stage > 0;
+  const size_t map_cap = (size_t)std::max<int64_t>(hub_stage / kHubChunk, hub_parts) + 64;
+  if (hubs) {
+    SCLAP_TRY(c->hub_chunk.ensure((Nz + 1) * sizeof(uint32_t), st));
+    SCLAP_TRY(c->hub_slice.ensure((Nz + 1) * sizeof(uint32_t), st));
+    SCLAP_TRY(c->hub_tab.ensure((Nz + 1) * sizeof(int64_t), st));
+    SCLAP_TRY(c->hub_P.ensure(Nz * sizeof(uint32_t), st));
+    SCLAP_TRY(c->hub_maps.ensure(2 * map_cap * sizeof(uint32_t), st));
+    SCLAP_TRY(c->hub_mat.ensure((size_t)std::max<int64_t>(hub_mat, 1) * sizeof(uint32_t), st));
+    SCLAP_TRY(c->hub_gkeys.ensure((size_t)hub_stage * sizeof(int2), st));
+    SCLAP_TRY(c->hub_gvals.ensure((size_t)hub_stage * sizeof(int2), st));
+    SCLAP_TRY(c->hub_pbase.ensure((size_t)hub_parts * sizeof(int64_t), st));
+    if (c->hub_parts_cap < hub_parts) {
+      SCLAP_TRY(c->hub_ptot.ensure((size_t)hub_parts * sizeof(uint32_t), st));
+      c->hub_parts_cap = (int64_t)(c->hub_ptot.bytes / sizeof(uint32_t));
+      SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, c->hub_parts_cap, 0, st));
+    }
+  }
   if (c->hub_own.bytes < Nz * sizeof(int64_t)) {
     SCLAP_TRY(c->hub_own.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
@@ -377,22 +394,14 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   int32_t* rated = (int32_t*)c->movers.p;
   int32_t* movers = rated + Nz;
   int32_t* bigm = movers + Nz;
-  if (c->hub_cap < hub_need || !c->hub_gkeys.p) {
-    const int64_t cap = std::max<int64_t>(hub_need, 1024);
-    SCLAP_TRY(c->hub_gkeys.ensure((size_t)cap * 4, st));
-    SCLAP_TRY(c->hub_gvals.ensure((size_t)cap * 4, st));
-    c->hub_cap = (int64_t)std::min(c->hub_gkeys.bytes, c->hub_gvals.bytes) / 4;
-    SCLAP_TRY(fill_i32((int32_t*)c->hub_gkeys.p, c->hub_cap, -1, st));
-    SCLAP_TRY(fill_i32((int32_t*)c->hub_gvals.p, c->hub_cap, 0, st));
-  }
   SCLAP_TRY(c->ckeys.ensure(Nz * 8, st));
   SCLAP_TRY(c->slots_dev.ensure((size_t)ns * sizeof(DevSlot), st));
   DevSlot* S = (DevSlot*)c->slots_dev.p;
   SCLAP_HIP(hipMemcpyAsync(S, c->pin_slots, (size_t)ns * sizeof(DevSlot), hipMemcpyHostToDevice, st));
   // Per-round counters (zeroed together with the slot counters after them):
-  // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and slices,
-  // [13] refinement movers, [15] big movers, [16] contended set too large
-  // for the one-workgroup path.  The binning results live in c->binmeta:
+  // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and label
+  // parts, [13] refinement movers, [15] big movers, [16] contended set too
+  // large for the one-workgroup path, [24..25] hub pair pool cursor (u64).  The binning results live in c->binmeta:
   // u32 [0..8] bin counts, [14] rated; u64 at byte 128: visits per bin.
   // Clustering rounds of the same jobs on the same levels rate the same
   // nodes, so their bins are reused.
@@ -420,23 +429,32 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     c->bin_sig_valid = all_cluster;
     c->bin_cap_used = bin_cap;
   }
-  RateHubScratch hub;
-  hub.chunk_off = (uint32_t*)c->hub_chunk.p;
-  hub.tab_off = (int64_t*)c->hub_tab.p;
-  hub.totals = small + 11;
-  hub.slice_off = (uint32_t*)c->hub_slice.p;
-  hub.chunk_hub = (uint32_t*)c->hub_maps.p;
-  hub.slice_hub = hub.chunk_hub + map_cap;
-  hub.map_cap = (uint32_t)map_cap;
-  hub.best = (unsigned long long*)c->hub_best.p;
-  hub.gkeys = (int32_t*)c->hub_gkeys.p;
-  hub.gvals = (int32_t*)c->hub_gvals.p;
-  hub.own = (int64_t*)c->hub_own.p;
-  hub.overflow = small + 10;
-  hub.tab_cap = c->hub_cap;
+  HubLayout hub{};
+  if (hubs) {
+    hub.chunk_off = (uint32_t*)c->hub_chunk.p;
+    hub.part_off = (uint32_t*)c->hub_slice.p;
+    hub.mat_off = (int64_t*)c->hub_tab.p;
+    hub.hub_P = (uint32_t*)c->hub_P.p;
+    hub.chunk_hub = (uint32_t*)c->hub_maps.p;
+    hub.part_hub = hub.chunk_hub + map_cap;
+    hub.map_cap = (int64_t)map_cap;
+    hub.totals = small + 11;
+    hub.pool_cursor = (unsigned long long*)(small + 24);
+    hub.part_total = (uint32_t*)c->hub_ptot.p;
+    hub.part_base = (int64_t*)c->hub_pbase.p;
+    hub.parts_cap = hub_parts;
+    hub.mat = (uint32_t*)c->hub_mat.p;
+    hub.mat_cap = hub_mat;
+    hub.stage = (int2*)c->hub_gkeys.p;
+    hub.pool = (int2*)c->hub_gvals.p;
+    hub.stage_cap = hub_stage;
+    hub.own = (int64_t*)c->hub_own.p;
+    hub.best = (unsigned long long*)c->hub_best.p;
+    hub.overflow = small + 10;
+  }
   bool unit_weights = true;
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
-  SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hub_need > 0, unit_weights, st,
+  SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights, st,
                         c->profile ? c->ev : nullptr));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
@@ -450,7 +468,13 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   const uint32_t* hs = (const uint32_t*)c->pin;
-  if (hs[10]) return fail(SCLAP_EHIP, "hub rating table too small");
+  if (hs[10]) {
+    // a hub label part beyond its LDS table (or a layout beyond its sizes):
+    // the part counters may be left nonzero, so they are cleared
+    if (c->hub_parts_cap > 0) SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, c->hub_parts_cap, 0, st));
+    (void)hipStreamSynchronize(st);
+    return fail(SCLAP_EHIP, "hub rating: a label part exceeds its table");
+  }
   if (hs[16]) {
     // contended set too large for one workgroup: device-wide sort and scan,
     // then the apply step that was skipped

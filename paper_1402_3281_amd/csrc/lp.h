@@ -5,20 +5,29 @@
 
 namespace sclap {
 
-struct RateHubScratch {
-  uint32_t* chunk_off;  // bin capacity + 1
-  uint32_t* slice_off;  // bin capacity + 1
-  uint32_t* chunk_hub;  // map_cap: hub of each chunk
-  uint32_t* slice_hub;  // map_cap: hub of each table slice
-  uint32_t map_cap;
-  unsigned long long* best;  // bin capacity, kept at 0 between rounds
-  int64_t* tab_off;     // bin capacity
-  uint32_t* totals;     // 2: chunks, slices
-  int32_t* gkeys;       // tab_cap, kept at -1 between rounds
-  int32_t* gvals;       // tab_cap, kept at 0 between rounds
-  int64_t* own;         // bin capacity, kept at 0 between rounds
-  uint32_t* overflow;   // 1
-  int64_t tab_cap;
+// Device layout of the hub rating path (degree > kBinBlock); see
+// lp_kernels.hip.  Arrays marked "kept 0" are zero between rounds.
+struct HubLayout {
+  uint32_t* chunk_off;    // hubs + 1: first chunk of every hub
+  uint32_t* part_off;     // hubs + 1: first label part of every hub
+  int64_t* mat_off;       // hubs + 1: first entry of every hub's chunk x part matrix
+  uint32_t* hub_P;        // hubs: label parts of every hub
+  uint32_t* chunk_hub;    // map_cap: hub of every chunk
+  uint32_t* part_hub;     // map_cap: hub of every part
+  int64_t map_cap;
+  uint32_t* totals;       // 2: chunks, parts
+  unsigned long long* pool_cursor;  // 1
+  uint32_t* part_total;   // parts_cap: pairs of every part (kept 0)
+  int64_t* part_base;     // parts_cap: segment of every part in the pool
+  int64_t parts_cap;
+  uint32_t* mat;          // mat_cap: per chunk, staged part offsets (P + 1) and reservations (P)
+  int64_t mat_cap;
+  int2* stage;            // stage_cap: (label, weight sum) pairs, kHubChunk per chunk
+  int2* pool;             // stage_cap: the same pairs grouped by part
+  int64_t stage_cap;
+  int64_t* own;           // hubs: own-label connection (kept 0)
+  unsigned long long* best;  // hubs: best foreign candidate key (kept 0)
+  uint32_t* overflow;     // 1
 };
 
 // Bins the rated nodes; also lists them all in `rated` (rated_cnt).
@@ -30,7 +39,7 @@ int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, uint64_t* bin
 // 8 (hub kernels, only if `hubs`).  evs (may be NULL): 5 events around them.
 constexpr int kRateGroups = 5;
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
-                const uint32_t* bin_cnt, const RateHubScratch& hub, int64_t n_hint, bool hubs, bool unit_weights,
+                const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
                 hipStream_t st, hipEvent_t* evs);
 // Small contended sets resolved on the device; sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,

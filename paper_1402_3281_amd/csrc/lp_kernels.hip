@@ -700,190 +700,358 @@ __global__ void __launch_bounds__(512) k_rate_large(const DevSlot* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Rating of hubs (degree > kBinBlock): chunks of kHubChunk entries per
-// workgroup, aggregated in LDS and flushed into a per-hub global table.
+// Rating of hubs (degree > kBinBlock), without global hash tables:
+//   prep     per hub: chunks of kHubChunk entries, label parts (a power of
+//            two, about kHubPartLabels distinct labels each), offsets
+//   chunk    per chunk: labels aggregated in an LDS table; the chunk's
+//            (label, sum) pairs are staged grouped by part, and every part
+//            reserves its range with one atomic on the part's counter
+//   alloc    per part: its segment of the pair pool (block scan + one
+//            atomic per workgroup)
+//   scatter  per chunk: staged pairs copied into their parts' segments
+//   part     per part: pairs aggregated in LDS; the best eligible label of
+//            the part, combined per hub with an integer maximum
+//   final    per hub: the own label against the best foreign one.
+// Every label of a hub falls in exactly one part, so the per-part sums are
+// the node's connections.
 // ---------------------------------------------------------------------------
+constexpr int kHubTable = 2 * kHubChunk;   // LDS table entries of a chunk or a part
+constexpr int kHubPartFill = kHubTable - kHubTable / 8;  // distinct labels one part may hold
 
-// One workgroup: exclusive offsets of chunk counts and table sizes.
-constexpr int kHubSlice = 4096;  // table entries scanned per workgroup in the final pass
+// Part of label t among P parts (bits independent of the LDS table slot).
+__device__ __forceinline__ uint32_t hub_part_of(int32_t t, uint32_t P) {
+  return (hash32((uint32_t)t) >> 19) & (P - 1);
+}
 
+// One workgroup: per hub chunk, part and matrix offsets (exclusive scans).
 template <bool ONE>
 __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr,
-                                                   uint32_t* __restrict__ chunk_off, int64_t* __restrict__ tab_off,
-                                                   uint32_t* __restrict__ slice_off,
-                                                   uint32_t* __restrict__ chunk_hub, uint32_t* __restrict__ slice_hub,
-                                                   uint32_t map_cap, uint32_t* __restrict__ totals, int64_t tab_cap,
-                                                   uint32_t* __restrict__ overflow) {
+                                                   const uint32_t* __restrict__ cnt_ptr, HubLayout L) {
   __shared__ uint32_t sc[1024];
-  __shared__ uint32_t ss[1024];
-  __shared__ int64_t st[1024];
-  __shared__ uint32_t carry_c, carry_s;
-  __shared__ int64_t carry_t;
+  __shared__ uint32_t sp[1024];
+  __shared__ int64_t sm[1024];
+  __shared__ uint32_t carry_c, carry_p;
+  __shared__ int64_t carry_m;
   const uint32_t cnt = *cnt_ptr;
   if (threadIdx.x == 0) {
     carry_c = 0;
-    carry_s = 0;
-    carry_t = 0;
+    carry_p = 0;
+    carry_m = 0;
+    *L.pool_cursor = 0;
   }
   __syncthreads();
   for (uint32_t base = 0; base < cnt; base += blockDim.x) {
     const uint32_t i = base + threadIdx.x;
-    uint32_t nc = 0, ns2 = 0;
-    int64_t tz = 0;
+    uint32_t nc = 0, np = 0;
+    int64_t nm = 0;
     if (i < cnt) {
       const int64_t u = list[i];
       const DevSlot& sl = S[SLOT(u)];
       const int64_t v = u - sl.nbase;
-      const int64_t d = sl.rp[v + 1] - sl.rp[v];
+      const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
       nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
-      tz = table_size(d, sl.nlabels);
-      ns2 = (uint32_t)((tz + kHubSlice - 1) / kHubSlice);
+      np = hub_parts(d, sl.nlabels);
+      nm = (int64_t)nc * (2 * np + 1);
+      L.hub_P[i] = np;
     }
     sc[threadIdx.x] = nc;
-    ss[threadIdx.x] = ns2;
-    st[threadIdx.x] = tz;
+    sp[threadIdx.x] = np;
+    sm[threadIdx.x] = nm;
     __syncthreads();
     for (uint32_t off = 1; off < blockDim.x; off <<= 1) {  // inclusive Hillis-Steele
-      uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
-      uint32_t a2 = threadIdx.x >= off ? ss[threadIdx.x - off] : 0;
-      int64_t b = threadIdx.x >= off ? st[threadIdx.x - off] : 0;
+      const uint32_t a = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+      const uint32_t a2 = threadIdx.x >= off ? sp[threadIdx.x - off] : 0;
+      const int64_t a3 = threadIdx.x >= off ? sm[threadIdx.x - off] : 0;
       __syncthreads();
       sc[threadIdx.x] += a;
-      ss[threadIdx.x] += a2;
-      st[threadIdx.x] += b;
+      sp[threadIdx.x] += a2;
+      sm[threadIdx.x] += a3;
       __syncthreads();
     }
     if (i < cnt) {
-      const uint32_t c0 = carry_c + sc[threadIdx.x] - nc, s0 = carry_s + ss[threadIdx.x] - ns2;
-      chunk_off[i] = c0;
-      slice_off[i] = s0;
-      tab_off[i] = carry_t + st[threadIdx.x] - tz;
-      if (c0 + nc <= map_cap && s0 + ns2 <= map_cap) {
-        for (uint32_t c = 0; c < nc; ++c) chunk_hub[c0 + c] = i;
-        for (uint32_t c = 0; c < ns2; ++c) slice_hub[s0 + c] = i;
+      const uint32_t c0 = carry_c + sc[threadIdx.x] - nc, p0 = carry_p + sp[threadIdx.x] - np;
+      L.chunk_off[i] = c0;
+      L.part_off[i] = p0;
+      L.mat_off[i] = carry_m + sm[threadIdx.x] - nm;
+      if ((int64_t)c0 + nc <= L.map_cap && (int64_t)p0 + np <= L.map_cap) {
+        for (uint32_t c = 0; c < nc; ++c) L.chunk_hub[c0 + c] = i;
+        for (uint32_t p = 0; p < np; ++p) L.part_hub[p0 + p] = i;
       } else {
-        *overflow = 1;
+        *L.overflow = 1;
       }
     }
     __syncthreads();
     if (threadIdx.x == blockDim.x - 1) {
       carry_c += sc[threadIdx.x];
-      carry_s += ss[threadIdx.x];
-      carry_t += st[threadIdx.x];
+      carry_p += sp[threadIdx.x];
+      carry_m += sm[threadIdx.x];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    totals[0] = carry_c;
-    totals[1] = carry_s;
-    chunk_off[cnt] = carry_c;
-    slice_off[cnt] = carry_s;
-    if (carry_t > tab_cap) *overflow = 1;
+    L.totals[0] = carry_c;
+    L.totals[1] = carry_p;
+    if ((int64_t)carry_c * kHubChunk > L.stage_cap || carry_m > L.mat_cap || carry_p > L.parts_cap)
+      *L.overflow = 1;
   }
 }
 
-constexpr int kHubLds = 2 * kHubChunk;
+constexpr int kHubChunkThreads = 512;
 
 template <bool ONE>
-__global__ void __launch_bounds__(256) k_hub_chunk(const DevSlot* __restrict__ S, int ns,
-                                                   const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr,
-                                                   const uint32_t* __restrict__ chunk_off,
-                                                   const int64_t* __restrict__ tab_off,
-                                                   const uint32_t* __restrict__ chunk_hub,
-                                                   const uint32_t* __restrict__ totals,
-                                                   int32_t* __restrict__ gkeys, int32_t* __restrict__ gvals,
-                                                   int64_t* __restrict__ hub_own,
-                                                   const uint32_t* __restrict__ overflow) {
-  __shared__ int32_t keys[kHubLds];
-  __shared__ int32_t vals[kHubLds];
-  __shared__ int64_t redi[4];
-  __shared__ int redo[4];
-  if (*overflow) return;
-  const uint32_t cnt = *cnt_ptr;
-  const uint32_t nchunks = totals[0];
+__global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* __restrict__ S, int ns,
+                                                                const int32_t* __restrict__ list, HubLayout L) {
+  constexpr int NT = kHubChunkThreads;
+  __shared__ int32_t keys[kHubTable];
+  __shared__ int32_t vals[kHubTable];
+  __shared__ uint32_t ulist[kHubChunk];  // used table slots (low 16 bits) | rank in their part << 16
+  __shared__ uint32_t loff[kHubMaxParts + 1];
+  __shared__ uint32_t cur[kHubMaxParts];
+  __shared__ int64_t redi[8];
+  __shared__ int redo[8];
+  __shared__ uint32_t s_wsum[8];
+  __shared__ uint32_t s_used;
+  if (*L.overflow) return;
+  const uint32_t nchunks = L.totals[0];
+  // the table is cleared once here, and after every chunk only where it was used
+  for (int j = threadIdx.x; j < kHubTable; j += NT) {
+    keys[j] = -1;
+    vals[j] = 0;
+  }
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint32_t i = chunk_hub[c];
+    const uint32_t i = L.chunk_hub[c];
+    const uint32_t lc = c - L.chunk_off[i];
+    const uint32_t P = L.hub_P[i];
     const int64_t u = list[i];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int64_t row0 = gld(sl.rp, v);
     const int64_t d = gld(sl.rp, v + 1) - row0;
-    const int64_t e_begin = (int64_t)(c - chunk_off[i]) * kHubChunk;
+    const int64_t e_begin = (int64_t)lc * kHubChunk;
     const int64_t e_end = e_begin + kHubChunk < d ? e_begin + kHubChunk : d;
     const int32_t own = gld(sl.lab, v);
-    for (int j = threadIdx.x; j < kHubLds; j += blockDim.x) {
-      keys[j] = -1;
-      vals[j] = 0;
-    }
+    for (uint32_t p = threadIdx.x; p < P; p += NT) cur[p] = 0;
+    if (threadIdx.x == 0) s_used = 0;
     __syncthreads();
+    // aggregate the chunk's entries by label, listing every slot taken
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<8>(sl, row0, e_begin + threadIdx.x, e_end, blockDim.x, own, keys, vals, kHubLds - 1, my_own, foreign);
+    for (int64_t e = e_begin + threadIdx.x; e < e_end; e += (int64_t)NT * 8) {
+      int32_t nb[8], wt[8], tt[8];
+      bool ok[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t ee = e + (int64_t)q * NT;
+        ok[q] = ee < e_end;
+        const int64_t ec = row0 + (ok[q] ? ee : e_end - 1);
+        nb[q] = gld(sl.col, ec);
+        wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) tt[q] = gld(sl.lab, nb[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int32_t tq = tt[q];
+        if (!ok[q]) continue;
+        if (tq == own) {
+          my_own += wt[q];
+          continue;
+        }
+        foreign = true;
+        if (dir_blocked(sl, tq, own)) continue;
+        uint32_t h = hash32((uint32_t)tq) & (kHubTable - 1);
+        for (;;) {
+          const int32_t prev = atomicCAS(&keys[h], -1, tq);
+          if (prev == -1 || prev == tq) {
+            if (prev == -1) ulist[atomicAdd(&s_used, 1u)] = h;
+            atomicAdd(&vals[h], wt[q]);
+            break;
+          }
+          h = (h + 1) & (kHubTable - 1);
+        }
+      }
+    }
     const int64_t co = block_reduce(my_own, redi, OpAdd64());
     const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
     if (threadIdx.x == 0) {
-      if (co) atomicAdd((unsigned long long*)&hub_own[i], (unsigned long long)co);
+      if (co) atomicAdd((unsigned long long*)&L.own[i], (unsigned long long)co);
       if (sl.mode == MODE_REFINE && boundary) gst(sl.flag_next, v, (uint8_t)1);
     }
-    const uint32_t gmask = table_size(d, sl.nlabels) - 1;
-    int32_t* gk = gkeys + tab_off[i];
-    int32_t* gv = gvals + tab_off[i];
-    for (int j = threadIdx.x; j < kHubLds; j += blockDim.x) {
-      const int32_t t = keys[j];
-      if (t >= 0) table_add(gk, gv, gmask, t, vals[j]);
+    const uint32_t nu = s_used;
+    // label part of every pair and its rank within the part
+    for (uint32_t k = threadIdx.x; k < nu; k += NT) {
+      const uint32_t h = ulist[k];
+      const uint32_t r = atomicAdd(&cur[hub_part_of(keys[h], P)], 1u);
+      ulist[k] = h | (r << 16);
+    }
+    __syncthreads();
+    {
+      // exclusive scan of cur[0..P) into loff[0..P]
+      constexpr int PT = kHubMaxParts / NT;
+      uint32_t mine[PT], tot = 0;
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const uint32_t p = threadIdx.x * PT + q;
+        mine[q] = p < P ? cur[p] : 0u;
+        tot += mine[q];
+      }
+      uint32_t incl = tot;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if ((int)lane_id() >= off) incl += o;
+      }
+      if (lane_id() == kWave - 1) s_wsum[threadIdx.x / kWave] = incl;
+      __syncthreads();
+      uint32_t run = incl - tot;
+      for (int k = 0; k < (int)(threadIdx.x / kWave); ++k) run += s_wsum[k];
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const uint32_t p = threadIdx.x * PT + q;
+        if (p <= P) loff[p] = run;
+        run += mine[q];
+      }
+    }
+    __syncthreads();
+    // chunk x part matrix: staged offsets and each part's reserved range
+    uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (2 * P + 1);
+    uint32_t* mat_pos = mat_loff + P + 1;
+    for (uint32_t p = threadIdx.x; p <= P; p += NT) {
+      mat_loff[p] = loff[p];
+      if (p < P) {
+        const uint32_t k = cur[p];
+        mat_pos[p] = k ? atomicAdd(&L.part_total[L.part_off[i] + p], k) : 0u;
+      }
+    }
+    // staged pairs grouped by part; the used slots are cleared
+    int2* stage = L.stage + (int64_t)c * kHubChunk;
+    for (uint32_t k = threadIdx.x; k < nu; k += NT) {
+      const uint32_t x = ulist[k];
+      const uint32_t h = x & 0xFFFFu;
+      const int32_t t = keys[h];
+      stage[loff[hub_part_of(t, P)] + (x >> 16)] = make_int2(t, vals[h]);
+      keys[h] = -1;
+      vals[h] = 0;
     }
     __syncthreads();
   }
 }
 
-// Slices of the hub tables: best eligible candidate per slice, combined per
-// hub with an integer maximum; the slice is reset for the next round.
+// Segment of every part in the pair pool.
+__global__ void __launch_bounds__(256) k_hub_alloc(HubLayout L) {
+  __shared__ uint64_t s_w[4];
+  __shared__ uint64_t s_base;
+  if (*L.overflow) return;
+  const uint32_t nparts = L.totals[1];
+  const int w = threadIdx.x / kWave;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < nparts; base += gridDim.x * blockDim.x) {
+    const uint32_t g = base + threadIdx.x;
+    const uint64_t t = g < nparts ? L.part_total[g] : 0;
+    uint64_t incl = t;
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint64_t o = __shfl_up(incl, off);
+      if ((int)lane_id() >= off) incl += o;
+    }
+    if (lane_id() == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t tot = 0;
+      for (int k = 0; k < 4; ++k) {
+        const uint64_t x = s_w[k];
+        s_w[k] = tot;
+        tot += x;
+      }
+      s_base = tot ? atomicAdd(L.pool_cursor, (unsigned long long)tot) : 0;
+    }
+    __syncthreads();
+    if (g < nparts) L.part_base[g] = (int64_t)(s_base + s_w[w] + incl - t);
+    __syncthreads();
+  }
+}
+
+// Staged pairs of every chunk into their parts' segments.
+__global__ void __launch_bounds__(256) k_hub_scatter(HubLayout L) {
+  if (*L.overflow) return;
+  const uint32_t nchunks = L.totals[0];
+  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const uint32_t i = L.chunk_hub[c];
+    const uint32_t lc = c - L.chunk_off[i];
+    const uint32_t P = L.hub_P[i];
+    const uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (2 * P + 1);
+    const uint32_t* mat_pos = mat_loff + P + 1;
+    const int64_t* pbase = L.part_base + L.part_off[i];
+    const uint32_t tot = mat_loff[P];
+    const int2* stage = L.stage + (int64_t)c * kHubChunk;
+    for (uint32_t j = threadIdx.x; j < tot; j += blockDim.x) {
+      const int2 pr = stage[j];
+      const uint32_t p = hub_part_of(pr.x, P);
+      L.pool[pbase[p] + mat_pos[p] + (j - mat_loff[p])] = pr;
+    }
+  }
+}
+
+// Best eligible label of every part; the part's counter is reset.
 template <bool ONE>
-__global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S, int ns,
-                                                  const int32_t* __restrict__ list,
-                                                  const uint32_t* __restrict__ cnt_ptr,
-                                                  const int64_t* __restrict__ tab_off,
-                                                  const uint32_t* __restrict__ slice_off,
-                                                  const uint32_t* __restrict__ slice_hub,
-                                                  const uint32_t* __restrict__ totals,
-                                                  int32_t* __restrict__ gkeys, int32_t* __restrict__ gvals,
-                                                  const int64_t* __restrict__ hub_own,
-                                                  unsigned long long* __restrict__ hub_best,
-                                                  const uint32_t* __restrict__ overflow) {
+__global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ list, HubLayout L) {
+  __shared__ int32_t keys[kHubTable];
+  __shared__ int32_t vals[kHubTable];
+  __shared__ uint32_t s_used;
   __shared__ uint64_t red64[8];
-  if (*overflow) return;
-  const uint32_t cnt = *cnt_ptr;
-  const uint32_t nslices = totals[1];
-  for (uint32_t c = blockIdx.x; c < nslices; c += gridDim.x) {
-    const uint32_t i = slice_hub[c];
+  if (*L.overflow) return;
+  const uint32_t nparts = L.totals[1];
+  for (uint32_t g = blockIdx.x; g < nparts; g += gridDim.x) {
+    const uint32_t i = L.part_hub[g];
     const int64_t u = list[i];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
     const int32_t own = gld(sl.lab, v);
-    const int64_t conn_own = hub_own[i];
     const int64_t cv = gld(sl.nw, v);
+    const int64_t conn_own = L.own[i];
     const bool own_ok = own_allowed(sl, own);
-    const uint32_t tsz = table_size(d, sl.nlabels);
-    const uint32_t j0 = (c - slice_off[i]) * kHubSlice;
-    const uint32_t j1 = j0 + kHubSlice < tsz ? j0 + kHubSlice : tsz;
-    int32_t* gk = gkeys + tab_off[i];
-    int32_t* gv = gvals + tab_off[i];
+    const uint32_t len = L.part_total[g];
+    const int2* seg = L.pool + L.part_base[g];
+    // table of at least twice the pairs (then it never fills), at most kHubTable
+    uint32_t tsz = 256;
+    while (tsz < 2 * len && tsz < (uint32_t)kHubTable) tsz <<= 1;
+    const uint32_t mask = tsz - 1;
+    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+      keys[j] = -1;
+      vals[j] = 0;
+    }
+    if (threadIdx.x == 0) s_used = 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
+      const int2 pr = seg[j];
+      uint32_t h = hash32((uint32_t)pr.x) & mask;
+      for (;;) {
+        const int32_t prev = atomicCAS(&keys[h], -1, pr.x);
+        if (prev == -1 || prev == pr.x) {
+          if (prev == -1) atomicAdd(&s_used, 1u);
+          atomicAdd(&vals[h], pr.y);
+          break;
+        }
+        h = (h + 1) & mask;
+      }
+      if (s_used > (uint32_t)kHubPartFill) break;  // table too full: reported below
+    }
+    __syncthreads();
+    if (s_used > (uint32_t)kHubPartFill) {
+      if (threadIdx.x == 0) *L.overflow = 1;
+      return;
+    }
     uint64_t best = 0;
-    for (uint32_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
-      const int32_t t = gk[j];
+    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+      const int32_t t = keys[j];
       if (t < 0) continue;
-      const int64_t cn = gv[j];
-      gk[j] = -1;
-      gv[j] = 0;
-      const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, cn);
+      const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, vals[j]);
       best = best > k ? best : k;
     }
     best = block_reduce(best, red64, OpMax64());
-    if (threadIdx.x == 0 && best) atomicMax(&hub_best[i], (unsigned long long)best);
+    if (threadIdx.x == 0) {
+      if (best) atomicMax(&L.best[i], (unsigned long long)best);
+      L.part_total[g] = 0;
+    }
     __syncthreads();
   }
 }
@@ -891,11 +1059,8 @@ __global__ void __launch_bounds__(256) k_hub_scan(const DevSlot* __restrict__ S,
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr,
-                                                   int64_t* __restrict__ hub_own,
-                                                   unsigned long long* __restrict__ hub_best,
-                                                   const uint32_t* __restrict__ overflow) {
-  if (*overflow) return;
+                                                   const uint32_t* __restrict__ cnt_ptr, HubLayout L) {
+  if (*L.overflow) return;
   const uint32_t cnt = *cnt_ptr;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
@@ -903,14 +1068,14 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int32_t own = gld(sl.lab, v);
-    uint64_t best = hub_best[i];
+    uint64_t best = L.best[i];
     if (own_allowed(sl, own)) {
-      const uint64_t ok = pack_key(hub_own[i], own);
+      const uint64_t ok = pack_key(L.own[i], own);
       best = best > ok ? best : ok;
     }
     gst(sl.desire, v, best ? key_label(best) : own);
-    hub_own[i] = 0;
-    hub_best[i] = 0;
+    L.own[i] = 0;
+    L.best[i] = 0;
   }
 }
 
@@ -1306,7 +1471,7 @@ int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, uint64_t* bin
 }
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
-                const uint32_t* bin_cnt, const RateHubScratch& hub, int64_t n_hint, bool hubs, bool unit_weights,
+                const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
                 hipStream_t st, hipEvent_t* evs) {
   const unsigned G = grid_for(n_hint, 64, 2048);
   auto rec = [&](int i) {
@@ -1326,13 +1491,12 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
   if (hubs) {
     const int32_t* hb = bins + 8 * bin_cap;
     const uint32_t* hc = bin_cnt + 8;
-    LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub.chunk_off, hub.tab_off, hub.slice_off, hub.chunk_hub,
-           hub.slice_hub, hub.map_cap, hub.totals, hub.tab_cap, hub.overflow);
-    LAUNCH(k_hub_chunk, G, 256, S, ns, hb, hc, hub.chunk_off, hub.tab_off, hub.chunk_hub, hub.totals, hub.gkeys,
-           hub.gvals, hub.own, hub.overflow);
-    LAUNCH(k_hub_scan, G, 256, S, ns, hb, hc, hub.tab_off, hub.slice_off, hub.slice_hub, hub.totals, hub.gkeys,
-           hub.gvals, hub.own, hub.best, hub.overflow);
-    LAUNCH(k_hub_final, 64, 256, S, ns, hb, hc, hub.own, hub.best, hub.overflow);
+    LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub);
+    LAUNCH(k_hub_chunk, G, kHubChunkThreads, S, ns, hb, hub);
+    hipLaunchKernelGGL(k_hub_alloc, dim3(G), dim3(256), 0, st, hub);
+    hipLaunchKernelGGL(k_hub_scatter, dim3(G), dim3(256), 0, st, hub);
+    LAUNCH(k_hub_part, G, 256, S, ns, hb, hub);
+    LAUNCH(k_hub_final, 64, 256, S, ns, hb, hc, hub);
   }
   rec(5);
   SCLAP_HIP(hipGetLastError());

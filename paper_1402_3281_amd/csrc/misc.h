@@ -11,8 +11,10 @@ int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 int fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
-// out4 (device, 5 entries): [sum c, max c, #nodes of degree > 0, hub table entries, #hubs]
-int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t nlabels, unsigned long long* out4,
+// out (device, kGraphTotals entries): sum c, max c, nodes of degree > 0 and
+// the hub rating path sizes (see k_graph_totals).
+constexpr int kGraphTotals = 9;
+int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t k, unsigned long long* out,
                  hipStream_t st);
 int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st);
 int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);

@@ -42,46 +42,48 @@ int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) { return fill_t
 // totals[2] += #degree>0 nodes, totals[3] += hub table entries for
 // `nlabels` labels, totals[4] += #hubs.
 // ---------------------------------------------------------------------------
+// Level totals: [0] sum c, [1] max c, [2] nodes of degree > 0, and for the
+// hub rating path [3] staged pair slots, [4] hubs, [5] label parts and
+// [6] matrix entries when clustering (labels = nodes), [7], [8] the same
+// when refining (labels = k blocks).
 __global__ void __launch_bounds__(256) k_graph_totals(const int64_t* __restrict__ rp, const int64_t* __restrict__ nw,
-                                                      int64_t n, int64_t nlabels, unsigned long long* __restrict__ out) {
-  int64_t s = 0, mx = 0, nz = 0, hub = 0, hubs = 0;
+                                                      int64_t n, int64_t k, unsigned long long* __restrict__ out) {
+  int64_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const int64_t c = nw[v];
-    s += c;
-    mx = c > mx ? c : mx;
+    acc[0] += c;
+    acc[1] = c > acc[1] ? c : acc[1];
     const int64_t d = rp[v + 1] - rp[v];
-    nz += d > 0;
+    acc[2] += d > 0;
     if (d > kBinBlock) {
-      const int64_t distinct = d < nlabels ? d : nlabels;
-      int64_t t = 64;
-      while (t < 2 * distinct) t <<= 1;
-      hub += t;
-      ++hubs;
+      const int64_t nc = (d + kHubChunk - 1) / kHubChunk;
+      const int64_t pc = hub_parts(d, n), pr = hub_parts(d, k);
+      acc[3] += nc * kHubChunk;
+      acc[4] += 1;
+      acc[5] += pc;
+      acc[6] += nc * (2 * pc + 1);
+      acc[7] += pr;
+      acc[8] += nc * (2 * pr + 1);
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    s += __shfl_xor(s, off);
-    const int64_t o = __shfl_xor(mx, off);
-    mx = o > mx ? o : mx;
-    nz += __shfl_xor(nz, off);
-    hub += __shfl_xor(hub, off);
-    hubs += __shfl_xor(hubs, off);
-  }
-  if (lane() == 0) {
-    atomicAdd(&out[0], (unsigned long long)s);
-    atomicMax(&out[1], (unsigned long long)mx);
-    atomicAdd(&out[2], (unsigned long long)nz);
-    atomicAdd(&out[3], (unsigned long long)hub);
-    atomicAdd(&out[4], (unsigned long long)hubs);
-  }
+  for (int off = 32; off > 0; off >>= 1)
+    for (int q = 0; q < 9; ++q) {
+      const int64_t o = __shfl_xor(acc[q], off);
+      acc[q] = q == 1 ? (o > acc[q] ? o : acc[q]) : acc[q] + o;
+    }
+  if (lane() == 0)
+    for (int q = 0; q < 9; ++q) {
+      if (q == 1) atomicMax(&out[1], (unsigned long long)acc[1]);
+      else if (acc[q]) atomicAdd(&out[q], (unsigned long long)acc[q]);
+    }
 }
 
-int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t nlabels, unsigned long long* out4,
+int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t k, unsigned long long* out,
                  hipStream_t st) {
-  SCLAP_TRY(fill_t((uint64_t*)out4, 5, (uint64_t)0, st));
+  SCLAP_TRY(fill_t((uint64_t*)out, kGraphTotals, (uint64_t)0, st));
   if (n <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_graph_totals, dim3(grid1(n, 2048)), dim3(256), 0, st, rp, nw, n, nlabels, out4);
+  hipLaunchKernelGGL(k_graph_totals, dim3(grid1(n, 2048)), dim3(256), 0, st, rp, nw, n, k, out);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
