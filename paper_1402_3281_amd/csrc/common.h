@@ -79,7 +79,7 @@ enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_N = 4 };
 constexpr int kBins = 9;
 constexpr int64_t kBinBlock = 4096;
 
-constexpr int kHubChunk = 4096;      // entries per workgroup in the multi-workgroup path
+constexpr int kHubChunk = 2048;      // entries per workgroup in the multi-workgroup path
 constexpr int kHubPartLabels = 2048; // target distinct labels per label part of a hub
 constexpr int kHubMaxParts = 2048;
 

@@ -715,8 +715,9 @@ __global__ void __launch_bounds__(512) k_rate_large(const DevSlot* __restrict__ 
 // Every label of a hub falls in exactly one part, so the per-part sums are
 // the node's connections.
 // ---------------------------------------------------------------------------
-constexpr int kHubTable = 2 * kHubChunk;   // LDS table entries of a chunk or a part
-constexpr int kHubPartFill = kHubTable - kHubTable / 8;  // distinct labels one part may hold
+constexpr int kHubTable = 2 * kHubChunk;   // LDS table entries of a chunk
+constexpr int kHubPartTable = 4096;        // LDS table entries of a label part
+constexpr int kHubPartFill = kHubPartTable - kHubPartTable / 8;  // distinct labels one part may hold
 
 // Part of label t among P parts (bits independent of the LDS table slot).
 __device__ __forceinline__ uint32_t hub_part_of(int32_t t, uint32_t P) {
@@ -990,12 +991,17 @@ __global__ void __launch_bounds__(256) k_hub_scatter(HubLayout L) {
   }
 }
 
-// Best eligible label of every part; the part's counter is reset.
+// Best eligible label of every part; the part's counter is reset.  A part
+// whose distinct labels would overfill the LDS table is taken in Q passes,
+// each over the labels of one residue of a further hash (Q doubles until the
+// passes fit), so any label distribution is handled exactly.
+constexpr uint32_t kHubMaxPasses = 64;
+
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S, int ns,
                                                   const int32_t* __restrict__ list, HubLayout L) {
-  __shared__ int32_t keys[kHubTable];
-  __shared__ int32_t vals[kHubTable];
+  __shared__ int32_t keys[kHubPartTable];
+  __shared__ int32_t vals[kHubPartTable];
   __shared__ uint32_t s_used;
   __shared__ uint64_t red64[8];
   if (*L.overflow) return;
@@ -1011,43 +1017,58 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
     const bool own_ok = own_allowed(sl, own);
     const uint32_t len = L.part_total[g];
     const int2* seg = L.pool + L.part_base[g];
-    // table of at least twice the pairs (then it never fills), at most kHubTable
-    uint32_t tsz = 256;
-    while (tsz < 2 * len && tsz < (uint32_t)kHubTable) tsz <<= 1;
-    const uint32_t mask = tsz - 1;
-    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
-      keys[j] = -1;
-      vals[j] = 0;
-    }
-    if (threadIdx.x == 0) s_used = 0;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
-      const int2 pr = seg[j];
-      uint32_t h = hash32((uint32_t)pr.x) & mask;
-      for (;;) {
-        const int32_t prev = atomicCAS(&keys[h], -1, pr.x);
-        if (prev == -1 || prev == pr.x) {
-          if (prev == -1) atomicAdd(&s_used, 1u);
-          atomicAdd(&vals[h], pr.y);
-          break;
-        }
-        h = (h + 1) & mask;
-      }
-      if (s_used > (uint32_t)kHubPartFill) break;  // table too full: reported below
-    }
-    __syncthreads();
-    if (s_used > (uint32_t)kHubPartFill) {
-      if (threadIdx.x == 0) *L.overflow = 1;
-      return;
-    }
     uint64_t best = 0;
-    for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
-      const int32_t t = keys[j];
-      if (t < 0) continue;
-      const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, vals[j]);
-      best = best > k ? best : k;
+    for (uint32_t Q = 1;; Q <<= 1) {
+      if (Q > kHubMaxPasses) {
+        if (threadIdx.x == 0) *L.overflow = 1;
+        return;
+      }
+      // one pass: a table of at least twice the pairs (then it never fills)
+      uint32_t tsz = 256;
+      while (tsz < 2 * len && tsz < (uint32_t)kHubPartTable) tsz <<= 1;
+      const uint32_t mask = tsz - 1;
+      bool fits = true;
+      best = 0;
+      for (uint32_t q = 0; q < Q && fits; ++q) {
+        for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+          keys[j] = -1;
+          vals[j] = 0;
+        }
+        if (threadIdx.x == 0) s_used = 0;
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
+          const int2 pr = seg[j];
+          const uint32_t hh = hash32((uint32_t)pr.x);
+          if (((hh >> 12) & (Q - 1)) != q) continue;
+          uint32_t h = hh & mask;
+          for (;;) {
+            const int32_t prev = atomicCAS(&keys[h], -1, pr.x);
+            if (prev == -1 || prev == pr.x) {
+              if (prev == -1) atomicAdd(&s_used, 1u);
+              atomicAdd(&vals[h], pr.y);
+              break;
+            }
+            h = (h + 1) & mask;
+          }
+          if (s_used > (uint32_t)kHubPartFill) break;  // table too full: more passes
+        }
+        __syncthreads();
+        fits = s_used <= (uint32_t)kHubPartFill;
+        if (fits) {
+          uint64_t b = 0;
+          for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+            const int32_t t = keys[j];
+            if (t < 0) continue;
+            const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, vals[j]);
+            b = b > k ? b : k;
+          }
+          b = block_reduce(b, red64, OpMax64());
+          best = best > b ? best : b;
+        }
+        __syncthreads();
+      }
+      if (fits) break;
     }
-    best = block_reduce(best, red64, OpMax64());
     if (threadIdx.x == 0) {
       if (best) atomicMax(&L.best[i], (unsigned long long)best);
       L.part_total[g] = 0;
@@ -1091,13 +1112,47 @@ __device__ __forceinline__ void agg_add(unsigned long long* hk, long long* hv, u
                                         long long val) {
   uint32_t h = hash32((uint32_t)key ^ (uint32_t)(key >> 32) * 0x9E3779B1u) & mask;
   for (;;) {
-    const unsigned long long prev = atomicCAS(&hk[h], kEmpty, key);
+    // a slot that already holds the key needs no compare-and-swap
+    unsigned long long prev = hk[h];
+    if (prev == kEmpty) prev = atomicCAS(&hk[h], kEmpty, key);
     if (prev == kEmpty || prev == key) {
       atomicAdd((unsigned long long*)&hv[h], (unsigned long long)val);
       return;
     }
     h = (h + 1) & mask;
   }
+}
+
+// Wave-wide combination of (key, value) pairs: a bitonic sort of the pairs
+// across the 64 lanes by key, then a sum over every run of equal keys.  On
+// return the first lane of every run holds the run's sum and returns true.
+// Lanes without a pair pass key = ~0 (sorted last) and value 0.  Many lanes
+// adding to one key then cost one table operation instead of a chain of
+// conflicting LDS atomics.
+__device__ __forceinline__ bool wave_reduce_by_key(unsigned long long& key, long long& val) {
+  const int lane = (int)lane_id();
+#pragma unroll
+  for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const unsigned long long pk = __shfl_xor(key, j);
+      const long long pv = __shfl_xor(val, j);
+      const bool up = (lane & k) == 0 || k == kWave;
+      const bool lower = (lane & j) == 0;
+      const bool take = lower == up ? pk < key : pk > key;
+      key = take ? pk : key;
+      val = take ? pv : val;
+    }
+  }
+  // suffix sums inside runs (runs are contiguous after the sort)
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const unsigned long long nk = __shfl_down(key, off);
+    const long long nv = __shfl_down(val, off);
+    if (lane + off < kWave && nk == key) val += nv;
+  }
+  const unsigned long long pk = __shfl_up(key, 1);
+  return key != kEmpty && (lane == 0 || pk != key);
 }
 
 constexpr int kAggNodes = 512;    // nodes per workgroup iteration
@@ -1142,11 +1197,18 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
       if (ok[it] && t[it] != own[it])
         agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it]);
     __syncthreads();
-    for (int j = threadIdx.x; j < kIncTable; j += blockDim.x) {
-      const unsigned long long k = hk[j];
-      if (k == kEmpty || hv[j] == 0) continue;
-      gadd64(S[k >> 32].inc, (uint32_t)k, hv[j]);
+    // flush: the table is read first so that the atomics are issued back to back
+    constexpr int FQ = kIncTable / 256;
+    unsigned long long fk[FQ];
+    long long fv[FQ];
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+      fk[q] = hk[threadIdx.x + q * 256];
+      fv[q] = hv[threadIdx.x + q * 256];
     }
+#pragma unroll
+    for (int q = 0; q < FQ; ++q)
+      if (fk[q] != kEmpty && fv[q] != 0) gadd64(S[ONE ? 0 : (fk[q] >> 32)].inc, (uint32_t)fk[q], fv[q]);
     __syncthreads();
   }
 }
@@ -1348,37 +1410,59 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       oo[it] = gld(sl.lab, uu[it] - sl.nbase);
     }
     for (int it = 0; it < IT; ++it) {
-      if (!ok[it]) continue;
       const int64_t u = uu[it];
       const int s = SLOT(u);
       const DevSlot& sl = S[s];
       const int64_t v = u - sl.nbase;
       const int32_t t = tt[it];
       const int32_t own = oo[it];
-      if (t == own) continue;
-      gst(sl.inc, t, (int64_t)0);
-      if (gld(sl.adm, v)) {
-        const int64_t cv = gld(sl.nw, v);
-        gst(sl.lab, v, t);
-        const unsigned long long ks = (unsigned long long)s << 32;
-        if (cv) {
-          agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
-          agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
+      bool admitted = false;
+      int64_t cv = 0;
+      if (ok[it] && t != own) {
+        gst(sl.inc, t, (int64_t)0);
+        admitted = gld(sl.adm, v) != 0;
+        if (admitted) {
+          cv = gld(sl.nw, v);
+          gst(sl.lab, v, t);
+          if (sl.mode == MODE_REFINE) s_mov[atomicAdd(&s_mcnt, 1u)] = (int32_t)u;
+        } else {
+          gst(sl.desire, v, own);
         }
+      }
+      // label weights (+c(v) to the target, -c(v) to the old label) and the
+      // moved count, combined across the wave first
+      const unsigned long long ks = (unsigned long long)s << 32;
+      if (admitted && cv != 0) {
+        agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
+        agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
+      }
+      // moved count: one LDS add per wave and slot run
+      const int s0 = __shfl(s, 0);
+      if (__all(s == s0)) {
+        const uint64_t m = __ballot(admitted);
+        if (lane_id() == 0 && m) agg_add(hk, hv, kApplyTable - 1, ((unsigned long long)s0 << 32) | kCountLabel,
+                                         (long long)__popcll(m));
+      } else if (admitted) {
         agg_add(hk, hv, kApplyTable - 1, ks | kCountLabel, 1);
-        if (sl.mode == MODE_REFINE) s_mov[atomicAdd(&s_mcnt, 1u)] = (int32_t)u;
-      } else {
-        gst(sl.desire, v, own);
       }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < kApplyTable; j += blockDim.x) {
-      const unsigned long long k = hk[j];
-      if (k == kEmpty || hv[j] == 0) continue;
-      const DevSlot& sl = S[k >> 32];
-      const uint32_t lab = (uint32_t)k;
-      if (lab == kCountLabel) gadd64(sl.ctr, CTR_MOVED, hv[j]);
-      else gadd64(sl.W, lab, hv[j]);
+    // flush: the table is read first so that the atomics are issued back to back
+    constexpr int FQ = kApplyTable / 256;
+    unsigned long long fk[FQ];
+    long long fv[FQ];
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+      fk[q] = hk[threadIdx.x + q * 256];
+      fv[q] = hv[threadIdx.x + q * 256];
+    }
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+      if (fk[q] == kEmpty || fv[q] == 0) continue;
+      const DevSlot& sl = S[ONE ? 0 : (fk[q] >> 32)];
+      const uint32_t lab = (uint32_t)fk[q];
+      if (lab == kCountLabel) gadd64(sl.ctr, CTR_MOVED, fv[q]);
+      else gadd64(sl.W, lab, fv[q]);
     }
     if (threadIdx.x == 0) s_mbase = s_mcnt ? atomicAdd(mcnt, s_mcnt) : 0;
     __syncthreads();

@@ -201,6 +201,37 @@ def test_row_order_and_repeat_invariance(sc, ctx):
         assert s1[f] == s2[f] == s3[f]
 
 
+def _hash32(x: int) -> int:
+    """The library's integer mixer, used here only to pick adversarial ids."""
+    x ^= x >> 16
+    x = (x * 0x7FEB352D) & 0xFFFFFFFF
+    x ^= x >> 15
+    x = (x * 0x846CA68B) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x
+
+
+def test_hub_labels_crowding_one_part(sc, ctx):
+    """A hub whose 5000 neighbour labels all fall into one of its label parts
+    (more than one part table holds): the part is taken in several passes and
+    the result still equals the oracle."""
+    leaves = []
+    x = 0
+    while len(leaves) < 5000:
+        if (_hash32(x) >> 19) & 3 == 0:
+            leaves.append(x)
+        x += 1
+    hub = x
+    n = hub + 1
+    edges = [(hub, v) for v in leaves]
+    rng = random.Random(9)
+    edges += [(leaves[i], leaves[i + 1]) for i in range(0, 4000, 7)]
+    rest = [v for v in range(n - 1) if (_hash32(v) >> 19) & 3 != 0]
+    edges += [(rest[i], rest[i + 1]) for i in range(0, len(rest) - 1, 2)]
+    g = from_edges(n, edges, rng=rng)
+    assert_cluster_parity(sc, ctx, g, 50, 4)
+
+
 def test_batch_equals_alone(sc, ctx):
     specs = graphgen.batch_specs(count=12, seed=11, lg_lo=8, lg_hi=13)
     graphs = [s.make() for s in specs]
