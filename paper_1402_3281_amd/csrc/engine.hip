@@ -567,7 +567,9 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   C.rows_sorted = 1;
   SCLAP_TRY(dalloc_t(&F.coarse_of, nn, st));
   SCLAP_TRY(dalloc_t(&C.own_nw, (size_t)std::max<int64_t>(nc, 1), st));
-  SCLAP_TRY(contract_coarse_of(j->lab, F.rp, F.nw, n, drop, cid, F.coarse_of, C.own_nw, nc, st));
+  // after a clustering of this level, the label weights are the cluster weights
+  const int64_t* Wl = (j->Wt && j->nlabels == n && j->kind == JOB_PARTITION) ? j->Wt : nullptr;
+  SCLAP_TRY(contract_coarse_of(j->lab, F.rp, F.nw, n, drop, cid, F.coarse_of, C.own_nw, nc, used, Wl, st));
   dfree(used, st);
   dfree(cid, st);
   const int bits = bits_for(nc);

@@ -24,8 +24,11 @@ int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const in
               unsigned long long* out, hipStream_t st);
 
 int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st);
+// coarse_of and coarse node weights; with W (label weights of the labels in
+// [0, n), as kept by the clustering) the weights are copied, else summed.
 int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw, int64_t n, int drop,
-                       const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, hipStream_t st);
+                       const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, const int32_t* used,
+                       const int64_t* W, hipStream_t st);
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals,
                    hipStream_t st);

@@ -407,8 +407,35 @@ int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, in
   return SCLAP_OK;
 }
 
+// coarse_of(v) = rank of lab(v) only (weights come from the label weights).
+__global__ void __launch_bounds__(256) k_coarse_map(const int32_t* __restrict__ lab, const int64_t* __restrict__ rp,
+                                                    int64_t n, int drop, const int32_t* __restrict__ cid,
+                                                    int32_t* __restrict__ cof) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    cof[v] = (drop && rp[v + 1] == rp[v]) ? -1 : cid[lab[v]];
+}
+
+// c'(cid(t)) = W(t) for every used label t: the weight of a cluster is the
+// weight of its coarse node, written by the label's single owner thread.
+__global__ void __launch_bounds__(256) k_coarse_w(const int32_t* __restrict__ used, const int32_t* __restrict__ cid,
+                                                  const int64_t* __restrict__ W, int64_t nlabels,
+                                                  int64_t* __restrict__ cnw) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nlabels; t += stride)
+    if (used[t]) cnw[cid[t]] = W[t];
+}
+
 int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw, int64_t n, int drop,
-                       const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, hipStream_t st) {
+                       const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, const int32_t* used,
+                       const int64_t* W, hipStream_t st) {
+  if (W) {
+    if (n <= 0) return SCLAP_OK;
+    hipLaunchKernelGGL(k_coarse_map, dim3(grid1(n)), dim3(256), 0, st, lab, rp, n, drop, cid, cof);
+    hipLaunchKernelGGL(k_coarse_w, dim3(grid1(n)), dim3(256), 0, st, used, cid, W, n, cnw);
+    SCLAP_HIP(hipGetLastError());
+    return SCLAP_OK;
+  }
   SCLAP_TRY(fill_i64(cnw, nc, 0, st));
   if (n <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_coarse_of, dim3(grid1(n)), dim3(256), 0, st, lab, rp, nw, n, drop, cid, cof, cnw);
