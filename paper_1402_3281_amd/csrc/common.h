@@ -57,6 +57,7 @@ struct DevSlot {
   int64_t n;
   int64_t m;              // stored entries of the graph
   int64_t nbase;
+  int64_t tbase;          // first binning tile of the slot
   int64_t nlabels;
   int64_t lbase;
   int64_t cap;

@@ -166,7 +166,8 @@ void ctx_release(Ctx* c, hipStream_t st) {
   Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
-                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_pbase, &c->hub_mat};
+                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_pbase, &c->hub_mat,
+                    &c->binscr, &c->cutbuf};
   c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
   (void)hipStreamSynchronize(st);
@@ -321,7 +322,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   const int ns = (int)jobs.size();
   if (ns == 0) return SCLAP_OK;
   SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
-  int64_t N = 0, Lt = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
+  int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
   for (int s = 0; s < ns; ++s) {
@@ -344,6 +345,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.n = L.n;
     d.m = L.m;
     d.nbase = N;
+    d.tbase = T_bin;
     d.nlabels = j->nlabels;
     d.lbase = Lt;
     const bool refine = j->stage == ST_REFINE;
@@ -353,6 +355,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.dir_rule = j->dir_rule;
     d.use_flags = refine && j->round > 1;
     N += L.n;
+    T_bin += bin_tiles(L.n);
     Lt += j->nlabels;
     hub_stage += L.hub_stage;
     hub_parts += refine ? L.hub_parts_r : L.hub_parts_c;
@@ -424,7 +427,10 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   uint64_t* binfo = (uint64_t*)c->binfo.p;
   if (!reuse_bins) {
     SCLAP_TRY(fill_u32(meta, 64, 0, st));
-    SCLAP_TRY(launch_bin(S, ns, N, bins, binfo, bin_cap, meta, bin_vis, rated, meta + 14, st));
+    const size_t bsb = bin_scratch_bytes(T_bin);
+    SCLAP_TRY(c->binscr.ensure(bsb, st));
+    SCLAP_TRY(launch_bin(S, ns, T_bin, bins, binfo, bin_cap, meta, bin_vis, rated, meta + 14, c->binscr.p,
+                         c->binscr.bytes, st));
     c->bin_sig = sig;
     c->bin_sig_valid = all_cluster;
     c->bin_cap_used = bin_cap;
@@ -574,9 +580,19 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   dfree(cid, st);
   const int bits = bits_for(nc);
   SCLAP_TRY(c->small.ensure(256, st));
-  unsigned long long* cnt = (unsigned long long*)c->small.p;
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, cnt, nullptr, nullptr, st));
-  SCLAP_HIP(hipMemcpyAsync(c->pin, cnt, 8, hipMemcpyDeviceToHost, st));
+  // cross entries per tile, their exclusive scan (entry T = the total)
+  const int T = cross_tiles(F.m);
+  int64_t *tcnt = nullptr, *toff = nullptr;
+  SCLAP_TRY(dalloc_t(&tcnt, (size_t)T + 1, st));
+  SCLAP_TRY(dalloc_t(&toff, (size_t)T + 1, st));
+  SCLAP_TRY(fill_i64(tcnt, (int64_t)T + 1, 0, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, st));
+  {
+    const size_t sb = prim_exscan_i64_bytes((size_t)T + 1);
+    SCLAP_TRY(c->prim.ensure(sb, st));
+    SCLAP_TRY(prim_exscan_i64(c->prim.p, sb, tcnt, toff, (size_t)T + 1, st));
+  }
+  SCLAP_HIP(hipMemcpyAsync(c->pin, toff + T, 8, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   const int64_t mx = c->pin[0];
   const size_t mz = (size_t)std::max<int64_t>(mx, 1);
@@ -586,7 +602,9 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&k2, mz, st));
   SCLAP_TRY(dalloc_t(&v1, mz, st));
   SCLAP_TRY(dalloc_t(&v2, mz, st));
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, cnt, k1, v1, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, st));
+  dfree(tcnt, st);
+  dfree(toff, st);
   const size_t tb = std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
   SCLAP_TRY(c->prim.ensure(tb, st));
   SCLAP_TRY(prim_sort_pairs(c->prim.p, tb, k1, k2, v1, v2, (size_t)mx, 2 * bits, st));
@@ -737,7 +755,8 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
 static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, hipStream_t st) {
   if (c->small.ensure(256, st) != SCLAP_OK) return -1;
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
-  if (cut_twice(L.rp, L.col, L.ew, part, L.n, L.m, d, st) != SCLAP_OK) return -1;
+  if (c->cutbuf.ensure((size_t)cut_partials(L.m) * 8, st) != SCLAP_OK) return -1;
+  if (cut_twice(L.rp, L.col, L.ew, part, L.n, L.m, d, (int64_t*)c->cutbuf.p, st) != SCLAP_OK) return -1;
   if (ctx_ensure_pin(c, 64) != SCLAP_OK) return -1;
   if (hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
   if (hipStreamSynchronize(st) != hipSuccess) return -1;

@@ -30,11 +30,15 @@ struct HubLayout {
   uint32_t* overflow;     // 1
 };
 
-// Bins the rated nodes; also lists them all in `rated` (rated_cnt).
+// Bins the rated nodes; also lists them all in `rated` (rated_cnt) and sets
+// every slot's CTR_VISITS.  T = total tiles (bin_tiles per slot, summed; the
+// tiles of slot s start at S[s].tbase); scratch holds bin_scratch_bytes(T).
 // binfo receives first entry | degree << 40 of every binned node except hubs.
-int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, uint64_t* binfo, int64_t bin_cap,
+int64_t bin_tiles(int64_t n);
+size_t bin_scratch_bytes(int64_t T);
+int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* binfo, int64_t bin_cap,
                uint32_t* bin_cnt, unsigned long long* bin_visits, int32_t* rated, uint32_t* rated_cnt,
-               hipStream_t st);
+               void* scratch, size_t scratch_bytes, hipStream_t st);
 // Rating launches: bins 0-4 (k_rate_small), 5-6 (k_rate_mid), 7 (k_rate_large),
 // 8 (hub kernels, only if `hubs`).  evs (may be NULL): 5 events around them.
 constexpr int kRateGroups = 5;

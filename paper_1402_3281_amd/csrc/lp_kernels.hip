@@ -19,10 +19,12 @@
 // first combined per workgroup in LDS.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
 #include "lp.h"
+#include "misc.h"
 
 namespace sclap {
 
@@ -48,114 +50,163 @@ __device__ __forceinline__ int bin_of(int64_t d, int64_t m) {
        : d <= kBinBlock ? 7 : 8;
 }
 
-// Per-workgroup sum of `val` per slot, flushed with one atomic per wave run
-// of equal slots.  All threads of the block must call it.
-__device__ __forceinline__ void block_slot_add(const DevSlot* __restrict__ S, int s, int which, int64_t val,
-                                               int* s_slot, int64_t* s_sum) {
-  const int w = threadIdx.x / kWave;
-  const int s0 = __shfl(s, 0);
-  const bool uni = __all(s == s0);
-  int64_t sum = val;
-  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-  if (!uni && val != 0) atomicAdd((unsigned long long*)&S[s].ctr[which], (unsigned long long)val);
-  if (lane_id() == 0) {
-    s_slot[w] = uni ? s0 : -1;
-    s_sum[w] = uni ? sum : 0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = blockDim.x / kWave;
-    int cur = -1;
-    int64_t acc = 0;
-    for (int i = 0; i < nw; ++i) {
-      if (s_slot[i] != cur) {
-        if (cur >= 0 && acc) atomicAdd((unsigned long long*)&S[cur].ctr[which], (unsigned long long)acc);
-        cur = s_slot[i];
-        acc = 0;
-      }
-      acc += s_sum[i];
-    }
-    if (cur >= 0 && acc) atomicAdd((unsigned long long*)&S[cur].ctr[which], (unsigned long long)acc);
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 // Binning: every node of an active slot with degree > 0 (and, in refinement
-// after round 1, in the rated set) is appended to its degree bin.  Positions
-// are reserved with one atomic per bin per workgroup.
+// after round 1, in the rated set) goes to its degree bin and to the rated
+// list.  The nodes of every slot are split into tiles of kBinTile; a tile
+// belongs to one slot.  bin_count writes per tile and bin the node count and
+// edge visits; an exclusive scan of those (bin-major) gives every tile its
+// place in each bin, so no counter is shared between workgroups.
 // ---------------------------------------------------------------------------
+constexpr int kBinTile = 256;
+constexpr int kBinRows = kBins + 1;  // the bins and the rated list
+
+// Slot of tile t (tiles of slot s start at S[s].tbase).
+__device__ __forceinline__ int slot_of_tile(const DevSlot* __restrict__ S, int ns, int64_t t) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (S[mid].tbase <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Bin of the node at lane position; take = rated this round.
+struct BinOf {
+  bool take;
+  int b;
+  int64_t e0, d, v;
+};
+
 template <bool ONE>
-__global__ void __launch_bounds__(256) k_bin(const DevSlot* __restrict__ S, int ns, int64_t N,
-                                             int32_t* __restrict__ bins, uint64_t* __restrict__ binfo,
-                                             int64_t bin_cap,
-                                             uint32_t* __restrict__ bin_cnt,
-                                             unsigned long long* __restrict__ bin_visits,
-                                             int32_t* __restrict__ rated, uint32_t* __restrict__ rated_cnt) {
-  __shared__ uint32_t s_w[4 * (kBins + 1)];  // 4 waves x (bins + rated list)
-  __shared__ uint32_t s_base[kBins + 1];
-  __shared__ unsigned long long s_vis[kBins];
-  __shared__ int s_slot[4];
-  __shared__ int64_t s_sum[4];
+__device__ __forceinline__ BinOf bin_node(const DevSlot& sl, int64_t v) {
+  BinOf r{false, 0, 0, 0, v};
+  if (v < sl.n && sl.round > 0 && (!sl.use_flags || gld(sl.flag_cur, v))) {
+    r.e0 = gld(sl.rp, v);
+    r.d = gld(sl.rp, v + 1) - r.e0;
+    r.take = r.d > 0;
+    r.b = bin_of(r.d, sl.m);
+  }
+  return r;
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(kBinTile) k_bin_count(const DevSlot* __restrict__ S, int ns, int64_t T,
+                                                        uint32_t* __restrict__ cnt, int64_t* __restrict__ vis) {
+  __shared__ uint32_t s_c[4][kBinRows];
+  __shared__ int64_t s_v[4][kBins];
+  const int w = threadIdx.x / kWave;
+  for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
+    const int s = ONE ? 0 : slot_of_tile(S, ns, t);
+    const DevSlot& sl = S[s];
+    const int64_t v = (t - sl.tbase) * kBinTile + threadIdx.x;
+    const BinOf r = bin_node<ONE>(sl, v);
+    // the rated set of the next round is rebuilt from scratch
+    if (v < sl.n && sl.round > 0 && sl.mode == MODE_REFINE) gst(sl.flag_next, v, (uint8_t)0);
+#pragma unroll
+    for (int j = 0; j < kBins; ++j) {
+      const bool in = r.take && r.b == j;
+      const uint64_t m = __ballot(in);
+      // visits of the bin in this wave (only bins present; below the hub bin
+      // the degrees are at most kBinBlock, so 32 bits hold the wave's sum)
+      int64_t dv = 0;
+      if (m) {
+        if (j < kBins - 1) {
+          uint32_t d32 = in ? (uint32_t)r.d : 0u;
+          for (int off = 32; off > 0; off >>= 1) d32 += __shfl_xor(d32, off);
+          dv = d32;
+        } else {
+          dv = in ? r.d : 0;
+          for (int off = 32; off > 0; off >>= 1) dv += __shfl_xor(dv, off);
+        }
+      }
+      if (lane_id() == 0) {
+        s_c[w][j] = (uint32_t)__popcll(m);
+        s_v[w][j] = dv;
+      }
+    }
+    {
+      const uint64_t m = __ballot(r.take);
+      if (lane_id() == 0) s_c[w][kBins] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < kBinRows) {
+      const int j = threadIdx.x;
+      cnt[(int64_t)j * T + t] = s_c[0][j] + s_c[1][j] + s_c[2][j] + s_c[3][j];
+      vis[(int64_t)j * T + t] = j < kBins ? s_v[0][j] + s_v[1][j] + s_v[2][j] + s_v[3][j] : 0;
+    }
+    __syncthreads();
+  }
+}
+
+// off: exclusive scan of cnt (bin-major), off[kBinRows * T] = total.
+template <bool ONE>
+__global__ void __launch_bounds__(kBinTile) k_bin_write(const DevSlot* __restrict__ S, int ns, int64_t T,
+                                                        const uint32_t* __restrict__ off,
+                                                        int32_t* __restrict__ bins, uint64_t* __restrict__ binfo,
+                                                        int64_t bin_cap, int32_t* __restrict__ rated) {
+  __shared__ uint32_t s_c[4][kBinRows];
   const int w = threadIdx.x / kWave;
   const uint64_t lt = (1ull << lane_id()) - 1ull;
-  if (threadIdx.x < kBins) s_vis[threadIdx.x] = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += stride) {
-    const int64_t u = base + threadIdx.x;
-    bool take = false;
-    int b = 0;
-    int s = 0;
-    int64_t d = 0, e0 = 0;
-    if (u < N) {
-      s = SLOT(u);
-      const DevSlot& sl = S[s];
-      const int64_t v = u - sl.nbase;
-      if (sl.round > 0 && (!sl.use_flags || gld(sl.flag_cur, v))) {
-        e0 = gld(sl.rp, v);
-        d = gld(sl.rp, v + 1) - e0;
-        take = d > 0;
-        b = bin_of(d, sl.m);
-      }
-      // the rated set of the next round is rebuilt from scratch
-      if (sl.round > 0 && sl.mode == MODE_REFINE) gst(sl.flag_next, v, (uint8_t)0);
-    }
-    constexpr int NB = kBins + 1;
+  for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
+    const int s = ONE ? 0 : slot_of_tile(S, ns, t);
+    const DevSlot& sl = S[s];
+    const int64_t v = (t - sl.tbase) * kBinTile + threadIdx.x;
+    const BinOf r = bin_node<ONE>(sl, v);
     uint32_t rank = 0, rrank = 0;
 #pragma unroll
     for (int j = 0; j < kBins; ++j) {
-      const uint64_t m = __ballot(take && b == j);
-      if (take && b == j) rank = (uint32_t)__popcll(m & lt);
-      if (lane_id() == 0) s_w[w * NB + j] = (uint32_t)__popcll(m);
+      const bool in = r.take && r.b == j;
+      const uint64_t m = __ballot(in);
+      if (in) rank = (uint32_t)__popcll(m & lt);
+      if (lane_id() == 0) s_c[w][j] = (uint32_t)__popcll(m);
     }
     {
-      const uint64_t m = __ballot(take);
+      const uint64_t m = __ballot(r.take);
       rrank = (uint32_t)__popcll(m & lt);
-      if (lane_id() == 0) s_w[w * NB + kBins] = (uint32_t)__popcll(m);
+      if (lane_id() == 0) s_c[w][kBins] = (uint32_t)__popcll(m);
     }
-    if (take) atomicAdd(&s_vis[b], (unsigned long long)d);
     __syncthreads();
-    if (threadIdx.x < NB) {
-      const int j = threadIdx.x;
-      uint32_t tot = 0;
-      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-        const uint32_t c = s_w[i * NB + j];
-        s_w[i * NB + j] = tot;
-        tot += c;
+    if (r.take) {
+      uint32_t before = 0, rbefore = 0;
+      for (int k = 0; k < w; ++k) {
+        before += s_c[k][r.b];
+        rbefore += s_c[k][kBins];
       }
-      s_base[j] = tot ? atomicAdd(j < kBins ? &bin_cnt[j] : rated_cnt, tot) : 0;
+      const int64_t u = sl.nbase + v;
+      const int64_t pos = (int64_t)r.b * bin_cap + (off[(int64_t)r.b * T + t] - off[(int64_t)r.b * T]) + before + rank;
+      bins[pos] = (int32_t)u;
+      if (r.b < kBins - 1) binfo[pos] = (uint64_t)r.e0 | ((uint64_t)r.d << 40);
+      rated[(off[(int64_t)kBins * T + t] - off[(int64_t)kBins * T]) + rbefore + rrank] = (int32_t)u;
     }
     __syncthreads();
-    if (take) {
-      const int64_t pos = b * bin_cap + s_base[b] + s_w[w * NB + b] + rank;
-      bins[pos] = (int32_t)u;
-      if (b < kBins - 1) binfo[pos] = (uint64_t)e0 | ((uint64_t)d << 40);
-      rated[s_base[kBins] + s_w[w * NB + kBins] + rrank] = (int32_t)u;
-    }
-    block_slot_add(S, s, CTR_VISITS, take ? d : 0, s_slot, s_sum);
   }
-  __syncthreads();
-  if (threadIdx.x < kBins && s_vis[threadIdx.x]) atomicAdd(&bin_visits[threadIdx.x], s_vis[threadIdx.x]);
+}
+
+// Totals: node count and visits per bin, rated count, edge visits per slot.
+__global__ void __launch_bounds__(256) k_bin_totals(const DevSlot* __restrict__ S, int ns, int64_t T,
+                                                    const uint32_t* __restrict__ off,
+                                                    const int64_t* __restrict__ voff, uint32_t* __restrict__ bin_cnt,
+                                                    unsigned long long* __restrict__ bin_visits,
+                                                    uint32_t* __restrict__ rated_cnt) {
+  if (threadIdx.x < kBinRows) {
+    const int j = threadIdx.x;
+    const uint32_t c = off[(int64_t)(j + 1) * T] - off[(int64_t)j * T];
+    if (j < kBins) {
+      bin_cnt[j] = c;
+      bin_visits[j] = (unsigned long long)(voff[(int64_t)(j + 1) * T] - voff[(int64_t)j * T]);
+    } else {
+      *rated_cnt = c;
+    }
+  }
+  // per slot: the visits of its tiles over all bins
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    const int64_t t0 = S[s].tbase, t1 = s + 1 < ns ? S[s + 1].tbase : T;
+    int64_t sum = 0;
+    for (int j = 0; j < kBins; ++j) sum += voff[(int64_t)j * T + t1] - voff[(int64_t)j * T + t0];
+    gst(S[s].ctr, CTR_VISITS, sum);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -252,7 +303,7 @@ __device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, i
       const int dlim = dm < G ? dm : G;
       const bool foreign = t[r] >= 0 && t[r] != own[r];
       const uint64_t fmask = __ballot(foreign);
-      const bool boundary = ((fmask >> gbase) & (G == 64 ? ~0ull : ((1ull << G) - 1ull))) != 0;
+      const bool boundary = ((fmask >> gbase) & (G == 64 ? ~0ull : ((1ull << (G & 63)) - 1ull))) != 0;
       const int32_t te = (foreign && dir_blocked(sl, t[r], own[r])) ? -1 : t[r];
       int64_t conn = 0, conn_own = 0;
       bool leader = te >= 0;
@@ -1546,10 +1597,38 @@ static inline unsigned grid_for(int64_t items, int per_block, unsigned cap) {
     else hipLaunchKernelGGL(kern<false>, dim3(grid), dim3(block), 0, st, __VA_ARGS__);       \
   } while (0)
 
-int launch_bin(const DevSlot* S, int ns, int64_t N, int32_t* bins, uint64_t* binfo, int64_t bin_cap,
+int64_t bin_tiles(int64_t n) { return (n + kBinTile - 1) / kBinTile; }
+
+size_t bin_scratch_bytes(int64_t T) {
+  const size_t rows = (size_t)kBinRows * (size_t)T + 1;
+  return rows * 4 * 2 + rows * 8 * 2 + 256 + std::max(prim_exscan_i32_bytes(rows), prim_exscan_i64_bytes(rows));
+}
+
+int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* binfo, int64_t bin_cap,
                uint32_t* bin_cnt, unsigned long long* bin_visits, int32_t* rated, uint32_t* rated_cnt,
-               hipStream_t st) {
-  LAUNCH(k_bin, grid_for(N, 256, 4096), 256, S, ns, N, bins, binfo, bin_cap, bin_cnt, bin_visits, rated, rated_cnt);
+               void* scratch, size_t scratch_bytes, hipStream_t st) {
+  const size_t rows = (size_t)kBinRows * (size_t)T + 1;
+  char* p = (char*)scratch;
+  uint32_t* cnt = (uint32_t*)p;
+  uint32_t* off = cnt + rows;
+  int64_t* vis = (int64_t*)(((uintptr_t)(off + rows) + 255) & ~(uintptr_t)255);
+  int64_t* voff = vis + rows;
+  void* tmp = voff + rows;
+  const size_t tmp_bytes = scratch_bytes - (size_t)((char*)tmp - p);
+  if (T > 0) {
+    const unsigned G = (unsigned)std::min<int64_t>(T, 4096);
+    // the entry after the last tile is the total of the scans
+    SCLAP_TRY(fill_u32(cnt + rows - 1, 1, 0, st));
+    SCLAP_TRY(fill_i64(vis + rows - 1, 1, 0, st));
+    LAUNCH(k_bin_count, G, kBinTile, S, ns, T, cnt, vis);
+    SCLAP_TRY(prim_exscan_i32(tmp, tmp_bytes, (const int32_t*)cnt, (int32_t*)off, rows, st));
+    SCLAP_TRY(prim_exscan_i64(tmp, tmp_bytes, vis, voff, rows, st));
+    LAUNCH(k_bin_write, G, kBinTile, S, ns, T, off, bins, binfo, bin_cap, rated);
+  } else {
+    SCLAP_TRY(fill_u32(off, 1, 0, st));
+    SCLAP_TRY(fill_i64(voff, 1, 0, st));
+  }
+  hipLaunchKernelGGL(k_bin_totals, dim3(1), dim3(256), 0, st, S, ns, T, off, voff, bin_cnt, bin_visits, rated_cnt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -20,8 +20,11 @@ int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st
 int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);
 int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st);
 int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, int64_t* W, hipStream_t st);
+// Workgroup partial sums cut_twice needs for m entries.
+int cut_partials(int64_t m);
+// *out = sum of w over stored entries joining different blocks (twice the cut).
 int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
-              unsigned long long* out, hipStream_t st);
+              unsigned long long* out, int64_t* partial, hipStream_t st);
 
 int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st);
 // coarse_of and coarse node weights; with W (label weights of the labels in
@@ -29,8 +32,12 @@ int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, in
 int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw, int64_t n, int drop,
                        const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, const int32_t* used,
                        const int64_t* W, hipStream_t st);
+// Entry tiles of the edge-centric contraction kernels (m entries).
+int cross_tiles(int64_t m);
+// mode 0: entries joining different coarse nodes per tile -> tcnt[tile];
+// mode 1: their keys and weights from toff[tile] on (exclusive scan of tcnt).
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
-                   int64_t m, int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals,
+                   int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
                    hipStream_t st);
 int contract_finish(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int64_t nc, int64_t* rp,
                     int32_t* col, int32_t* ew, unsigned* overflow, hipStream_t st);

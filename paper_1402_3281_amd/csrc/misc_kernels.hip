@@ -67,23 +67,30 @@ __global__ void __launch_bounds__(256) k_graph_totals(const int64_t* __restrict_
       acc[8] += nc * (2 * pr + 1);
     }
   }
+  // wave, then workgroup combination: one atomic per workgroup and counter
+  __shared__ int64_t red[4][9];
   for (int off = 32; off > 0; off >>= 1)
     for (int q = 0; q < 9; ++q) {
       const int64_t o = __shfl_xor(acc[q], off);
       acc[q] = q == 1 ? (o > acc[q] ? o : acc[q]) : acc[q] + o;
     }
   if (lane() == 0)
-    for (int q = 0; q < 9; ++q) {
-      if (q == 1) atomicMax(&out[1], (unsigned long long)acc[1]);
-      else if (acc[q]) atomicAdd(&out[q], (unsigned long long)acc[q]);
-    }
+    for (int q = 0; q < 9; ++q) red[threadIdx.x / kWave][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    const int q = threadIdx.x;
+    int64_t a = red[0][q];
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) a = q == 1 ? (red[w][q] > a ? red[w][q] : a) : a + red[w][q];
+    if (q == 1) atomicMax(&out[1], (unsigned long long)a);
+    else if (a) atomicAdd(&out[q], (unsigned long long)a);
+  }
 }
 
 int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t k, unsigned long long* out,
                  hipStream_t st) {
   SCLAP_TRY(fill_t((uint64_t*)out, kGraphTotals, (uint64_t)0, st));
   if (n <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_graph_totals, dim3(grid1(n, 2048)), dim3(256), 0, st, rp, nw, n, k, out);
+  hipLaunchKernelGGL(k_graph_totals, dim3(grid1(n, 512)), dim3(256), 0, st, rp, nw, n, k, out);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -236,7 +243,7 @@ __device__ __forceinline__ int64_t edge_row(const int64_t* __restrict__ rp, cons
 // the host.  Nodes with part -1 have no entries.
 __global__ void __launch_bounds__(256) k_cut(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                              const int32_t* __restrict__ ew, const int32_t* __restrict__ part,
-                                             int64_t n, int64_t m, unsigned long long* __restrict__ out) {
+                                             int64_t n, int64_t m, int64_t* __restrict__ partial) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   int64_t acc = 0;
@@ -250,8 +257,23 @@ __global__ void __launch_bounds__(256) k_cut(const int64_t* __restrict__ rp, con
       if (part[u] != part[col[e]]) acc += ew ? ew[e] : 1;
     }
   }
+  __shared__ int64_t red[4];
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+  if (lane() == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// out = sum of the k partial results (one workgroup).
+__global__ void __launch_bounds__(256) k_sum_partials(const int64_t* __restrict__ partial, int k,
+                                                      unsigned long long* __restrict__ out) {
+  __shared__ int64_t red[4];
+  int64_t a = 0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) a += partial[i];
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+  if (lane() == 0) red[threadIdx.x / kWave] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = (unsigned long long)(red[0] + red[1] + red[2] + red[3]);
 }
 
 static inline unsigned grid_edges(int64_t m) {
@@ -260,11 +282,18 @@ static inline unsigned grid_edges(int64_t m) {
   return (unsigned)(g < 8192 ? g : 8192);
 }
 
+
+
+int cut_partials(int64_t m) { return (int)grid_edges(m); }
+
 int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
-              unsigned long long* out, hipStream_t st) {
+              unsigned long long* out, int64_t* partial, hipStream_t st) {
   SCLAP_TRY(fill_t((uint64_t*)out, 1, (uint64_t)0, st));
   if (n <= 0 || m <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_cut, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, part, n, m, out);
+  // per-workgroup partial sums, added by one workgroup
+  const unsigned G = grid_edges(m);
+  hipLaunchKernelGGL(k_cut, dim3(G), dim3(256), 0, st, rp, col, ew, part, n, m, partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)G, out);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -301,18 +330,21 @@ __global__ void __launch_bounds__(256) k_coarse_of(const int32_t* __restrict__ l
 }
 
 // Count (mode 0) or emit (mode 1) the entries that join different coarse
-// nodes, as keys x * 2^b + y with their weights.
+// nodes, as keys x * 2^b + y with their weights.  Tile t holds the entries
+// [t * kEpb, (t + 1) * kEpb): mode 0 writes its count to tcnt[t], mode 1
+// writes its keys from position toff[t] on (an exclusive scan of tcnt), so
+// no counter is shared between workgroups.
 __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const int32_t* __restrict__ ew, const int32_t* __restrict__ cof,
                                                int64_t n, int64_t m, int bits, int mode,
-                                               unsigned long long* __restrict__ cnt, uint64_t* __restrict__ keys,
-                                               int32_t* __restrict__ vals) {
+                                               int64_t* __restrict__ tcnt, const int64_t* __restrict__ toff,
+                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   __shared__ int64_t s_w[4];
-  __shared__ unsigned long long s_base;
-  int64_t total = 0;
-  for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < m; E0 += (int64_t)gridDim.x * kEpb) {
+  const int64_t ntiles = (m + kEpb - 1) / kEpb;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t E0 = t * kEpb;
     const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
     int32_t xs[kItems], ys[kItems];
     int mine = 0;
@@ -330,11 +362,7 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
         ++mine;
       }
     }
-    if (mode == 0) {
-      total += mine;
-      continue;
-    }
-    // block exclusive scan of `mine`, one atomic per block
+    // workgroup exclusive scan of `mine`
     int64_t incl = mine;
     for (int off = 1; off < kWave; off <<= 1) {
       const int64_t o = __shfl_up(incl, off);
@@ -343,17 +371,16 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
     const int w = threadIdx.x / kWave;
     if (lane() == kWave - 1) s_w[w] = incl;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t t = 0;
-      for (int i = 0; i < 4; ++i) {
-        const int64_t c = s_w[i];
-        s_w[i] = t;
-        t += c;
-      }
-      s_base = t ? atomicAdd(cnt, (unsigned long long)t) : 0;
+    int64_t before = 0, total = 0;
+    for (int i = 0; i < 4; ++i) {
+      before += i < w ? s_w[i] : 0;
+      total += s_w[i];
     }
-    __syncthreads();
-    int64_t p = (int64_t)s_base + s_w[w] + incl - mine;
+    if (mode == 0) {
+      if (threadIdx.x == 0) tcnt[t] = total;
+      continue;
+    }
+    int64_t p = toff[t] + before + incl - mine;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       if (xs[j] < 0) continue;
@@ -362,10 +389,6 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
       vals[p] = ew ? ew[e] : 1;
       ++p;
     }
-  }
-  if (mode == 0) {
-    for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off);
-    if (lane() == 0 && total) atomicAdd(cnt, (unsigned long long)total);
   }
 }
 
@@ -443,13 +466,14 @@ int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw,
   return SCLAP_OK;
 }
 
+int cross_tiles(int64_t m) { return (int)((m + kEpb - 1) / kEpb); }
+
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
-                   int64_t m, int bits, int mode, unsigned long long* cnt, uint64_t* keys, int32_t* vals,
+                   int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
                    hipStream_t st) {
-  SCLAP_TRY(fill_t((uint64_t*)cnt, 1, (uint64_t)0, st));
   if (n <= 0 || m <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, cnt, keys,
-                     vals);
+  hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
+                     keys, vals);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
