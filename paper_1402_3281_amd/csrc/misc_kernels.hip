@@ -518,13 +518,17 @@ int project(const int32_t* cof, const int32_t* pc, int64_t n, int32_t* pf, hipSt
 constexpr int kIpThreads = 1024;
 constexpr int kIpWaves = kIpThreads / kWave;
 
+// One workgroup owns a graph's search state; its waves share the CU's
+// caches and order their accesses with workgroup barriers, and kernel
+// boundaries order them with the grid-wide level kernels.  Plain accesses
+// therefore suffice (no device-scope coherence is needed).
 template <class T>
 __device__ __forceinline__ T ld_acq(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return gld(p, 0);
 }
 template <class T>
 __device__ __forceinline__ void st_rel(T* p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  gst(p, 0, v);
 }
 
 // Exclusive block scan of one int64 per thread; returns the block total.
