@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 RATE_KERNELS = ["k_rate_tiny (degree 1-32)", "k_rate_small (degree 33-128)", "k_rate_mid (degree 129-1024)",
-                "k_rate_large (degree 1025-4096)", "hub path (4 kernels, degree > 4096)"]
+                "k_rate_large (degree 1025-4096)", "hub path (6 kernels, degree > 4096)"]
 
 
 def log(msg: str) -> None:
@@ -174,13 +174,13 @@ def run_two_graphs(args) -> int:
         for g in graphs:
             og = oracle.OGraph.of(g)
             _, _, U = oracle.bounds(g.n, 1, k, 3, 100, 14)
-            r = oracle.cluster(og, U, 10, 1, 1)
+            r = oracle.cluster(og, U, 10, 0, 1)
             cv += r.visits
             rounds += r.rounds
         ct = time.perf_counter() - t1
         cpu = {"value": cv / ct, "unit": "edge visits/s", "cores": 1, "kind": "oracle",
-               "sample": "oracle level-0 clustering (up to 10 LP rounds with the coarsening stop rule) of both "
-                         f"graphs, single thread, gcc -O2: {rounds} rounds, {cv} visits in {ct:.1f}s"}
+               "sample": "oracle level-0 clustering (10 LP rounds) of both graphs, single thread, gcc -O2: "
+                         f"{rounds} rounds, {cv} visits in {ct:.1f}s"}
 
     line = base_line(
         "SCLaP edge visits/s (multilevel partition, clustering + refinement rounds)", visits / elapsed,
