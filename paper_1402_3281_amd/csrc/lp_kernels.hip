@@ -520,39 +520,121 @@ __device__ __forceinline__ uint32_t table_size(int64_t d, int64_t nlabels) {
   return tsz;
 }
 
-// Walk entries [lo, hi) of a row with stride `step` starting at `first`,
-// loading B entries (ids, then labels) before inserting them; accumulates
-// the own label's connection and whether a foreign label was seen.
+// Loads of a binned node that its iteration needs first: the list entry and
+// row (issued one node ahead), then the own label and weight and the first B
+// entries of the row for this thread (issued while the node before is being
+// finished), so that a node starts with its label gathers.
 template <int B>
-__device__ __forceinline__ void table_fill(const DevSlot& sl, int64_t row0, int64_t first, int64_t hi, int step,
-                                           int32_t own, int32_t* keys, int32_t* vals, uint32_t mask,
-                                           int64_t& my_own, bool& foreign) {
-  for (int64_t e = first; e < hi; e += (int64_t)step * B) {
-    int32_t nb[B], wt[B], tt[B];
-    bool ok[B];
+struct NodePre {
+  int64_t u;
+  uint64_t x;
+  int32_t own;
+  int64_t cv;
+  int32_t nb[B], wt[B];
+};
+
+template <int B, bool ONE>
+__device__ __forceinline__ void pre_row(NodePre<B>& p, const DevSlot* __restrict__ S, int ns, int first, int step) {
+  const DevSlot& sl = S[SLOT(p.u)];
+  const int64_t v = p.u - sl.nbase;
+  const int64_t e0 = info_e0(p.x);
+  const int d = info_d(p.x);
+  p.own = gld(sl.lab, v);
+  p.cv = gld(sl.nw, v);
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int ee = first + q * step;
+    const int64_t ec = e0 + (ee < d ? ee : d - 1);
+    p.nb[q] = gld(sl.col, ec);
+    p.wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
+  }
+}
+
+// Aggregate the d entries of a row into the table: this thread takes entries
+// first, first + step, ..., B at a time, the first B already loaded (nb, wt).
+// The next B entries are loaded before the current ones are inserted.  Labels
+// outside [lo, hi] (the direction rule) are not inserted; the own label's
+// connection and whether a foreign label was seen are accumulated.
+template <int B>
+__device__ __forceinline__ void table_fill(const int32_t* __restrict__ col, const int32_t* __restrict__ ew,
+                                           const int32_t* __restrict__ lab, int64_t row0, int first, int d, int step,
+                                           int32_t own, int32_t lo, int32_t hi, int32_t* keys, int32_t* vals,
+                                           uint32_t mask, int32_t (&nb)[B], int32_t (&wt)[B], int64_t& my_own,
+                                           bool& foreign) {
+  for (int base = 0; base < d; base += step * B) {
+    int32_t tt[B], cw[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      const int64_t ee = e + (int64_t)q * step;
-      ok[q] = ee < hi;
-      const int64_t ec = row0 + (ok[q] ? ee : hi - 1);
-      nb[q] = gld(sl.col, ec);
-      wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
+      tt[q] = gld(lab, nb[q]);
+      cw[q] = wt[q];
     }
+    const int nbase = base + step * B;
+    if (nbase < d) {
 #pragma unroll
-    for (int q = 0; q < B; ++q) tt[q] = gld(sl.lab, nb[q]);
+      for (int q = 0; q < B; ++q) {
+        const int ee = nbase + first + q * step;
+        const int64_t ec = row0 + (ee < d ? ee : d - 1);
+        nb[q] = gld(col, ec);
+        wt[q] = ew ? gld(ew, ec) : 1;
+      }
+    }
 #pragma unroll
     for (int q = 0; q < B; ++q) {
       const int32_t tq = tt[q];
-      if (!ok[q]) continue;
+      if (base + first + q * step >= d) continue;
       if (tq == own) {
-        my_own += wt[q];
+        my_own += cw[q];
         continue;
       }
       foreign = true;
-      if (dir_blocked(sl, tq, own)) continue;
-      table_add(keys, vals, mask, tq, wt[q]);
+      if (tq < lo || tq > hi) continue;
+      table_add(keys, vals, mask, tq, cw[q]);
     }
   }
+}
+
+// Labels that the direction rule lets a node with label own choose, as an
+// interval: odd rounds only smaller labels, even rounds only larger ones.
+__device__ __forceinline__ void dir_interval(const DevSlot& sl, int32_t own, int32_t& lo, int32_t& hi) {
+  const bool down = sl.dir_rule && (sl.round & 1), up = sl.dir_rule && !(sl.round & 1);
+  lo = up ? own + 1 : INT32_MIN;
+  hi = down ? own - 1 : INT32_MAX;
+}
+
+// Best eligible candidate among the table slots first, first + step, ...
+// below tsz (keys -1 = empty).  C slots per thread are read at a time and
+// their W lookups are issued together, so that a thread waits for one round
+// of gathers per C slots rather than one per candidate.  A slot that cannot
+// beat the own label reads W(own) instead (always a valid label).
+template <int C>
+__device__ __forceinline__ uint64_t scan_table(const DevSlot& sl, const int32_t* keys, const int32_t* vals,
+                                               uint32_t tsz, uint32_t first, uint32_t step, bool own_ok,
+                                               int64_t conn_own, int32_t own, int64_t cv) {
+  uint64_t best = 0;
+  for (uint32_t j0 = first; j0 < tsz; j0 += step * C) {
+    int32_t t[C], c[C];
+    int64_t wt[C];
+    bool b[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const uint32_t j = j0 + (uint32_t)q * step;
+      const uint32_t jc = j < tsz ? j : tsz - 1;
+      t[q] = j < tsz ? keys[jc] : -1;
+      c[q] = vals[jc];
+    }
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int64_t cq = c[q];
+      b[q] = t[q] >= 0 && (!own_ok || cq > conn_own || (cq == conn_own && t[q] < own));
+      wt[q] = gld(sl.W, b[q] ? t[q] : own);
+    }
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const uint64_t k = (b[q] && wt[q] + cv <= sl.cap) ? pack_key(c[q], t[q]) : 0ull;
+      best = best > k ? best : k;
+    }
+  }
+  return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -562,19 +644,32 @@ template <int TS, bool ONE>
 __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
                                                const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
                                                uint32_t nblk, int32_t* lds) {
+  constexpr int B = 4;
   const int w = threadIdx.x / kWave;
   int32_t* keys = lds + w * TS;
   int32_t* vals = lds + 4 * TS + w * TS;
   const int lane = (int)lane_id();
-  for (uint32_t i = __builtin_amdgcn_readfirstlane(bid * 4 + w); i < cnt; i += nblk * 4) {
-    const int64_t u = gld(list, i);
-    const uint64_t x = gld(info, i);
+  const uint32_t stride = nblk * 4;
+  uint32_t i = __builtin_amdgcn_readfirstlane(bid * 4 + w);
+  if (i >= cnt) return;
+  NodePre<B> p;
+  p.u = gld(list, i);
+  p.x = gld(info, i);
+  pre_row<B, ONE>(p, S, ns, lane, kWave);
+  for (; i < cnt; i += stride) {
+    const bool has_next = i + stride < cnt;
+    const uint32_t in = has_next ? i + stride : i;
+    const int64_t un = gld(list, in);
+    const uint64_t xn = gld(info, in);
+    const int64_t u = p.u;
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t e0 = info_e0(x);
-    const int d = info_d(x);
-    const int32_t own = gld(sl.lab, v);
-    const int64_t cv = gld(sl.nw, v);
+    const int64_t e0 = info_e0(p.x);
+    const int d = info_d(p.x);
+    const int32_t own = __builtin_amdgcn_readfirstlane(p.own);
+    const int64_t cv = p.cv;
+    int32_t lo, hi;
+    dir_interval(sl, own, lo, hi);
     const uint32_t tsz = table_size(d, sl.nlabels);
     for (uint32_t j = lane; j < tsz; j += kWave) {
       keys[j] = -1;
@@ -583,18 +678,17 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
     wave_sync();
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<4>(sl, e0, lane, d, kWave, own, keys, vals, tsz - 1, my_own, foreign);
+    table_fill<B>(sl.col, sl.ew, sl.lab, e0, lane, d, kWave, own, lo, hi, keys, vals, tsz - 1, p.nb, p.wt, my_own,
+                  foreign);
     for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
     const bool boundary = __ballot(foreign) != 0;
     wave_sync();
     const bool own_ok = own_allowed(sl, own);
-    uint64_t best = 0;
-    for (uint32_t j = lane; j < tsz; j += kWave) {
-      const int32_t t = keys[j];
-      if (t < 0) continue;
-      const uint64_t k = cand_key(sl, own_ok, my_own, own, cv, t, vals[j]);
-      best = best > k ? best : k;
-    }
+    uint64_t best = scan_table<TS / kWave < 8 ? TS / kWave : 8>(sl, keys, vals, tsz, lane, kWave, own_ok, my_own,
+                                                                 own, cv);
+    p.u = un;
+    p.x = xn;
+    if (has_next) pre_row<B, ONE>(p, S, ns, lane, kWave);
     for (int off = 32; off > 0; off >>= 1) {
       const uint64_t o = __shfl_xor(best, off);
       best = best > o ? best : o;
@@ -641,20 +735,32 @@ template <int TS, int NT, bool ONE>
 __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
                                                 const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
                                                 uint32_t nblk, int32_t* lds) {
+  constexpr int B = 4;
   int32_t* keys = lds;
   int32_t* vals = lds + TS;
   __shared__ uint64_t red64[8];
   __shared__ int64_t redi[8];
   __shared__ int redo[8];
-  for (uint32_t i = bid; i < cnt; i += nblk) {
-    const int64_t u = gld(list, i);
-    const uint64_t x = gld(info, i);
+  uint32_t i = bid;
+  if (i >= cnt) return;
+  NodePre<B> p;
+  p.u = gld(list, i);
+  p.x = gld(info, i);
+  pre_row<B, ONE>(p, S, ns, threadIdx.x, NT);
+  for (; i < cnt; i += nblk) {
+    const bool has_next = i + nblk < cnt;
+    const uint32_t in = has_next ? i + nblk : i;
+    const int64_t un = gld(list, in);
+    const uint64_t xn = gld(info, in);
+    const int64_t u = p.u;
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
-    const int64_t e0 = info_e0(x);
-    const int d = info_d(x);
-    const int32_t own = gld(sl.lab, v);
-    const int64_t cv = gld(sl.nw, v);
+    const int64_t e0 = info_e0(p.x);
+    const int d = info_d(p.x);
+    const int32_t own = __builtin_amdgcn_readfirstlane(p.own);
+    const int64_t cv = p.cv;
+    int32_t lo, hi;
+    dir_interval(sl, own, lo, hi);
     const uint32_t tsz = table_size(d, sl.nlabels);
     const uint32_t mask = tsz - 1;
     for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
@@ -664,17 +770,15 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     __syncthreads();
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<4>(sl, e0, threadIdx.x, d, NT, own, keys, vals, mask, my_own, foreign);
+    table_fill<B>(sl.col, sl.ew, sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask, p.nb, p.wt, my_own,
+                  foreign);
     const int64_t conn_own = block_reduce(my_own, redi, OpAdd64());
     const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
     const bool own_ok = own_allowed(sl, own);
-    uint64_t best = 0;
-    for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
-      const int32_t t = keys[j];
-      if (t < 0) continue;
-      const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, vals[j]);
-      best = best > k ? best : k;
-    }
+    uint64_t best = scan_table<8>(sl, keys, vals, tsz, threadIdx.x, NT, own_ok, conn_own, own, cv);
+    p.u = un;
+    p.x = xn;
+    if (has_next) pre_row<B, ONE>(p, S, ns, threadIdx.x, NT);
     best = block_reduce(best, red64, OpMax64());
     if (threadIdx.x == 0) {
       if (own_ok) {
@@ -1106,13 +1210,7 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
         __syncthreads();
         fits = s_used <= (uint32_t)kHubPartFill;
         if (fits) {
-          uint64_t b = 0;
-          for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
-            const int32_t t = keys[j];
-            if (t < 0) continue;
-            const uint64_t k = cand_key(sl, own_ok, conn_own, own, cv, t, vals[j]);
-            b = b > k ? b : k;
-          }
+          uint64_t b = scan_table<8>(sl, keys, vals, tsz, threadIdx.x, blockDim.x, own_ok, conn_own, own, cv);
           b = block_reduce(b, red64, OpMax64());
           best = best > b ? best : b;
         }
