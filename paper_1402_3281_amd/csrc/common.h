@@ -65,11 +65,25 @@ struct DevSlot {
   int32_t mode;           // MODE_CLUSTER / MODE_REFINE
   int32_t dir_rule;
   int32_t use_flags;      // rate only nodes with flag_cur set
-  int32_t hub_off_valid;  // unused padding for alignment
-  int32_t pad;
+  int32_t conn_k;         // refine: columns of conn (the block count k)
+  int32_t conn_mode;      // CONN_NONE / CONN_BUILD / CONN_RATE
+  int32_t* conn;          // refine: n x conn_k block connections conn(v, b), or nullptr
 };
 
-enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_N = 4 };
+// Refinement with block connections kept per node: the first round of a
+// level builds them (CONN_BUILD); later rounds rate from them (CONN_RATE),
+// and every move updates the rows of the mover's neighbours.  A round whose
+// movers are more than 1 / kConnPushDiv of the nodes does not update them (two
+// atomics per entry of every mover would cost more than rebuilding): the next
+// round rebuilds the rows of its rated nodes, which include every node with a
+// moved neighbour.
+enum : int { CONN_NONE = 0, CONN_BUILD = 1, CONN_RATE = 2 };
+constexpr int kConnMaxK = 64;  // at most one wave of columns
+constexpr int64_t kConnPushDiv = 16;
+
+// CTR_STALE: the moves of the round were not added to the block
+// connections (the rows of the next rated set are rebuilt instead).
+enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_STALE = 3, CTR_N = 4 };
 
 // Degree bins of the rating kernels:
 //   0: 1..8       8 lanes per node        5: 129..512    one wave, 1024-entry LDS table

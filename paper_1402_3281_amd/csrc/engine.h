@@ -67,6 +67,8 @@ struct Job {
   int64_t* inc = nullptr;
   uint8_t* fcur = nullptr;
   uint8_t* fnext = nullptr;
+  int32_t* conn = nullptr;         // refine: n x k block connections (k <= kConnMaxK)
+  bool conn_stale = false;         // the last round's moves were not added to conn
   int64_t nlabels = 0;
   // outputs
   int32_t* part_out = nullptr;     // caller buffer (level-0 blocks / labels)

@@ -238,6 +238,8 @@ void job_release_lp(Job* j, hipStream_t st, bool keep_lab) {
   dfree(j->inc, st);
   dfree(j->fcur, st);
   dfree(j->fnext, st);
+  dfree(j->conn, st);
+  j->conn = nullptr;
   j->desire = nullptr;
   j->adm = nullptr;
   j->Wt = nullptr;
@@ -304,6 +306,12 @@ int job_begin_refine(Ctx* c, Job* j, int32_t* part, bool owned, hipStream_t st) 
   SCLAP_TRY(dalloc_t(&j->fcur, nn, st));
   SCLAP_TRY(dalloc_t(&j->fnext, nn, st));
   SCLAP_TRY(fill_i64(j->inc, j->k, 0, st));
+  j->conn_stale = false;
+  if (j->k <= kConnMaxK && n > 0) {
+    // block connections: built in the first round, kept by every move
+    SCLAP_TRY(dalloc_t(&j->conn, (size_t)n * kk, st));
+    SCLAP_TRY(fill_i32(j->conn, n * (int64_t)j->k, 0, st));
+  }
   SCLAP_TRY(fill_u8(j->fnext, n, 0, st));
   SCLAP_TRY(fill_u8(j->fcur, n, 0, st));
   SCLAP_TRY(copy_i32(part, j->desire, n, st));
@@ -325,6 +333,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
+  bool any_build = false, any_cached = false;
   for (int s = 0; s < ns; ++s) {
     Job* j = jobs[s];
     const Level& L = j->lv[j->cur];
@@ -354,12 +363,19 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.mode = refine ? MODE_REFINE : MODE_CLUSTER;
     d.dir_rule = j->dir_rule;
     d.use_flags = refine && j->round > 1;
+    d.conn = refine ? j->conn : nullptr;
+    d.conn_k = j->k;
+    d.conn_mode = d.conn ? (j->round == 1 || j->conn_stale ? CONN_BUILD : CONN_RATE) : CONN_NONE;
+    any_build = any_build || d.conn_mode == CONN_BUILD;
+    any_cached = any_cached || d.conn_mode == CONN_RATE;
     N += L.n;
     T_bin += bin_tiles(L.n);
     Lt += j->nlabels;
-    hub_stage += L.hub_stage;
-    hub_parts += refine ? L.hub_parts_r : L.hub_parts_c;
-    hub_mat += refine ? L.hub_mat_r : L.hub_mat_c;
+    if (d.conn_mode != CONN_RATE) {  // nodes rated from block connections skip the bins
+      hub_stage += L.hub_stage;
+      hub_parts += refine ? L.hub_parts_r : L.hub_parts_c;
+      hub_mat += refine ? L.hub_mat_r : L.hub_mat_c;
+    }
   }
   if (N >= ((int64_t)1 << 31) || Lt >= ((int64_t)1 << 32))
     return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
@@ -393,10 +409,12 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_best.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
   }
-  SCLAP_TRY(c->movers.ensure(3 * Nz * sizeof(int32_t), st));  // rated list, movers, big movers
+  // rated list, movers, big movers, old blocks of the movers
+  SCLAP_TRY(c->movers.ensure(4 * Nz * sizeof(int32_t), st));
   int32_t* rated = (int32_t*)c->movers.p;
   int32_t* movers = rated + Nz;
   int32_t* bigm = movers + Nz;
+  int32_t* movers_old = bigm + Nz;
   SCLAP_TRY(c->ckeys.ensure(Nz * 8, st));
   SCLAP_TRY(c->slots_dev.ensure((size_t)ns * sizeof(DevSlot), st));
   DevSlot* S = (DevSlot*)c->slots_dev.p;
@@ -462,13 +480,16 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
   SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights, st,
                         c->profile ? c->ev : nullptr));
+  if (any_build) SCLAP_TRY(launch_conn_build(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, st));
+  if (any_cached) SCLAP_TRY(launch_rate_cached(S, ns, N, rated, meta + 14, st));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
   SCLAP_TRY(launch_incoming_decide(S, ns, N, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
   SCLAP_TRY(launch_contended_small(S, ns, (const uint64_t*)c->ckeys.p, small + 9, node_bits, small + 16, st));
   bool any_refine = false;
   for (int s = 0; s < ns; ++s) any_refine = any_refine || c->pin_slots[s].mode == MODE_REFINE;
-  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, small + 13, bigm, small + 15, any_refine, small + 16, st));
+  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, movers_old, small + 13, bigm, small + 15, any_refine,
+                         small + 16, st));
   const size_t rd = 256 + (size_t)ns * CTR_N * sizeof(int64_t);
   SCLAP_TRY(ctx_ensure_pin(c, rd + 512));
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
@@ -499,7 +520,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                (int64_t*)c->prefix.p, cc, st));
     SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                     (const int64_t*)c->prefix.p, st));
-    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, small + 13, bigm, small + 15, any_refine, nullptr, st));
+    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, movers_old, small + 13, bigm, small + 15, any_refine,
+                           nullptr, st));
     SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
   }
@@ -909,6 +931,7 @@ int step_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st, bool* all_done_ou
         j->rst.visits += visits;
         j->rst.ms += dt;
         j->zero_streak = moved == 0 ? j->zero_streak + 1 : 0;
+        j->conn_stale = c->pin[s * CTR_N + CTR_STALE] != 0;
         const bool done = r >= j->ref_rounds || j->zero_streak >= 2;
         if (done) {
           j->st.rounds_r[j->cur] = r;

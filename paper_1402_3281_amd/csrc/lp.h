@@ -56,9 +56,18 @@ int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32
                           const int64_t* prefix, hipStream_t st);
 // movers (N entries) and mcnt (zeroed) collect the moved nodes of refinement slots.
 // skip (may be NULL): when *skip != 0 the launch does nothing.
+// Refinement with block connections: build them for CONN_BUILD slots from
+// this round's bins (after launch_rate, which laid out the hub chunks), and
+// rate the rated nodes of CONN_RATE slots from them.
+int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
+                      const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, hipStream_t st);
+int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
+                       hipStream_t st);
+// Applies admitted moves; in refinement lists the movers with their old
+// blocks (movers_old) and marks their neighbours (updating block connections).
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* movers,
-                 uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine, const uint32_t* skip,
-                 hipStream_t st);
+                 int32_t* movers_old, uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine,
+                 const uint32_t* skip, hipStream_t st);
 
 // Library primitives (rocPRIM) used as steps: sorts, scans, reductions.
 size_t prim_sort_keys_bytes(size_t n);

@@ -53,7 +53,8 @@ __device__ __forceinline__ int bin_of(int64_t d, int64_t m) {
 // ---------------------------------------------------------------------------
 // Binning: every node of an active slot with degree > 0 (and, in refinement
 // after round 1, in the rated set) goes to its degree bin and to the rated
-// list.  The nodes of every slot are split into tiles of kBinTile; a tile
+// list (nodes rated from block connections go to the rated list only, and
+// their edge visits are counted in its row).  The nodes of every slot are split into tiles of kBinTile; a tile
 // belongs to one slot.  bin_count writes per tile and bin the node count and
 // edge visits; an exclusive scan of those (bin-major) gives every tile its
 // place in each bin, so no counter is shared between workgroups.
@@ -86,7 +87,8 @@ __device__ __forceinline__ BinOf bin_node(const DevSlot& sl, int64_t v) {
     r.e0 = gld(sl.rp, v);
     r.d = gld(sl.rp, v + 1) - r.e0;
     r.take = r.d > 0;
-    r.b = bin_of(r.d, sl.m);
+    // rated from the block connections: the rated list only
+    r.b = sl.conn_mode == CONN_RATE ? kBins : bin_of(r.d, sl.m);
   }
   return r;
 }
@@ -95,7 +97,7 @@ template <bool ONE>
 __global__ void __launch_bounds__(kBinTile) k_bin_count(const DevSlot* __restrict__ S, int ns, int64_t T,
                                                         uint32_t* __restrict__ cnt, int64_t* __restrict__ vis) {
   __shared__ uint32_t s_c[4][kBinRows];
-  __shared__ int64_t s_v[4][kBins];
+  __shared__ int64_t s_v[4][kBinRows];
   const int w = threadIdx.x / kWave;
   for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
     const int s = ONE ? 0 : slot_of_tile(S, ns, t);
@@ -128,13 +130,23 @@ __global__ void __launch_bounds__(kBinTile) k_bin_count(const DevSlot* __restric
     }
     {
       const uint64_t m = __ballot(r.take);
-      if (lane_id() == 0) s_c[w][kBins] = (uint32_t)__popcll(m);
+      // visits of the nodes outside the bins (rated from block connections)
+      const bool cn = r.take && r.b == kBins;
+      int64_t dv = 0;
+      if (__ballot(cn)) {
+        dv = cn ? r.d : 0;
+        for (int off = 32; off > 0; off >>= 1) dv += __shfl_xor(dv, off);
+      }
+      if (lane_id() == 0) {
+        s_c[w][kBins] = (uint32_t)__popcll(m);
+        s_v[w][kBins] = dv;
+      }
     }
     __syncthreads();
     if (threadIdx.x < kBinRows) {
       const int j = threadIdx.x;
       cnt[(int64_t)j * T + t] = s_c[0][j] + s_c[1][j] + s_c[2][j] + s_c[3][j];
-      vis[(int64_t)j * T + t] = j < kBins ? s_v[0][j] + s_v[1][j] + s_v[2][j] + s_v[3][j] : 0;
+      vis[(int64_t)j * T + t] = s_v[0][j] + s_v[1][j] + s_v[2][j] + s_v[3][j];
     }
     __syncthreads();
   }
@@ -171,13 +183,16 @@ __global__ void __launch_bounds__(kBinTile) k_bin_write(const DevSlot* __restric
     if (r.take) {
       uint32_t before = 0, rbefore = 0;
       for (int k = 0; k < w; ++k) {
-        before += s_c[k][r.b];
+        before += r.b < kBins ? s_c[k][r.b] : 0u;
         rbefore += s_c[k][kBins];
       }
       const int64_t u = sl.nbase + v;
-      const int64_t pos = (int64_t)r.b * bin_cap + (off[(int64_t)r.b * T + t] - off[(int64_t)r.b * T]) + before + rank;
-      bins[pos] = (int32_t)u;
-      if (r.b < kBins - 1) binfo[pos] = (uint64_t)r.e0 | ((uint64_t)r.d << 40);
+      if (r.b < kBins) {
+        const int64_t pos =
+            (int64_t)r.b * bin_cap + (off[(int64_t)r.b * T + t] - off[(int64_t)r.b * T]) + before + rank;
+        bins[pos] = (int32_t)u;
+        if (r.b < kBins - 1) binfo[pos] = (uint64_t)r.e0 | ((uint64_t)r.d << 40);
+      }
       rated[(off[(int64_t)kBins * T + t] - off[(int64_t)kBins * T]) + rbefore + rrank] = (int32_t)u;
     }
     __syncthreads();
@@ -204,7 +219,7 @@ __global__ void __launch_bounds__(256) k_bin_totals(const DevSlot* __restrict__ 
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     const int64_t t0 = S[s].tbase, t1 = s + 1 < ns ? S[s + 1].tbase : T;
     int64_t sum = 0;
-    for (int j = 0; j < kBins; ++j) sum += voff[(int64_t)j * T + t1] - voff[(int64_t)j * T + t0];
+    for (int j = 0; j < kBinRows; ++j) sum += voff[(int64_t)j * T + t1] - voff[(int64_t)j * T + t0];
     gst(S[s].ctr, CTR_VISITS, sum);
   }
 }
@@ -1527,11 +1542,12 @@ __global__ void __launch_bounds__(1024) k_contended_small(const DevSlot* __restr
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, int ns,
                                                const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
-                                               int32_t* __restrict__ movers, uint32_t* __restrict__ mcnt,
-                                               const uint32_t* __restrict__ skip) {
+                                               int32_t* __restrict__ movers, int32_t* __restrict__ movers_old,
+                                               uint32_t* __restrict__ mcnt, const uint32_t* __restrict__ skip) {
   __shared__ unsigned long long hk[kApplyTable];
   __shared__ long long hv[kApplyTable];
   __shared__ int32_t s_mov[kAggNodes];
+  __shared__ int32_t s_old[kAggNodes];
   __shared__ uint32_t s_mcnt, s_mbase;
   if (skip && *skip) return;  // the admission is completed on the host-driven path first
   const int64_t N = *rcnt;
@@ -1551,12 +1567,19 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       ok[it] = i < N;
       uu[it] = gld(rated, ok[it] ? i : N - 1);
     }
+    // every load of the iteration is issued before its first store (memory
+    // operations complete in order, so a load after a store waits for it)
     int32_t tt[IT], oo[IT];
+    uint8_t aa[IT];
+    int64_t ww[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const DevSlot& sl = S[SLOT(uu[it])];
-      tt[it] = gld(sl.desire, uu[it] - sl.nbase);
-      oo[it] = gld(sl.lab, uu[it] - sl.nbase);
+      const int64_t v = uu[it] - sl.nbase;
+      tt[it] = gld(sl.desire, v);
+      oo[it] = gld(sl.lab, v);
+      aa[it] = gld(sl.adm, v);
+      ww[it] = gld(sl.nw, v);
     }
     for (int it = 0; it < IT; ++it) {
       const int64_t u = uu[it];
@@ -1569,11 +1592,15 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       int64_t cv = 0;
       if (ok[it] && t != own) {
         gst(sl.inc, t, (int64_t)0);
-        admitted = gld(sl.adm, v) != 0;
+        admitted = aa[it] != 0;
         if (admitted) {
-          cv = gld(sl.nw, v);
+          cv = ww[it];
           gst(sl.lab, v, t);
-          if (sl.mode == MODE_REFINE) s_mov[atomicAdd(&s_mcnt, 1u)] = (int32_t)u;
+          if (sl.mode == MODE_REFINE) {
+            const uint32_t q = atomicAdd(&s_mcnt, 1u);
+            s_mov[q] = (int32_t)u;
+            s_old[q] = own;
+          }
         } else {
           gst(sl.desire, v, own);
         }
@@ -1615,23 +1642,104 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
     }
     if (threadIdx.x == 0) s_mbase = s_mcnt ? atomicAdd(mcnt, s_mcnt) : 0;
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < s_mcnt; j += blockDim.x) movers[s_mbase + j] = s_mov[j];
+    for (uint32_t j = threadIdx.x; j < s_mcnt; j += blockDim.x) {
+      movers[s_mbase + j] = s_mov[j];
+      movers_old[s_mbase + j] = s_old[j];
+    }
     __syncthreads();
   }
 }
 
-// Refinement: the neighbours of moved nodes join the next rated set.  Each
-// wave takes 64 movers; rows of up to 64 entries are walked by their lane,
-// rows of up to kMarkBig entries by the whole wave; longer rows are listed
-// and walked by all workgroups together (k_mark_big).
+// Refinement: the neighbours of moved nodes join the next rated set, and
+// where block connections are kept, every entry (u, v, w) of a mover u from
+// block a to block b moves w from conn(v, a) to conn(v, b).  Each wave takes
+// 64 movers; rows of up to 64 entries are walked by their lane, rows of up
+// to kMarkBig entries by the whole wave; longer rows are listed (by mover
+// index) and walked by all workgroups together (k_mark_big).
 constexpr int64_t kMarkBig = 4096;
+
+__device__ __forceinline__ void conn_add(int32_t* conn, int64_t i, int32_t v) {
+  __hip_atomic_fetch_add((SCLAP_GLOBAL int*)(conn + i), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Entries first, first + step, ... below d of a mover's row starting at e0:
+// mark every neighbour, and move the entry's weight from block a to block b in
+// the neighbour's connections (a < 0: no connections).  The next B entries
+// are loaded before the current ones are written, so that a thread does not
+// wait for its stores and atomics (memory operations complete in order).
+template <int B>
+__device__ __forceinline__ void mark_row(const DevSlot& sl, int64_t e0, int64_t first, int64_t d, int step,
+                                         int32_t a, int32_t b) {
+  if (first >= d) return;
+  const bool conn = a >= 0;
+  int32_t nb[B], w[B];
+#pragma unroll
+  for (int q = 0; q < B; ++q) {
+    const int64_t ee = first + (int64_t)q * step;
+    const int64_t ec = e0 + (ee < d ? ee : d - 1);
+    nb[q] = gld(sl.col, ec);
+    w[q] = conn && sl.ew ? gld(sl.ew, ec) : 1;
+  }
+  for (int64_t base = first; base < d; base += (int64_t)step * B) {
+    int32_t cn[B], cw[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      cn[q] = nb[q];
+      cw[q] = w[q];
+    }
+    const int64_t next = base + (int64_t)step * B;
+    if (next < d) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int64_t ee = next + (int64_t)q * step;
+        const int64_t ec = e0 + (ee < d ? ee : d - 1);
+        nb[q] = gld(sl.col, ec);
+        w[q] = conn && sl.ew ? gld(sl.ew, ec) : 1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      if (base + (int64_t)q * step >= d) continue;
+      gst(sl.flag_next, cn[q], (uint8_t)1);
+      if (conn) {
+        const int64_t r = (int64_t)cn[q] * sl.conn_k;
+        conn_add(sl.conn, r + a, -cw[q]);
+        conn_add(sl.conn, r + b, cw[q]);
+      }
+    }
+  }
+}
+
+// Whether the moves of the round are added to the slot's block connections
+// (the same answer for every thread: it depends on the final moved count).
+__device__ __forceinline__ bool conn_push(const DevSlot& sl) {
+  return sl.conn && gld(sl.ctr, CTR_MOVED) * kConnPushDiv <= sl.n;
+}
+
+// Blocks (a, b) of mover i when its moves are added to block connections,
+// else -1.
+__device__ __forceinline__ void mover_blocks(const DevSlot& sl, const int32_t* movers_old, uint32_t i, int64_t v,
+                                             int32_t& a, int32_t& b) {
+  a = b = -1;
+  if (conn_push(sl)) {
+    const int32_t oa = gld(movers_old, i), nb = gld(sl.lab, v);
+    if ((uint32_t)oa < (uint32_t)sl.conn_k && (uint32_t)nb < (uint32_t)sl.conn_k) {
+      a = oa;
+      b = nb;
+    }
+  }
+}
 
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int ns,
-                                              const int32_t* __restrict__ movers, const uint32_t* __restrict__ mcnt,
+                                              const int32_t* __restrict__ movers,
+                                              const int32_t* __restrict__ movers_old, const uint32_t* __restrict__ mcnt,
                                               int32_t* __restrict__ big, uint32_t* __restrict__ big_cnt,
                                               const uint32_t* __restrict__ skip) {
   if (skip && *skip) return;
+  if (blockIdx.x == 0)
+    for (int s = threadIdx.x; s < ns; s += blockDim.x)
+      if (S[s].conn && !conn_push(S[s])) gst(S[s].ctr, CTR_STALE, (int64_t)1);
   const uint32_t cnt = *mcnt;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -1639,43 +1747,239 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
     const uint32_t i = base + lane_id();
     const DevSlot* sl = nullptr;
     int64_t e0 = 0, d = 0;
-    int32_t u = 0;
+    int32_t u = 0, a = -1, b = -1;
     if (i < cnt) {
       u = movers[i];
       sl = &S[SLOT(u)];
       const int64_t v = u - sl->nbase;
       e0 = gld(sl->rp, v);
       d = gld(sl->rp, v + 1) - e0;
+      mover_blocks(*sl, movers_old, i, v, a, b);
     }
-    if (d <= kWave)
-      for (int64_t e = e0; e < e0 + d; ++e) gst(sl->flag_next, gld(sl->col, e), (uint8_t)1);
-    if (d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = u;
+    if (d <= kWave && d > 0) mark_row<4>(*sl, e0, 0, d, 1, a, b);
+    if (d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
     uint64_t mid = __ballot(d > kWave && d <= kMarkBig);
     while (mid) {
       const int l = __ffsll((unsigned long long)mid) - 1;
       mid &= mid - 1;
       const int64_t be0 = __shfl(e0, l), bd = __shfl(d, l);
-      const int32_t bu = __shfl(u, l);
+      const int32_t bu = __shfl(u, l), ba = __shfl(a, l), bb = __shfl(b, l);
       const DevSlot& bs = S[SLOT(bu)];
-      for (int64_t e = be0 + lane_id(); e < be0 + bd; e += kWave) gst(bs.flag_next, gld(bs.col, e), (uint8_t)1);
+      mark_row<4>(bs, be0, lane_id(), bd, kWave, ba, bb);
     }
   }
 }
 
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark_big(const DevSlot* __restrict__ S, int ns,
+                                                  const int32_t* __restrict__ movers,
+                                                  const int32_t* __restrict__ movers_old,
                                                   const int32_t* __restrict__ big, const uint32_t* __restrict__ big_cnt,
                                                   const uint32_t* __restrict__ skip) {
   if (skip && *skip) return;
   const uint32_t cnt = *big_cnt;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (uint32_t i = 0; i < cnt; ++i) {
-    const int64_t u = big[i];
+    const uint32_t mi = (uint32_t)big[i];
+    const int64_t u = movers[mi];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
+    int32_t a, b;
+    mover_blocks(sl, movers_old, mi, v, a, b);
     const int64_t e0 = sl.rp[v], e1 = sl.rp[v + 1];
-    for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += stride)
-      gst(sl.flag_next, gld(sl.col, e), (uint8_t)1);
+    mark_row<4>(sl, e0, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, e1 - e0, (int)stride, a, b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block connections, first round of a refined level: conn(v, b) for every
+// binned node of a CONN_BUILD slot, by G lanes per node (degree bins 0-7)
+// adding into a per-node LDS row, or one wave per hub chunk (bin 8) adding
+// its LDS row to the (zeroed) global row.
+// ---------------------------------------------------------------------------
+template <int G, bool ONE>
+__device__ __forceinline__ void conn_build_group(const DevSlot* __restrict__ S, int ns,
+                                                 const int32_t* __restrict__ list, const uint64_t* __restrict__ info,
+                                                 uint32_t cnt, uint32_t wid, uint32_t nwaves, int32_t* rows) {
+  constexpr int NG = kWave / G;
+  constexpr int B = 4;
+  const int lane = (int)lane_id(), gl = lane & (G - 1), gi = lane / G;
+  int32_t* my = rows + gi * kConnMaxK;
+  for (uint32_t base = wid * NG; base < cnt; base += nwaves * NG) {
+    const uint32_t i = base + gi;
+    const bool valid = i < cnt;
+    const uint32_t ic = valid ? i : cnt - 1;
+    const int64_t u = gld(list, ic);
+    const uint64_t x = gld(info, ic);
+    const DevSlot& sl = S[SLOT(u)];
+    const bool build = valid && sl.conn_mode == CONN_BUILD;
+    const int K = sl.conn_k;
+    for (int t = gl; t < kConnMaxK; t += G) my[t] = 0;
+    wave_sync();
+    if (build) {
+      const int64_t e0 = info_e0(x);
+      const int d = info_d(x);
+      for (int e = gl; e < d; e += G * B) {
+        int32_t nb[B], w[B], t[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          const int ee = e + q * G;
+          const int64_t ec = e0 + (ee < d ? ee : d - 1);
+          nb[q] = gld(sl.col, ec);
+          w[q] = sl.ew ? gld(sl.ew, ec) : 1;
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) t[q] = gld(sl.lab, nb[q]);
+#pragma unroll
+        for (int q = 0; q < B; ++q)
+          if (e + q * G < d && (uint32_t)t[q] < (uint32_t)K) atomicAdd(&my[t[q]], w[q]);
+      }
+    }
+    wave_sync();
+    if (build) {
+      const int64_t r = (u - sl.nbase) * K;
+      for (int t = gl; t < K; t += G) gst(sl.conn, r + t, my[t]);
+    }
+    wave_sync();
+  }
+}
+
+template <bool ONE>
+__device__ __forceinline__ void conn_build_hubs(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
+                                                const HubLayout& L, uint32_t wid, uint32_t nwaves, int32_t* row) {
+  constexpr int B = 4;
+  const int lane = (int)lane_id();
+  const uint32_t nchunks = L.totals[0];
+  for (uint32_t c = wid; c < nchunks; c += nwaves) {
+    const uint32_t h = L.chunk_hub[c];
+    const int64_t u = gld(list, h);
+    const DevSlot& sl = S[SLOT(u)];
+    if (sl.conn_mode != CONN_BUILD) continue;
+    const int K = sl.conn_k;
+    const int64_t v = u - sl.nbase;
+    const int64_t e0 = gld(sl.rp, v), d = gld(sl.rp, v + 1) - e0;
+    const int64_t c0 = (int64_t)(c - L.chunk_off[h]) * kHubChunk;
+    const int64_t c1 = c0 + kHubChunk < d ? c0 + kHubChunk : d;
+    row[lane] = 0;
+    wave_sync();
+    for (int64_t e = c0 + lane; e < c1; e += kWave * B) {
+      int32_t nb[B], w[B], t[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int64_t ee = e + q * kWave;
+        const int64_t ec = e0 + (ee < c1 ? ee : c1 - 1);
+        nb[q] = gld(sl.col, ec);
+        w[q] = sl.ew ? gld(sl.ew, ec) : 1;
+      }
+#pragma unroll
+      for (int q = 0; q < B; ++q) t[q] = gld(sl.lab, nb[q]);
+#pragma unroll
+      for (int q = 0; q < B; ++q)
+        if (e + q * kWave < c1 && (uint32_t)t[q] < (uint32_t)K) atomicAdd(&row[t[q]], w[q]);
+    }
+    wave_sync();
+    if (lane < K && row[lane]) conn_add(sl.conn, v * K + lane, row[lane]);
+    wave_sync();
+  }
+}
+
+// Rows of the hubs of CONN_BUILD slots cleared (their chunks add into them).
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_conn_zero_hubs(const DevSlot* __restrict__ S, int ns,
+                                                        const int32_t* __restrict__ list,
+                                                        const uint32_t* __restrict__ cnt_ptr) {
+  const uint32_t cnt = *cnt_ptr;
+  const int lane = (int)lane_id();
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; i < cnt; i += waves) {
+    const int64_t u = gld(list, i);
+    const DevSlot& sl = S[SLOT(u)];
+    if (sl.conn_mode != CONN_BUILD || lane >= sl.conn_k) continue;
+    gst(sl.conn, (u - sl.nbase) * sl.conn_k + lane, 0);
+  }
+}
+
+// Blocks [b * nblk, (b + 1) * nblk) serve bin b (0-7); blocks from 8 * nblk
+// the hub chunks (when `hubs`).
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_conn_build(const DevSlot* __restrict__ S, int ns,
+                                                    const int32_t* __restrict__ bins,
+                                                    const uint64_t* __restrict__ binfo, int64_t bin_cap,
+                                                    const uint32_t* __restrict__ bin_cnt, uint32_t nblk, int hubs,
+                                                    HubLayout L) {
+  __shared__ int32_t rows[4][8 * kConnMaxK];
+  const int w = threadIdx.x / kWave;
+  const uint32_t b = blockIdx.x / nblk, bid = blockIdx.x % nblk;
+  const uint32_t wid = bid * 4 + w, nw = nblk * 4;
+  if (b == 8) {
+    if (hubs && !*L.overflow) conn_build_hubs<ONE>(S, ns, bins + 8 * bin_cap, L, wid, nw, rows[w]);
+    return;
+  }
+  const int32_t* list = bins + b * bin_cap;
+  const uint64_t* info = binfo + b * bin_cap;
+  const uint32_t cnt = bin_cnt[b];
+  if (b == 0) conn_build_group<8, ONE>(S, ns, list, info, cnt, wid, nw, rows[w]);
+  else if (b == 1) conn_build_group<16, ONE>(S, ns, list, info, cnt, wid, nw, rows[w]);
+  else if (b == 2) conn_build_group<32, ONE>(S, ns, list, info, cnt, wid, nw, rows[w]);
+  else conn_build_group<64, ONE>(S, ns, list, info, cnt, wid, nw, rows[w]);
+}
+
+// ---------------------------------------------------------------------------
+// Rating from block connections: one thread per rated node of a CONN_RATE
+// slot (the nodes of other slots were rated from the bins).  The candidates
+// are the blocks with conn(v, b) > 0; the choice is the same as from the
+// neighbour labels.
+// ---------------------------------------------------------------------------
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_rate_cached(const DevSlot* __restrict__ S, int ns,
+                                                     const int32_t* __restrict__ rated,
+                                                     const uint32_t* __restrict__ rcnt) {
+  const uint32_t cnt = *rcnt;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+    const int64_t u = gld(rated, i);
+    const DevSlot& sl = S[SLOT(u)];
+    if (sl.conn_mode != CONN_RATE) continue;
+    const int64_t v = u - sl.nbase;
+    const int K = sl.conn_k;
+    const int32_t own = gld(sl.lab, v);
+    const int64_t cv = gld(sl.nw, v);
+    const int32_t* row = sl.conn + v * K;
+    int32_t lo, hi;
+    dir_interval(sl, own, lo, hi);
+    const bool own_ok = own_allowed(sl, own);
+    const int64_t conn_own = (uint32_t)own < (uint32_t)K ? gld(row, own) : 0;
+    bool foreign = false;
+    uint64_t best = 0;
+    auto consider = [&](int t, int64_t c) {
+      if (c <= 0 || t == own) return;
+      foreign = true;
+      if (t < lo || t > hi) return;
+      const bool beats = !own_ok || c > conn_own || (c == conn_own && t < own);
+      if (beats && gld(sl.W, t) + cv <= sl.cap) {
+        const uint64_t k = pack_key(c, t);
+        best = best > k ? best : k;
+      }
+    };
+    if ((K & 3) == 0) {
+      // rows of a multiple of 4 columns are 16-byte aligned
+      const int4* row4 = (const int4*)row;
+      for (int t = 0; t < K; t += 4) {
+        const int4 q = row4[t >> 2];
+        consider(t, q.x);
+        consider(t + 1, q.y);
+        consider(t + 2, q.z);
+        consider(t + 3, q.w);
+      }
+    } else {
+      for (int t = 0; t < K; ++t) consider(t, gld(row, t));
+    }
+    if (own_ok) {
+      const uint64_t ok = pack_key(conn_own, own);
+      best = best > ok ? best : ok;
+    }
+    gst(sl.desire, v, best ? key_label(best) : own);
+    if (foreign) gst(sl.flag_next, v, (uint8_t)1);
   }
 }
 
@@ -1764,6 +2068,22 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
   return SCLAP_OK;
 }
 
+int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
+                      const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, hipStream_t st) {
+  const unsigned G = grid_for(n_hint, 256, 1024);
+  if (hubs) LAUNCH(k_conn_zero_hubs, 64, 256, S, ns, bins + 8 * bin_cap, bin_cnt + 8);
+  LAUNCH(k_conn_build, 9 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G, hubs ? 1 : 0, hub);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
+                       hipStream_t st) {
+  LAUNCH(k_rate_cached, grid_for(N, 256, 4096), 256, S, ns, rated, rcnt);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
 int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
                            uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st) {
   LAUNCH(k_incoming, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt);
@@ -1796,12 +2116,12 @@ int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const
 }
 
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* movers,
-                 uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine, const uint32_t* skip,
-                 hipStream_t st) {
-  LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, movers, mcnt, skip);
+                 int32_t* movers_old, uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine,
+                 const uint32_t* skip, hipStream_t st) {
+  LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, movers, movers_old, mcnt, skip);
   if (any_refine) {
-    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, movers, mcnt, big, big_cnt, skip);
-    LAUNCH(k_mark_big, 1024, 256, S, ns, big, big_cnt, skip);
+    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, movers, movers_old, mcnt, big, big_cnt, skip);
+    LAUNCH(k_mark_big, 1024, 256, S, ns, movers, movers_old, big, big_cnt, skip);
   }
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;

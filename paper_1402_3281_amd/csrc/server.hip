@@ -52,13 +52,15 @@ struct ServedJob {
 };
 
 // Device bytes a job may hold at once: its input copy, a hierarchy of at
-// most two weighted copies of the input, the LP state of a level and the
+// most two weighted copies of the input, the LP state of a level (with the
+// block connections of refinement, n x k int32 for k <= kConnMaxK) and the
 // initial-partition scratch.
-int64_t footprint_of(const sclap_csr& g) {
+int64_t footprint_of(const sclap_csr& g, int32_t k) {
   const int64_t n = g.n, m = g.m;
   const int64_t input = 8 * (n + 1) + 4 * m + (g.ew ? 4 * m : 0) + (g.nw ? (int64_t)g.nw_bytes * n : 0);
   const int64_t hierarchy = 2 * (8 * (n + 1) + 8 * m + 8 * n + 4 * n);
-  return input + hierarchy + 48 * n + 4096;
+  const int64_t conn = k <= kConnMaxK ? 4 * n * (int64_t)k : 0;
+  return input + hierarchy + 48 * n + conn + 4096;
 }
 
 void free_input(ServedJob* sj, hipStream_t st) {
@@ -210,7 +212,7 @@ int sclap_server_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticke
     return fail(SCLAP_EINVAL, "bad job");
   if (g.nw && g.nw_bytes != 4 && g.nw_bytes != 8) return fail(SCLAP_EINVAL, "nw_bytes must be 4 or 8");
   ServedJob* sj = new ServedJob();
-  sj->footprint = footprint_of(g);
+  sj->footprint = footprint_of(g, job->k);
   if (sj->footprint > srv->budget) {
     delete sj;
     return fail(SCLAP_EBUDGET, "job larger than the server's memory budget");

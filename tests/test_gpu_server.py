@@ -34,8 +34,9 @@ def test_served_equals_alone(sc, ctx):
     devs = [sc.DeviceGraph.from_host(g) for g in graphs]
     parts = [torch.full((g.n,), -1, dtype=torch.int32, device="cuda") for g in graphs]
     # a budget of about two of the largest jobs (a job holds about 20 B per
-    # edge and 100 B per node), so admission waits for retirements
-    budget = 2 * max(20 * g.m + 100 * g.n + 8192 for g in graphs)
+    # edge, 100 B per node and 4 B per node and block of refinement), so
+    # admission waits for retirements
+    budget = 2 * max(20 * g.m + 100 * g.n + 4 * g.n * s.k + 8192 for g, s in zip(graphs, specs))
     srv = sc.Server(ctx, hbm_budget_bytes=budget, max_active=8)
     try:
         tickets = [srv.submit(d, s.k, p) for d, s, p in zip(devs, specs, parts)]
