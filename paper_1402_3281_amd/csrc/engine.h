@@ -94,7 +94,7 @@ struct Ctx {
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
-  Scratch hub_P, hub_ptot, hub_pbase, hub_mat, binscr, cutbuf;
+  Scratch hub_P, hub_ptot, hub_pbase, hub_mat, binscr, cutbuf, tadm;
   // jobs and levels whose nodes the current bins hold (clustering rounds only)
   std::vector<std::pair<const void*, int>> bin_sig;
   bool bin_sig_valid = false;

@@ -167,7 +167,7 @@ void ctx_release(Ctx* c, hipStream_t st) {
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
                     &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_pbase, &c->hub_mat,
-                    &c->binscr, &c->cutbuf};
+                    &c->binscr, &c->cutbuf, &c->tadm};
   c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
   (void)hipStreamSynchronize(st);
@@ -333,7 +333,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
-  bool any_build = false, any_cached = false;
+  bool any_build = false, any_cached = false, any_tile = false, any_other = false;
+  int tile_kmax = 0;
   for (int s = 0; s < ns; ++s) {
     Job* j = jobs[s];
     const Level& L = j->lv[j->cur];
@@ -368,6 +369,13 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.conn_mode = d.conn ? (j->round == 1 || j->conn_stale ? CONN_BUILD : CONN_RATE) : CONN_NONE;
     any_build = any_build || d.conn_mode == CONN_BUILD;
     any_cached = any_cached || d.conn_mode == CONN_RATE;
+    // refinement slots with few blocks are admitted by tiles
+    if (refine && j->nlabels <= kConnMaxK) {
+      any_tile = true;
+      tile_kmax = std::max<int>(tile_kmax, (int)j->nlabels);
+    } else {
+      any_other = true;
+    }
     N += L.n;
     T_bin += bin_tiles(L.n);
     Lt += j->nlabels;
@@ -409,12 +417,11 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_best.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
   }
-  // rated list, movers, big movers, old blocks of the movers
-  SCLAP_TRY(c->movers.ensure(4 * Nz * sizeof(int32_t), st));
+  // rated list, old blocks of the movers by rated position, big movers
+  SCLAP_TRY(c->movers.ensure(3 * Nz * sizeof(int32_t), st));
   int32_t* rated = (int32_t*)c->movers.p;
-  int32_t* movers = rated + Nz;
-  int32_t* bigm = movers + Nz;
-  int32_t* movers_old = bigm + Nz;
+  int32_t* mold = rated + Nz;
+  int32_t* bigm = mold + Nz;
   SCLAP_TRY(c->ckeys.ensure(Nz * 8, st));
   SCLAP_TRY(c->slots_dev.ensure((size_t)ns * sizeof(DevSlot), st));
   DevSlot* S = (DevSlot*)c->slots_dev.p;
@@ -484,12 +491,20 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (any_cached) SCLAP_TRY(launch_rate_cached(S, ns, N, rated, meta + 14, st));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
-  SCLAP_TRY(launch_incoming_decide(S, ns, N, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
-  SCLAP_TRY(launch_contended_small(S, ns, (const uint64_t*)c->ckeys.p, small + 9, node_bits, small + 16, st));
+  if (any_other) {
+    SCLAP_TRY(launch_incoming_decide(S, ns, N, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
+    SCLAP_TRY(launch_contended_small(S, ns, (const uint64_t*)c->ckeys.p, small + 9, node_bits, small + 16, st));
+  }
+  if (any_tile) {
+    // the binning scratch still holds this round's rated-list offsets
+    const size_t tb = tile_adm_bytes(T_bin, tile_kmax);
+    SCLAP_TRY(c->tadm.ensure(tb, st));
+    SCLAP_TRY(launch_tile_admission(S, ns, rated, bin_rated_offsets(c->binscr.p, T_bin), T_bin, tile_kmax, c->tadm.p,
+                                    c->tadm.bytes, mold, st));
+  }
   bool any_refine = false;
   for (int s = 0; s < ns; ++s) any_refine = any_refine || c->pin_slots[s].mode == MODE_REFINE;
-  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, movers_old, small + 13, bigm, small + 15, any_refine,
-                         small + 16, st));
+  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, bigm, small + 15, any_other, any_refine, small + 16, st));
   const size_t rd = 256 + (size_t)ns * CTR_N * sizeof(int64_t);
   SCLAP_TRY(ctx_ensure_pin(c, rd + 512));
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
@@ -520,8 +535,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                (int64_t*)c->prefix.p, cc, st));
     SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                     (const int64_t*)c->prefix.p, st));
-    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, movers, movers_old, small + 13, bigm, small + 15, any_refine,
-                           nullptr, st));
+    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, bigm, small + 15, any_other, any_refine, nullptr, st));
     SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
   }

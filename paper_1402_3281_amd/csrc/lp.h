@@ -63,11 +63,32 @@ int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint6
                       const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, hipStream_t st);
 int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
                        hipStream_t st);
-// Applies admitted moves; in refinement lists the movers with their old
-// blocks (movers_old) and marks their neighbours (updating block connections).
-int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* movers,
-                 int32_t* movers_old, uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine,
-                 const uint32_t* skip, hipStream_t st);
+// Applies admitted moves of the slots not admitted by tiles (run_apply); in
+// refinement writes the old block of every admitted mover by rated position
+// (mold, -1: stayed) and then marks the movers' neighbours (updating block
+// connections) for every refinement slot.
+int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
+                 int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
+                 hipStream_t st);
+// Admission and application of the moves of refinement slots with at most
+// kConnMaxK blocks, by binning tiles (roff: the rated-list offsets of the
+// tiles from launch_bin's scratch, see bin_rated_offsets; kmax: the largest
+// block count of those slots; scratch: tile_adm_bytes(T, kmax)).  Writes mold
+// for their rated positions, updates W and the moved counters.
+struct TileAdm {
+  const uint32_t* roff;  // T + 1: rated-list offsets of the tiles (relative to roff[0])
+  int64_t T;
+  int kmax;              // rows of the matrices below
+  int64_t* tsum;         // kmax x T: movers' weight per target block and tile
+  int64_t* tpre;         // kmax x T: inclusive scan of tsum per (block, slot)
+  int64_t* dW;           // kmax x T: per tile, the change of every block weight
+  int64_t* tmoved;       // T: admitted movers per tile
+  uint32_t* keys;        // kmax x T: scan segments (block x slot)
+};
+size_t tile_adm_bytes(int64_t T, int kmax);
+int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const uint32_t* roff, int64_t T, int kmax,
+                          void* scratch, size_t scratch_bytes, int32_t* mold, hipStream_t st);
+const uint32_t* bin_rated_offsets(void* scratch, int64_t T);
 
 // Library primitives (rocPRIM) used as steps: sorts, scans, reductions.
 size_t prim_sort_keys_bytes(size_t n);

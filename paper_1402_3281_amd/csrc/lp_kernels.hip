@@ -245,6 +245,13 @@ __device__ __forceinline__ bool dir_blocked(const DevSlot& sl, int32_t t, int32_
   return sl.dir_rule && ((sl.round & 1) ? t > own : t < own);
 }
 
+// Refinement slots with at most kConnMaxK blocks are admitted by tiles
+// (k_ta_*), without global atomics on their few targets; the other slots go
+// through k_incoming / k_decide / k_apply.
+__device__ __forceinline__ bool tile_admission(const DevSlot& sl) {
+  return sl.mode == MODE_REFINE && sl.nlabels <= kConnMaxK;
+}
+
 // Row of a binned node: first entry | degree << 40.
 __device__ __forceinline__ int64_t info_e0(uint64_t x) { return (int64_t)(x & ((1ull << 40) - 1ull)); }
 __device__ __forceinline__ int info_d(uint64_t x) { return (int)(x >> 40); }
@@ -1358,7 +1365,7 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it)
-      if (ok[it] && t[it] != own[it])
+      if (ok[it] && t[it] != own[it] && !tile_admission(S[sv[it]]))
         agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it]);
     __syncthreads();
     // flush: the table is read first so that the atomics are issued back to back
@@ -1401,7 +1408,7 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
       const int64_t v = u - sl.nbase;
       const int32_t t = gld(sl.desire, v);
       const int32_t own = gld(sl.lab, v);
-      if (ok && t != own) {
+      if (ok && t != own && !tile_admission(sl)) {
         if (gld(sl.W, t) + gld(sl.inc, t) <= sl.cap) {
           gst(sl.adm, v, (uint8_t)1);
         } else {
@@ -1542,13 +1549,9 @@ __global__ void __launch_bounds__(1024) k_contended_small(const DevSlot* __restr
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, int ns,
                                                const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
-                                               int32_t* __restrict__ movers, int32_t* __restrict__ movers_old,
-                                               uint32_t* __restrict__ mcnt, const uint32_t* __restrict__ skip) {
+                                               int32_t* __restrict__ mold, const uint32_t* __restrict__ skip) {
   __shared__ unsigned long long hk[kApplyTable];
   __shared__ long long hv[kApplyTable];
-  __shared__ int32_t s_mov[kAggNodes];
-  __shared__ int32_t s_old[kAggNodes];
-  __shared__ uint32_t s_mcnt, s_mbase;
   if (skip && *skip) return;  // the admission is completed on the host-driven path first
   const int64_t N = *rcnt;
   for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
@@ -1556,7 +1559,6 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       hk[j] = kEmpty;
       hv[j] = 0;
     }
-    if (threadIdx.x == 0) s_mcnt = 0;
     __syncthreads();
     constexpr int IT = kAggNodes / 256;
     int64_t uu[IT];
@@ -1590,21 +1592,19 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       const int32_t own = oo[it];
       bool admitted = false;
       int64_t cv = 0;
-      if (ok[it] && t != own) {
+      const bool mine = ok[it] && !tile_admission(sl);
+      if (mine && t != own) {
         gst(sl.inc, t, (int64_t)0);
         admitted = aa[it] != 0;
         if (admitted) {
           cv = ww[it];
           gst(sl.lab, v, t);
-          if (sl.mode == MODE_REFINE) {
-            const uint32_t q = atomicAdd(&s_mcnt, 1u);
-            s_mov[q] = (int32_t)u;
-            s_old[q] = own;
-          }
         } else {
           gst(sl.desire, v, own);
         }
       }
+      // refinement: old block of every admitted mover by rated position (-1: stayed)
+      if (mine && sl.mode == MODE_REFINE) gst(mold, base + it * 256 + threadIdx.x, admitted ? own : -1);
       // label weights (+c(v) to the target, -c(v) to the old label) and the
       // moved count, combined across the wave first
       const unsigned long long ks = (unsigned long long)s << 32;
@@ -1639,12 +1639,6 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       const uint32_t lab = (uint32_t)fk[q];
       if (lab == kCountLabel) gadd64(sl.ctr, CTR_MOVED, fv[q]);
       else gadd64(sl.W, lab, fv[q]);
-    }
-    if (threadIdx.x == 0) s_mbase = s_mcnt ? atomicAdd(mcnt, s_mcnt) : 0;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < s_mcnt; j += blockDim.x) {
-      movers[s_mbase + j] = s_mov[j];
-      movers_old[s_mbase + j] = s_old[j];
     }
     __syncthreads();
   }
@@ -1716,13 +1710,12 @@ __device__ __forceinline__ bool conn_push(const DevSlot& sl) {
   return sl.conn && gld(sl.ctr, CTR_MOVED) * kConnPushDiv <= sl.n;
 }
 
-// Blocks (a, b) of mover i when its moves are added to block connections,
-// else -1.
-__device__ __forceinline__ void mover_blocks(const DevSlot& sl, const int32_t* movers_old, uint32_t i, int64_t v,
-                                             int32_t& a, int32_t& b) {
+// Blocks (a, b) of a mover from block oa when its moves are added to block
+// connections, else -1.
+__device__ __forceinline__ void mover_blocks(const DevSlot& sl, int32_t oa, int64_t v, int32_t& a, int32_t& b) {
   a = b = -1;
   if (conn_push(sl)) {
-    const int32_t oa = gld(movers_old, i), nb = gld(sl.lab, v);
+    const int32_t nb = gld(sl.lab, v);
     if ((uint32_t)oa < (uint32_t)sl.conn_k && (uint32_t)nb < (uint32_t)sl.conn_k) {
       a = oa;
       b = nb;
@@ -1730,17 +1723,19 @@ __device__ __forceinline__ void mover_blocks(const DevSlot& sl, const int32_t* m
   }
 }
 
+// Movers: rated positions i of refinement slots with mold[i] >= 0 (the old
+// block).
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int ns,
-                                              const int32_t* __restrict__ movers,
-                                              const int32_t* __restrict__ movers_old, const uint32_t* __restrict__ mcnt,
+                                              const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
+                                              const int32_t* __restrict__ mold,
                                               int32_t* __restrict__ big, uint32_t* __restrict__ big_cnt,
                                               const uint32_t* __restrict__ skip) {
   if (skip && *skip) return;
   if (blockIdx.x == 0)
     for (int s = threadIdx.x; s < ns; s += blockDim.x)
       if (S[s].conn && !conn_push(S[s])) gst(S[s].ctr, CTR_STALE, (int64_t)1);
-  const uint32_t cnt = *mcnt;
+  const uint32_t cnt = *rcnt;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   for (uint32_t base = wid * kWave; base < cnt; base += waves * kWave) {
@@ -1749,12 +1744,15 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
     int64_t e0 = 0, d = 0;
     int32_t u = 0, a = -1, b = -1;
     if (i < cnt) {
-      u = movers[i];
+      u = gld(rated, i);
       sl = &S[SLOT(u)];
-      const int64_t v = u - sl->nbase;
-      e0 = gld(sl->rp, v);
-      d = gld(sl->rp, v + 1) - e0;
-      mover_blocks(*sl, movers_old, i, v, a, b);
+      const int32_t oa = sl->mode == MODE_REFINE ? gld(mold, i) : -1;
+      if (oa >= 0) {
+        const int64_t v = u - sl->nbase;
+        e0 = gld(sl->rp, v);
+        d = gld(sl->rp, v + 1) - e0;
+        mover_blocks(*sl, oa, v, a, b);
+      }
     }
     if (d <= kWave && d > 0) mark_row<4>(*sl, e0, 0, d, 1, a, b);
     if (d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
@@ -1772,8 +1770,7 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
 
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark_big(const DevSlot* __restrict__ S, int ns,
-                                                  const int32_t* __restrict__ movers,
-                                                  const int32_t* __restrict__ movers_old,
+                                                  const int32_t* __restrict__ rated, const int32_t* __restrict__ mold,
                                                   const int32_t* __restrict__ big, const uint32_t* __restrict__ big_cnt,
                                                   const uint32_t* __restrict__ skip) {
   if (skip && *skip) return;
@@ -1781,13 +1778,149 @@ __global__ void __launch_bounds__(256) k_mark_big(const DevSlot* __restrict__ S,
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (uint32_t i = 0; i < cnt; ++i) {
     const uint32_t mi = (uint32_t)big[i];
-    const int64_t u = movers[mi];
+    const int64_t u = rated[mi];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     int32_t a, b;
-    mover_blocks(sl, movers_old, mi, v, a, b);
+    mover_blocks(sl, mold[mi], v, a, b);
     const int64_t e0 = sl.rp[v], e1 = sl.rp[v + 1];
     mark_row<4>(sl, e0, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, e1 - e0, (int)stride, a, b);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Admission of tile-admitted refinement slots by binning tiles (the rated
+// nodes of a tile form a node-ordered range of the rated list, and a tile
+// belongs to one slot):
+//   sums    per tile and target block: the weight of its movers
+//   (scan)  per target and slot, an inclusive scan of the tile sums
+//   admit   a mover's inclusive prefix among the movers to its target in node
+//           order = earlier tiles + earlier waves of the tile + earlier lanes
+//           + its own weight; admitted iff W(t) + prefix <= cap (Section 3:
+//           the longest fitting prefix, as every weight is >= 0).  Moves are
+//           applied at once; per tile the block weight changes and the moved
+//           count are written out
+//   reduce  per slot and block: W(b) += the tiles' changes, and the moved count.
+// ---------------------------------------------------------------------------
+template <bool ONE>
+__global__ void __launch_bounds__(kBinTile) k_ta_sums(const DevSlot* __restrict__ S, int ns,
+                                                      const int32_t* __restrict__ rated, TileAdm A) {
+  __shared__ unsigned long long sums[kConnMaxK];
+  for (int64_t t = blockIdx.x; t < A.T; t += gridDim.x) {
+    const int s = ONE ? 0 : slot_of_tile(S, ns, t);
+    const DevSlot& sl = S[s];
+    const bool on = tile_admission(sl) && sl.round > 0;
+    if (threadIdx.x < kConnMaxK) sums[threadIdx.x] = 0;
+    __syncthreads();
+    if (on) {
+      const uint32_t i = A.roff[t] - A.roff[0] + threadIdx.x;
+      if (i < A.roff[t + 1] - A.roff[0]) {
+        const int64_t v = gld(rated, i) - sl.nbase;
+        const int32_t tt = gld(sl.desire, v), own = gld(sl.lab, v);
+        if (tt != own && (uint32_t)tt < (uint32_t)sl.nlabels)
+          atomicAdd(&sums[tt], (unsigned long long)gld(sl.nw, v));
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < A.kmax) {
+      A.tsum[threadIdx.x * A.T + t] = on ? (int64_t)sums[threadIdx.x] : 0;
+      A.keys[threadIdx.x * A.T + t] = threadIdx.x * (uint32_t)ns + (uint32_t)s;
+    }
+    __syncthreads();
+  }
+}
+
+template <bool ONE>
+__global__ void __launch_bounds__(kBinTile) k_ta_admit(const DevSlot* __restrict__ S, int ns,
+                                                       const int32_t* __restrict__ rated, TileAdm A,
+                                                       int32_t* __restrict__ mold) {
+  __shared__ long long wtot[kBinTile / kWave][kConnMaxK];
+  __shared__ unsigned long long dsum[kConnMaxK];
+  __shared__ uint32_t s_moved;
+  const int w = threadIdx.x / kWave;
+  const int lane = (int)lane_id();
+  for (int64_t t = blockIdx.x; t < A.T; t += gridDim.x) {
+    const int s = ONE ? 0 : slot_of_tile(S, ns, t);
+    const DevSlot& sl = S[s];
+    if (!(tile_admission(sl) && sl.round > 0)) continue;  // the same for the whole workgroup
+    for (int j = threadIdx.x; j < (kBinTile / kWave) * kConnMaxK; j += blockDim.x) (&wtot[0][0])[j] = 0;
+    if (threadIdx.x < kConnMaxK) dsum[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_moved = 0;
+    __syncthreads();
+    const uint32_t i = A.roff[t] - A.roff[0] + threadIdx.x;
+    const bool valid = i < A.roff[t + 1] - A.roff[0];
+    int64_t v = 0, c = 0;
+    int32_t tt = -1, own = -1;
+    if (valid) {
+      v = gld(rated, i) - sl.nbase;
+      tt = gld(sl.desire, v);
+      own = gld(sl.lab, v);
+      c = gld(sl.nw, v);
+    }
+    const bool mover =
+        valid && tt != own && (uint32_t)tt < (uint32_t)sl.nlabels && (uint32_t)own < (uint32_t)sl.nlabels;
+    // exclusive prefix among the wave's movers to the same target
+    int64_t excl = 0;
+    uint64_t rem = __ballot(mover);
+    while (rem) {
+      const int lead = __ffsll((unsigned long long)rem) - 1;
+      const int32_t j0 = __shfl(tt, lead);
+      const bool mine = mover && tt == j0;
+      const uint64_t m = __ballot(mine);
+      int64_t x = mine ? c : 0;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+      }
+      if (mine) excl = x - c;
+      if (lane == kWave - 1) wtot[w][j0] = x;
+      rem &= ~m;
+    }
+    __syncthreads();
+    bool adm = false;
+    if (mover) {
+      int64_t before = 0;
+      for (int q = 0; q < w; ++q) before += wtot[q][tt];
+      const int64_t k = (int64_t)tt * A.T + t;
+      const int64_t incl = (A.tpre[k] - A.tsum[k]) + before + excl + c;
+      adm = gld(sl.W, tt) + incl <= sl.cap;
+    }
+    if (valid) {
+      if (adm) {
+        gst(sl.lab, v, tt);
+        atomicAdd(&dsum[tt], (unsigned long long)c);
+        atomicAdd(&dsum[own], (unsigned long long)(-c));
+      } else if (mover) {
+        gst(sl.desire, v, own);
+      }
+      gst(mold, i, adm ? own : -1);
+    }
+    const uint64_t am = __ballot(adm);
+    if (lane == 0 && am) atomicAdd(&s_moved, (uint32_t)__popcll(am));
+    __syncthreads();
+    if ((int)threadIdx.x < A.kmax) A.dW[threadIdx.x * A.T + t] = (int64_t)dsum[threadIdx.x];
+    if (threadIdx.x == 0) A.tmoved[t] = s_moved;
+    __syncthreads();
+  }
+}
+
+// Workgroup (s, j): slot s, block j < kmax (its weight) or j = kmax (moved).
+__global__ void __launch_bounds__(256) k_ta_reduce(const DevSlot* __restrict__ S, int ns, TileAdm A) {
+  __shared__ int64_t red[8];
+  const int s = (int)(blockIdx.x / (uint32_t)(A.kmax + 1)), j = (int)(blockIdx.x % (uint32_t)(A.kmax + 1));
+  const DevSlot& sl = S[s];
+  if (!(tile_admission(sl) && sl.round > 0) || (j < A.kmax && j >= sl.nlabels)) return;
+  const int64_t t0 = sl.tbase, t1 = s + 1 < ns ? S[s + 1].tbase : A.T;
+  int64_t sum = 0;
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) sum += j < A.kmax ? A.dW[(int64_t)j * A.T + t] : A.tmoved[t];
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t tot = 0;
+    for (int q = 0; q < (int)(blockDim.x / kWave); ++q) tot += red[q];
+    if (j < A.kmax) gst(sl.W, j, gld(sl.W, j) + tot);
+    else gst(sl.ctr, CTR_MOVED, tot);
   }
 }
 
@@ -2068,6 +2201,40 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
   return SCLAP_OK;
 }
 
+size_t tile_adm_bytes(int64_t T, int kmax) {
+  const size_t n = (size_t)kmax * (size_t)T;
+  return n * 8 * 3 + n * 4 + (size_t)T * 8 + 1024 + prim_scan_by_key_bytes(std::max<size_t>(n, 1));
+}
+
+int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const uint32_t* roff, int64_t T, int kmax,
+                          void* scratch, size_t scratch_bytes, int32_t* mold, hipStream_t st) {
+  if (T == 0) return SCLAP_OK;
+  const size_t n = (size_t)kmax * (size_t)T;
+  TileAdm A{};
+  A.roff = roff;
+  A.T = T;
+  A.kmax = kmax;
+  char* p = (char*)scratch;
+  A.tsum = (int64_t*)p;
+  A.tpre = A.tsum + n;
+  A.dW = A.tpre + n;
+  A.tmoved = A.dW + n;
+  A.keys = (uint32_t*)(A.tmoved + T);
+  void* tmp = (void*)(((uintptr_t)(A.keys + n) + 255) & ~(uintptr_t)255);
+  const size_t tmp_bytes = scratch_bytes - (size_t)((char*)tmp - p);
+  const unsigned G = (unsigned)std::min<int64_t>(T, 4096);
+  LAUNCH(k_ta_sums, G, kBinTile, S, ns, rated, A);
+  SCLAP_TRY(prim_scan_by_key(tmp, tmp_bytes, A.keys, A.tsum, A.tpre, n, st));
+  LAUNCH(k_ta_admit, G, kBinTile, S, ns, rated, A, mold);
+  hipLaunchKernelGGL(k_ta_reduce, dim3((unsigned)(ns * (kmax + 1))), dim3(256), 0, st, S, ns, A);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+const uint32_t* bin_rated_offsets(void* scratch, int64_t T) {
+  return (const uint32_t*)scratch + (size_t)kBinRows * (size_t)T + 1 + (size_t)kBins * (size_t)T;
+}
+
 int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                       const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, hipStream_t st) {
   const unsigned G = grid_for(n_hint, 256, 1024);
@@ -2115,13 +2282,13 @@ int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const
   return SCLAP_OK;
 }
 
-int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* movers,
-                 int32_t* movers_old, uint32_t* mcnt, int32_t* big, uint32_t* big_cnt, bool any_refine,
-                 const uint32_t* skip, hipStream_t st) {
-  LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, movers, movers_old, mcnt, skip);
+int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
+                 int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
+                 hipStream_t st) {
+  if (run_apply) LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, mold, skip);
   if (any_refine) {
-    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, movers, movers_old, mcnt, big, big_cnt, skip);
-    LAUNCH(k_mark_big, 1024, 256, S, ns, movers, movers_old, big, big_cnt, skip);
+    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, skip);
+    LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, skip);
   }
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
