@@ -622,7 +622,10 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&tcnt, (size_t)T + 1, st));
   SCLAP_TRY(dalloc_t(&toff, (size_t)T + 1, st));
   SCLAP_TRY(fill_i64(tcnt, (int64_t)T + 1, 0, st));
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, st));
+  int32_t* ycache = nullptr;
+  SCLAP_TRY(dalloc_t(&ycache, (size_t)std::max<int64_t>(F.m, 1), st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, ycache,
+                           st));
   {
     const size_t sb = prim_exscan_i64_bytes((size_t)T + 1);
     SCLAP_TRY(c->prim.ensure(sb, st));
@@ -632,24 +635,34 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_HIP(hipStreamSynchronize(st));
   const int64_t mx = c->pin[0];
   const size_t mz = (size_t)std::max<int64_t>(mx, 1);
+  // unit edge weights: the sums are the run lengths of the sorted keys
+  const bool unit = F.ew == nullptr;
   uint64_t *k1 = nullptr, *k2 = nullptr;
   int32_t *v1 = nullptr, *v2 = nullptr;
   SCLAP_TRY(dalloc_t(&k1, mz, st));
   SCLAP_TRY(dalloc_t(&k2, mz, st));
-  SCLAP_TRY(dalloc_t(&v1, mz, st));
-  SCLAP_TRY(dalloc_t(&v2, mz, st));
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, st));
+  if (!unit) {
+    SCLAP_TRY(dalloc_t(&v1, mz, st));
+    SCLAP_TRY(dalloc_t(&v2, mz, st));
+  }
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, ycache, st));
+  dfree(ycache, st);
   dfree(tcnt, st);
   dfree(toff, st);
-  const size_t tb = std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
+  const size_t tb = unit ? std::max(prim_sort_keys_bytes(mz), prim_rle_bytes(mz))
+                         : std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
   SCLAP_TRY(c->prim.ensure(tb, st));
-  SCLAP_TRY(prim_sort_pairs(c->prim.p, tb, k1, k2, v1, v2, (size_t)mx, 2 * bits, st));
+  if (unit) SCLAP_TRY(prim_sort_keys(c->prim.p, tb, k1, k2, (size_t)mx, 2 * bits, st));
+  else SCLAP_TRY(prim_sort_pairs(c->prim.p, tb, k1, k2, v1, v2, (size_t)mx, 2 * bits, st));
   // reduce equal (x, y) keys: unique keys into k1, sums into an int64 buffer
   int64_t* aggs = nullptr;
   SCLAP_TRY(dalloc_t(&aggs, mz, st));
   uint32_t* ucount = (uint32_t*)((char*)c->small.p + 64);
   SCLAP_TRY(fill_u32(ucount, 2, 0, st));
-  if (mx > 0) SCLAP_TRY(prim_reduce_by_key(c->prim.p, tb, k2, v2, k1, aggs, ucount, (size_t)mx, st));
+  if (mx > 0) {
+    if (unit) SCLAP_TRY(prim_rle(c->prim.p, tb, k2, k1, aggs, ucount, (size_t)mx, st));
+    else SCLAP_TRY(prim_reduce_by_key(c->prim.p, tb, k2, v2, k1, aggs, ucount, (size_t)mx, st));
+  }
   SCLAP_HIP(hipMemcpyAsync(c->pin, ucount, 4, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   const int64_t mc = (int64_t)((uint32_t*)c->pin)[0];

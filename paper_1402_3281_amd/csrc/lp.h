@@ -104,6 +104,10 @@ size_t prim_exscan_i32_bytes(size_t n);
 int prim_exscan_i32(void* tmp, size_t tmp_bytes, const int32_t* in, int32_t* out, size_t n, hipStream_t st);
 size_t prim_exscan_i64_bytes(size_t n);
 int prim_exscan_i64(void* tmp, size_t tmp_bytes, const int64_t* in, int64_t* out, size_t n, hipStream_t st);
+// Runs of equal keys (sorted input): the keys and their lengths (n < 2^32).
+size_t prim_rle_bytes(size_t n);
+int prim_rle(void* tmp, size_t tmp_bytes, const uint64_t* keys, uint64_t* ukeys, int64_t* counts, uint32_t* runs,
+             size_t n, hipStream_t st);
 size_t prim_reduce_by_key_bytes(size_t n);
 int prim_reduce_by_key(void* tmp, size_t tmp_bytes, const uint64_t* keys, const int32_t* vals, uint64_t* ukeys,
                        int64_t* aggs, uint32_t* count, size_t n, hipStream_t st);

@@ -338,7 +338,8 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
                                                const int32_t* __restrict__ ew, const int32_t* __restrict__ cof,
                                                int64_t n, int64_t m, int bits, int mode,
                                                int64_t* __restrict__ tcnt, const int64_t* __restrict__ toff,
-                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                               int32_t* __restrict__ ycache) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   __shared__ int64_t s_w[4];
@@ -355,7 +356,16 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
       ys[j] = -1;
       if (e >= r.e1) continue;
       const int32_t x = cof[edge_row(rp, r, s_rp, e)];
-      const int32_t y = cof[col[e]];
+      // mode 0 gathers the neighbour's coarse id and keeps it (-1: same
+      // coarse node) for mode 1, which then reads it in entry order
+      int32_t y;
+      if (mode == 0) {
+        y = cof[col[e]];
+        if (ycache) ycache[e] = x != y ? y : -1;
+      } else {
+        y = ycache ? ycache[e] : cof[col[e]];
+        if (y < 0) y = x;
+      }
       if (x != y) {
         xs[j] = x;
         ys[j] = y;
@@ -386,7 +396,7 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
       if (xs[j] < 0) continue;
       const int64_t e = E0 + j * 256 + threadIdx.x;
       keys[p] = ((uint64_t)(uint32_t)xs[j] << bits) | (uint64_t)(uint32_t)ys[j];
-      vals[p] = ew ? ew[e] : 1;
+      if (vals) vals[p] = ew ? ew[e] : 1;
       ++p;
     }
   }
@@ -470,10 +480,10 @@ int cross_tiles(int64_t m) { return (int)((m + kEpb - 1) / kEpb); }
 
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   hipStream_t st) {
+                   int32_t* ycache, hipStream_t st) {
   if (n <= 0 || m <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
-                     keys, vals);
+                     keys, vals, ycache);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -86,6 +86,19 @@ int prim_exscan_i64(void* tmp, size_t tmp_bytes, const int64_t* in, int64_t* out
   return SCLAP_OK;
 }
 
+size_t prim_rle_bytes(size_t n) {
+  size_t b = 0;
+  (void)rocprim::run_length_encode(nullptr, b, (const uint64_t*)nullptr, (unsigned)n, (uint64_t*)nullptr,
+                                   (int64_t*)nullptr, (uint32_t*)nullptr);
+  return b;
+}
+
+int prim_rle(void* tmp, size_t tmp_bytes, const uint64_t* keys, uint64_t* ukeys, int64_t* counts, uint32_t* runs,
+             size_t n, hipStream_t st) {
+  PRIM_CALL(rocprim::run_length_encode(tmp, tmp_bytes, keys, (unsigned)n, ukeys, counts, runs, st));
+  return SCLAP_OK;
+}
+
 size_t prim_reduce_by_key_bytes(size_t n) {
   size_t b = 0;
   (void)rocprim::reduce_by_key(nullptr, b, (const uint64_t*)nullptr, (const int32_t*)nullptr, n, (uint64_t*)nullptr,
