@@ -333,7 +333,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
-  bool any_build = false, any_cached = false, any_tile = false, any_other = false;
+  bool any_build = false, any_cached = false, any_tile = false, any_other = false, any_binned = false;
   int tile_kmax = 0;
   for (int s = 0; s < ns; ++s) {
     Job* j = jobs[s];
@@ -369,6 +369,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.conn_mode = d.conn ? (j->round == 1 || j->conn_stale ? CONN_BUILD : CONN_RATE) : CONN_NONE;
     any_build = any_build || d.conn_mode == CONN_BUILD;
     any_cached = any_cached || d.conn_mode == CONN_RATE;
+    any_binned = any_binned || d.conn_mode != CONN_RATE;
     // refinement slots with few blocks are admitted by tiles
     if (refine && j->nlabels <= kConnMaxK) {
       any_tile = true;
@@ -485,8 +486,13 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   }
   bool unit_weights = true;
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
-  SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights, st,
-                        c->profile ? c->ev : nullptr));
+  // rounds whose every slot rates from block connections leave the bins empty
+  if (any_binned) {
+    SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights, st,
+                          c->profile ? c->ev : nullptr));
+  } else if (c->profile) {
+    for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));
+  }
   if (any_build) SCLAP_TRY(launch_conn_build(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, st));
   if (any_cached) SCLAP_TRY(launch_rate_cached(S, ns, N, rated, meta + 14, st));
   const int node_bits = bits_for(N);

@@ -642,7 +642,58 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       continue;
     }
     const int64_t F = tail - head;
-    if (allow_yield && sl.rows_sorted) {
+    bool E_known = false;
+    if (sl.rows_sorted && F <= kIpThreads) {
+      // a frontier of one chunk: its rows are read once; with at most one
+      // entry per thread, each thread keeps its entry through the claim and
+      // emit passes, and the new nodes' positions are written at once
+      int64_t d = 0, e0 = 0;
+      if ((int64_t)threadIdx.x < F) {
+        const int32_t f = ld_acq(&sl.order[head + threadIdx.x]);
+        e0 = sl.rp[f];
+        d = sl.rp[f + 1] - e0;
+      }
+      int64_t ex;
+      const int64_t Tc = block_exscan(d, &ex, sh);
+      if (allow_yield && Tc > big_entries) {
+        if (threadIdx.x == 0) {
+          sl.state[0] = head;
+          sl.state[1] = tail;
+          sl.state[2] = next;
+          sl.state[3] = 1;
+        }
+        return;
+      }
+      E_known = true;
+      if (Tc <= kIpThreads) {
+        s_pre[threadIdx.x] = ex;
+        s_e0[threadIdx.x] = e0;
+        __syncthreads();
+        const bool has = (int64_t)threadIdx.x < Tc;
+        int32_t u = 0;
+        int l = 0;
+        if (has) {
+          l = lds_upper(s_pre, (int)F, threadIdx.x);
+          u = sl.col[s_e0[l] + threadIdx.x - s_pre[l]];
+          if (ld_acq(&sl.pos[u]) == -1) atomicMin(&sl.claim[u], (int32_t)l);
+        }
+        __syncthreads();
+        const bool ch = has && ld_acq(&sl.claim[u]) == (int32_t)l && ld_acq(&sl.pos[u]) == -1;
+        int64_t cx;
+        const int64_t T = block_exscan(ch ? 1 : 0, &cx, sh);  // all reads above precede the writes
+        if (ch) {
+          st_rel(&sl.order[tail + cx], u);
+          st_rel(&sl.pos[u], (int32_t)(tail + cx));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          s_head = tail;
+          s_tail = tail + T;
+        }
+        continue;
+      }
+    }
+    if (allow_yield && sl.rows_sorted && !E_known) {
       int64_t E = 0;
       for (int64_t fc = 0; fc < F; fc += kIpThreads) {
         const int64_t fi = fc + threadIdx.x;
