@@ -68,6 +68,8 @@ struct DevSlot {
   int32_t conn_k;         // refine: columns of conn (the block count k)
   int32_t conn_mode;      // CONN_NONE / CONN_BUILD / CONN_RATE
   int32_t* conn;          // refine: n x conn_k block connections conn(v, b), or nullptr
+  int32_t last_round;     // no LP round of this stage follows (its moves need no bookkeeping)
+  int32_t pad;
 };
 
 // Refinement with block connections kept per node: the first round of a

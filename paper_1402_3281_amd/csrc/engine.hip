@@ -367,6 +367,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.conn = refine ? j->conn : nullptr;
     d.conn_k = j->k;
     d.conn_mode = d.conn ? (j->round == 1 || j->conn_stale ? CONN_BUILD : CONN_RATE) : CONN_NONE;
+    d.last_round = j->round >= (refine ? j->ref_rounds : j->lp_rounds);
     any_build = any_build || d.conn_mode == CONN_BUILD;
     any_cached = any_cached || d.conn_mode == CONN_RATE;
     any_binned = any_binned || d.conn_mode != CONN_RATE;
@@ -498,7 +499,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
   if (any_other) {
-    SCLAP_TRY(launch_incoming_decide(S, ns, N, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits, st));
+    SCLAP_TRY(launch_incoming_decide(S, ns, N, Lt, rated, meta + 14, (uint64_t*)c->ckeys.p, small + 9, node_bits,
+                                     st));
     SCLAP_TRY(launch_contended_small(S, ns, (const uint64_t*)c->ckeys.p, small + 9, node_bits, small + 16, st));
   }
   if (any_tile) {

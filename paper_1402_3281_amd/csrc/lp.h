@@ -48,8 +48,11 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
 // Small contended sets resolved on the device; sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,
                            uint32_t* big_flag, hipStream_t st);
-int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
-                           uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st);
+// Incoming weight per target, the fast admission of targets that take all
+// their movers (adm = 2; their arrivals go to W at once, and inc is cleared
+// for all labels: Lt = the labels of all slots), contended keys for the rest.
+int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, int64_t Lt, const int32_t* rated,
+                           const uint32_t* rcnt, uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st);
 int launch_contended_split(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
                            uint32_t* tkey, int64_t* wv, hipStream_t st);
 int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,

@@ -1410,7 +1410,7 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
       const int32_t own = gld(sl.lab, v);
       if (ok && t != own && !tile_admission(sl)) {
         if (gld(sl.W, t) + gld(sl.inc, t) <= sl.cap) {
-          gst(sl.adm, v, (uint8_t)1);
+          gst(sl.adm, v, (uint8_t)2);  // the target takes all its movers (k_fold adds them)
         } else {
           gst(sl.adm, v, (uint8_t)0);
           contended = true;
@@ -1433,6 +1433,34 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
     __syncthreads();
     if (contended) ckeys[s_base + s_w[w] + (uint32_t)__popcll(m & lt)] = key;
     __syncthreads();
+  }
+}
+
+// Targets whose whole incoming weight fits take it at once: W(t) += inc(t);
+// inc is cleared for every label.  Runs after k_decide (which made the same
+// test per mover) and before any other change of W in the round.
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_fold(const DevSlot* __restrict__ S, int ns, int64_t Lt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < Lt; g += stride) {
+    int s = 0;
+    if (!ONE) {
+      int lo = 0, hi = ns - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S[mid].lbase <= g) lo = mid;
+        else hi = mid - 1;
+      }
+      s = lo;
+    }
+    const DevSlot& sl = S[s];
+    const int64_t t = g - sl.lbase;
+    if (t >= sl.nlabels || tile_admission(sl)) continue;
+    const int64_t x = gld(sl.inc, t);
+    if (x == 0) continue;
+    const int64_t w = gld(sl.W, t);
+    if (w + x <= sl.cap) gst(sl.W, t, w + x);
+    gst(sl.inc, t, (int64_t)0);
   }
 }
 
@@ -1593,9 +1621,10 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       bool admitted = false;
       int64_t cv = 0;
       const bool mine = ok[it] && !tile_admission(sl);
+      bool fast = false;
       if (mine && t != own) {
-        gst(sl.inc, t, (int64_t)0);
         admitted = aa[it] != 0;
+        fast = aa[it] == 2;
         if (admitted) {
           cv = ww[it];
           gst(sl.lab, v, t);
@@ -1609,7 +1638,8 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       // moved count, combined across the wave first
       const unsigned long long ks = (unsigned long long)s << 32;
       if (admitted && cv != 0) {
-        agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
+        // arrivals at targets that take all their movers were added by k_fold
+        if (!fast) agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
         agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
       }
       // moved count: one LDS add per wave and slot run
@@ -1707,7 +1737,7 @@ __device__ __forceinline__ void mark_row(const DevSlot& sl, int64_t e0, int64_t 
 // Whether the moves of the round are added to the slot's block connections
 // (the same answer for every thread: it depends on the final moved count).
 __device__ __forceinline__ bool conn_push(const DevSlot& sl) {
-  return sl.conn && gld(sl.ctr, CTR_MOVED) * kConnPushDiv <= sl.n;
+  return sl.conn && !sl.last_round && gld(sl.ctr, CTR_MOVED) * kConnPushDiv <= sl.n;
 }
 
 // Blocks (a, b) of a mover from block oa when its moves are added to block
@@ -1734,7 +1764,7 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
   if (skip && *skip) return;
   if (blockIdx.x == 0)
     for (int s = threadIdx.x; s < ns; s += blockDim.x)
-      if (S[s].conn && !conn_push(S[s])) gst(S[s].ctr, CTR_STALE, (int64_t)1);
+      if (S[s].conn && !S[s].last_round && !conn_push(S[s])) gst(S[s].ctr, CTR_STALE, (int64_t)1);
   const uint32_t cnt = *rcnt;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -1746,7 +1776,8 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
     if (i < cnt) {
       u = gld(rated, i);
       sl = &S[SLOT(u)];
-      const int32_t oa = sl->mode == MODE_REFINE ? gld(mold, i) : -1;
+      // the last round of a stage has no next rated set to mark
+      const int32_t oa = sl->mode == MODE_REFINE && !sl->last_round ? gld(mold, i) : -1;
       if (oa >= 0) {
         const int64_t v = u - sl->nbase;
         e0 = gld(sl->rp, v);
@@ -2251,10 +2282,11 @@ int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated
   return SCLAP_OK;
 }
 
-int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
-                           uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st) {
+int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, int64_t Lt, const int32_t* rated,
+                           const uint32_t* rcnt, uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st) {
   LAUNCH(k_incoming, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt);
   LAUNCH(k_decide, grid_for(N, 256, 4096), 256, S, ns, rated, rcnt, ckeys, ccnt, node_bits);
+  LAUNCH(k_fold, grid_for(Lt, 256, 4096), 256, S, ns, Lt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
