@@ -174,6 +174,28 @@ def test_partition_mid(sc, ctx, idx):
     assert_partition_parity(sc, ctx, gw, 4)
 
 
+@pytest.mark.parametrize("idx", [2, 5])
+def test_partition_many_blocks(sc, ctx, idx):
+    """k above the limit for kept block connections (64): refinement rates
+    from the bins in every round and admits through the general path."""
+    name, g = mid_graphs()[idx]
+    assert_partition_parity(sc, ctx, g, 96)
+
+
+def test_batch_mixed_block_counts(sc, ctx):
+    """One fused batch whose refinement slots take both admission paths (k up
+    to 64: block connections and tiles; k above: the general path)."""
+    specs = graphgen.batch_specs(count=6, seed=5, lg_lo=10, lg_hi=13)
+    graphs = [s.make() for s in specs]
+    ks = [8, 96, 16, 80, 2, 70]
+    devs = [dev(sc, g) for g in graphs]
+    parts, sts = sc.partition_batch(ctx, devs, ks)
+    for g, k, p, st in zip(graphs, ks, parts, sts):
+        want_part, want = oracle.partition(g, k)
+        assert np.array_equal(host(p), want_part), (g.name, k)
+        assert st["cut"] == want["cut"] and st["moved_r"] == want["moved_r"], (g.name, k)
+
+
 def test_config1_cluster_contract(sc, ctx):
     """R-MAT scale 14, edge factor 8, U = 602, exactly 10 rounds, then one
     contraction; the cluster cut is the coarse edge weight / 2."""
