@@ -704,12 +704,12 @@ constexpr int64_t kIpBigLevel = 1 << 18;  // entries of a BFS level expanded gri
 
 // Expand yielded BFS levels of one slot with grid-wide kernels until the
 // workgroup kernel finishes.
-static int ip_single_loop(Ctx* c, IpSlot* dslot, int64_t* dstate, hipStream_t st) {
+static int ip_single_loop(Ctx* c, IpSlot* dslot, int64_t n, int64_t* dstate, hipStream_t st) {
   int64_t *deg = nullptr, *dpre = nullptr;
   int32_t *flags = nullptr, *fpos = nullptr;
   SCLAP_TRY(ctx_ensure_pin(c, 256));
   for (int iter = 0;; ++iter) {
-    SCLAP_TRY(initial_partition(dslot, 1, 1, kIpBigLevel, st));
+    SCLAP_TRY(initial_partition(dslot, 1, n, 1, kIpBigLevel, st));
     SCLAP_HIP(hipMemcpyAsync(c->pin, dstate, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
     if (c->pin[3] == 0) break;
@@ -796,10 +796,12 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
   SCLAP_HIP(hipMemcpyAsync(c->ip_slots.p, c->pin, (size_t)cnt * sizeof(IpSlot), hipMemcpyHostToDevice, st));
   SCLAP_HIP(hipStreamSynchronize(st));  // pinned staging is reused right after
   const Level& L0 = jobs[0]->lv[jobs[0]->cur];
+  int64_t max_n = 0;
+  for (int s = 0; s < cnt; ++s) max_n = std::max<int64_t>(max_n, hs[s].n);
   if (cnt == 1 && L0.rows_sorted && L0.m > kIpBigLevel) {
-    SCLAP_TRY(ip_single_loop(c, (IpSlot*)c->ip_slots.p, states, st));
+    SCLAP_TRY(ip_single_loop(c, (IpSlot*)c->ip_slots.p, L0.n, states, st));
   } else {
-    SCLAP_TRY(initial_partition((const IpSlot*)c->ip_slots.p, cnt, 0, 0, st));
+    SCLAP_TRY(initial_partition((const IpSlot*)c->ip_slots.p, cnt, max_n, 0, 0, st));
   }
   for (int s = 0; s < cnt; ++s) dfree(scratch[s], st);
   dfree(states, st);

@@ -63,7 +63,10 @@ struct IpSlot {
   int64_t* state;  // 4: head, tail, next seed, yielded (zero before the first launch)
 };
 // One workgroup per slot; see k_ip_bfs for allow_yield / big_entries.
-int initial_partition(const IpSlot* dev_slots, int count, int allow_yield, int64_t big_entries, hipStream_t st);
+// max_n: the largest n over the slots (graphs of up to 2^18 nodes keep
+// their search state in LDS).
+int initial_partition(const IpSlot* dev_slots, int count, int64_t max_n, int allow_yield, int64_t big_entries,
+                      hipStream_t st);
 // Grid-wide expansion of one level of the BFS of a single slot.
 int ip_level_deg(const IpSlot* slot, int64_t head, int64_t F, int64_t* deg, hipStream_t st);
 int ip_level_entries(const IpSlot* slot, int64_t head, int64_t F, const int64_t* dpre, int64_t E, int mode,

@@ -586,23 +586,52 @@ __device__ __forceinline__ int lds_upper(const int64_t* pre, int cnt, int64_t x)
   return lo;
 }
 
+// LDS search state of graphs of at most kIpBitmapNodes nodes: a visited bit
+// per node (kept equal to pos != -1) and a claim table for levels of at most
+// kIpFastEntries entries (kIpClaimSlots keys, a neighbour id -> its first
+// entry index).
+constexpr int64_t kIpBitmapNodes = 1 << 18;
+constexpr int kIpFastEntries = 4 * kIpThreads;
+constexpr int kIpClaimSlots = 2 * kIpFastEntries;
+
+size_t ip_dynamic_lds(int64_t max_n) {
+  if (max_n > kIpBitmapNodes) return 0;
+  return (size_t)((max_n + 31) / 32 + 2 * kIpClaimSlots) * 4;
+}
+
+__device__ __forceinline__ bool bm_test(const uint32_t* bm, int32_t u) { return (bm[u >> 5] >> (u & 31)) & 1u; }
+__device__ __forceinline__ void bm_set(uint32_t* bm, int32_t u) { atomicOr(&bm[u >> 5], 1u << (u & 31)); }
+
 // state[0..3] = head, tail, next seed, yielded flag.  With allow_yield the
 // kernel stops before a level whose frontier has more than big_entries
 // stored entries (rows ascending only); the host expands that level with
-// grid-wide kernels and relaunches.
+// grid-wide kernels and relaunches.  bm_words > 0: the dynamic LDS holds the
+// visited bitmap (bm_words words, at least (n + 31) / 32) and the claim table.
 __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict__ slots, int allow_yield,
-                                                      int64_t big_entries) {
+                                                      int64_t big_entries, int bm_words) {
   const IpSlot sl = slots[blockIdx.x];
   __shared__ int64_t sh[kIpWaves];
   __shared__ int64_t s_head, s_tail, s_next;
   __shared__ int64_t s_pre[kIpThreads];
   __shared__ int64_t s_e0[kIpThreads];
+  extern __shared__ uint32_t s_dyn[];
+  uint32_t* bm = bm_words > 0 ? s_dyn : nullptr;
+  int32_t* ckey = (int32_t*)(s_dyn + bm_words);
+  int32_t* cval = ckey + kIpClaimSlots;
   const int64_t n = sl.n;
   const int wv = threadIdx.x / kWave;
   if (threadIdx.x == 0) {
     s_head = sl.state[0];
     s_tail = sl.state[1];
     s_next = sl.state[2];
+  }
+  if (bm) {
+    // the visited bits of the current state (the grid-wide level kernels
+    // between launches update pos only)
+    for (int j = threadIdx.x; j < bm_words; j += kIpThreads) bm[j] = 0;
+    __syncthreads();
+    for (int64_t v = threadIdx.x; v < n; v += kIpThreads)
+      if (ld_acq(&sl.pos[v]) != -1) bm_set(bm, (int32_t)v);
   }
   __syncthreads();
   for (;;) {
@@ -619,7 +648,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       bool unv = false;
       if (valid) {
         d = sl.rp[id + 1] - sl.rp[id];
-        unv = ld_acq(&sl.pos[id]) == -1;
+        unv = bm ? !bm_test(bm, (int32_t)id) : ld_acq(&sl.pos[id]) == -1;
       }
       const bool skip = valid && sl.skip_isolated && d == 0;
       const bool iso = unv && !skip && d == 0;
@@ -631,6 +660,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       if (take) {
         st_rel(&sl.order[tail + ex], (int32_t)id);
         st_rel(&sl.pos[id], (int32_t)(tail + ex));
+        if (bm) bm_set(bm, (int32_t)id);
       }
       __syncthreads();
       if (threadIdx.x == 0) {
@@ -665,6 +695,69 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
         return;
       }
       E_known = true;
+      if (bm && Tc <= kIpFastEntries) {
+        // claims in LDS: a neighbour goes to its first entry in frontier
+        // order (= the smallest frontier position), read from the claim table
+        s_pre[threadIdx.x] = ex;
+        s_e0[threadIdx.x] = e0;
+        for (int j = threadIdx.x; j < kIpClaimSlots; j += kIpThreads) {
+          ckey[j] = -1;
+          cval[j] = INT32_MAX;
+        }
+        __syncthreads();
+        constexpr int Q = kIpFastEntries / kIpThreads;
+        int32_t uq[Q];
+        bool hq[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int64_t idx = (int64_t)q * kIpThreads + threadIdx.x;
+          hq[q] = idx < Tc;
+          uq[q] = 0;
+          if (hq[q]) {
+            const int l = lds_upper(s_pre, (int)F, idx);
+            uq[q] = sl.col[s_e0[l] + idx - s_pre[l]];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          hq[q] = hq[q] && !bm_test(bm, uq[q]);
+          if (!hq[q]) continue;
+          uint32_t h = hash32((uint32_t)uq[q]) & (kIpClaimSlots - 1);
+          for (;;) {
+            const int32_t prev = atomicCAS(&ckey[h], -1, uq[q]);
+            if (prev == -1 || prev == uq[q]) {
+              atomicMin(&cval[h], (int32_t)(q * kIpThreads + threadIdx.x));
+              break;
+            }
+            h = (h + 1) & (kIpClaimSlots - 1);
+          }
+        }
+        __syncthreads();
+        int64_t T = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          bool ch = false;
+          if (hq[q]) {
+            uint32_t h = hash32((uint32_t)uq[q]) & (kIpClaimSlots - 1);
+            while (ckey[h] != uq[q]) h = (h + 1) & (kIpClaimSlots - 1);
+            ch = cval[h] == (int32_t)(q * kIpThreads + threadIdx.x);
+          }
+          int64_t cx;
+          const int64_t ct = block_exscan(ch ? 1 : 0, &cx, sh);
+          if (ch) {
+            st_rel(&sl.order[tail + T + cx], uq[q]);
+            st_rel(&sl.pos[uq[q]], (int32_t)(tail + T + cx));
+            bm_set(bm, uq[q]);
+          }
+          T += ct;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          s_head = tail;
+          s_tail = tail + T;
+        }
+        continue;
+      }
       if (Tc <= kIpThreads) {
         s_pre[threadIdx.x] = ex;
         s_e0[threadIdx.x] = e0;
@@ -819,6 +912,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
     for (int64_t i = threadIdx.x; i < T; i += kIpThreads) {
       const int32_t u = ld_acq(&sl.order[tail + i]);
       st_rel(&sl.pos[u], (int32_t)(tail + i));
+      if (bm) bm_set(bm, u);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -933,9 +1027,19 @@ __global__ void __launch_bounds__(256) k_lvl_pos(const IpSlot* __restrict__ slp,
     sl.pos[sl.order[tail + i]] = (int32_t)(tail + i);
 }
 
-int initial_partition(const IpSlot* dev_slots, int count, int allow_yield, int64_t big_entries, hipStream_t st) {
+int initial_partition(const IpSlot* dev_slots, int count, int64_t max_n, int allow_yield, int64_t big_entries,
+                      hipStream_t st) {
   if (count <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_ip_bfs, dim3(count), dim3(kIpThreads), 0, st, dev_slots, allow_yield, big_entries);
+  const size_t lds = ip_dynamic_lds(max_n);
+  static bool attr_set = false;
+  if (!attr_set) {
+    SCLAP_HIP(hipFuncSetAttribute((const void*)k_ip_bfs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)ip_dynamic_lds(kIpBitmapNodes)));
+    attr_set = true;
+  }
+  const int bm_words = lds ? (int)((max_n + 31) / 32) : 0;
+  hipLaunchKernelGGL(k_ip_bfs, dim3(count), dim3(kIpThreads), lds, st, dev_slots, allow_yield, big_entries,
+                     bm_words);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
