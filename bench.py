@@ -89,9 +89,15 @@ def roofline(prof: dict, workload: str) -> tuple[dict, list]:
     per_kernel = [{"kernel": RATE_KERNELS[b], "ms_per_round": prof["kernels"][b]["ms"] / launches,
                    "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
                    if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(5)]
+    traffic = traffic_for(RATE_KERNELS[dom], workload)
     rl = {"bound": "hbm", "kernel": RATE_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(RATE_KERNELS[dom], workload),
+          "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
           "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": launches}
+    if traffic and avg_ms > 0:
+        # the bytes the memory interface actually moved (whole lines for the
+        # 4-byte label gathers), over the same launch duration
+        rl["traffic_GBps"] = traffic / (avg_ms * 1e-3) / 1e9
+        rl["traffic_frac"] = rl["traffic_GBps"] / HBM_PEAK_GBS
     return rl, per_kernel
 
 
