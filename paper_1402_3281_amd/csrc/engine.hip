@@ -630,9 +630,9 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&tcnt, (size_t)T + 1, st));
   SCLAP_TRY(dalloc_t(&toff, (size_t)T + 1, st));
   SCLAP_TRY(fill_i64(tcnt, (int64_t)T + 1, 0, st));
-  int32_t* ycache = nullptr;
-  SCLAP_TRY(dalloc_t(&ycache, (size_t)std::max<int64_t>(F.m, 1), st));
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, ycache,
+  uint64_t* kcache = nullptr;
+  SCLAP_TRY(dalloc_t(&kcache, (size_t)std::max<int64_t>(F.m, 1), st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, kcache,
                            st));
   {
     const size_t sb = prim_exscan_i64_bytes((size_t)T + 1);
@@ -653,8 +653,8 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
     SCLAP_TRY(dalloc_t(&v1, mz, st));
     SCLAP_TRY(dalloc_t(&v2, mz, st));
   }
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, ycache, st));
-  dfree(ycache, st);
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, kcache, st));
+  dfree(kcache, st);
   dfree(tcnt, st);
   dfree(toff, st);
   const size_t tb = unit ? std::max(prim_sort_keys_bytes(mz), prim_rle_bytes(mz))

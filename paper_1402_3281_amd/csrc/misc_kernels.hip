@@ -339,66 +339,68 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
                                                int64_t n, int64_t m, int bits, int mode,
                                                int64_t* __restrict__ tcnt, const int64_t* __restrict__ toff,
                                                uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                               int32_t* __restrict__ ycache) {
+                                               uint64_t* __restrict__ kcache) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
-  __shared__ int64_t s_w[4];
+  __shared__ uint32_t s_cnt[4][kItems];
+  constexpr uint64_t kSame = ~0ull;
+  const int w = threadIdx.x / kWave;
+  const uint64_t lt = (1ull << lane()) - 1ull;
   const int64_t ntiles = (m + kEpb - 1) / kEpb;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t E0 = t * kEpb;
-    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
-    int32_t xs[kItems], ys[kItems];
-    int mine = 0;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-      const int64_t e = E0 + j * 256 + threadIdx.x;
-      xs[j] = -1;
-      ys[j] = -1;
-      if (e >= r.e1) continue;
-      const int32_t x = cof[edge_row(rp, r, s_rp, e)];
-      // mode 0 gathers the neighbour's coarse id and keeps it (-1: same
-      // coarse node) for mode 1, which then reads it in entry order
-      int32_t y;
-      if (mode == 0) {
-        y = cof[col[e]];
-        if (ycache) ycache[e] = x != y ? y : -1;
-      } else {
-        y = ycache ? ycache[e] : cof[col[e]];
-        if (y < 0) y = x;
-      }
-      if (x != y) {
-        xs[j] = x;
-        ys[j] = y;
-        ++mine;
-      }
-    }
-    // workgroup exclusive scan of `mine`
-    int64_t incl = mine;
-    for (int off = 1; off < kWave; off <<= 1) {
-      const int64_t o = __shfl_up(incl, off);
-      if ((int)lane() >= off) incl += o;
-    }
-    const int w = threadIdx.x / kWave;
-    if (lane() == kWave - 1) s_w[w] = incl;
-    __syncthreads();
-    int64_t before = 0, total = 0;
-    for (int i = 0; i < 4; ++i) {
-      before += i < w ? s_w[i] : 0;
-      total += s_w[i];
-    }
+    uint64_t kk[kItems];
+    uint32_t rank[kItems];
     if (mode == 0) {
-      if (threadIdx.x == 0) tcnt[t] = total;
-      continue;
+      // the key of every entry joining two coarse nodes, kSame otherwise
+      const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const int64_t e = E0 + j * 256 + threadIdx.x;
+        kk[j] = kSame;
+        if (e >= r.e1) continue;
+        const int32_t x = cof[edge_row(rp, r, s_rp, e)];
+        const int32_t y = cof[col[e]];
+        if (x != y) kk[j] = ((uint64_t)(uint32_t)x << bits) | (uint64_t)(uint32_t)y;
+        kcache[e] = kk[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const int64_t e = E0 + j * 256 + threadIdx.x;
+        kk[j] = e < m ? kcache[e] : kSame;
+      }
     }
-    int64_t p = toff[t] + before + incl - mine;
+    // ranks: entry-slot j of wave w takes the places after every earlier
+    // slot of the tile and the same slot of earlier waves
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-      if (xs[j] < 0) continue;
-      const int64_t e = E0 + j * 256 + threadIdx.x;
-      keys[p] = ((uint64_t)(uint32_t)xs[j] << bits) | (uint64_t)(uint32_t)ys[j];
-      if (vals) vals[p] = ew ? ew[e] : 1;
-      ++p;
+      const uint64_t b = __ballot(kk[j] != kSame);
+      rank[j] = (uint32_t)__popcll(b & lt);
+      if (lane() == 0) s_cnt[w][j] = (uint32_t)__popcll(b);
     }
+    __syncthreads();
+    if (mode == 0) {
+      if (threadIdx.x == 0) {
+        int64_t total = 0;
+        for (int j = 0; j < kItems; ++j) total += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
+        tcnt[t] = total;
+      }
+    } else {
+      int64_t base = toff[t];
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        int64_t before = 0;
+        for (int q = 0; q < w; ++q) before += s_cnt[q][j];
+        if (kk[j] != kSame) {
+          const int64_t pos = base + before + rank[j];
+          keys[pos] = kk[j];
+          if (vals) vals[pos] = ew ? ew[E0 + j * 256 + threadIdx.x] : 1;
+        }
+        base += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -480,10 +482,10 @@ int cross_tiles(int64_t m) { return (int)((m + kEpb - 1) / kEpb); }
 
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   int32_t* ycache, hipStream_t st) {
+                   uint64_t* kcache, hipStream_t st) {
   if (n <= 0 || m <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
-                     keys, vals, ycache);
+                     keys, vals, kcache);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
