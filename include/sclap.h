@@ -187,7 +187,10 @@ int sclap_initial_partition(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int32
  * that take no part) with label propagation under cap lmax; a node of an
  * overloaded block ignores its own block.  Only boundary nodes are rated
  * after round 1 (exact: an interior node cannot move).  Stops after
- * p->max_rounds rounds or two consecutive rounds without a move. */
+ * p->max_rounds rounds or two consecutive rounds without a move.
+ * For k <= 64 the library keeps every node's connection to every block
+ * (n x k int32 of device memory while a level is refined) and rates later
+ * rounds from it; the result is the same. */
 int sclap_refine(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int64_t lmax, const sclap_lp_params* p,
                  int32_t* part_inout, sclap_round_stats* st, void* stream);
 

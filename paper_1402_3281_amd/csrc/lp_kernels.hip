@@ -1294,38 +1294,6 @@ __device__ __forceinline__ void agg_add(unsigned long long* hk, long long* hv, u
   }
 }
 
-// Wave-wide combination of (key, value) pairs: a bitonic sort of the pairs
-// across the 64 lanes by key, then a sum over every run of equal keys.  On
-// return the first lane of every run holds the run's sum and returns true.
-// Lanes without a pair pass key = ~0 (sorted last) and value 0.  Many lanes
-// adding to one key then cost one table operation instead of a chain of
-// conflicting LDS atomics.
-__device__ __forceinline__ bool wave_reduce_by_key(unsigned long long& key, long long& val) {
-  const int lane = (int)lane_id();
-#pragma unroll
-  for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const unsigned long long pk = __shfl_xor(key, j);
-      const long long pv = __shfl_xor(val, j);
-      const bool up = (lane & k) == 0 || k == kWave;
-      const bool lower = (lane & j) == 0;
-      const bool take = lower == up ? pk < key : pk > key;
-      key = take ? pk : key;
-      val = take ? pv : val;
-    }
-  }
-  // suffix sums inside runs (runs are contiguous after the sort)
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const unsigned long long nk = __shfl_down(key, off);
-    const long long nv = __shfl_down(val, off);
-    if (lane + off < kWave && nk == key) val += nv;
-  }
-  const unsigned long long pk = __shfl_up(key, 1);
-  return key != kEmpty && (lane == 0 || pk != key);
-}
-
 constexpr int kAggNodes = 512;    // nodes per workgroup iteration
 constexpr int kIncTable = 1024;   // >= 2 x distinct keys of one iteration
 constexpr int kApplyTable = 2048;
