@@ -510,9 +510,14 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(launch_tile_admission(S, ns, rated, bin_rated_offsets(c->binscr.p, T_bin), T_bin, tile_kmax, c->tadm.p,
                                     c->tadm.bytes, mold, st));
   }
-  bool any_refine = false;
-  for (int s = 0; s < ns; ++s) any_refine = any_refine || c->pin_slots[s].mode == MODE_REFINE;
-  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, bigm, small + 15, any_other, any_refine, small + 16, st));
+  bool any_refine = false, any_big = false;
+  for (int s = 0; s < ns; ++s) {
+    const bool r = c->pin_slots[s].mode == MODE_REFINE;
+    any_refine = any_refine || r;
+    any_big = any_big || (r && jobs[s]->lv[jobs[s]->cur].hubs > 0);  // rows above 4096 entries
+  }
+  int32_t* big = any_big ? bigm : nullptr;
+  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, small + 16, st));
   const size_t rd = 256 + (size_t)ns * CTR_N * sizeof(int64_t);
   SCLAP_TRY(ctx_ensure_pin(c, rd + 512));
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
@@ -543,7 +548,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                (int64_t*)c->prefix.p, cc, st));
     SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                     (const int64_t*)c->prefix.p, st));
-    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, bigm, small + 15, any_other, any_refine, nullptr, st));
+    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, nullptr, st));
     SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
   }

@@ -69,7 +69,8 @@ int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated
 // Applies admitted moves of the slots not admitted by tiles (run_apply); in
 // refinement writes the old block of every admitted mover by rated position
 // (mold, -1: stayed) and then marks the movers' neighbours (updating block
-// connections) for every refinement slot.
+// connections) for every refinement slot.  big == NULL: no row has more than
+// 4096 entries (no grid-wide walk is launched).
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
                  int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
                  hipStream_t st);

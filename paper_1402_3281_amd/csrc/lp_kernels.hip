@@ -1754,8 +1754,9 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
       }
     }
     if (d <= kWave && d > 0) mark_row<4>(*sl, e0, 0, d, 1, a, b);
-    if (d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
-    uint64_t mid = __ballot(d > kWave && d <= kMarkBig);
+    // without a big list (no row above kMarkBig) the wave walks every row
+    if (big && d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
+    uint64_t mid = __ballot(d > kWave && (d <= kMarkBig || !big));
     while (mid) {
       const int l = __ffsll((unsigned long long)mid) - 1;
       mid &= mid - 1;
@@ -2288,7 +2289,7 @@ int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, cons
   if (run_apply) LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, mold, skip);
   if (any_refine) {
     LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, skip);
-    LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, skip);
+    if (big) LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, skip);
   }
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
