@@ -648,24 +648,30 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_HIP(hipStreamSynchronize(st));
   const int64_t mx = c->pin[0];
   const size_t mz = (size_t)std::max<int64_t>(mx, 1);
-  // unit edge weights: the sums are the run lengths of the sorted keys
+  // unit edge weights: the sums are the run lengths of the sorted keys;
+  // weighted keys of at most 32 bits carry their weight in the low half of
+  // one 64-bit item (one key-only sort instead of key-value pairs)
   const bool unit = F.ew == nullptr;
+  const bool packed = !unit && 2 * bits <= 32;
   uint64_t *k1 = nullptr, *k2 = nullptr;
   int32_t *v1 = nullptr, *v2 = nullptr;
   SCLAP_TRY(dalloc_t(&k1, mz, st));
   SCLAP_TRY(dalloc_t(&k2, mz, st));
-  if (!unit) {
+  if (!unit && !packed) {
     SCLAP_TRY(dalloc_t(&v1, mz, st));
     SCLAP_TRY(dalloc_t(&v2, mz, st));
   }
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, kcache, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, kcache, st,
+                           packed ? 1 : 0));
   dfree(kcache, st);
   dfree(tcnt, st);
   dfree(toff, st);
-  const size_t tb = unit ? std::max(prim_sort_keys_bytes(mz), prim_rle_bytes(mz))
-                         : std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
+  const size_t tb = unit     ? std::max(prim_sort_keys_bytes(mz), prim_rle_bytes(mz))
+                    : packed ? std::max(prim_sort_keys_bytes(mz), prim_reduce_packed_bytes(mz))
+                             : std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
   SCLAP_TRY(c->prim.ensure(tb, st));
   if (unit) SCLAP_TRY(prim_sort_keys(c->prim.p, tb, k1, k2, (size_t)mx, 2 * bits, st));
+  else if (packed) SCLAP_TRY(prim_sort_keys(c->prim.p, tb, k1, k2, (size_t)mx, 32 + 2 * bits, st, 32));
   else SCLAP_TRY(prim_sort_pairs(c->prim.p, tb, k1, k2, v1, v2, (size_t)mx, 2 * bits, st));
   // reduce equal (x, y) keys: unique keys into k1, sums into an int64 buffer
   int64_t* aggs = nullptr;
@@ -674,6 +680,7 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(fill_u32(ucount, 2, 0, st));
   if (mx > 0) {
     if (unit) SCLAP_TRY(prim_rle(c->prim.p, tb, k2, k1, aggs, ucount, (size_t)mx, st));
+    else if (packed) SCLAP_TRY(prim_reduce_packed(c->prim.p, tb, k2, k1, aggs, ucount, (size_t)mx, st));
     else SCLAP_TRY(prim_reduce_by_key(c->prim.p, tb, k2, v2, k1, aggs, ucount, (size_t)mx, st));
   }
   SCLAP_HIP(hipMemcpyAsync(c->pin, ucount, 4, hipMemcpyDeviceToHost, st));

@@ -96,8 +96,9 @@ const uint32_t* bin_rated_offsets(void* scratch, int64_t T);
 
 // Library primitives (rocPRIM) used as steps: sorts, scans, reductions.
 size_t prim_sort_keys_bytes(size_t n);
+// Sort by bits [begin_bit, end_bit) of the 64-bit keys.
 int prim_sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, size_t n, int end_bit,
-                   hipStream_t st);
+                   hipStream_t st, int begin_bit = 0);
 size_t prim_sort_pairs_bytes(size_t n);
 int prim_sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
                     int32_t* vout, size_t n, int end_bit, hipStream_t st);
@@ -112,6 +113,11 @@ int prim_exscan_i64(void* tmp, size_t tmp_bytes, const int64_t* in, int64_t* out
 size_t prim_rle_bytes(size_t n);
 int prim_rle(void* tmp, size_t tmp_bytes, const uint64_t* keys, uint64_t* ukeys, int64_t* counts, uint32_t* runs,
              size_t n, hipStream_t st);
+// Sorted items key << 32 | weight (weight < 2^32): unique keys (as 64-bit
+// values) and the sum of their weights.
+size_t prim_reduce_packed_bytes(size_t n);
+int prim_reduce_packed(void* tmp, size_t tmp_bytes, const uint64_t* items, uint64_t* ukeys, int64_t* sums,
+                       uint32_t* count, size_t n, hipStream_t st);
 size_t prim_reduce_by_key_bytes(size_t n);
 int prim_reduce_by_key(void* tmp, size_t tmp_bytes, const uint64_t* keys, const int32_t* vals, uint64_t* ukeys,
                        int64_t* aggs, uint32_t* count, size_t n, hipStream_t st);

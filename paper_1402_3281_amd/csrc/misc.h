@@ -37,10 +37,11 @@ int cross_tiles(int64_t m);
 // mode 0: entries joining different coarse nodes per tile -> tcnt[tile],
 // and every entry's key x * 2^bits + y (~0: same coarse node) -> kcache (m);
 // mode 1: the keys and weights (vals may be NULL: not written) of those
-// entries from toff[tile] on (exclusive scan of tcnt), read from kcache.
+// entries from toff[tile] on (exclusive scan of tcnt), read from kcache;
+// packed (2 bits <= 32): keys hold key << 32 | weight.
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   uint64_t* kcache, hipStream_t st);
+                   uint64_t* kcache, hipStream_t st, int packed = 0);
 int contract_finish(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int64_t nc, int64_t* rp,
                     int32_t* col, int32_t* ew, unsigned* overflow, hipStream_t st);
 int project(const int32_t* cof, const int32_t* pc, int64_t n, int32_t* pf, hipStream_t st);

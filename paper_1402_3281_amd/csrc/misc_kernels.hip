@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
                                                int64_t n, int64_t m, int bits, int mode,
                                                int64_t* __restrict__ tcnt, const int64_t* __restrict__ toff,
                                                uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                               uint64_t* __restrict__ kcache) {
+                                               uint64_t* __restrict__ kcache, int packed) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   __shared__ uint32_t s_cnt[4][kItems];
@@ -394,8 +394,10 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
         for (int q = 0; q < w; ++q) before += s_cnt[q][j];
         if (kk[j] != kSame) {
           const int64_t pos = base + before + rank[j];
-          keys[pos] = kk[j];
-          if (vals) vals[pos] = ew ? ew[E0 + j * 256 + threadIdx.x] : 1;
+          const int32_t wgt = ew ? ew[E0 + j * 256 + threadIdx.x] : 1;
+          // packed: key << 32 | weight in one item (keys of at most 32 bits)
+          keys[pos] = packed ? (kk[j] << 32) | (uint32_t)wgt : kk[j];
+          if (vals) vals[pos] = wgt;
         }
         base += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
       }
@@ -482,10 +484,10 @@ int cross_tiles(int64_t m) { return (int)((m + kEpb - 1) / kEpb); }
 
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   uint64_t* kcache, hipStream_t st) {
+                   uint64_t* kcache, hipStream_t st, int packed) {
   if (n <= 0 || m <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
-                     keys, vals, kcache);
+                     keys, vals, kcache, packed);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -25,9 +25,9 @@ size_t prim_sort_keys_bytes(size_t n) {
 }
 
 int prim_sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, size_t n, int end_bit,
-                   hipStream_t st) {
+                   hipStream_t st, int begin_bit) {
   if (n == 0) return SCLAP_OK;
-  PRIM_CALL(rocprim::radix_sort_keys(tmp, tmp_bytes, in, out, n, 0, (unsigned)end_bit, st));
+  PRIM_CALL(rocprim::radix_sort_keys(tmp, tmp_bytes, in, out, n, (unsigned)begin_bit, (unsigned)end_bit, st));
   return SCLAP_OK;
 }
 
@@ -96,6 +96,31 @@ size_t prim_rle_bytes(size_t n) {
 int prim_rle(void* tmp, size_t tmp_bytes, const uint64_t* keys, uint64_t* ukeys, int64_t* counts, uint32_t* runs,
              size_t n, hipStream_t st) {
   PRIM_CALL(rocprim::run_length_encode(tmp, tmp_bytes, keys, (unsigned)n, ukeys, counts, runs, st));
+  return SCLAP_OK;
+}
+
+// Packed items key << 32 | weight (sorted by key): the upper and lower halves.
+struct PackedKey {
+  __host__ __device__ uint32_t operator()(uint64_t v) const { return (uint32_t)(v >> 32); }
+};
+struct PackedWeight {
+  __host__ __device__ int64_t operator()(uint64_t v) const { return (int64_t)(uint32_t)v; }
+};
+
+size_t prim_reduce_packed_bytes(size_t n) {
+  size_t b = 0;
+  const uint64_t* p = nullptr;
+  (void)rocprim::reduce_by_key(nullptr, b, rocprim::make_transform_iterator(p, PackedKey()),
+                               rocprim::make_transform_iterator(p, PackedWeight()), n, (uint64_t*)nullptr,
+                               (int64_t*)nullptr, (uint32_t*)nullptr, rocprim::plus<int64_t>());
+  return b;
+}
+
+int prim_reduce_packed(void* tmp, size_t tmp_bytes, const uint64_t* items, uint64_t* ukeys, int64_t* sums,
+                       uint32_t* count, size_t n, hipStream_t st) {
+  PRIM_CALL(rocprim::reduce_by_key(tmp, tmp_bytes, rocprim::make_transform_iterator(items, PackedKey()),
+                                   rocprim::make_transform_iterator(items, PackedWeight()), n, ukeys, sums, count,
+                                   rocprim::plus<int64_t>(), rocprim::equal_to<uint32_t>(), st));
   return SCLAP_OK;
 }
 
