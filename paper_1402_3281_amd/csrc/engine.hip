@@ -330,7 +330,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   const int ns = (int)jobs.size();
   if (ns == 0) return SCLAP_OK;
   SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
-  int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0;
+  int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0, max_tiles = 0;
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
   bool any_build = false, any_cached = false, any_tile = false, any_other = false, any_binned = false;
@@ -380,6 +380,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     }
     N += L.n;
     T_bin += bin_tiles(L.n);
+    max_tiles = std::max<int64_t>(max_tiles, bin_tiles(L.n));
     Lt += j->nlabels;
     if (d.conn_mode != CONN_RATE) {  // nodes rated from block connections skip the bins
       hub_stage += L.hub_stage;
@@ -453,7 +454,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kRateGroups + 1], st));
   uint64_t* binfo = (uint64_t*)c->binfo.p;
   if (!reuse_bins) {
-    SCLAP_TRY(fill_u32(meta, 64, 0, st));
     const size_t bsb = bin_scratch_bytes(T_bin);
     SCLAP_TRY(c->binscr.ensure(bsb, st));
     SCLAP_TRY(launch_bin(S, ns, T_bin, bins, binfo, bin_cap, meta, bin_vis, rated, meta + 14, c->binscr.p,
@@ -507,8 +507,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     // the binning scratch still holds this round's rated-list offsets
     const size_t tb = tile_adm_bytes(T_bin, tile_kmax);
     SCLAP_TRY(c->tadm.ensure(tb, st));
-    SCLAP_TRY(launch_tile_admission(S, ns, rated, bin_rated_offsets(c->binscr.p, T_bin), T_bin, tile_kmax, c->tadm.p,
-                                    c->tadm.bytes, mold, st));
+    SCLAP_TRY(launch_tile_admission(S, ns, rated, bin_rated_offsets(c->binscr.p, T_bin), T_bin, tile_kmax, max_tiles,
+                                    c->tadm.p, c->tadm.bytes, mold, st));
   }
   bool any_refine = false, any_big = false;
   for (int s = 0; s < ns; ++s) {

@@ -90,8 +90,11 @@ struct TileAdm {
   uint32_t* keys;        // kmax x T: scan segments (block x slot)
 };
 size_t tile_adm_bytes(int64_t T, int kmax);
+// max_slot_tiles: the largest tile count of one slot (small ones are scanned
+// by one workgroup per block and slot).
 int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const uint32_t* roff, int64_t T, int kmax,
-                          void* scratch, size_t scratch_bytes, int32_t* mold, hipStream_t st);
+                          int64_t max_slot_tiles, void* scratch, size_t scratch_bytes, int32_t* mold,
+                          hipStream_t st);
 const uint32_t* bin_rated_offsets(void* scratch, int64_t T);
 
 // Library primitives (rocPRIM) used as steps: sorts, scans, reductions.

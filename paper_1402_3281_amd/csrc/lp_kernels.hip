@@ -99,6 +99,11 @@ __global__ void __launch_bounds__(kBinTile) k_bin_count(const DevSlot* __restric
   __shared__ uint32_t s_c[4][kBinRows];
   __shared__ int64_t s_v[4][kBinRows];
   const int w = threadIdx.x / kWave;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // the entry after the last tile: the scans' totals land there
+    cnt[(int64_t)kBinRows * T] = 0;
+    vis[(int64_t)kBinRows * T] = 0;
+  }
   for (int64_t t = blockIdx.x; t < T; t += gridDim.x) {
     const int s = ONE ? 0 : slot_of_tile(S, ns, t);
     const DevSlot& sl = S[s];
@@ -196,6 +201,58 @@ __global__ void __launch_bounds__(kBinTile) k_bin_write(const DevSlot* __restric
       rated[(off[(int64_t)kBins * T + t] - off[(int64_t)kBins * T]) + rbefore + rrank] = (int32_t)u;
     }
     __syncthreads();
+  }
+}
+
+// Exclusive scans of cnt and vis (rows entries, the last one 0) in one
+// workgroup of kScan1Threads threads, for small tile counts (one launch
+// instead of the device-wide scans).
+constexpr int kScan1Threads = 1024;
+constexpr int64_t kScan1Rows = 64 * kScan1Threads;
+
+__global__ void __launch_bounds__(kScan1Threads) k_bin_scan1(const uint32_t* __restrict__ cnt,
+                                                            const int64_t* __restrict__ vis, int64_t rows,
+                                                            uint32_t* __restrict__ off, int64_t* __restrict__ voff) {
+  __shared__ uint32_t sc[kScan1Threads / kWave];
+  __shared__ int64_t sv[kScan1Threads / kWave];
+  const int64_t per = (rows + kScan1Threads - 1) / kScan1Threads;
+  const int64_t b = threadIdx.x * per, e = b + per < rows ? b + per : rows;
+  uint32_t c = 0;
+  int64_t v = 0;
+  for (int64_t i = b; i < e; ++i) {
+    c += cnt[i];
+    v += vis[i];
+  }
+  // exclusive scan of the thread sums
+  uint32_t ci = c;
+  int64_t vi = v;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t c2 = __shfl_up(ci, o);
+    const int64_t v2 = __shfl_up(vi, o);
+    if ((int)lane_id() >= o) {
+      ci += c2;
+      vi += v2;
+    }
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) {
+    sc[w] = ci;
+    sv[w] = vi;
+  }
+  __syncthreads();
+  uint32_t cb = 0;
+  int64_t vb = 0;
+  for (int q = 0; q < w; ++q) {
+    cb += sc[q];
+    vb += sv[q];
+  }
+  cb += ci - c;
+  vb += vi - v;
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = cb;
+    voff[i] = vb;
+    cb += cnt[i];
+    vb += vis[i];
   }
 }
 
@@ -1904,6 +1961,45 @@ __global__ void __launch_bounds__(kBinTile) k_ta_admit(const DevSlot* __restrict
   }
 }
 
+// Inclusive scan of the tile sums of workgroup (j, s): block j, slot s, for
+// slots of at most kTaScanTiles tiles (one launch instead of the
+// device-wide scan-by-key).
+constexpr int kTaScanTiles = 4 * 1024;
+
+__global__ void __launch_bounds__(1024) k_ta_scan_small(const DevSlot* __restrict__ S, int ns, TileAdm A) {
+  __shared__ int64_t sh[1024 / kWave];
+  const int j = (int)(blockIdx.x % (uint32_t)A.kmax), s = (int)(blockIdx.x / (uint32_t)A.kmax);
+  const DevSlot& sl = S[s];
+  if (!(tile_admission(sl) && sl.round > 0) || j >= sl.nlabels) return;
+  const int64_t t0 = sl.tbase, t1 = s + 1 < ns ? S[s + 1].tbase : A.T;
+  constexpr int Q = kTaScanTiles / 1024;
+  const int64_t* in = A.tsum + (int64_t)j * A.T;
+  int64_t* out = A.tpre + (int64_t)j * A.T;
+  int64_t x[Q], sum = 0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t t = t0 + (int64_t)threadIdx.x * Q + q;
+    x[q] = t < t1 ? in[t] : 0;
+    sum += x[q];
+  }
+  int64_t incl = sum;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(incl, o);
+    if ((int)lane_id() >= o) incl += y;
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) sh[w] = incl;
+  __syncthreads();
+  int64_t run = incl - sum;
+  for (int q = 0; q < w; ++q) run += sh[q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int64_t t = t0 + (int64_t)threadIdx.x * Q + q;
+    run += x[q];
+    if (t < t1) out[t] = run;
+  }
+}
+
 // Workgroup (s, j): slot s, block j < kmax (its weight) or j = kmax (moved).
 __global__ void __launch_bounds__(256) k_ta_reduce(const DevSlot* __restrict__ S, int ns, TileAdm A) {
   __shared__ int64_t red[8];
@@ -2153,11 +2249,13 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
   if (T > 0) {
     const unsigned G = (unsigned)std::min<int64_t>(T, 4096);
     // the entry after the last tile is the total of the scans
-    SCLAP_TRY(fill_u32(cnt + rows - 1, 1, 0, st));
-    SCLAP_TRY(fill_i64(vis + rows - 1, 1, 0, st));
     LAUNCH(k_bin_count, G, kBinTile, S, ns, T, cnt, vis);
-    SCLAP_TRY(prim_exscan_i32(tmp, tmp_bytes, (const int32_t*)cnt, (int32_t*)off, rows, st));
-    SCLAP_TRY(prim_exscan_i64(tmp, tmp_bytes, vis, voff, rows, st));
+    if ((int64_t)rows <= kScan1Rows) {
+      hipLaunchKernelGGL(k_bin_scan1, dim3(1), dim3(kScan1Threads), 0, st, cnt, vis, (int64_t)rows, off, voff);
+    } else {
+      SCLAP_TRY(prim_exscan_i32(tmp, tmp_bytes, (const int32_t*)cnt, (int32_t*)off, rows, st));
+      SCLAP_TRY(prim_exscan_i64(tmp, tmp_bytes, vis, voff, rows, st));
+    }
     LAUNCH(k_bin_write, G, kBinTile, S, ns, T, off, bins, binfo, bin_cap, rated);
   } else {
     SCLAP_TRY(fill_u32(off, 1, 0, st));
@@ -2207,7 +2305,8 @@ size_t tile_adm_bytes(int64_t T, int kmax) {
 }
 
 int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const uint32_t* roff, int64_t T, int kmax,
-                          void* scratch, size_t scratch_bytes, int32_t* mold, hipStream_t st) {
+                          int64_t max_slot_tiles, void* scratch, size_t scratch_bytes, int32_t* mold,
+                          hipStream_t st) {
   if (T == 0) return SCLAP_OK;
   const size_t n = (size_t)kmax * (size_t)T;
   TileAdm A{};
@@ -2224,7 +2323,11 @@ int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const 
   const size_t tmp_bytes = scratch_bytes - (size_t)((char*)tmp - p);
   const unsigned G = (unsigned)std::min<int64_t>(T, 4096);
   LAUNCH(k_ta_sums, G, kBinTile, S, ns, rated, A);
-  SCLAP_TRY(prim_scan_by_key(tmp, tmp_bytes, A.keys, A.tsum, A.tpre, n, st));
+  if (max_slot_tiles <= kTaScanTiles) {
+    hipLaunchKernelGGL(k_ta_scan_small, dim3((unsigned)(ns * kmax)), dim3(1024), 0, st, S, ns, A);
+  } else {
+    SCLAP_TRY(prim_scan_by_key(tmp, tmp_bytes, A.keys, A.tsum, A.tpre, n, st));
+  }
   LAUNCH(k_ta_admit, G, kBinTile, S, ns, rated, A, mold);
   hipLaunchKernelGGL(k_ta_reduce, dim3((unsigned)(ns * (kmax + 1))), dim3(256), 0, st, S, ns, A);
   SCLAP_HIP(hipGetLastError());
