@@ -33,6 +33,7 @@ struct Level {
   int32_t* coarse_of = nullptr;  // n: map to the next coarser level
   int rows_sorted = 0;
   int64_t n_active = 0;          // nodes of degree > 0
+  int64_t max_deg = 0;
   // sizes of the hub rating path on this level (degree > kBinBlock)
   int64_t hubs = 0;
   int64_t hub_stage = 0;         // staged pair slots

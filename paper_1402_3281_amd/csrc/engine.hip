@@ -225,6 +225,7 @@ int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipSt
   L->hub_mat_c = c->pin[6];
   L->hub_parts_r = c->pin[7];
   L->hub_mat_r = c->pin[8];
+  L->max_deg = c->pin[9];
   return SCLAP_OK;
 }
 
@@ -331,6 +332,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (ns == 0) return SCLAP_OK;
   SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
   int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0, max_tiles = 0;
+  int64_t bin_max_deg = 0;  // largest degree of a slot whose nodes go to the bins
+  bool tiny_graph = false;  // a binned slot with fewer than 32 entries (degree <= 64 in the 64-lane bin)
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
   bool any_build = false, any_cached = false, any_tile = false, any_other = false, any_binned = false;
@@ -383,6 +386,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     max_tiles = std::max<int64_t>(max_tiles, bin_tiles(L.n));
     Lt += j->nlabels;
     if (d.conn_mode != CONN_RATE) {  // nodes rated from block connections skip the bins
+      bin_max_deg = std::max<int64_t>(bin_max_deg, L.max_deg);
+      tiny_graph = tiny_graph || L.m < 32;
       hub_stage += L.hub_stage;
       hub_parts += refine ? L.hub_parts_r : L.hub_parts_c;
       hub_mat += refine ? L.hub_mat_r : L.hub_mat_c;
@@ -489,7 +494,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
   // rounds whose every slot rates from block connections leave the bins empty
   if (any_binned) {
-    SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights, st,
+    SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights,
+                          tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, st,
                           c->profile ? c->ev : nullptr));
   } else if (c->profile) {
     for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));

@@ -42,9 +42,11 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 // Rating launches: bins 0-4 (k_rate_small), 5-6 (k_rate_mid), 7 (k_rate_large),
 // 8 (hub kernels, only if `hubs`).  evs (may be NULL): 5 events around them.
 constexpr int kRateGroups = 5;
+// max_deg: no binned node has a larger degree (the launches of bins above
+// it are left out).
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                hipStream_t st, hipEvent_t* evs);
+                int64_t max_deg, hipStream_t st, hipEvent_t* evs);
 // Small contended sets resolved on the device; sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,
                            uint32_t* big_flag, hipStream_t st);

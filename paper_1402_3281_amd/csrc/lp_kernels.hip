@@ -210,9 +210,17 @@ __global__ void __launch_bounds__(kBinTile) k_bin_write(const DevSlot* __restric
 constexpr int kScan1Threads = 1024;
 constexpr int64_t kScan1Rows = 64 * kScan1Threads;
 
+__device__ void bin_totals(const DevSlot* __restrict__ S, int ns, int64_t T, const uint32_t* __restrict__ off,
+                           const int64_t* __restrict__ voff, uint32_t* __restrict__ bin_cnt,
+                           unsigned long long* __restrict__ bin_visits, uint32_t* __restrict__ rated_cnt);
+
 __global__ void __launch_bounds__(kScan1Threads) k_bin_scan1(const uint32_t* __restrict__ cnt,
                                                             const int64_t* __restrict__ vis, int64_t rows,
-                                                            uint32_t* __restrict__ off, int64_t* __restrict__ voff) {
+                                                            uint32_t* __restrict__ off, int64_t* __restrict__ voff,
+                                                            const DevSlot* __restrict__ S, int ns, int64_t T,
+                                                            uint32_t* __restrict__ bin_cnt,
+                                                            unsigned long long* __restrict__ bin_visits,
+                                                            uint32_t* __restrict__ rated_cnt) {
   __shared__ uint32_t sc[kScan1Threads / kWave];
   __shared__ int64_t sv[kScan1Threads / kWave];
   const int64_t per = (rows + kScan1Threads - 1) / kScan1Threads;
@@ -254,14 +262,15 @@ __global__ void __launch_bounds__(kScan1Threads) k_bin_scan1(const uint32_t* __r
     cb += cnt[i];
     vb += vis[i];
   }
+  // then the totals (the scans are complete in this workgroup)
+  __syncthreads();
+  bin_totals(S, ns, T, off, voff, bin_cnt, bin_visits, rated_cnt);
 }
 
 // Totals: node count and visits per bin, rated count, edge visits per slot.
-__global__ void __launch_bounds__(256) k_bin_totals(const DevSlot* __restrict__ S, int ns, int64_t T,
-                                                    const uint32_t* __restrict__ off,
-                                                    const int64_t* __restrict__ voff, uint32_t* __restrict__ bin_cnt,
-                                                    unsigned long long* __restrict__ bin_visits,
-                                                    uint32_t* __restrict__ rated_cnt) {
+__device__ void bin_totals(const DevSlot* __restrict__ S, int ns, int64_t T, const uint32_t* __restrict__ off,
+                           const int64_t* __restrict__ voff, uint32_t* __restrict__ bin_cnt,
+                           unsigned long long* __restrict__ bin_visits, uint32_t* __restrict__ rated_cnt) {
   if (threadIdx.x < kBinRows) {
     const int j = threadIdx.x;
     const uint32_t c = off[(int64_t)(j + 1) * T] - off[(int64_t)j * T];
@@ -279,6 +288,14 @@ __global__ void __launch_bounds__(256) k_bin_totals(const DevSlot* __restrict__ 
     for (int j = 0; j < kBinRows; ++j) sum += voff[(int64_t)j * T + t1] - voff[(int64_t)j * T + t0];
     gst(S[s].ctr, CTR_VISITS, sum);
   }
+}
+
+__global__ void __launch_bounds__(256) k_bin_totals(const DevSlot* __restrict__ S, int ns, int64_t T,
+                                                    const uint32_t* __restrict__ off,
+                                                    const int64_t* __restrict__ voff, uint32_t* __restrict__ bin_cnt,
+                                                    unsigned long long* __restrict__ bin_visits,
+                                                    uint32_t* __restrict__ rated_cnt) {
+  bin_totals(S, ns, T, off, voff, bin_cnt, bin_visits, rated_cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -2251,24 +2268,27 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
     // the entry after the last tile is the total of the scans
     LAUNCH(k_bin_count, G, kBinTile, S, ns, T, cnt, vis);
     if ((int64_t)rows <= kScan1Rows) {
-      hipLaunchKernelGGL(k_bin_scan1, dim3(1), dim3(kScan1Threads), 0, st, cnt, vis, (int64_t)rows, off, voff);
+      hipLaunchKernelGGL(k_bin_scan1, dim3(1), dim3(kScan1Threads), 0, st, cnt, vis, (int64_t)rows, off, voff, S, ns,
+                         T, bin_cnt, bin_visits, rated_cnt);
     } else {
       SCLAP_TRY(prim_exscan_i32(tmp, tmp_bytes, (const int32_t*)cnt, (int32_t*)off, rows, st));
       SCLAP_TRY(prim_exscan_i64(tmp, tmp_bytes, vis, voff, rows, st));
+      hipLaunchKernelGGL(k_bin_totals, dim3(1), dim3(256), 0, st, S, ns, T, off, voff, bin_cnt, bin_visits,
+                         rated_cnt);
     }
     LAUNCH(k_bin_write, G, kBinTile, S, ns, T, off, bins, binfo, bin_cap, rated);
   } else {
     SCLAP_TRY(fill_u32(off, 1, 0, st));
     SCLAP_TRY(fill_i64(voff, 1, 0, st));
+    hipLaunchKernelGGL(k_bin_totals, dim3(1), dim3(256), 0, st, S, ns, T, off, voff, bin_cnt, bin_visits, rated_cnt);
   }
-  hipLaunchKernelGGL(k_bin_totals, dim3(1), dim3(256), 0, st, S, ns, T, off, voff, bin_cnt, bin_visits, rated_cnt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                hipStream_t st, hipEvent_t* evs) {
+                int64_t max_deg, hipStream_t st, hipEvent_t* evs) {
   const unsigned G = grid_for(n_hint, 64, 2048);
   auto rec = [&](int i) {
     if (evs) (void)hipEventRecord(evs[i], st);
@@ -2276,13 +2296,13 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
   rec(0);
   const int uw = unit_weights ? 1 : 0;
   LAUNCH(k_rate_tiny, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G, uw);
-  LAUNCH(k_rate_b32, G, 256, S, ns, bins + 2 * bin_cap, binfo + 2 * bin_cap, bin_cnt + 2, uw);
+  if (max_deg > 16) LAUNCH(k_rate_b32, G, 256, S, ns, bins + 2 * bin_cap, binfo + 2 * bin_cap, bin_cnt + 2, uw);
   rec(1);
-  LAUNCH(k_rate_small, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
+  if (max_deg > 32) LAUNCH(k_rate_small, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(2);
-  LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
+  if (max_deg > 128) LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(3);
-  LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
+  if (max_deg > 1024) LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
   rec(4);
   if (hubs) {
     const int32_t* hb = bins + 8 * bin_cap;

@@ -11,9 +11,9 @@ int fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t st);
 int fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
-// out (device, kGraphTotals entries): sum c, max c, nodes of degree > 0 and
-// the hub rating path sizes (see k_graph_totals).
-constexpr int kGraphTotals = 9;
+// out (device, kGraphTotals entries): sum c, max c, nodes of degree > 0,
+// the hub rating path sizes (see k_graph_totals), and the largest degree.
+constexpr int kGraphTotals = 10;
 int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t k, unsigned long long* out,
                  hipStream_t st);
 int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st);

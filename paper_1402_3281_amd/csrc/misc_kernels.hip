@@ -48,7 +48,7 @@ int fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) { return fill_t
 // when refining (labels = k blocks).
 __global__ void __launch_bounds__(256) k_graph_totals(const int64_t* __restrict__ rp, const int64_t* __restrict__ nw,
                                                       int64_t n, int64_t k, unsigned long long* __restrict__ out) {
-  int64_t acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t acc[kGraphTotals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const int64_t c = nw[v];
@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(256) k_graph_totals(const int64_t* __restrict_
     acc[1] = c > acc[1] ? c : acc[1];
     const int64_t d = rp[v + 1] - rp[v];
     acc[2] += d > 0;
+    acc[9] = d > acc[9] ? d : acc[9];
     if (d > kBinBlock) {
       const int64_t nc = (d + kHubChunk - 1) / kHubChunk;
       const int64_t pc = hub_parts(d, n), pr = hub_parts(d, k);
@@ -68,20 +69,22 @@ __global__ void __launch_bounds__(256) k_graph_totals(const int64_t* __restrict_
     }
   }
   // wave, then workgroup combination: one atomic per workgroup and counter
-  __shared__ int64_t red[4][9];
+  // entries 1 and 9 are maxima, the others sums
+  __shared__ int64_t red[4][kGraphTotals];
   for (int off = 32; off > 0; off >>= 1)
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 0; q < kGraphTotals; ++q) {
       const int64_t o = __shfl_xor(acc[q], off);
-      acc[q] = q == 1 ? (o > acc[q] ? o : acc[q]) : acc[q] + o;
+      acc[q] = (q == 1 || q == 9) ? (o > acc[q] ? o : acc[q]) : acc[q] + o;
     }
   if (lane() == 0)
-    for (int q = 0; q < 9; ++q) red[threadIdx.x / kWave][q] = acc[q];
+    for (int q = 0; q < kGraphTotals; ++q) red[threadIdx.x / kWave][q] = acc[q];
   __syncthreads();
-  if (threadIdx.x < 9) {
+  if (threadIdx.x < kGraphTotals) {
     const int q = threadIdx.x;
+    const bool mx = q == 1 || q == 9;
     int64_t a = red[0][q];
-    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) a = q == 1 ? (red[w][q] > a ? red[w][q] : a) : a + red[w][q];
-    if (q == 1) atomicMax(&out[1], (unsigned long long)a);
+    for (int w = 1; w < (int)(blockDim.x / kWave); ++w) a = mx ? (red[w][q] > a ? red[w][q] : a) : a + red[w][q];
+    if (mx) atomicMax(&out[q], (unsigned long long)a);
     else if (a) atomicAdd(&out[q], (unsigned long long)a);
   }
 }
