@@ -554,6 +554,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                (int64_t*)c->prefix.p, cc, st));
     SCLAP_TRY(launch_contended_mark(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                     (const int64_t*)c->prefix.p, st));
+    SCLAP_TRY(launch_contended_add(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
+                                   (const int64_t*)c->prefix.p, st));
     SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, nullptr, st));
     SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));

@@ -47,7 +47,8 @@ constexpr int kRateGroups = 5;
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
                 int64_t max_deg, hipStream_t st, hipEvent_t* evs);
-// Small contended sets resolved on the device; sets *big_flag if too large.
+// Small contended sets resolved on the device (admission, then the admitted
+// weight added to each target's W); sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,
                            uint32_t* big_flag, hipStream_t st);
 // Incoming weight per target, the fast admission of targets that take all
@@ -59,6 +60,9 @@ int launch_contended_split(const DevSlot* S, int ns, const uint64_t* keys, uint3
                            uint32_t* tkey, int64_t* wv, hipStream_t st);
 int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
                           const int64_t* prefix, hipStream_t st);
+// After launch_contended_mark: W(t) += the admitted weight of every target.
+int launch_contended_add(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
+                         const int64_t* prefix, hipStream_t st);
 // movers (N entries) and mcnt (zeroed) collect the moved nodes of refinement slots.
 // skip (may be NULL): when *skip != 0 the launch does nothing.
 // Refinement with block connections: build them for CONN_BUILD slots from

@@ -1350,10 +1350,16 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
 // ---------------------------------------------------------------------------
 
 // LDS table combining int64 additions to (slot, label) keys within a workgroup.
+// Additions from many workgroups to one address are serialised by the
+// memory system, and a few labels (the targets of hubs' neighbours, a block)
+// receive most of them; so the admission kernels run a bounded grid, each
+// workgroup walks one contiguous range of the rated list and keeps its table
+// over the whole range, flushing it only when it fills or at the end.
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr uint32_t kCountLabel = 0xFFFFFFFFu;  // key label used for per-slot counters
 
-__device__ __forceinline__ void agg_add(unsigned long long* hk, long long* hv, uint32_t mask, unsigned long long key,
+// Returns whether the key was new to the table.
+__device__ __forceinline__ bool agg_add(unsigned long long* hk, long long* hv, uint32_t mask, unsigned long long key,
                                         long long val) {
   uint32_t h = hash32((uint32_t)key ^ (uint32_t)(key >> 32) * 0x9E3779B1u) & mask;
   for (;;) {
@@ -1362,15 +1368,61 @@ __device__ __forceinline__ void agg_add(unsigned long long* hk, long long* hv, u
     if (prev == kEmpty) prev = atomicCAS(&hk[h], kEmpty, key);
     if (prev == kEmpty || prev == key) {
       atomicAdd((unsigned long long*)&hv[h], (unsigned long long)val);
-      return;
+      return prev == kEmpty;
     }
     h = (h + 1) & mask;
   }
 }
 
 constexpr int kAggNodes = 512;    // nodes per workgroup iteration
-constexpr int kIncTable = 1024;   // >= 2 x distinct keys of one iteration
-constexpr int kApplyTable = 2048;
+constexpr int kAggGrid = 1024;    // workgroups of the admission kernels at most
+constexpr int kIncTable = 2048;   // new keys per iteration: at most kAggNodes
+constexpr int kApplyTable = 4096; // new keys per iteration: at most 2 x kAggNodes
+constexpr int kDecideBuf = 2048;  // contended keys buffered per workgroup
+
+// Range [b, e) of the N rated entries walked by this workgroup: whole
+// iterations of `per_iter` entries, split evenly over the grid.
+__device__ __forceinline__ void agg_range(int64_t N, int per_iter, int64_t& b, int64_t& e) {
+  const int64_t iters = (N + per_iter - 1) / per_iter;
+  const int64_t per = (iters + gridDim.x - 1) / gridDim.x;
+  b = (int64_t)blockIdx.x * per * per_iter;
+  e = b + per * per_iter < N ? b + per * per_iter : N;
+  if (b > e) b = e;
+}
+
+template <int T>
+__device__ __forceinline__ void agg_clear(unsigned long long* hk, long long* hv) {
+  for (int j = threadIdx.x; j < T; j += blockDim.x) {
+    hk[j] = kEmpty;
+    hv[j] = 0;
+  }
+}
+
+// Number of keys the workgroup's threads inserted (each passes its own
+// count), added to *used by one lane per wave.
+__device__ __forceinline__ void agg_count(uint32_t mine, uint32_t* used) {
+  for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+  if (lane_id() == 0 && mine) atomicAdd(used, mine);
+}
+
+// Flush of a table by a 256-thread workgroup: every thread reads and clears
+// its slots, then issues its global additions back to back.
+template <int T, class Emit>
+__device__ __forceinline__ void agg_flush(unsigned long long* hk, long long* hv, Emit emit) {
+  constexpr int FQ = T / 256;
+  unsigned long long fk[FQ];
+  long long fv[FQ];
+#pragma unroll
+  for (int q = 0; q < FQ; ++q) {
+    fk[q] = hk[threadIdx.x + q * 256];
+    fv[q] = hv[threadIdx.x + q * 256];
+    hk[threadIdx.x + q * 256] = kEmpty;
+    hv[threadIdx.x + q * 256] = 0;
+  }
+#pragma unroll
+  for (int q = 0; q < FQ; ++q)
+    if (fk[q] != kEmpty && fv[q] != 0) emit(fk[q], fv[q]);
+}
 
 // inc(t) += c(v) for every mover v -> t (movers are rated nodes).
 template <bool ONE>
@@ -1378,13 +1430,15 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
                                                   const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt) {
   __shared__ unsigned long long hk[kIncTable];
   __shared__ long long hv[kIncTable];
-  const int64_t N = *rcnt;
-  for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
-    for (int j = threadIdx.x; j < kIncTable; j += blockDim.x) {
-      hk[j] = kEmpty;
-      hv[j] = 0;
-    }
-    __syncthreads();
+  __shared__ uint32_t s_used;  // keys inserted since the kernel began
+  int64_t b, e;
+  agg_range(*rcnt, kAggNodes, b, e);
+  if (b == e) return;
+  agg_clear<kIncTable>(hk, hv);
+  if (threadIdx.x == 0) s_used = 0;
+  uint32_t flushed = 0;  // s_used at the last flush
+  __syncthreads();
+  for (int64_t base = b; base < e; base += kAggNodes) {
     constexpr int IT = kAggNodes / 256;
     int64_t u[IT], v[IT], cv[IT];
     int sv[IT];
@@ -1393,8 +1447,8 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int64_t i = base + it * 256 + threadIdx.x;
-      ok[it] = i < N;
-      u[it] = gld(rated, ok[it] ? i : N - 1);
+      ok[it] = i < e;
+      u[it] = gld(rated, ok[it] ? i : e - 1);
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -1405,23 +1459,20 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
       own[it] = gld(sl.lab, v[it]);
       cv[it] = gld(sl.nw, v[it]);
     }
+    uint32_t ins = 0;
 #pragma unroll
     for (int it = 0; it < IT; ++it)
       if (ok[it] && t[it] != own[it] && !tile_admission(S[sv[it]]))
-        agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it]);
+        ins += agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it]);
+    agg_count(ins, &s_used);
     __syncthreads();
-    // flush: the table is read first so that the atomics are issued back to back
-    constexpr int FQ = kIncTable / 256;
-    unsigned long long fk[FQ];
-    long long fv[FQ];
-#pragma unroll
-    for (int q = 0; q < FQ; ++q) {
-      fk[q] = hk[threadIdx.x + q * 256];
-      fv[q] = hv[threadIdx.x + q * 256];
+    const uint32_t used = s_used;
+    if (base + kAggNodes >= e || used - flushed + kAggNodes > kIncTable * 3 / 4) {
+      agg_flush<kIncTable>(hk, hv, [&](unsigned long long k, long long x) {
+        gadd64(S[ONE ? 0 : (k >> 32)].inc, (uint32_t)k, x);
+      });
+      flushed = used;
     }
-#pragma unroll
-    for (int q = 0; q < FQ; ++q)
-      if (fk[q] != kEmpty && fv[q] != 0) gadd64(S[ONE ? 0 : (fk[q] >> 32)].inc, (uint32_t)fk[q], fv[q]);
     __syncthreads();
   }
 }
@@ -1434,18 +1485,22 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
                                                 uint64_t* __restrict__ ckeys, uint32_t* __restrict__ ccnt,
                                                 int node_bits) {
   __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_base;
+  __shared__ uint32_t s_n, s_base;
+  __shared__ uint64_t buf[kDecideBuf];  // contended keys not yet reserved in ckeys
   const int w = threadIdx.x / kWave;
   const uint64_t lt = (1ull << lane_id()) - 1ull;
-  const int64_t N = *rcnt;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += stride) {
+  int64_t b, e;
+  agg_range(*rcnt, 256, b, e);
+  if (b == e) return;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  for (int64_t base = b; base < e; base += 256) {
     const int64_t i = base + threadIdx.x;
     bool contended = false;
     uint64_t key = 0;
     {
-      const bool ok = i < N;
-      const int64_t u = gld(rated, ok ? i : N - 1);
+      const bool ok = i < e;
+      const int64_t u = gld(rated, ok ? i : e - 1);
       const DevSlot& sl = S[SLOT(u)];
       const int64_t v = u - sl.nbase;
       const int32_t t = gld(sl.desire, v);
@@ -1463,17 +1518,25 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
     const uint64_t m = __ballot(contended);
     if (lane_id() == 0) s_w[w] = (uint32_t)__popcll(m);
     __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t tot = 0;
-      for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
-        const uint32_t c = s_w[i];
-        s_w[i] = tot;
-        tot += c;
-      }
-      s_base = tot ? atomicAdd(ccnt, tot) : 0;
+    const uint32_t n0 = s_n;
+    uint32_t off = n0, tot = 0;
+    for (int q = 0; q < 4; ++q) {
+      if (q < w) off += s_w[q];
+      tot += s_w[q];
     }
+    if (contended) buf[off + (uint32_t)__popcll(m & lt)] = key;
     __syncthreads();
-    if (contended) ckeys[s_base + s_w[w] + (uint32_t)__popcll(m & lt)] = key;
+    // one reservation in ckeys per buffer load
+    const uint32_t n1 = n0 + tot;
+    if (n1 > 0 && (base + 256 >= e || n1 + 256 > kDecideBuf)) {
+      if (threadIdx.x == 0) s_base = atomicAdd(ccnt, n1);
+      __syncthreads();
+      const uint32_t at = s_base;
+      for (uint32_t j = threadIdx.x; j < n1; j += 256) ckeys[at + j] = buf[j];
+      if (threadIdx.x == 0) s_n = 0;
+    } else if (threadIdx.x == 0) {
+      s_n = n1;
+    }
     __syncthreads();
   }
 }
@@ -1536,6 +1599,29 @@ __global__ void __launch_bounds__(256) k_contended_mark(const DevSlot* __restric
   sl.adm[v] = sl.W[t] + prefix[i] <= sl.cap ? 1 : 0;
 }
 
+// Arrivals of the admitted contended movers (after k_contended_mark): the last
+// admitted entry of each target's segment adds its inclusive prefix to W.
+template <bool ONE>
+__global__ void __launch_bounds__(256) k_contended_add(const DevSlot* __restrict__ S, int ns,
+                                                       const uint64_t* __restrict__ keys, uint32_t cnt,
+                                                       int node_bits, const int64_t* __restrict__ prefix) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cnt) return;
+  const uint64_t nmask = (1ull << node_bits) - 1ull;
+  const uint64_t k = keys[i];
+  const int64_t u = (int64_t)(k & nmask);
+  const DevSlot& sl = S[SLOT(u)];
+  const int64_t v = u - sl.nbase;
+  if (!sl.adm[v]) return;
+  if (i + 1 < cnt && (keys[i + 1] >> node_bits) == (k >> node_bits)) {
+    const int64_t u2 = (int64_t)(keys[i + 1] & nmask);
+    const DevSlot& s2 = S[SLOT(u2)];
+    if (s2.adm[u2 - s2.nbase]) return;
+  }
+  const int32_t t = sl.desire[v];
+  gst(sl.W, t, gld(sl.W, t) + prefix[i]);
+}
+
 // Contended movers, when at most kSmallContended: one workgroup sorts the
 // (target, node) keys in LDS (bitonic), scans the weights per target and
 // admits the inclusive prefixes that fit.  Larger sets are left to the
@@ -1550,6 +1636,7 @@ __global__ void __launch_bounds__(1024) k_contended_small(const DevSlot* __restr
   __shared__ uint64_t k[kSmallContended];
   __shared__ int64_t w[kSmallContended];
   __shared__ int8_t head[kSmallContended];
+  __shared__ int8_t ad[kSmallContended];
   const uint32_t cnt = *ccnt;
   if (cnt == 0) return;
   if (cnt > kSmallContended) {
@@ -1610,7 +1697,19 @@ __global__ void __launch_bounds__(1024) k_contended_small(const DevSlot* __restr
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
     const int32_t t = sl.desire[v];
-    sl.adm[v] = sl.W[t] + w[i] <= sl.cap ? 1 : 0;
+    ad[i] = sl.W[t] + w[i] <= sl.cap ? 1 : 0;
+    sl.adm[v] = ad[i];
+  }
+  __syncthreads();
+  // the admitted movers of a target are a prefix of its segment (weights are
+  // positive): the last of them adds the prefix sum to the target's weight
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    if (!ad[i]) continue;
+    if (i + 1 < cnt && ad[i + 1] && (k[i + 1] >> node_bits) == (k[i] >> node_bits)) continue;
+    const int64_t u = (int64_t)(k[i] & nmask);
+    const DevSlot& sl = S[SLOT(u)];
+    const int32_t t = sl.desire[u - sl.nbase];
+    gst(sl.W, t, gld(sl.W, t) + w[i]);
   }
 }
 
@@ -1622,22 +1721,29 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
                                                int32_t* __restrict__ mold, const uint32_t* __restrict__ skip) {
   __shared__ unsigned long long hk[kApplyTable];
   __shared__ long long hv[kApplyTable];
+  __shared__ uint32_t s_used;  // keys inserted since the kernel began
+  __shared__ int s_cs[4];      // per wave: slot of the moved count carried to the end
+  __shared__ long long s_cv[4];
   if (skip && *skip) return;  // the admission is completed on the host-driven path first
-  const int64_t N = *rcnt;
-  for (int64_t base = (int64_t)blockIdx.x * kAggNodes; base < N; base += (int64_t)gridDim.x * kAggNodes) {
-    for (int j = threadIdx.x; j < kApplyTable; j += blockDim.x) {
-      hk[j] = kEmpty;
-      hv[j] = 0;
-    }
-    __syncthreads();
+  int64_t b, e;
+  agg_range(*rcnt, kAggNodes, b, e);
+  if (b == e) return;
+  agg_clear<kApplyTable>(hk, hv);
+  if (threadIdx.x == 0) s_used = 0;
+  uint32_t flushed = 0;
+  // moved count of the wave's current slot run (lane 0)
+  int cnt_slot = -1;
+  long long cnt_val = 0;
+  __syncthreads();
+  for (int64_t base = b; base < e; base += kAggNodes) {
     constexpr int IT = kAggNodes / 256;
     int64_t uu[IT];
     bool ok[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int64_t i = base + it * 256 + threadIdx.x;
-      ok[it] = i < N;
-      uu[it] = gld(rated, ok[it] ? i : N - 1);
+      ok[it] = i < e;
+      uu[it] = gld(rated, ok[it] ? i : e - 1);
     }
     // every load of the iteration is issued before its first store (memory
     // operations complete in order, so a load after a store waits for it)
@@ -1653,6 +1759,7 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       aa[it] = gld(sl.adm, v);
       ww[it] = gld(sl.nw, v);
     }
+    uint32_t ins = 0;
     for (int it = 0; it < IT; ++it) {
       const int64_t u = uu[it];
       const int s = SLOT(u);
@@ -1663,10 +1770,8 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       bool admitted = false;
       int64_t cv = 0;
       const bool mine = ok[it] && !tile_admission(sl);
-      bool fast = false;
       if (mine && t != own) {
         admitted = aa[it] != 0;
-        fast = aa[it] == 2;
         if (admitted) {
           cv = ww[it];
           gst(sl.lab, v, t);
@@ -1676,43 +1781,55 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       }
       // refinement: old block of every admitted mover by rated position (-1: stayed)
       if (mine && sl.mode == MODE_REFINE) gst(mold, base + it * 256 + threadIdx.x, admitted ? own : -1);
-      // label weights (+c(v) to the target, -c(v) to the old label) and the
-      // moved count, combined across the wave first
+      // departures (-c(v) from the old label); the arrivals were added
+      // before (k_fold for targets that take all their movers, the exact
+      // path for the others)
       const unsigned long long ks = (unsigned long long)s << 32;
-      if (admitted && cv != 0) {
-        // arrivals at targets that take all their movers were added by k_fold
-        if (!fast) agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)t, cv);
-        agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
-      }
-      // moved count: one LDS add per wave and slot run
+      if (admitted && cv != 0) ins += agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
+      // moved count: carried by the wave while its slot does not change
       const int s0 = __shfl(s, 0);
       if (__all(s == s0)) {
         const uint64_t m = __ballot(admitted);
-        if (lane_id() == 0 && m) agg_add(hk, hv, kApplyTable - 1, ((unsigned long long)s0 << 32) | kCountLabel,
-                                         (long long)__popcll(m));
+        if (lane_id() == 0 && m) {
+          if (s0 != cnt_slot) {
+            if (cnt_val) gadd64(S[cnt_slot].ctr, CTR_MOVED, cnt_val);
+            cnt_slot = s0;
+            cnt_val = 0;
+          }
+          cnt_val += (long long)__popcll(m);
+        }
       } else if (admitted) {
-        agg_add(hk, hv, kApplyTable - 1, ks | kCountLabel, 1);
+        gadd64(sl.ctr, CTR_MOVED, (int64_t)1);
       }
     }
+    agg_count(ins, &s_used);
     __syncthreads();
-    // flush: the table is read first so that the atomics are issued back to back
-    constexpr int FQ = kApplyTable / 256;
-    unsigned long long fk[FQ];
-    long long fv[FQ];
-#pragma unroll
-    for (int q = 0; q < FQ; ++q) {
-      fk[q] = hk[threadIdx.x + q * 256];
-      fv[q] = hv[threadIdx.x + q * 256];
-    }
-#pragma unroll
-    for (int q = 0; q < FQ; ++q) {
-      if (fk[q] == kEmpty || fv[q] == 0) continue;
-      const DevSlot& sl = S[ONE ? 0 : (fk[q] >> 32)];
-      const uint32_t lab = (uint32_t)fk[q];
-      if (lab == kCountLabel) gadd64(sl.ctr, CTR_MOVED, fv[q]);
-      else gadd64(sl.W, lab, fv[q]);
+    const uint32_t used = s_used;
+    if (base + kAggNodes >= e || used - flushed + 2 * kAggNodes > kApplyTable * 3 / 4) {
+      agg_flush<kApplyTable>(hk, hv, [&](unsigned long long k, long long x) {
+        gadd64(S[ONE ? 0 : (k >> 32)].W, (uint32_t)k, x);
+      });
+      flushed = used;
     }
     __syncthreads();
+  }
+  // moved counts: the waves' carried counts combined per slot
+  if (lane_id() == 0) {
+    s_cs[threadIdx.x / kWave] = cnt_val ? cnt_slot : -1;
+    s_cv[threadIdx.x / kWave] = cnt_val;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 4; ++q) {
+      if (s_cs[q] < 0) continue;
+      long long x = s_cv[q];
+      for (int r = q + 1; r < 4; ++r)
+        if (s_cs[r] == s_cs[q]) {
+          x += s_cv[r];
+          s_cs[r] = -1;
+        }
+      gadd64(S[s_cs[q]].ctr, CTR_MOVED, (int64_t)x);
+    }
   }
 }
 
@@ -2376,8 +2493,8 @@ int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated
 
 int launch_incoming_decide(const DevSlot* S, int ns, int64_t N, int64_t Lt, const int32_t* rated,
                            const uint32_t* rcnt, uint64_t* ckeys, uint32_t* ccnt, int node_bits, hipStream_t st) {
-  LAUNCH(k_incoming, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt);
-  LAUNCH(k_decide, grid_for(N, 256, 4096), 256, S, ns, rated, rcnt, ckeys, ccnt, node_bits);
+  LAUNCH(k_incoming, grid_for(N, kAggNodes, kAggGrid), 256, S, ns, rated, rcnt);
+  LAUNCH(k_decide, grid_for(N, 256, kAggGrid), 256, S, ns, rated, rcnt, ckeys, ccnt, node_bits);
   LAUNCH(k_fold, grid_for(Lt, 256, 4096), 256, S, ns, Lt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
@@ -2399,6 +2516,14 @@ int launch_contended_mark(const DevSlot* S, int ns, const uint64_t* keys, uint32
   return SCLAP_OK;
 }
 
+int launch_contended_add(const DevSlot* S, int ns, const uint64_t* keys, uint32_t cnt, int node_bits,
+                         const int64_t* prefix, hipStream_t st) {
+  if (cnt == 0) return SCLAP_OK;
+  LAUNCH(k_contended_add, (cnt + 255) / 256, 256, S, ns, keys, cnt, node_bits, prefix);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,
                            uint32_t* big_flag, hipStream_t st) {
   LAUNCH(k_contended_small, 1, 1024, S, ns, keys, ccnt, node_bits, big_flag);
@@ -2409,7 +2534,7 @@ int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
                  int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
                  hipStream_t st) {
-  if (run_apply) LAUNCH(k_apply, grid_for(N, kAggNodes, 4096), 256, S, ns, rated, rcnt, mold, skip);
+  if (run_apply) LAUNCH(k_apply, grid_for(N, kAggNodes, kAggGrid), 256, S, ns, rated, rcnt, mold, skip);
   if (any_refine) {
     LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, skip);
     if (big) LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, skip);
