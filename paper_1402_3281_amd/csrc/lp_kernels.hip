@@ -1358,9 +1358,10 @@ __global__ void __launch_bounds__(256) k_hub_final(const DevSlot* __restrict__ S
 constexpr unsigned long long kEmpty = ~0ull;
 constexpr uint32_t kCountLabel = 0xFFFFFFFFu;  // key label used for per-slot counters
 
-// Returns whether the key was new to the table.
+// Returns whether the key was new to the table; a key found there is marked
+// hot (hot may be null).
 __device__ __forceinline__ bool agg_add(unsigned long long* hk, long long* hv, uint32_t mask, unsigned long long key,
-                                        long long val) {
+                                        long long val, uint8_t* hot = nullptr) {
   uint32_t h = hash32((uint32_t)key ^ (uint32_t)(key >> 32) * 0x9E3779B1u) & mask;
   for (;;) {
     // a slot that already holds the key needs no compare-and-swap
@@ -1368,6 +1369,7 @@ __device__ __forceinline__ bool agg_add(unsigned long long* hk, long long* hv, u
     if (prev == kEmpty) prev = atomicCAS(&hk[h], kEmpty, key);
     if (prev == kEmpty || prev == key) {
       atomicAdd((unsigned long long*)&hv[h], (unsigned long long)val);
+      if (hot && prev == key) hot[h] = 1;
       return prev == kEmpty;
     }
     h = (h + 1) & mask;
@@ -1390,38 +1392,89 @@ __device__ __forceinline__ void agg_range(int64_t N, int per_iter, int64_t& b, i
   if (b > e) b = e;
 }
 
+// Counters of a carried table: keys inserted, keys removed by flushes, and
+// hot keys counted at flushes (all only grow).
+struct AggCtr {
+  uint32_t ins, rem, hot;
+};
+
 template <int T>
-__device__ __forceinline__ void agg_clear(unsigned long long* hk, long long* hv) {
+__device__ __forceinline__ void agg_init(unsigned long long* hk, long long* hv, uint8_t* hot, AggCtr* c) {
   for (int j = threadIdx.x; j < T; j += blockDim.x) {
     hk[j] = kEmpty;
     hv[j] = 0;
+    hot[j] = 0;
   }
+  if (threadIdx.x == 0) c->ins = c->rem = c->hot = 0;
 }
 
 // Number of keys the workgroup's threads inserted (each passes its own
-// count), added to *used by one lane per wave.
-__device__ __forceinline__ void agg_count(uint32_t mine, uint32_t* used) {
+// count), added to *ctr by one lane per wave.
+__device__ __forceinline__ void agg_count(uint32_t mine, uint32_t* ctr) {
   for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
-  if (lane_id() == 0 && mine) atomicAdd(used, mine);
+  if (lane_id() == 0 && mine) atomicAdd(ctr, mine);
 }
 
-// Flush of a table by a 256-thread workgroup: every thread reads and clears
-// its slots, then issues its global additions back to back.
+// End of an iteration of a 256-thread workgroup in which this thread
+// inserted `ins` keys.  When the next iteration (at most `knew` new keys)
+// could fill the table past 3/4, or at the end of the range (`last`), the
+// table is flushed: every key is added to global memory by `emit` and
+// removed, except, when not `last`, the keys added to more than once since
+// the last flush if they are at most T/4 (they stay and keep summing: the
+// labels most movers go to).  Then at most T/4 + knew <= 3T/4 slots are
+// taken when the next flush is decided, so the table never fills.  A
+// removed slot can cut the probe chain of a kept key; a later add of that
+// key then takes a second slot, and both are emitted, so the sums stay
+// exact.
 template <int T, class Emit>
-__device__ __forceinline__ void agg_flush(unsigned long long* hk, long long* hv, Emit emit) {
+__device__ __forceinline__ void agg_step(unsigned long long* hk, long long* hv, uint8_t* hot, AggCtr* c,
+                                         uint32_t ins, bool last, int knew, uint32_t& hot_seen, Emit emit) {
   constexpr int FQ = T / 256;
-  unsigned long long fk[FQ];
-  long long fv[FQ];
+  static_assert(T % 256 == 0, "table size");
+  agg_count(ins, &c->ins);
+  __syncthreads();
+  const uint32_t live = c->ins - c->rem;
+  if (last || live + (uint32_t)knew > (uint32_t)T * 3 / 4) {
+    bool keep = false;
+    if (!last) {
+      uint32_t nh = 0;
 #pragma unroll
-  for (int q = 0; q < FQ; ++q) {
-    fk[q] = hk[threadIdx.x + q * 256];
-    fv[q] = hv[threadIdx.x + q * 256];
-    hk[threadIdx.x + q * 256] = kEmpty;
-    hv[threadIdx.x + q * 256] = 0;
+      for (int q = 0; q < FQ; ++q) {
+        const int j = threadIdx.x + q * 256;
+        nh += hk[j] != kEmpty && hot[j] ? 1u : 0u;
+      }
+      agg_count(nh, &c->hot);
+      __syncthreads();
+      const uint32_t now = c->hot;
+      keep = now - hot_seen <= (uint32_t)T / 4;
+      hot_seen = now;
+    }
+    unsigned long long fk[FQ];
+    long long fv[FQ];
+    uint32_t rem = 0;
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+      const int j = threadIdx.x + q * 256;
+      fk[q] = hk[j];
+      fv[q] = hv[j];
+      if (fk[q] == kEmpty) continue;
+      if (keep && hot[j]) {
+        hot[j] = 0;
+        fk[q] = kEmpty;
+      } else {
+        hk[j] = kEmpty;
+        hv[j] = 0;
+        hot[j] = 0;
+        ++rem;
+      }
+    }
+    agg_count(rem, &c->rem);
+    // the table is read first so that the atomics are issued back to back
+#pragma unroll
+    for (int q = 0; q < FQ; ++q)
+      if (fk[q] != kEmpty && fv[q] != 0) emit(fk[q], fv[q]);
   }
-#pragma unroll
-  for (int q = 0; q < FQ; ++q)
-    if (fk[q] != kEmpty && fv[q] != 0) emit(fk[q], fv[q]);
+  __syncthreads();
 }
 
 // inc(t) += c(v) for every mover v -> t (movers are rated nodes).
@@ -1430,13 +1483,13 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
                                                   const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt) {
   __shared__ unsigned long long hk[kIncTable];
   __shared__ long long hv[kIncTable];
-  __shared__ uint32_t s_used;  // keys inserted since the kernel began
+  __shared__ uint8_t hot[kIncTable];
+  __shared__ AggCtr ctr;
   int64_t b, e;
   agg_range(*rcnt, kAggNodes, b, e);
   if (b == e) return;
-  agg_clear<kIncTable>(hk, hv);
-  if (threadIdx.x == 0) s_used = 0;
-  uint32_t flushed = 0;  // s_used at the last flush
+  agg_init<kIncTable>(hk, hv, hot, &ctr);
+  uint32_t hot_seen = 0;
   __syncthreads();
   for (int64_t base = b; base < e; base += kAggNodes) {
     constexpr int IT = kAggNodes / 256;
@@ -1463,22 +1516,16 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
 #pragma unroll
     for (int it = 0; it < IT; ++it)
       if (ok[it] && t[it] != own[it] && !tile_admission(S[sv[it]]))
-        ins += agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it]);
-    agg_count(ins, &s_used);
-    __syncthreads();
-    const uint32_t used = s_used;
-    if (base + kAggNodes >= e || used - flushed + kAggNodes > kIncTable * 3 / 4) {
-      agg_flush<kIncTable>(hk, hv, [&](unsigned long long k, long long x) {
-        gadd64(S[ONE ? 0 : (k >> 32)].inc, (uint32_t)k, x);
-      });
-      flushed = used;
-    }
-    __syncthreads();
+        ins += agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it], hot);
+    agg_step<kIncTable>(hk, hv, hot, &ctr, ins, base + kAggNodes >= e, kAggNodes, hot_seen,
+                        [&](unsigned long long k, long long x) { gadd64(S[ONE ? 0 : (k >> 32)].inc, (uint32_t)k, x); });
   }
 }
 
 // Movers into targets whose whole incoming weight fits are admitted; the
-// others are appended as (target, node) keys for the exact path.
+// others are appended as (target, node) keys for the exact path.  adm(v):
+// bit 0 admitted by the exact path, bit 1 admitted at once, bit 2 alone.
+constexpr uint8_t kAdmExact = 1, kAdmFast = 2, kAdmAlone = 4;
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, int ns,
                                                 const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
@@ -1506,10 +1553,14 @@ __global__ void __launch_bounds__(256) k_decide(const DevSlot* __restrict__ S, i
       const int32_t t = gld(sl.desire, v);
       const int32_t own = gld(sl.lab, v);
       if (ok && t != own && !tile_admission(sl)) {
+        // kAdmAlone: W(own) = c(v), so every other member of the label has
+        // weight 0 (node weights are >= 0) and v's departure is the only
+        // change of W(own) in k_apply (departures of weight 0 are skipped)
+        const uint8_t alone = gld(sl.W, own) == gld(sl.nw, v) ? kAdmAlone : 0;
         if (gld(sl.W, t) + gld(sl.inc, t) <= sl.cap) {
-          gst(sl.adm, v, (uint8_t)2);  // the target takes all its movers (k_fold adds them)
+          gst(sl.adm, v, (uint8_t)(kAdmFast | alone));  // the target takes all its movers (k_fold adds them)
         } else {
-          gst(sl.adm, v, (uint8_t)0);
+          gst(sl.adm, v, alone);
           contended = true;
           key = ((uint64_t)(sl.lbase + t) << node_bits) | (uint64_t)u;
         }
@@ -1596,7 +1647,7 @@ __global__ void __launch_bounds__(256) k_contended_mark(const DevSlot* __restric
   const DevSlot& sl = S[SLOT(u)];
   const int64_t v = u - sl.nbase;
   const int32_t t = sl.desire[v];
-  sl.adm[v] = sl.W[t] + prefix[i] <= sl.cap ? 1 : 0;
+  sl.adm[v] = (uint8_t)((sl.adm[v] & kAdmAlone) | (sl.W[t] + prefix[i] <= sl.cap ? kAdmExact : 0));
 }
 
 // Arrivals of the admitted contended movers (after k_contended_mark): the last
@@ -1612,11 +1663,11 @@ __global__ void __launch_bounds__(256) k_contended_add(const DevSlot* __restrict
   const int64_t u = (int64_t)(k & nmask);
   const DevSlot& sl = S[SLOT(u)];
   const int64_t v = u - sl.nbase;
-  if (!sl.adm[v]) return;
+  if (!(sl.adm[v] & kAdmExact)) return;
   if (i + 1 < cnt && (keys[i + 1] >> node_bits) == (k >> node_bits)) {
     const int64_t u2 = (int64_t)(keys[i + 1] & nmask);
     const DevSlot& s2 = S[SLOT(u2)];
-    if (s2.adm[u2 - s2.nbase]) return;
+    if (s2.adm[u2 - s2.nbase] & kAdmExact) return;
   }
   const int32_t t = sl.desire[v];
   gst(sl.W, t, gld(sl.W, t) + prefix[i]);
@@ -1698,7 +1749,7 @@ __global__ void __launch_bounds__(1024) k_contended_small(const DevSlot* __restr
     const int64_t v = u - sl.nbase;
     const int32_t t = sl.desire[v];
     ad[i] = sl.W[t] + w[i] <= sl.cap ? 1 : 0;
-    sl.adm[v] = ad[i];
+    sl.adm[v] = (uint8_t)((sl.adm[v] & kAdmAlone) | ad[i]);
   }
   __syncthreads();
   // the admitted movers of a target are a prefix of its segment (weights are
@@ -1721,16 +1772,16 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
                                                int32_t* __restrict__ mold, const uint32_t* __restrict__ skip) {
   __shared__ unsigned long long hk[kApplyTable];
   __shared__ long long hv[kApplyTable];
-  __shared__ uint32_t s_used;  // keys inserted since the kernel began
+  __shared__ uint8_t hot[kApplyTable];
+  __shared__ AggCtr ctr;
   __shared__ int s_cs[4];      // per wave: slot of the moved count carried to the end
   __shared__ long long s_cv[4];
   if (skip && *skip) return;  // the admission is completed on the host-driven path first
   int64_t b, e;
   agg_range(*rcnt, kAggNodes, b, e);
   if (b == e) return;
-  agg_clear<kApplyTable>(hk, hv);
-  if (threadIdx.x == 0) s_used = 0;
-  uint32_t flushed = 0;
+  agg_init<kApplyTable>(hk, hv, hot, &ctr);
+  uint32_t hot_seen = 0;
   // moved count of the wave's current slot run (lane 0)
   int cnt_slot = -1;
   long long cnt_val = 0;
@@ -1770,8 +1821,10 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       bool admitted = false;
       int64_t cv = 0;
       const bool mine = ok[it] && !tile_admission(sl);
+      bool alone = false;
       if (mine && t != own) {
-        admitted = aa[it] != 0;
+        admitted = (aa[it] & (kAdmExact | kAdmFast)) != 0;
+        alone = (aa[it] & kAdmAlone) != 0;
         if (admitted) {
           cv = ww[it];
           gst(sl.lab, v, t);
@@ -1785,7 +1838,10 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       // before (k_fold for targets that take all their movers, the exact
       // path for the others)
       const unsigned long long ks = (unsigned long long)s << 32;
-      if (admitted && cv != 0) ins += agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv);
+      if (admitted && cv != 0) {
+        if (alone) gst(sl.W, own, gld(sl.W, own) - cv);  // no other change of W(own) here
+        else ins += agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv, hot);
+      }
       // moved count: carried by the wave while its slot does not change
       const int s0 = __shfl(s, 0);
       if (__all(s == s0)) {
@@ -1802,16 +1858,8 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
         gadd64(sl.ctr, CTR_MOVED, (int64_t)1);
       }
     }
-    agg_count(ins, &s_used);
-    __syncthreads();
-    const uint32_t used = s_used;
-    if (base + kAggNodes >= e || used - flushed + 2 * kAggNodes > kApplyTable * 3 / 4) {
-      agg_flush<kApplyTable>(hk, hv, [&](unsigned long long k, long long x) {
-        gadd64(S[ONE ? 0 : (k >> 32)].W, (uint32_t)k, x);
-      });
-      flushed = used;
-    }
-    __syncthreads();
+    agg_step<kApplyTable>(hk, hv, hot, &ctr, ins, base + kAggNodes >= e, 2 * kAggNodes, hot_seen,
+                          [&](unsigned long long k, long long x) { gadd64(S[ONE ? 0 : (k >> 32)].W, (uint32_t)k, x); });
   }
   // moved counts: the waves' carried counts combined per slot
   if (lane_id() == 0) {

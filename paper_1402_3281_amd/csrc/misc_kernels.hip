@@ -619,6 +619,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
   const IpSlot sl = slots[blockIdx.x];
   __shared__ int64_t sh[kIpWaves];
   __shared__ int64_t s_head, s_tail, s_next;
+  __shared__ int s_frv;  // the frontier's rows are in LDS: start in s_e0, degree in s_pre
   __shared__ int64_t s_pre[kIpThreads];
   __shared__ int64_t s_e0[kIpThreads];
   extern __shared__ uint32_t s_dyn[];
@@ -631,6 +632,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
     s_head = sl.state[0];
     s_tail = sl.state[1];
     s_next = sl.state[2];
+    s_frv = 0;
   }
   if (bm) {
     // the visited bits of the current state (the grid-wide level kernels
@@ -644,6 +646,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
   for (;;) {
     __syncthreads();
     const int64_t head = s_head, tail = s_tail, next = s_next;
+    const bool frv = s_frv != 0;
     __syncthreads();
     if (head == tail) {
       if (next >= n) break;
@@ -671,6 +674,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       }
       __syncthreads();
       if (threadIdx.x == 0) {
+        s_frv = 0;
         s_tail = tail + tot;
         s_next = first != INT64_MAX ? first + 1 : next + kIpThreads;
         // degree-0 nodes have nothing to expand: the frontier is the seed
@@ -686,9 +690,14 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       // emit passes, and the new nodes' positions are written at once
       int64_t d = 0, e0 = 0;
       if ((int64_t)threadIdx.x < F) {
-        const int32_t f = ld_acq(&sl.order[head + threadIdx.x]);
-        e0 = sl.rp[f];
-        d = sl.rp[f + 1] - e0;
+        if (frv) {
+          e0 = s_e0[threadIdx.x];
+          d = s_pre[threadIdx.x];
+        } else {
+          const int32_t f = ld_acq(&sl.order[head + threadIdx.x]);
+          e0 = sl.rp[f];
+          d = sl.rp[f + 1] - e0;
+        }
       }
       int64_t ex;
       const int64_t Tc = block_exscan(d, &ex, sh);
@@ -704,7 +713,10 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
       E_known = true;
       if (bm && Tc <= kIpFastEntries) {
         // claims in LDS: a neighbour goes to its first entry in frontier
-        // order (= the smallest frontier position), read from the claim table
+        // order (= the smallest frontier position), read from the claim table.
+        // Thread t takes the consecutive entries tQ .. tQ+Q-1, so one scan of
+        // the per-thread claim counts orders the new nodes; their rows are
+        // loaded with the candidates and left in LDS for the next level.
         s_pre[threadIdx.x] = ex;
         s_e0[threadIdx.x] = e0;
         for (int j = threadIdx.x; j < kIpClaimSlots; j += kIpThreads) {
@@ -713,55 +725,78 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
         }
         __syncthreads();
         constexpr int Q = kIpFastEntries / kIpThreads;
+        const int64_t i0 = (int64_t)threadIdx.x * Q;
         int32_t uq[Q];
         bool hq[Q];
+        int l = i0 < Tc ? lds_upper(s_pre, (int)F, i0) : 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          const int64_t idx = (int64_t)q * kIpThreads + threadIdx.x;
+          const int64_t idx = i0 + q;
           hq[q] = idx < Tc;
           uq[q] = 0;
           if (hq[q]) {
-            const int l = lds_upper(s_pre, (int)F, idx);
+            while (l + 1 < (int)F && s_pre[l + 1] <= idx) ++l;
             uq[q] = sl.col[s_e0[l] + idx - s_pre[l]];
+          }
+        }
+        int64_t re0[Q], re1[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          hq[q] = hq[q] && !bm_test(bm, uq[q]);
+          re0[q] = re1[q] = 0;
+          if (hq[q]) {
+            re0[q] = sl.rp[uq[q]];
+            re1[q] = sl.rp[uq[q] + 1];
           }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          hq[q] = hq[q] && !bm_test(bm, uq[q]);
           if (!hq[q]) continue;
           uint32_t h = hash32((uint32_t)uq[q]) & (kIpClaimSlots - 1);
           for (;;) {
             const int32_t prev = atomicCAS(&ckey[h], -1, uq[q]);
             if (prev == -1 || prev == uq[q]) {
-              atomicMin(&cval[h], (int32_t)(q * kIpThreads + threadIdx.x));
+              atomicMin(&cval[h], (int32_t)(i0 + q));
               break;
             }
             h = (h + 1) & (kIpClaimSlots - 1);
           }
         }
+        int32_t rd[Q];  // degrees of the candidates (at most n)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) rd[q] = (int32_t)(re1[q] - re0[q]);
         __syncthreads();
-        int64_t T = 0;
+        bool ch[Q];
+        int64_t mine = 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          bool ch = false;
+          ch[q] = false;
           if (hq[q]) {
             uint32_t h = hash32((uint32_t)uq[q]) & (kIpClaimSlots - 1);
             while (ckey[h] != uq[q]) h = (h + 1) & (kIpClaimSlots - 1);
-            ch = cval[h] == (int32_t)(q * kIpThreads + threadIdx.x);
+            ch[q] = cval[h] == (int32_t)(i0 + q);
           }
-          int64_t cx;
-          const int64_t ct = block_exscan(ch ? 1 : 0, &cx, sh);
-          if (ch) {
-            st_rel(&sl.order[tail + T + cx], uq[q]);
-            st_rel(&sl.pos[uq[q]], (int32_t)(tail + T + cx));
-            bm_set(bm, uq[q]);
+          mine += ch[q] ? 1 : 0;
+        }
+        int64_t p;
+        const int64_t T = block_exscan(mine, &p, sh);  // every LDS row read above precedes the writes below
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          if (!ch[q]) continue;
+          st_rel(&sl.order[tail + p], uq[q]);
+          st_rel(&sl.pos[uq[q]], (int32_t)(tail + p));
+          bm_set(bm, uq[q]);
+          if (p < kIpThreads) {
+            s_e0[p] = re0[q];
+            s_pre[p] = rd[q];
           }
-          T += ct;
+          ++p;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
           s_head = tail;
           s_tail = tail + T;
+          s_frv = T <= kIpThreads ? 1 : 0;
         }
         continue;
       }
@@ -789,6 +824,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
         if (threadIdx.x == 0) {
           s_head = tail;
           s_tail = tail + T;
+          s_frv = 0;
         }
         continue;
       }
@@ -925,6 +961,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
     if (threadIdx.x == 0) {
       s_head = tail;
       s_tail = tail + T;
+      s_frv = 0;
     }
   }
   __syncthreads();
