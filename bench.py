@@ -79,20 +79,24 @@ def copy_calibration(mbytes: int) -> int:
 def roofline(prof: dict, workload: str) -> tuple[dict, list]:
     """Roofline of the dominant rating kernel: algorithmic bytes per launch
     (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge visit,
-    32 B per rated node) / mean launch duration from HIP events."""
-    launches = max(prof["kernel_launches"], 1)
+    32 B per rated node) / mean launch duration from HIP events.  A launch is
+    a round in which the group's kernels ran (groups with no node in their
+    degree range are left out of a round)."""
     dom = max(range(4), key=lambda b: prof["kernels"][b]["ms"])
     kd = prof["kernels"][dom]
+    launches = max(kd["launches"], 1)
     avg_ms = kd["ms"] / launches
     bpl = kd["bytes"] / launches
     achieved = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    per_kernel = [{"kernel": RATE_KERNELS[b], "ms_per_round": prof["kernels"][b]["ms"] / launches,
+    per_kernel = [{"kernel": RATE_KERNELS[b], "launches": prof["kernels"][b]["launches"],
+                   "ms_per_launch": prof["kernels"][b]["ms"] / max(prof["kernels"][b]["launches"], 1),
                    "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
                    if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(5)]
     traffic = traffic_for(RATE_KERNELS[dom], workload)
     rl = {"bound": "hbm", "kernel": RATE_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-          "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": launches}
+          "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": launches,
+          "rounds": prof["kernel_launches"]}
     if traffic and avg_ms > 0:
         # the bytes the memory interface actually moved (whole lines for the
         # 4-byte label gathers), over the same launch duration

@@ -277,14 +277,17 @@ int sclap_profile_enable(sclap_ctx* ctx, int32_t on);
  * visits and nodes rated, whole-round device ms and rounds. */
 int sclap_profile_read(sclap_ctx* ctx, double* rate_ms, int64_t* rate_launches, int64_t* visits, int64_t* nodes,
                        double* round_ms, int64_t* rounds);
-/* Per rating launch (0: degree 1-32, one thread per node; 1: degree 33-128,
- * 64 lanes per node or one wave with an LDS table; 2: degree 129-1024;
- * 3: degree 1025-4096, one workgroup with an LDS table; 4: the multi-
- * workgroup hub path): device ms, algorithmic bytes (4 B neighbour id + 4 B
- * neighbour label [+ 4 B edge weight] per visit, 32 B per rated node), edge
- * visits and nodes, summed over rounds; *launches = rounds profiled. */
+/* Per rating launch group (0: degree 1-32, one thread per node; 1: degree
+ * 33-128, 64 lanes per node or one wave with an LDS table; 2: degree
+ * 129-1024; 3: degree 1025-4096, one workgroup with an LDS table; 4: the
+ * multi-workgroup hub path), `count` entries each (any pointer may be NULL):
+ * device ms, algorithmic bytes (4 B neighbour id + 4 B neighbour label [+ 4 B
+ * edge weight] per visit, 32 B per rated node), edge visits and nodes, summed
+ * over rounds, and launches = rounds in which the group's kernels ran (a
+ * group is left out when no node of the round falls in its degree range).
+ * *rounds = rating rounds profiled. */
 int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
-                          int64_t* launches);
+                          int64_t* launches, int64_t* rounds);
 
 #ifdef __cplusplus
 }

@@ -205,11 +205,11 @@ class Context:
         K = 5
         kms, kb = (ctypes.c_double * K)(), (ctypes.c_double * K)()
         kv, kn = (ctypes.c_int64 * K)(), (ctypes.c_int64 * K)()
-        kl = ctypes.c_int64()
-        _check(self.lib.sclap_profile_kernels(self.h, K, kms, kb, kv, kn, ctypes.byref(kl)))
-        out["kernels"] = [{"bin": i, "ms": kms[i], "bytes": kb[i], "visits": kv[i], "nodes": kn[i]}
-                          for i in range(K)]
-        out["kernel_launches"] = kl.value
+        kl, kr = (ctypes.c_int64 * K)(), ctypes.c_int64()
+        _check(self.lib.sclap_profile_kernels(self.h, K, kms, kb, kv, kn, kl, ctypes.byref(kr)))
+        out["kernels"] = [{"bin": i, "ms": kms[i], "bytes": kb[i], "visits": kv[i], "nodes": kn[i],
+                           "launches": kl[i]} for i in range(K)]
+        out["kernel_launches"] = kr.value
         return out
 
 

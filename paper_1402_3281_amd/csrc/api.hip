@@ -497,12 +497,13 @@ int sclap_profile_enable(sclap_ctx* ctx, int32_t on) {
     ctx->c.prof_k_bytes[b] = 0;
     ctx->c.prof_k_visits[b] = 0;
     ctx->c.prof_k_nodes[b] = 0;
+    ctx->c.prof_k_group_launches[b] = 0;
   }
   return SCLAP_OK;
 }
 
 int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
-                          int64_t* launches) {
+                          int64_t* launches, int64_t* rounds) {
   if (!ctx || count < 0) return fail(SCLAP_EINVAL, "bad argument");
   const Ctx& c = ctx->c;
   for (int b = 0; b < count && b < kBins; ++b) {
@@ -510,8 +511,9 @@ int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* byt
     if (bytes) bytes[b] = c.prof_k_bytes[b];
     if (visits) visits[b] = c.prof_k_visits[b];
     if (nodes) nodes[b] = c.prof_k_nodes[b];
+    if (launches) launches[b] = c.prof_k_group_launches[b];
   }
-  if (launches) *launches = c.prof_k_launches;
+  if (rounds) *rounds = c.prof_k_launches;
   return SCLAP_OK;
 }
 

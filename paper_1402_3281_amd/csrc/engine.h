@@ -119,7 +119,8 @@ struct Ctx {
   double prof_k_bytes[kBins] = {}; // algorithmic bytes moved by that kernel
   int64_t prof_k_visits[kBins] = {};
   int64_t prof_k_nodes[kBins] = {};
-  int64_t prof_k_launches = 0;
+  int64_t prof_k_launches = 0;     // rounds profiled
+  int64_t prof_k_group_launches[kBins] = {};  // rounds in which the group's kernels ran
 };
 
 int ctx_ensure_pin(Ctx* c, size_t bytes);

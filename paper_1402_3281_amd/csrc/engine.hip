@@ -493,10 +493,11 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   bool unit_weights = true;
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
   // rounds whose every slot rates from block connections leave the bins empty
+  unsigned groups = 0;  // rating launch groups that ran
   if (any_binned) {
     SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights,
                           tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, st,
-                          c->profile ? c->ev : nullptr));
+                          c->profile ? c->ev : nullptr, &groups));
   } else if (c->profile) {
     for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));
   }
@@ -576,6 +577,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
       float ms = 0;
       SCLAP_HIP(hipEventElapsedTime(&ms, c->ev[g], c->ev[g + 1]));
       c->prof_k_ms[g] += ms;
+      if ((groups >> g) & 1u) c->prof_k_group_launches[g] += 1;
     }
     for (int b = 0; b < kBins; ++b) {
       const int g = group_of[b];

@@ -43,10 +43,11 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 // 8 (hub kernels, only if `hubs`).  evs (may be NULL): 5 events around them.
 constexpr int kRateGroups = 5;
 // max_deg: no binned node has a larger degree (the launches of bins above
-// it are left out).
+// it are left out).  *groups (may be NULL): bit g set when launch group g
+// (the intervals between evs[g] and evs[g + 1]) ran a kernel.
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, hipStream_t st, hipEvent_t* evs);
+                int64_t max_deg, hipStream_t st, hipEvent_t* evs, unsigned* groups);
 // Small contended sets resolved on the device (admission, then the admitted
 // weight added to each target's W); sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,

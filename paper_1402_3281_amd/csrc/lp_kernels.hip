@@ -2453,8 +2453,10 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, hipStream_t st, hipEvent_t* evs) {
+                int64_t max_deg, hipStream_t st, hipEvent_t* evs, unsigned* groups) {
   const unsigned G = grid_for(n_hint, 64, 2048);
+  if (groups) *groups = 1u | (max_deg > 32 ? 2u : 0u) | (max_deg > 128 ? 4u : 0u) | (max_deg > 1024 ? 8u : 0u) |
+                        (hubs ? 16u : 0u);
   auto rec = [&](int i) {
     if (evs) (void)hipEventRecord(evs[i], st);
   };
