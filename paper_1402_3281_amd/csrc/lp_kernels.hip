@@ -1960,18 +1960,76 @@ __device__ __forceinline__ void mover_blocks(const DevSlot& sl, int32_t oa, int6
   }
 }
 
+// Entries x .. of the short rows listed in a wave's LDS arrays (ex: exclusive
+// prefix of the row lengths, e0: first entry, ab: blocks a | b << 32 or a < 0,
+// sl: slot): lane l takes entry x0 + l of the concatenated rows and loads its
+// neighbour and weight.
+struct ShortRows {
+  int32_t* ex;
+  int64_t* e0;
+  int64_t* ab;
+  int32_t* sl;
+};
+
+struct ShortEntry {
+  int32_t nb, w, a, b, s;
+};
+
+template <bool ONE>
+__device__ __forceinline__ ShortEntry short_entry(const DevSlot* __restrict__ S, const ShortRows& R, int32_t x,
+                                                  int32_t tot) {
+  ShortEntry r{-1, 0, -1, -1, 0};
+  if (x >= tot) return r;
+  int lo = 0, hi = kWave - 1;  // the last row starting at or before x
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (R.ex[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  r.s = ONE ? 0 : R.sl[lo];
+  const DevSlot& q = S[r.s];
+  const int64_t e = R.e0[lo] + (x - R.ex[lo]);
+  const int64_t ab = R.ab[lo];
+  r.nb = gld(q.col, e);
+  r.a = (int32_t)ab;
+  r.b = (int32_t)(ab >> 32);
+  r.w = r.a >= 0 && q.ew ? gld(q.ew, e) : 1;
+  return r;
+}
+
+template <bool ONE>
+__device__ __forceinline__ void short_apply(const DevSlot* __restrict__ S, const ShortEntry& r) {
+  if (r.nb < 0) return;
+  const DevSlot& q = S[r.s];
+  gst(q.flag_next, r.nb, (uint8_t)1);
+  if (r.a >= 0) {
+    const int64_t row = (int64_t)r.nb * q.conn_k;
+    conn_add(q.conn, row + r.a, -r.w);
+    conn_add(q.conn, row + r.b, r.w);
+  }
+}
+
 // Movers: rated positions i of refinement slots with mold[i] >= 0 (the old
-// block).
+// block).  Rows of up to 64 entries are walked by the whole wave over their
+// concatenated entries (a batch costs its total entries / 64 steps rather
+// than its longest row), the next step's loads issued before the current
+// step's stores.
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int ns,
                                               const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
                                               const int32_t* __restrict__ mold,
                                               int32_t* __restrict__ big, uint32_t* __restrict__ big_cnt,
                                               const uint32_t* __restrict__ skip) {
+  __shared__ int32_t s_ex[4][kWave];
+  __shared__ int64_t s_e0[4][kWave];
+  __shared__ int64_t s_ab[4][kWave];
+  __shared__ int32_t s_sl[4][kWave];
   if (skip && *skip) return;
   if (blockIdx.x == 0)
     for (int s = threadIdx.x; s < ns; s += blockDim.x)
       if (S[s].conn && !S[s].last_round && !conn_push(S[s])) gst(S[s].ctr, CTR_STALE, (int64_t)1);
+  const int wv = threadIdx.x / kWave;
+  const ShortRows R{s_ex[wv], s_e0[wv], s_ab[wv], s_sl[wv]};
   const uint32_t cnt = *rcnt;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   const uint32_t wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
@@ -1979,10 +2037,11 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
     const uint32_t i = base + lane_id();
     const DevSlot* sl = nullptr;
     int64_t e0 = 0, d = 0;
-    int32_t u = 0, a = -1, b = -1;
+    int32_t u = 0, a = -1, b = -1, si = 0;
     if (i < cnt) {
       u = gld(rated, i);
-      sl = &S[SLOT(u)];
+      si = SLOT(u);
+      sl = &S[si];
       // the last round of a stage has no next rated set to mark
       const int32_t oa = sl->mode == MODE_REFINE && !sl->last_round ? gld(mold, i) : -1;
       if (oa >= 0) {
@@ -1992,7 +2051,29 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
         mover_blocks(*sl, oa, v, a, b);
       }
     }
-    if (d <= kWave && d > 0) mark_row<4>(*sl, e0, 0, d, 1, a, b);
+    {
+      const int32_t ds = d > 0 && d <= kWave ? (int32_t)d : 0;
+      int32_t incl = ds;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t o = __shfl_up(incl, off);
+        if ((int)lane_id() >= off) incl += o;
+      }
+      const int32_t tot = __shfl(incl, kWave - 1);
+      if (tot > 0) {
+        R.ex[lane_id()] = incl - ds;
+        R.e0[lane_id()] = e0;
+        R.ab[lane_id()] = (int64_t)((uint64_t)(uint32_t)a | ((uint64_t)(uint32_t)b << 32));
+        R.sl[lane_id()] = si;
+        wave_sync();
+        ShortEntry cur = short_entry<ONE>(S, R, (int32_t)lane_id(), tot);
+        for (int32_t x0 = 0; x0 < tot; x0 += kWave) {
+          const ShortEntry nxt = short_entry<ONE>(S, R, x0 + kWave + (int32_t)lane_id(), tot);
+          short_apply<ONE>(S, cur);
+          cur = nxt;
+        }
+        wave_sync();  // the rows are read before the next batch writes them
+      }
+    }
     // without a big list (no row above kMarkBig) the wave walks every row
     if (big && d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
     uint64_t mid = __ballot(d > kWave && (d <= kMarkBig || !big));
