@@ -433,7 +433,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_TRY(c->ckeys.ensure(Nz * 8, st));
   SCLAP_TRY(c->slots_dev.ensure((size_t)ns * sizeof(DevSlot), st));
   DevSlot* S = (DevSlot*)c->slots_dev.p;
-  SCLAP_HIP(hipMemcpyAsync(S, c->pin_slots, (size_t)ns * sizeof(DevSlot), hipMemcpyHostToDevice, st));
   // Per-round counters (zeroed together with the slot counters after them):
   // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and label
   // parts, [13] refinement movers, [15] big movers, [16] contended set too
@@ -445,7 +444,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_TRY(c->binmeta.ensure(256, st));
   uint32_t* meta = (uint32_t*)c->binmeta.p;
   unsigned long long* bin_vis = (unsigned long long*)((char*)meta + 128);
-  SCLAP_TRY(fill_u32(small, 64 + (int64_t)ns * CTR_N * 2, 0, st));
+  SCLAP_TRY(round_begin(c->pin_slots, ns, S, small, 64 + (int64_t)ns * CTR_N * 2, st));
   int32_t* bins = (int32_t*)c->bins.p;
   const int64_t bin_cap = (int64_t)Nz;
   std::vector<std::pair<const void*, int>> sig;

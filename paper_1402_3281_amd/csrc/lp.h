@@ -34,6 +34,10 @@ struct HubLayout {
 // every slot's CTR_VISITS.  T = total tiles (bin_tiles per slot, summed; the
 // tiles of slot s start at S[s].tbase); scratch holds bin_scratch_bytes(T).
 // binfo receives first entry | degree << 40 of every binned node except hubs.
+// Stores the round's slot descriptors (host_slots, ns entries; pinned or
+// pageable host memory, free for reuse on return) in S and zeroes zero[0,
+// nzero) on stream st, in one launch when ns is small.
+int round_begin(const DevSlot* host_slots, int ns, DevSlot* S, uint32_t* zero, int64_t nzero, hipStream_t st);
 int64_t bin_tiles(int64_t n);
 size_t bin_scratch_bytes(int64_t T);
 int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* binfo, int64_t bin_cap,

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 
 #include "common.h"
@@ -2492,6 +2493,39 @@ static inline unsigned grid_for(int64_t items, int per_block, unsigned cap) {
   } while (0)
 
 int64_t bin_tiles(int64_t n) { return (n + kBinTile - 1) / kBinTile; }
+
+// Start of a round with at most kArgSlots slots: the slot descriptors travel
+// as kernel arguments and one launch stores them and zeroes the round's
+// counters (instead of a host-to-device copy and a fill).
+constexpr int kArgSlots = 8;
+struct SlotArgs {
+  DevSlot s[kArgSlots];
+};
+
+__global__ void __launch_bounds__(256) k_round_begin(const SlotArgs a, int ns, DevSlot* __restrict__ S,
+                                                     uint32_t* __restrict__ zero, int nzero) {
+  static_assert(sizeof(DevSlot) % 8 == 0, "slot descriptor size");
+  constexpr int W = (int)(sizeof(DevSlot) / 8);
+  uint64_t* dst = reinterpret_cast<uint64_t*>(S);
+  for (int i = threadIdx.x; i < ns * W; i += blockDim.x) {
+    uint64_t x;
+    __builtin_memcpy(&x, reinterpret_cast<const char*>(&a.s[i / W]) + (i % W) * 8, 8);
+    dst[i] = x;
+  }
+  for (int i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0;
+}
+
+int round_begin(const DevSlot* host_slots, int ns, DevSlot* S, uint32_t* zero, int64_t nzero, hipStream_t st) {
+  if (ns <= kArgSlots && nzero <= (int64_t)1 << 20) {
+    SlotArgs a;
+    std::memcpy(a.s, host_slots, (size_t)ns * sizeof(DevSlot));
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(256), 0, st, a, ns, S, zero, (int)nzero);
+    SCLAP_HIP(hipGetLastError());
+    return SCLAP_OK;
+  }
+  SCLAP_HIP(hipMemcpyAsync(S, host_slots, (size_t)ns * sizeof(DevSlot), hipMemcpyHostToDevice, st));
+  return fill_u32(zero, nzero, 0, st);
+}
 
 size_t bin_scratch_bytes(int64_t T) {
   const size_t rows = (size_t)kBinRows * (size_t)T + 1;
