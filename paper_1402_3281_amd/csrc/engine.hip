@@ -694,20 +694,52 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   }
   SCLAP_HIP(hipMemcpyAsync(c->pin, ucount, 4, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
-  const int64_t mc = (int64_t)((uint32_t*)c->pin)[0];
+  // k1[0, mh): the coarse edges x < y with their weights; the mirror (y, x)
+  // is sorted on its own and the two halves are placed row by row
+  const int64_t mh = (int64_t)((uint32_t*)c->pin)[0];
+  const int64_t mc = 2 * mh;
   C.m = mc;
+  dfree(k2, st);
+  k2 = nullptr;
+  dfree(v2, st);
+  v2 = nullptr;
+  const bool mpacked = 2 * bits <= 32;
+  const size_t hz = (size_t)std::max<int64_t>(mh, 1);
+  uint64_t *mk = nullptr, *mks = nullptr;
+  int32_t *mw = nullptr, *mws = nullptr;
+  SCLAP_TRY(dalloc_t(&mk, hz, st));
+  SCLAP_TRY(dalloc_t(&mks, hz, st));
+  if (!mpacked) {
+    SCLAP_TRY(dalloc_t(&mw, hz, st));
+    SCLAP_TRY(dalloc_t(&mws, hz, st));
+  }
+  unsigned* ovf = (unsigned*)ucount + 1;
+  SCLAP_TRY(contract_mirror(k1, aggs, mh, bits, mpacked ? 1 : 0, mk, mw, ovf, st));
+  if (mh > 0) {
+    const size_t tb2 = mpacked ? prim_sort_keys_bytes(hz) : prim_sort_pairs_bytes(hz);
+    SCLAP_TRY(c->prim.ensure(tb2, st));
+    if (mpacked) SCLAP_TRY(prim_sort_keys(c->prim.p, tb2, mk, mks, (size_t)mh, 32 + 2 * bits, st, 32));
+    else SCLAP_TRY(prim_sort_pairs(c->prim.p, tb2, mk, mks, mw, mws, (size_t)mh, 2 * bits, st));
+  }
+  dfree(mk, st);
+  dfree(mw, st);
+  int64_t *ru = nullptr, *rl = nullptr;
+  SCLAP_TRY(dalloc_t(&ru, (size_t)nc + 1, st));
+  SCLAP_TRY(dalloc_t(&rl, (size_t)nc + 1, st));
   SCLAP_TRY(dalloc_t(&C.own_rp, (size_t)nc + 1, st));
   SCLAP_TRY(dalloc_t(&C.own_col, (size_t)std::max<int64_t>(mc, 1), st));
   SCLAP_TRY(dalloc_t(&C.own_ew, (size_t)std::max<int64_t>(mc, 1), st));
-  unsigned* ovf = (unsigned*)ucount + 1;
-  SCLAP_TRY(contract_finish(k1, aggs, mc, bits, nc, C.own_rp, C.own_col, C.own_ew, ovf, st));
+  SCLAP_TRY(contract_finish2(k1, aggs, mh, mks, mws, mh, bits, mpacked ? 1 : 0, nc, ru, rl, C.own_rp, C.own_col,
+                             C.own_ew, st));
   SCLAP_HIP(hipMemcpyAsync(c->pin, ovf, 4, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   const unsigned overflow = ((uint32_t*)c->pin)[0];
+  dfree(ru, st);
+  dfree(rl, st);
+  dfree(mks, st);
+  dfree(mws, st);
   dfree(k1, st);
-  dfree(k2, st);
   dfree(v1, st);
-  dfree(v2, st);
   dfree(aggs, st);
   C.rp = C.own_rp;
   C.col = C.own_col;

@@ -34,16 +34,27 @@ int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw,
                        const int64_t* W, hipStream_t st);
 // Entry tiles of the edge-centric contraction kernels (m entries).
 int cross_tiles(int64_t m);
-// mode 0: entries joining different coarse nodes per tile -> tcnt[tile],
-// and every entry's key x * 2^bits + y (~0: same coarse node) -> kcache (m);
+// mode 0: entries joining coarse nodes x < y per tile -> tcnt[tile], and
+// every entry's key x * 2^bits + y (~0: x >= y, i.e. the same coarse node or
+// the mirror of another entry of the symmetric graph) -> kcache (m);
 // mode 1: the keys and weights (vals may be NULL: not written) of those
 // entries from toff[tile] on (exclusive scan of tcnt), read from kcache;
 // packed (2 bits <= 32): keys hold key << 32 | weight.
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
                    uint64_t* kcache, hipStream_t st, int packed = 0);
-int contract_finish(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int64_t nc, int64_t* rp,
-                    int32_t* col, int32_t* ew, unsigned* overflow, hipStream_t st);
+// The reduced upper entries (ukeys x * 2^bits + y with x < y, ascending; aggs
+// their weights, m of them) mirrored to keys y * 2^bits + x with int32
+// weights in mw (packed: key << 32 | weight in mkeys, mw unused); *overflow
+// set if a weight exceeds int32.
+int contract_mirror(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int packed, uint64_t* mkeys,
+                    int32_t* mw, unsigned* overflow, hipStream_t st);
+// Coarse CSR from the upper entries (mu) and the sorted mirror (ml, lkeys/lw
+// as from contract_mirror, sorted): rows ascending, lower neighbours first.
+// ru, rl: nc + 1 scratch entries each; rp: nc + 1.
+int contract_finish2(const uint64_t* ukeys, const int64_t* aggs, int64_t mu, const uint64_t* lkeys, const int32_t* lw,
+                     int64_t ml, int bits, int packed, int64_t nc, int64_t* ru, int64_t* rl, int64_t* rp,
+                     int32_t* col, int32_t* ew, hipStream_t st);
 int project(const int32_t* cof, const int32_t* pc, int64_t n, int32_t* pf, hipStream_t st);
 
 // One graph of a fused initial-partition launch.

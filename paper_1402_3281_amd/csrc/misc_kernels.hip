@@ -364,7 +364,9 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
         if (e >= r.e1) continue;
         const int32_t x = cof[edge_row(rp, r, s_rp, e)];
         const int32_t y = cof[col[e]];
-        if (x != y) kk[j] = ((uint64_t)(uint32_t)x << bits) | (uint64_t)(uint32_t)y;
+        // the graph is symmetric: the entries with x < y carry every coarse
+        // edge once, the mirror is added after their reduction
+        if (x < y) kk[j] = ((uint64_t)(uint32_t)x << bits) | (uint64_t)(uint32_t)y;
         kcache[e] = kk[j];
       }
     } else {
@@ -409,34 +411,107 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
   }
 }
 
-// Coarse neighbour ids and weights from the reduced keys.
-__global__ void __launch_bounds__(256) k_coarse_cols(const uint64_t* __restrict__ ukeys, const int64_t* __restrict__ aggs,
-                                                     int64_t m, int bits, int32_t* __restrict__ col,
-                                                     int32_t* __restrict__ ew, unsigned* __restrict__ overflow) {
+// Mirror of the reduced upper entries: (x, y, w) -> key y * 2^bits + x with
+// weight w (packed: key << 32 | w), for the lower half of the coarse CSR.
+__global__ void __launch_bounds__(256) k_coarse_mirror(const uint64_t* __restrict__ ukeys,
+                                                       const int64_t* __restrict__ aggs, int64_t m, int bits,
+                                                       int packed, uint64_t* __restrict__ mkeys,
+                                                       int32_t* __restrict__ mw, unsigned* __restrict__ overflow) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const uint64_t mask = (1ull << bits) - 1ull;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-    col[i] = (int32_t)(ukeys[i] & mask);
+    const uint64_t k = ukeys[i];
+    const uint64_t mk = ((k & mask) << bits) | (k >> bits);
     const int64_t a = aggs[i];
     if (a > INT32_MAX) *overflow = 1;
-    ew[i] = (int32_t)a;
+    if (packed) {
+      mkeys[i] = (mk << 32) | (uint32_t)(int32_t)a;
+    } else {
+      mkeys[i] = mk;
+      mw[i] = (int32_t)a;
+    }
   }
 }
 
-// row_ptr(x) = first entry with row >= x.
-__global__ void __launch_bounds__(256) k_coarse_rowptr(const uint64_t* __restrict__ ukeys, int64_t m, int bits,
-                                                       int64_t nc, int64_t* __restrict__ rp) {
+// Row starts of the two sorted halves (upper: keys; lower: mirrored keys,
+// compared above bit mshift) and of the coarse CSR: rp = ru + rl.
+__global__ void __launch_bounds__(256) k_coarse_rowptr2(const uint64_t* __restrict__ ukeys, int64_t mu,
+                                                        const uint64_t* __restrict__ lkeys, int64_t ml, int bits,
+                                                        int lshift, int64_t nc, int64_t* __restrict__ ru,
+                                                        int64_t* __restrict__ rl, int64_t* __restrict__ rp) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= nc; x += stride) {
     const uint64_t key = (uint64_t)x << bits;
-    int64_t lo = 0, hi = m;
+    int64_t lo = 0, hi = mu;
     while (lo < hi) {
       const int64_t mid = (lo + hi) >> 1;
       if (ukeys[mid] < key) lo = mid + 1;
       else hi = mid;
     }
-    rp[x] = lo;
+    const int64_t a = lo;
+    const uint64_t lkey = key << lshift;
+    lo = 0;
+    hi = ml;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (lkeys[mid] < lkey) lo = mid + 1;
+      else hi = mid;
+    }
+    ru[x] = a;
+    rl[x] = lo;
+    rp[x] = a + lo;
   }
+}
+
+// Row x of the coarse CSR: its lower entries (neighbours < x, from the sorted
+// mirror) then its upper entries (neighbours > x), each ascending.  Upper
+// entry i of row x lands at rp(x) + (rl(x+1) - rl(x)) + (i - ru(x)) =
+// i + rl(x+1); lower entry j of row y at rp(y) + (j - rl(y)) = j + ru(y).
+__global__ void __launch_bounds__(256) k_coarse_place(const uint64_t* __restrict__ ukeys,
+                                                      const int64_t* __restrict__ aggs, int64_t mu,
+                                                      const uint64_t* __restrict__ lkeys,
+                                                      const int32_t* __restrict__ lw, int64_t ml, int bits,
+                                                      int packed, const int64_t* __restrict__ ru,
+                                                      const int64_t* __restrict__ rl, int32_t* __restrict__ col,
+                                                      int32_t* __restrict__ ew) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t mask = (1ull << bits) - 1ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mu + ml; i += stride) {
+    if (i < mu) {
+      const uint64_t k = ukeys[i];
+      const int64_t pos = i + rl[(k >> bits) + 1];
+      col[pos] = (int32_t)(k & mask);
+      ew[pos] = (int32_t)aggs[i];
+    } else {
+      const int64_t j = i - mu;
+      const uint64_t item = lkeys[j];
+      const uint64_t k = packed ? item >> 32 : item;
+      const int64_t pos = j + ru[k >> bits];
+      col[pos] = (int32_t)(k & mask);
+      ew[pos] = packed ? (int32_t)(uint32_t)item : lw[j];
+    }
+  }
+}
+
+int contract_mirror(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int packed, uint64_t* mkeys,
+                    int32_t* mw, unsigned* overflow, hipStream_t st) {
+  if (m <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_coarse_mirror, dim3(grid1(m)), dim3(256), 0, st, ukeys, aggs, m, bits, packed, mkeys, mw,
+                     overflow);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int contract_finish2(const uint64_t* ukeys, const int64_t* aggs, int64_t mu, const uint64_t* lkeys, const int32_t* lw,
+                     int64_t ml, int bits, int packed, int64_t nc, int64_t* ru, int64_t* rl, int64_t* rp,
+                     int32_t* col, int32_t* ew, hipStream_t st) {
+  hipLaunchKernelGGL(k_coarse_rowptr2, dim3(grid1(nc + 1)), dim3(256), 0, st, ukeys, mu, lkeys, ml, bits,
+                     packed ? 32 : 0, nc, ru, rl, rp);
+  if (mu + ml > 0)
+    hipLaunchKernelGGL(k_coarse_place, dim3(grid1(mu + ml)), dim3(256), 0, st, ukeys, aggs, mu, lkeys, lw, ml, bits,
+                       packed, ru, rl, col, ew);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
 }
 
 int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st) {
@@ -491,15 +566,6 @@ int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, con
   if (n <= 0 || m <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
                      keys, vals, kcache, packed);
-  SCLAP_HIP(hipGetLastError());
-  return SCLAP_OK;
-}
-
-int contract_finish(const uint64_t* ukeys, const int64_t* aggs, int64_t m, int bits, int64_t nc, int64_t* rp,
-                    int32_t* col, int32_t* ew, unsigned* overflow, hipStream_t st) {
-  if (m > 0)
-    hipLaunchKernelGGL(k_coarse_cols, dim3(grid1(m)), dim3(256), 0, st, ukeys, aggs, m, bits, col, ew, overflow);
-  hipLaunchKernelGGL(k_coarse_rowptr, dim3(grid1(nc + 1)), dim3(256), 0, st, ukeys, m, bits, nc, rp);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
