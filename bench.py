@@ -79,6 +79,7 @@ def copy_calibration(mbytes: int) -> int:
 def roofline(prof: dict, workload: str) -> tuple[dict, list]:
     """Roofline of the dominant rating kernel: algorithmic bytes per launch
     (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge visit,
+    no label bytes in a level's first clustering round, whose labels are the ids;
     32 B per rated node) / mean launch duration from HIP events.  A launch is
     a round in which the group's kernels ran (groups with no node in their
     degree range are left out of a round)."""

@@ -281,7 +281,8 @@ int sclap_profile_read(sclap_ctx* ctx, double* rate_ms, int64_t* rate_launches, 
  * 33-128, 64 lanes per node or one wave with an LDS table; 2: degree
  * 129-1024; 3: degree 1025-4096, one workgroup with an LDS table; 4: the
  * multi-workgroup hub path), `count` entries each (any pointer may be NULL):
- * device ms, algorithmic bytes (4 B neighbour id + 4 B neighbour label [+ 4 B
+ * device ms, algorithmic bytes (4 B neighbour id + 4 B neighbour label, not
+ * read in the first clustering round of a level, where labels are node ids [+ 4 B
  * edge weight] per visit, 32 B per rated node), edge visits and nodes, summed
  * over rounds, and launches = rounds in which the group's kernels ran (a
  * group is left out when no node of the round falls in its degree range).

@@ -69,7 +69,7 @@ struct DevSlot {
   int32_t conn_mode;      // CONN_NONE / CONN_BUILD / CONN_RATE
   int32_t* conn;          // refine: n x conn_k block connections conn(v, b), or nullptr
   int32_t last_round;     // no LP round of this stage follows (its moves need no bookkeeping)
-  int32_t pad;
+  int32_t ident;          // first clustering round of a level: lab(v) = v, so a neighbour's label is its id
 };
 
 // Refinement with block connections kept per node: the first round of a

@@ -365,6 +365,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.cap = refine ? j->lmax : j->U;
     d.round = j->round;
     d.mode = refine ? MODE_REFINE : MODE_CLUSTER;
+    d.ident = !refine && j->round == 1 ? 1 : 0;  // clustering starts from lab(v) = v
     d.dir_rule = j->dir_rule;
     d.use_flags = refine && j->round > 1;
     d.conn = refine ? j->conn : nullptr;
@@ -569,8 +570,11 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_HIP(hipMemcpyAsync(hm, meta, 256, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
     const unsigned long long* hv = (const unsigned long long*)((const char*)hm + 128);
-    bool weighted = false;
-    for (int s = 0; s < ns; ++s) weighted = weighted || c->pin_slots[s].ew != nullptr;
+    bool weighted = false, gather = false;  // gather: some slot reads its neighbours' labels
+    for (int s = 0; s < ns; ++s) {
+      weighted = weighted || c->pin_slots[s].ew != nullptr;
+      gather = gather || !c->pin_slots[s].ident;
+    }
     const int group_of[kBins] = {0, 0, 0, 1, 1, 2, 2, 3, 4};
     for (int g = 0; g < kRateGroups; ++g) {
       float ms = 0;
@@ -582,7 +586,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
       const int g = group_of[b];
       c->prof_k_visits[g] += (int64_t)hv[b];
       c->prof_k_nodes[g] += hm[b];
-      c->prof_k_bytes[g] += (double)hv[b] * (weighted ? 12.0 : 8.0) + (double)hm[b] * 32.0;
+      c->prof_k_bytes[g] += (double)hv[b] * (4.0 + (weighted ? 4.0 : 0.0) + (gather ? 4.0 : 0.0)) + (double)hm[b] * 32.0;
       c->prof_rate_nodes += hm[b];
     }
     float a = 0, b2 = 0;

@@ -382,7 +382,7 @@ __device__ __forceinline__ void rate_group_body(const DevSlot* __restrict__ S, i
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const DevSlot& sl = S[SLOT(u[r])];
-      const int32_t tl = gld(sl.lab, nb[r]);
+      const int32_t tl = sl.ident ? nb[r] : gld(sl.lab, nb[r]);
       t[r] = gl < d[r] ? tl : -1;
       w[r] = gl < d[r] ? w[r] : 0;
     }
@@ -535,7 +535,9 @@ __device__ __forceinline__ void rate_thread_body(const DevSlot* __restrict__ S, 
         w[q] = wb ? gld(wb, q) : 1;
       }
     }
-    if (ONE && sl.n < ((int64_t)1 << 30)) {
+    if (sl.ident) {
+      // labels are node ids: the neighbour ids are the labels
+    } else if (ONE && sl.n < ((int64_t)1 << 30)) {
       // one slot: the label gathers go through a buffer resource (scalar
       // base, 32-bit offsets, range-checked by the hardware)
       const __amdgpu_buffer_rsrc_t rs =
@@ -651,7 +653,8 @@ __device__ __forceinline__ void pre_row(NodePre<B>& p, const DevSlot* __restrict
 // first, first + step, ..., B at a time, the first B already loaded (nb, wt).
 // The next B entries are loaded before the current ones are inserted.  Labels
 // outside [lo, hi] (the direction rule) are not inserted; the own label's
-// connection and whether a foreign label was seen are accumulated.
+// connection and whether a foreign label was seen are accumulated.  lab may
+// be null: the labels are the node ids.
 template <int B>
 __device__ __forceinline__ void table_fill(const int32_t* __restrict__ col, const int32_t* __restrict__ ew,
                                            const int32_t* __restrict__ lab, int64_t row0, int first, int d, int step,
@@ -662,7 +665,7 @@ __device__ __forceinline__ void table_fill(const int32_t* __restrict__ col, cons
     int32_t tt[B], cw[B];
 #pragma unroll
     for (int q = 0; q < B; ++q) {
-      tt[q] = gld(lab, nb[q]);
+      tt[q] = lab ? gld(lab, nb[q]) : nb[q];
       cw[q] = wt[q];
     }
     const int nbase = base + step * B;
@@ -775,7 +778,8 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
     wave_sync();
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<B>(sl.col, sl.ew, sl.lab, e0, lane, d, kWave, own, lo, hi, keys, vals, tsz - 1, p.nb, p.wt, my_own,
+    table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, lane, d, kWave, own, lo, hi, keys, vals, tsz - 1,
+                  p.nb, p.wt, my_own,
                   foreign);
     for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
     const bool boundary = __ballot(foreign) != 0;
@@ -867,7 +871,8 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     __syncthreads();
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<B>(sl.col, sl.ew, sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask, p.nb, p.wt, my_own,
+    table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask,
+                  p.nb, p.wt, my_own,
                   foreign);
     const int64_t conn_own = block_reduce(my_own, redi, OpAdd64());
     const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
@@ -1102,7 +1107,7 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
         wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tt[q] = gld(sl.lab, nb[q]);
+      for (int q = 0; q < 8; ++q) tt[q] = sl.ident ? nb[q] : gld(sl.lab, nb[q]);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int32_t tq = tt[q];
