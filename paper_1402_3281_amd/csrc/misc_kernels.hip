@@ -634,6 +634,26 @@ __device__ int64_t block_exscan(int64_t x, int64_t* excl, int64_t* sh) {
   return total;
 }
 
+// The same without the leading barrier: the caller guarantees that no thread
+// still reads sh from an earlier scan (a barrier since its last use).
+__device__ int64_t block_exscan_nb(int64_t x, int64_t* excl, int64_t* sh) {
+  int64_t incl = x;
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int64_t o = __shfl_up(incl, off);
+    if ((int)lane() >= off) incl += o;
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane() == kWave - 1) sh[w] = incl;
+  __syncthreads();
+  int64_t before = 0, total = 0;
+  for (int i = 0; i < kIpWaves; ++i) {
+    if (i < w) before += sh[i];
+    total += sh[i];
+  }
+  *excl = before + incl - x;
+  return total;
+}
+
 __device__ int64_t block_min64(int64_t x, int64_t* sh) {
   for (int off = 32; off > 0; off >>= 1) {
     const int64_t o = __shfl_xor(x, off);
@@ -684,6 +704,7 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
                                                       int64_t big_entries, int bm_words) {
   const IpSlot sl = slots[blockIdx.x];
   __shared__ int64_t sh[kIpWaves];
+  __shared__ int64_t sh2[kIpWaves];  // the claim-count scan of the LDS fast path
   __shared__ int64_t s_head, s_tail, s_next;
   __shared__ int s_frv;  // the frontier's rows are in LDS: start in s_e0, degree in s_pre
   __shared__ int64_t s_pre[kIpThreads];
@@ -710,10 +731,11 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
   }
   __syncthreads();
   for (;;) {
+    // thread 0 updates these at the end of an iteration, after a barrier
+    // that follows every thread's read here
     __syncthreads();
     const int64_t head = s_head, tail = s_tail, next = s_next;
     const bool frv = s_frv != 0;
-    __syncthreads();
     if (head == tail) {
       if (next >= n) break;
       // seeds: unvisited degree-0 nodes before the first unvisited node with
@@ -766,7 +788,8 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
         }
       }
       int64_t ex;
-      const int64_t Tc = block_exscan(d, &ex, sh);
+      // sh was last read before the barrier above
+      const int64_t Tc = block_exscan_nb(d, &ex, sh);
       if (allow_yield && Tc > big_entries) {
         if (threadIdx.x == 0) {
           sl.state[0] = head;
@@ -845,7 +868,9 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
           mine += ch[q] ? 1 : 0;
         }
         int64_t p;
-        const int64_t T = block_exscan(mine, &p, sh);  // every LDS row read above precedes the writes below
+        // sh2 was last read in the previous level; the LDS rows read above
+        // were read before the claim barrier
+        const int64_t T = block_exscan_nb(mine, &p, sh2);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           if (!ch[q]) continue;
