@@ -337,6 +337,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
   bool any_build = false, any_cached = false, any_tile = false, any_other = false, any_binned = false;
+  bool any_plain = false;  // a slot rated from the bins (no block connections)
   int tile_kmax = 0;
   for (int s = 0; s < ns; ++s) {
     Job* j = jobs[s];
@@ -375,6 +376,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     any_build = any_build || d.conn_mode == CONN_BUILD;
     any_cached = any_cached || d.conn_mode == CONN_RATE;
     any_binned = any_binned || d.conn_mode != CONN_RATE;
+    any_plain = any_plain || d.conn_mode == CONN_NONE;
     // refinement slots with few blocks are admitted by tiles
     if (refine && j->nlabels <= kConnMaxK) {
       any_tile = true;
@@ -494,15 +496,20 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
   // rounds whose every slot rates from block connections leave the bins empty
   unsigned groups = 0;  // rating launch groups that ran
-  if (any_binned) {
+  if (any_plain) {
+    // (binned nodes of CONN_BUILD slots are rated here too, and again, with
+    // the same result, from their new rows below)
     SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights,
                           tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, st,
                           c->profile ? c->ev : nullptr, &groups));
-  } else if (c->profile) {
-    for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));
+  } else {
+    // every binned slot builds its block connections and is rated from them
+    if (any_binned && hubs) SCLAP_TRY(launch_hub_prep(S, ns, bins, bin_cap, meta, hub, st));
+    if (c->profile)
+      for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));
   }
   if (any_build) SCLAP_TRY(launch_conn_build(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, st));
-  if (any_cached) SCLAP_TRY(launch_rate_cached(S, ns, N, rated, meta + 14, st));
+  if (any_cached || any_build) SCLAP_TRY(launch_rate_cached(S, ns, N, rated, meta + 14, st));
   const int node_bits = bits_for(N);
   const int lab_bits = bits_for(Lt);
   if (any_other) {
@@ -584,6 +591,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     }
     for (int b = 0; b < kBins; ++b) {
       const int g = group_of[b];
+      if (!((groups >> g) & 1u)) continue;  // binned for the block connections only
       c->prof_k_visits[g] += (int64_t)hv[b];
       c->prof_k_nodes[g] += hm[b];
       c->prof_k_bytes[g] += (double)hv[b] * (4.0 + (weighted ? 4.0 : 0.0) + (gather ? 4.0 : 0.0)) + (double)hm[b] * 32.0;

@@ -75,6 +75,12 @@ int launch_contended_add(const DevSlot* S, int ns, const uint64_t* keys, uint32_
 // rate the rated nodes of CONN_RATE slots from them.
 int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                       const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, hipStream_t st);
+// The hub chunk layout alone (what launch_conn_build needs from launch_rate
+// when no binned node is rated by the bins).
+int launch_hub_prep(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_cap, const uint32_t* bin_cnt,
+                    const HubLayout& hub, hipStream_t st);
+// Rates the rated nodes of slots with block connections (CONN_RATE, and
+// CONN_BUILD after launch_conn_build) from their rows.
 int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
                        hipStream_t st);
 // Applies admitted moves of the slots not admitted by tiles (run_apply); in

@@ -2437,7 +2437,7 @@ __global__ void __launch_bounds__(256) k_rate_cached(const DevSlot* __restrict__
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
     const int64_t u = gld(rated, i);
     const DevSlot& sl = S[SLOT(u)];
-    if (sl.conn_mode != CONN_RATE) continue;
+    if (sl.conn_mode == CONN_NONE) continue;  // CONN_BUILD rows were just built
     const int64_t v = u - sl.nbase;
     const int K = sl.conn_k;
     const int32_t own = gld(sl.lab, v);
@@ -2643,6 +2643,13 @@ int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const 
 
 const uint32_t* bin_rated_offsets(void* scratch, int64_t T) {
   return (const uint32_t*)scratch + (size_t)kBinRows * (size_t)T + 1 + (size_t)kBins * (size_t)T;
+}
+
+int launch_hub_prep(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_cap, const uint32_t* bin_cnt,
+                    const HubLayout& hub, hipStream_t st) {
+  LAUNCH(k_hub_prep, 1, 1024, S, ns, bins + 8 * bin_cap, bin_cnt + 8, hub);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
 }
 
 int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
