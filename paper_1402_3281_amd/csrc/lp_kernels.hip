@@ -2423,9 +2423,10 @@ __global__ void __launch_bounds__(256) k_conn_build(const DevSlot* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Rating from block connections: one thread per rated node of a CONN_RATE
-// slot (the nodes of other slots were rated from the bins).  The candidates
-// are the blocks with conn(v, b) > 0; the choice is the same as from the
+// Rating from block connections: one thread per rated node of a slot that
+// keeps them (CONN_RATE, or CONN_BUILD once k_conn_build has written the
+// rows; nodes of other slots are rated from the bins).  The candidates are
+// the blocks with conn(v, b) > 0; the choice is the same as from the
 // neighbour labels.
 // ---------------------------------------------------------------------------
 template <bool ONE>
