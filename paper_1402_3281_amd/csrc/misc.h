@@ -34,9 +34,10 @@ int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw,
                        const int64_t* W, hipStream_t st);
 // Entry tiles of the edge-centric contraction kernels (m entries).
 int cross_tiles(int64_t m);
-// mode 0: entries joining coarse nodes x < y per tile -> tcnt[tile], and
-// every entry's key x * 2^bits + y (~0: x >= y, i.e. the same coarse node or
-// the mirror of another entry of the symmetric graph) -> kcache (m);
+// mode 0: per tile, the entries (u, v) with u < v whose ends lie in coarse
+// nodes x != y (one per undirected edge of the symmetric graph) -> tcnt[tile],
+// and every entry's key min(x, y) * 2^bits + max(x, y) (~0 for the other
+// entries) -> kcache (m);
 // mode 1: the keys and weights (vals may be NULL: not written) of those
 // entries from toff[tile] on (exclusive scan of tcnt), read from kcache;
 // packed (2 bits <= 32): keys hold key << 32 | weight.

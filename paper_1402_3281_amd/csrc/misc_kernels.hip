@@ -362,11 +362,19 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
         const int64_t e = E0 + j * 256 + threadIdx.x;
         kk[j] = kSame;
         if (e >= r.e1) continue;
-        const int32_t x = cof[edge_row(rp, r, s_rp, e)];
-        const int32_t y = cof[col[e]];
-        // the graph is symmetric: the entries with x < y carry every coarse
-        // edge once, the mirror is added after their reduction
-        if (x < y) kk[j] = ((uint64_t)(uint32_t)x << bits) | (uint64_t)(uint32_t)y;
+        // the graph is symmetric with equal weights: the entry (u, v) with
+        // u < v stands for its undirected edge (only its endpoints' coarse
+        // ids are gathered), keyed by the coarse pair in ascending order;
+        // the mirror is added after the reduction
+        const int64_t u = edge_row(rp, r, s_rp, e);
+        const int32_t v = col[e];
+        if (u < v) {
+          const int32_t x = cof[u], y = cof[v];
+          if (x != y) {
+            const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+            kk[j] = ((uint64_t)(uint32_t)lo << bits) | (uint64_t)(uint32_t)hi;
+          }
+        }
         kcache[e] = kk[j];
       }
     } else {
