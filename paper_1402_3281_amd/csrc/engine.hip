@@ -880,11 +880,11 @@ static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, hipStream_t
   if (c->small.ensure(256, st) != SCLAP_OK) return -1;
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
   if (c->cutbuf.ensure((size_t)cut_partials(L.m) * 8, st) != SCLAP_OK) return -1;
-  if (cut_twice(L.rp, L.col, L.ew, part, L.n, L.m, d, (int64_t*)c->cutbuf.p, st) != SCLAP_OK) return -1;
+  if (cut_edges(L.rp, L.col, L.ew, part, L.n, L.m, d, (int64_t*)c->cutbuf.p, st) != SCLAP_OK) return -1;
   if (ctx_ensure_pin(c, 64) != SCLAP_OK) return -1;
   if (hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
   if (hipStreamSynchronize(st) != hipSuccess) return -1;
-  return c->pin[0] / 2;
+  return c->pin[0];
 }
 
 // Allocate the block array of level i (level 0 writes the caller's buffer).

@@ -20,10 +20,11 @@ int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st
 int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);
 int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st);
 int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, int64_t* W, hipStream_t st);
-// Workgroup partial sums cut_twice needs for m entries.
+// Workgroup partial sums cut_edges needs for m entries.
 int cut_partials(int64_t m);
-// *out = sum of w over stored entries joining different blocks (twice the cut).
-int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
+// *out = the cut: sum of w over the undirected edges (entries u < v of the
+// symmetric graph) joining different blocks.
+int cut_edges(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
               unsigned long long* out, int64_t* partial, hipStream_t st);
 
 int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st);

@@ -242,8 +242,9 @@ __device__ __forceinline__ int64_t edge_row(const int64_t* __restrict__ rp, cons
   return row_search(rp, r.ulo, r.uhi, e);
 }
 
-// Cut: sum of w(u, v) over stored entries with part(u) != part(v), halved on
-// the host.  Nodes with part -1 have no entries.
+// Cut: sum of w(u, v) over the entries with u < v and part(u) != part(v) (one
+// per undirected edge of the symmetric graph).  Nodes with part -1 have no
+// entries.
 __global__ void __launch_bounds__(256) k_cut(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                              const int32_t* __restrict__ ew, const int32_t* __restrict__ part,
                                              int64_t n, int64_t m, int64_t* __restrict__ partial) {
@@ -257,7 +258,9 @@ __global__ void __launch_bounds__(256) k_cut(const int64_t* __restrict__ rp, con
       const int64_t e = E0 + j * 256 + threadIdx.x;
       if (e >= r.e1) continue;
       const int64_t u = edge_row(rp, r, s_rp, e);
-      if (part[u] != part[col[e]]) acc += ew ? ew[e] : 1;
+      const int32_t v = col[e];
+      // each undirected edge once: its entry with u < v (the graph is symmetric)
+      if (u < v && part[u] != part[v]) acc += ew ? ew[e] : 1;
     }
   }
   __shared__ int64_t red[4];
@@ -289,7 +292,7 @@ static inline unsigned grid_edges(int64_t m) {
 
 int cut_partials(int64_t m) { return (int)grid_edges(m); }
 
-int cut_twice(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
+int cut_edges(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
               unsigned long long* out, int64_t* partial, hipStream_t st) {
   SCLAP_TRY(fill_t((uint64_t*)out, 1, (uint64_t)0, st));
   if (n <= 0 || m <= 0) return SCLAP_OK;
