@@ -832,16 +832,21 @@ struct OpOr {
 // ---------------------------------------------------------------------------
 // Rating, one workgroup per node (degree <= TS / 2), LDS hash table.
 // ---------------------------------------------------------------------------
+// LDS scratch of its block reductions (up to 8 waves); the caller places it,
+// so that a kernel whose table array has room to spare adds no LDS for it.
+struct BlockRed {
+  uint64_t best[8];
+  int64_t conn[8];
+  int flag[8];
+};
+
 template <int TS, int NT, bool ONE>
 __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, int ns, const int32_t* __restrict__ list,
                                                 const uint64_t* __restrict__ info, uint32_t cnt, uint32_t bid,
-                                                uint32_t nblk, int32_t* lds) {
+                                                uint32_t nblk, int32_t* lds, BlockRed* red) {
   constexpr int B = 4;
   int32_t* keys = lds;
   int32_t* vals = lds + TS;
-  __shared__ uint64_t red64[8];
-  __shared__ int64_t redi[8];
-  __shared__ int redo[8];
   uint32_t i = bid;
   if (i >= cnt) return;
   NodePre<B> p;
@@ -874,14 +879,14 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask,
                   p.nb, p.wt, my_own,
                   foreign);
-    const int64_t conn_own = block_reduce(my_own, redi, OpAdd64());
-    const int boundary = block_reduce(foreign ? 1 : 0, redo, OpOr());
+    const int64_t conn_own = block_reduce(my_own, red->conn, OpAdd64());
+    const int boundary = block_reduce(foreign ? 1 : 0, red->flag, OpOr());
     const bool own_ok = own_allowed(sl, own);
     uint64_t best = scan_table<8>(sl, keys, vals, tsz, threadIdx.x, NT, own_ok, conn_own, own, cv);
     p.u = un;
     p.x = xn;
     if (has_next) pre_row<B, ONE>(p, S, ns, threadIdx.x, NT);
-    best = block_reduce(best, red64, OpMax64());
+    best = block_reduce(best, red->best, OpMax64());
     if (threadIdx.x == 0) {
       if (own_ok) {
         const uint64_t ok = pack_key(conn_own, own);
@@ -938,13 +943,16 @@ __global__ void __launch_bounds__(256) k_rate_mid(const DevSlot* __restrict__ S,
                                                   const int32_t* __restrict__ bins,
                                                   const uint64_t* __restrict__ binfo, int64_t bin_cap,
                                                   const uint32_t* __restrict__ bin_cnt, uint32_t nblk) {
-  __shared__ int32_t lds[8 * 1024];
+  // bin 5: four wave tables of 2 x 1024; bin 6: one table of 2 x 2048 and
+  // the reduction scratch after it (32 KB in all: five workgroups per CU)
+  __shared__ __align__(16) int32_t lds[8 * 1024];
   const uint32_t b = 5 + blockIdx.x / nblk, bid = blockIdx.x % nblk;
   const int32_t* list = bins + b * bin_cap;
   const uint64_t* info = binfo + b * bin_cap;
   const uint32_t cnt = bin_cnt[b];
   if (b == 5) rate_wave_body<1024, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
-  else rate_block_body<2048, 256, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
+  else rate_block_body<2048, 256, ONE>(S, ns, list, info, cnt, bid, nblk, lds,
+                                        reinterpret_cast<BlockRed*>(lds + 2 * 2048));
 }
 
 template <bool ONE>
@@ -953,7 +961,8 @@ __global__ void __launch_bounds__(512) k_rate_large(const DevSlot* __restrict__ 
                                                     const uint64_t* __restrict__ info,
                                                     const uint32_t* __restrict__ cnt_ptr) {
   __shared__ int32_t lds[2 * 8192];
-  rate_block_body<8192, 512, ONE>(S, ns, list, info, *cnt_ptr, blockIdx.x, gridDim.x, lds);
+  __shared__ BlockRed red;
+  rate_block_body<8192, 512, ONE>(S, ns, list, info, *cnt_ptr, blockIdx.x, gridDim.x, lds, &red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1385,7 +1394,7 @@ __device__ __forceinline__ bool agg_add(unsigned long long* hk, long long* hv, u
 constexpr int kAggNodes = 512;    // nodes per workgroup iteration
 constexpr int kAggGrid = 1024;    // workgroups of the admission kernels at most
 constexpr int kIncTable = 2048;   // new keys per iteration: at most kAggNodes
-constexpr int kApplyTable = 4096; // new keys per iteration: at most 2 x kAggNodes
+constexpr int kApplyTable = 2048; // new keys per iteration (departures): at most kAggNodes
 constexpr int kDecideBuf = 2048;  // contended keys buffered per workgroup
 
 // Range [b, e) of the N rated entries walked by this workgroup: whole
@@ -1864,7 +1873,7 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
         gadd64(sl.ctr, CTR_MOVED, (int64_t)1);
       }
     }
-    agg_step<kApplyTable>(hk, hv, hot, &ctr, ins, base + kAggNodes >= e, 2 * kAggNodes, hot_seen,
+    agg_step<kApplyTable>(hk, hv, hot, &ctr, ins, base + kAggNodes >= e, kAggNodes, hot_seen,
                           [&](unsigned long long k, long long x) { gadd64(S[ONE ? 0 : (k >> 32)].W, (uint32_t)k, x); });
   }
   // moved counts: the waves' carried counts combined per slot
