@@ -21,6 +21,10 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls are stream-ordered; calls that return host results synchronize
  *    the stream before returning.
+ *  - An empty graph (n = 0) is valid input: every call returns its trivial
+ *    result (no labels, an empty coarse graph, cut 0) without a launch, and
+ *    round statistics count the rounds the stop rules give when nothing
+ *    moves (clustering: all max_rounds; refinement: two).
  *  - Every call returns SCLAP_OK (0) or a negative SCLAP_E* code and never
  *    throws.  sclap_last_error() returns a description of the last failure
  *    on the calling thread.

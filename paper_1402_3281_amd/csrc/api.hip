@@ -105,6 +105,22 @@ int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t e
   j->stop_rule = 1;
   j->part_out = part_out;
   std::memset(&j->st, 0, sizeof(j->st));
+  if (g->n == 0) {
+    // an empty graph is done at once, with no launch: one level, no
+    // clustering (0 nodes are below any threshold), and the refinement
+    // rounds that the stop rule gives when nothing moves (two)
+    SCLAP_TRY(bounds_impl(0, 0, k, eps_num, eps_den, p->f, &j->lmax, &j->W, &j->U));
+    j->threshold = p->threshold > 0 ? p->threshold : 60 * (int64_t)k;
+    j->st.lmax = j->lmax;
+    j->st.W = j->W;
+    j->st.U = j->U;
+    j->st.threshold = j->threshold;
+    j->st.levels = 1;
+    j->st.rounds_r[0] = std::min<int32_t>(j->ref_rounds, 2);
+    j->st.ms_total = now_ms() - j->t_start;
+    j->stage = ST_DONE;
+    return SCLAP_OK;
+  }
   SCLAP_TRY(check_edge_total(c, g, st));
   SCLAP_TRY(job_set_input(c, j, g, st));
   int64_t C = 0, maxc = 0;
@@ -221,6 +237,16 @@ int sclap_cluster(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_
   SCLAP_TRY(check_csr(g));
   SCLAP_TRY(check_lp(p));
   if (g->n > 0 && !labels_out) return fail(SCLAP_EINVAL, "labels_out is NULL");
+  if (g->n == 0) {
+    // an empty graph, with no launch: no clusters; the 5% rule never holds
+    // for 0 nodes, so every round runs (and moves nothing)
+    if (n_clusters) *n_clusters = 0;
+    if (rs) {
+      std::memset(rs, 0, sizeof(*rs));
+      rs->rounds = p->max_rounds;
+    }
+    return SCLAP_OK;
+  }
   Ctx* c = &ctx->c;
   CtxScope scope(c);
   hipStream_t st = as_stream(stream);
@@ -281,6 +307,23 @@ int sclap_contract(sclap_ctx* ctx, const sclap_csr* g, const int32_t* labels, in
   Ctx* c = &ctx->c;
   CtxScope scope(c);
   hipStream_t st = as_stream(stream);
+  if (g->n == 0) {
+    // an empty graph contracts to an empty graph: row_ptr = {0}
+    Level L;
+    SCLAP_TRY(dalloc_t(&L.own_rp, 1, st));
+    int rc = fill_i64(L.own_rp, 1, 0, st);
+    if (rc == SCLAP_OK) rc = hipStreamSynchronize(st) == hipSuccess ? SCLAP_OK : fail(SCLAP_EHIP, "sync");
+    if (rc != SCLAP_OK) {
+      dfree(L.own_rp, st);
+      return rc;
+    }
+    L.rp = L.own_rp;
+    L.rows_sorted = 1;
+    sclap_graph* out = new sclap_graph();
+    out->L = L;
+    *coarse_out = out;
+    return SCLAP_OK;
+  }
   SCLAP_TRY(check_edge_total(c, g, st));
   Job j;
   j.kind = JOB_CLUSTER;
@@ -352,6 +395,7 @@ int sclap_initial_partition(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int32
   SCLAP_TRY(check_csr(g));
   if (k < 1) return fail(SCLAP_EINVAL, "k must be >= 1");
   if (g->n > 0 && !part_out) return fail(SCLAP_EINVAL, "part_out is NULL");
+  if (g->n == 0) return SCLAP_OK;  // an empty graph: nothing to place, no launch
   Ctx* c = &ctx->c;
   CtxScope scope(c);
   hipStream_t st = as_stream(stream);
@@ -379,6 +423,15 @@ int sclap_refine(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int64_t lmax, co
   SCLAP_TRY(check_lp(p));
   if (k < 1) return fail(SCLAP_EINVAL, "k must be >= 1");
   if (g->n > 0 && !part_inout) return fail(SCLAP_EINVAL, "part_inout is NULL");
+  if (g->n == 0) {
+    // an empty graph, with no launch: nothing moves, and the stop rule ends
+    // the refinement after two such rounds
+    if (rs) {
+      std::memset(rs, 0, sizeof(*rs));
+      rs->rounds = std::min<int32_t>(p->max_rounds, 2);
+    }
+    return SCLAP_OK;
+  }
   Ctx* c = &ctx->c;
   CtxScope scope(c);
   hipStream_t st = as_stream(stream);
@@ -444,7 +497,7 @@ int sclap_partition(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int64_t eps_n
   hipStream_t st = as_stream(stream);
   Job j;
   int rc = setup_partition_job(c, &j, g, k, eps_num, eps_den, p, part_out, st);
-  if (rc == SCLAP_OK) {
+  if (rc == SCLAP_OK && j.stage != ST_DONE) {
     std::vector<Job*> jobs{&j};
     rc = run_jobs(c, jobs, st);
     if (rc == SCLAP_OK && j.stage == ST_ERROR) rc = j.status;

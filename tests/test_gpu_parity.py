@@ -275,3 +275,32 @@ def test_validate(sc, ctx):
     sl = from_edges(3, [(0, 1), (1, 2)])
     sl.col[0] = 0  # a self-loop in row 0
     assert sc.validate(ctx, dev(sc, sl)) == sc.ENOTSYM
+
+
+def test_empty_graph(sc, ctx):
+    """n = 0: every entry point gives the oracle's trivial result (no labels,
+    an empty coarse graph, cut 0, the rounds of the stop rules), also inside
+    a batch beside a non-empty graph."""
+    g = graphgen.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32), name="empty")
+    for rule in (0, 1):
+        want = oracle.cluster(g, 5, 7, rule, 1)
+        lab, ncl, rs = sc.cluster(ctx, dev(sc, g), 5, 7, rule, 1)
+        assert host(lab).size == 0 and ncl == 0
+        assert rs["rounds"] == want.rounds and rs["moved"] == want.moved and rs["visits"] == want.visits
+    assert_contract_parity(sc, ctx, g, np.zeros(0, np.int32), 0)
+    assert host(sc.initial_partition(ctx, dev(sc, g), 3)).size == 0
+    _, rounds, moved, visits = oracle.refine(g, np.zeros(0, np.int32), 2, 0, 8)
+    p = torch.zeros(0, dtype=torch.int32, device="cuda")
+    _, rs = sc.refine(ctx, dev(sc, g), p, 2, 0, 8)
+    assert rs["rounds"] == rounds and rs["moved"] == moved and rs["visits"] == visits
+    want_cut, bw = oracle.cut(g, np.zeros(0, np.int32), 3)
+    got, gbw = sc.cut(ctx, dev(sc, g), torch.zeros(0, dtype=torch.int32, device="cuda"), 3)
+    assert got == want_cut and list(bw) == gbw
+    for k in (1, 4):
+        assert_partition_parity(sc, ctx, g, k)
+    small = graphgen.rmat(10, 4, seed=2)
+    parts, sts = sc.partition_batch(ctx, [dev(sc, g), dev(sc, small)], [4, 4])
+    for gg, pp, st in zip((g, small), parts, sts):
+        want_part, want = oracle.partition(gg, 4)
+        assert np.array_equal(host(pp), want_part), gg.name
+        assert st["cut"] == want["cut"] and st["rounds_r"] == want["rounds_r"], gg.name
