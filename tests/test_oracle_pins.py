@@ -438,3 +438,28 @@ def test_quality_gate_vs_sequential_sclap():
                 ratios.append(max(1, s_sync["cut"]) / max(1, s_seq["cut"]))
     gm = math.exp(sum(math.log(r) for r in ratios) / len(ratios))
     assert gm <= 1.10, gm
+
+
+def test_empty_and_edgeless_stop_rules():
+    """Degenerate inputs of the round loop (Section 3.1): with no node able
+    to move, the 5% rule (fewer than n/20 of the nodes moved in the last two
+    rounds) holds from round 2 on when n > 0 and never when n = 0 (0 < 0
+    is false), and refinement ends after two rounds without a move."""
+    empty = graphgen.Graph(np.zeros(1, np.int64), np.zeros(0, np.int32), name="empty")
+    edgeless = from_edges(7, [])
+    for rule in (0, 1):
+        r = oracle.cluster(empty, 5, 6, rule, 1)
+        assert (r.rounds, list(r.moved), r.visits, r.labels.size) == (6, [0] * 6, 0, 0)
+    assert oracle.cluster(edgeless, 5, 6, 1, 1).rounds == 2
+    assert oracle.cluster(edgeless, 5, 6, 0, 1).rounds == 6
+    for g in (empty, edgeless):
+        part = np.zeros(g.n, np.int32)
+        got, rounds, moved, visits = oracle.refine(g, part, 2, g.n, 8)
+        assert (rounds, list(moved), visits) == (2, [0, 0], 0)
+        assert np.array_equal(got, part)
+    cut, bw = oracle.cut(empty, np.zeros(0, np.int32), 3)
+    assert cut == 0 and list(bw) == [0, 0, 0]
+    part, st = oracle.partition(empty, 4)
+    assert part.size == 0
+    assert (st["levels"], st["rounds_c"], st["rounds_r"]) == (1, [0], [2])
+    assert (st["lmax"], st["W"], st["U"], st["cut"], st["threshold"]) == (0, 0, 0, 0, 240)
