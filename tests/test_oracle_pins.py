@@ -380,6 +380,127 @@ def test_refine_caps_and_overload():
         assert visits >= g.m  # round 1 rates every node
 
 
+def brute_refine(g, part, k, lmax, max_rounds, dir_rule=1):
+    """Refinement written out from Section 3.1 (last paragraph) and the
+    active-node rule of Section 4, round by round: rate every rated node over
+    all k blocks (brute_rate, refinement mode), admit each block's movers in
+    id order by their inclusive prefix (brute_admit with cap L_max), then the
+    next rated set = rated nodes with a neighbour in another block (before the
+    moves) plus all neighbours of admitted movers.  Returns the parts and, per
+    round, (moved, visits, admitted-at-exactly-L_max, rejected movers,
+    movers out of an overloaded block)."""
+    c = g.node_weights()
+    N = nbrs(g)
+    part = np.array(part, np.int32)
+    rated = set(range(g.n))
+    log = []
+    zero = 0
+    for r in range(1, max_rounds + 1):
+        W = np.zeros(k, np.int64)
+        for v in range(g.n):
+            W[part[v]] += c[v]
+        visits = sum(len(N[v]) for v in rated)
+        desire = brute_rate(g, part, W, lmax, r, dir_rule, 1, k)
+        for v in range(g.n):
+            # an unrated node is interior: its only candidate is its own block
+            assert v in rated or desire[v] == part[v], ("unrated node wants to move", r, v)
+        new, adm = brute_admit(g, desire, part, W, lmax)
+        exact = 0
+        for t in range(k):
+            movers = [v for v in range(g.n) if adm[v] and new[v] == t]
+            if movers and W[t] + sum(int(c[v]) for v in movers) == lmax:
+                exact += 1
+        rejected = int(sum(1 for v in range(g.n) if desire[v] != part[v] and not adm[v]))
+        overloaded_out = int(sum(1 for v in range(g.n) if adm[v] and W[part[v]] > lmax))
+        nxt = {v for v in rated if any(part[u] != part[v] for u, _ in N[v])}
+        for v in range(g.n):
+            if adm[v]:
+                nxt.update(u for u, _ in N[v])
+        moved = int(adm.sum())
+        part = new
+        rated = nxt
+        log.append((moved, visits, exact, rejected, overloaded_out))
+        zero = zero + 1 if moved == 0 else 0
+        if zero >= 2:
+            break
+    return part, log
+
+
+def test_refine_matches_brute_force():
+    """orc_refine against brute_refine on the tiny family: blocks after every
+    round, moved counts and the edge visits of every round (cumulative visits
+    of runs cut after 1, 2, ... rounds)."""
+    rng = random.Random(31)
+    seen = {"exact": 0, "rejected": 0, "overloaded": 0, "cases": 0}
+    for name, g in family(seed=29):
+        if g.n < 2:
+            continue
+        for trial in range(3):
+            k = rng.choice((2, 3, 4))
+            part = np.array([rng.randrange(k) for _ in range(g.n)], np.int32)
+            c = g.node_weights()
+            W0 = np.zeros(k, np.int64)
+            for v in range(g.n):
+                W0[part[v]] += c[v]
+            total = int(c.sum())
+            lmax = rng.choice((max(1, -(-total // k)), int(W0.max()), int(W0.max()) - 1, int(W0.min()) + 1,
+                               total, max(1, total // k + rng.randint(0, 3))))
+            lmax = max(lmax, 1)
+            want_part, log = brute_refine(g, part, k, lmax, 8)
+            got_part, rounds, moved, visits = oracle.refine(g, part, k, lmax, max_rounds=8)
+            assert rounds == len(log), (name, trial)
+            assert moved == [x[0] for x in log], (name, trial)
+            assert visits == sum(x[1] for x in log), (name, trial)
+            assert np.array_equal(got_part, want_part), (name, trial)
+            cum = 0
+            for r in range(1, rounds + 1):
+                cum += log[r - 1][1]
+                p_r, rr, m_r, v_r = oracle.refine(g, part, k, lmax, max_rounds=r)
+                assert v_r == cum and m_r == [x[0] for x in log[:r]], (name, trial, r)
+            seen["exact"] += sum(x[2] for x in log)
+            seen["rejected"] += sum(x[3] for x in log)
+            seen["overloaded"] += sum(x[4] for x in log)
+            seen["cases"] += 1
+    # the family reaches the cases the admission rule decides: blocks filled
+    # to exactly L_max, movers turned away, and nodes leaving overloaded blocks
+    assert seen["cases"] > 250 and seen["exact"] > 20 and seen["rejected"] > 20 and seen["overloaded"] > 20, seen
+
+
+def test_hand_worked_refinement():
+    """tests/golden/refine_example.json, worked by hand: per round the rated
+    set's edge visits, every node's choice, the admitted moves (one lands
+    exactly on L_max, a lighter mover behind a rejected one is rejected too),
+    and the stop after two rounds without a move."""
+    gold = json.load(open(os.path.join(GOLDEN, "refine_example.json")))
+    gg = gold["graph"]
+    g = from_edges(gg["n"], [tuple(e) for e in gg["edges"]], nw=gg["node_weights"])
+    k, lmax = gold["k"], gold["lmax"]
+    part0 = np.array(gold["initial_part"], np.int32)
+    _, bw = oracle.cut(g, part0, k)
+    assert list(bw) == gold["initial_block_weights"]
+    part = part0.copy()
+    cum = 0
+    for rd in gold["rounds"]:
+        r = rd["round"]
+        _, W = oracle.cut(g, part, k)
+        desire = oracle.rate(g, part, W, lmax, r, gold["direction_rule"], 1)
+        assert list(desire) == rd["desire"], r
+        assert sum(int(g.row_ptr[v + 1] - g.row_ptr[v]) for v in rd["rated"]) == rd["visits"], r
+        cum += rd["visits"]
+        got, rounds, moved, visits = oracle.refine(g, part0, k, lmax, max_rounds=r)
+        assert list(got) == rd["part_after"], r
+        assert moved[-1] == rd["moved"] and visits == cum, r
+        _, W = oracle.cut(g, got, k)
+        assert list(W) == rd["block_weights_after"], r
+        part = got
+    got, rounds, moved, visits = oracle.refine(g, part0, k, lmax, max_rounds=10)
+    assert rounds == gold["rounds_run"] and visits == gold["total_visits"]
+    assert moved == [rd["moved"] for rd in gold["rounds"]]
+    # the brute force agrees with the hand-worked rounds as well
+    want_part, log = brute_refine(g, part0, k, lmax, 10)
+    assert [x[0] for x in log] == moved and [x[1] for x in log] == [rd["visits"] for rd in gold["rounds"]]
+
+
 def opt_bisection(g, lmax):
     best = None
     c = g.node_weights()
