@@ -345,6 +345,10 @@ def run_serve(args) -> int:
     log(f"plain: {n_plain} jobs in {tp:.2f}s ({plain_jps:.1f} jobs/s)")
 
     budget = args.budget_gb << 30
+    # the plain runs' cached device blocks would sit beside the server's
+    # budget: hand them back to HIP first
+    torch.cuda.synchronize()
+    ctx.trim()
 
     def serve(rate: float, count: int):
         srv = sc.Server(ctx, hbm_budget_bytes=budget, max_active=args.max_active)

@@ -134,7 +134,13 @@ typedef struct sclap_stats {
  * time. */
 int sclap_create(sclap_ctx** out, int device);
 int sclap_destroy(sclap_ctx* ctx);
-const char* sclap_last_error(void);
+/* Description of the last failure on the calling thread (the text is kept
+ * per thread, so ctx may be NULL). */
+const char* sclap_last_error(const sclap_ctx* ctx);
+/* Return the device blocks that the context keeps cached for reuse to HIP
+ * (synchronises the device first).  Other contexts and servers on the same
+ * device can then allocate that memory. */
+int sclap_trim(sclap_ctx* ctx);
 
 /* Check the CSR preconditions (symmetry with equal weights, no self-loops,
  * no repeated neighbours, weights in range) on the device.  Returns
@@ -249,22 +255,38 @@ typedef struct sclap_job_result {
   double queue_ms;         /* submit -> admission */
 } sclap_job_result;
 
-/* A server owns a worker thread that admits queued jobs while the sum of
- * their device footprints stays within hbm_budget_bytes, keeps each admitted
+/* A server owns a worker thread that keeps the sum of the device footprints
+ * of its queued and running jobs within hbm_budget_bytes, admits up to
+ * max_active queued jobs to the device in arrival order, keeps each admitted
  * job's graph hierarchy resident on the device, and advances all admitted
  * jobs together step by step, so that jobs admitted while others run share
  * their launches.  A job's result equals sclap_partition on it alone. */
 int sclap_server_create(sclap_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_active, sclap_server** out);
 /* Copies job->graph (device memory that must be complete: the caller has
  * synchronised the stream that wrote it) and queues the job.  SCLAP_EBUDGET
- * if the job's footprint alone exceeds the budget.  part_out stays owned by
- * the caller and must stay allocated until the job's result was taken. */
+ * if the job's footprint alone exceeds the budget.  Blocks while the job's
+ * footprint does not fit in the budget beside the queued and running jobs.
+ * part_out stays owned by the caller and must stay allocated until the
+ * job's result was taken. */
 int sclap_server_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticket);
 /* SCLAP_OK with *res filled once done (part_out is then complete on the
  * device), after which the ticket is forgotten; SCLAP_EAGAIN while pending;
  * SCLAP_ENOTFOUND for an unknown or already taken ticket. */
 int sclap_server_poll(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
 int sclap_server_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
+/* The same calls under the names of the served-job interface: submit,
+ * poll and wait a job of the server. */
+int sclap_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticket);
+int sclap_poll(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
+int sclap_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
+/* The device bytes a server charges against its budget for a job on graph
+ * g with k blocks, from submission (when the input is copied) to completion
+ * (host math, no device access): input_bytes of the copy, and the footprint,
+ * which bounds everything the job holds at once: the input copy, two
+ * weighted copies of the hierarchy, the LP state of a level with the block
+ * connections of refinement, its share of the context scratch of the fused
+ * rounds, and the temporaries of a contraction. */
+int sclap_server_footprint(const sclap_csr* g, int32_t k, int64_t* input_bytes, int64_t* footprint_bytes);
 /* Latency percentiles over completed jobs and throughput since creation. */
 int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double* jobs_per_s,
                        int64_t* completed, int64_t* peak_bytes);

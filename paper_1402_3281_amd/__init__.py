@@ -108,7 +108,8 @@ _i32, _i64, _u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
 SIGNATURES = {
     "sclap_create": (ctypes.c_int, [_P(_vp), ctypes.c_int]),
     "sclap_destroy": (ctypes.c_int, [_vp]),
-    "sclap_last_error": (ctypes.c_char_p, []),
+    "sclap_last_error": (ctypes.c_char_p, [_vp]),
+    "sclap_trim": (ctypes.c_int, [_vp]),
     "sclap_validate": (ctypes.c_int, [_vp, _P(Csr), _vp]),
     "sclap_bounds": (ctypes.c_int, [_i64, _i64, _i32, _i64, _i64, _i32, _P(_i64), _P(_i64), _P(_i64)]),
     "sclap_cluster": (ctypes.c_int, [_vp, _P(Csr), _i64, _P(LpParams), _vp, _P(_i64), _P(RoundStats), _vp]),
@@ -126,6 +127,10 @@ SIGNATURES = {
     "sclap_server_submit": (ctypes.c_int, [_vp, _P(Job), _P(_u64)]),
     "sclap_server_poll": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
     "sclap_server_wait": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
+    "sclap_submit": (ctypes.c_int, [_vp, _P(Job), _P(_u64)]),
+    "sclap_poll": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
+    "sclap_wait": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
+    "sclap_server_footprint": (ctypes.c_int, [_P(Csr), _i32, _P(_i64), _P(_i64)]),
     "sclap_server_stats": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double),
                                           _P(_i64), _P(_i64)]),
     "sclap_server_destroy": (ctypes.c_int, [_vp]),
@@ -156,7 +161,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
 
 def _check(rc: int) -> None:
     if rc != OK:
-        msg = load_library().sclap_last_error()
+        msg = load_library().sclap_last_error(None)
         raise SclapError(rc, msg.decode() if msg else "")
 
 
@@ -191,6 +196,10 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    def trim(self) -> None:
+        """Return the device blocks the context keeps cached to HIP."""
+        _check(self.lib.sclap_trim(self.h))
 
     def profile(self, on: bool = True) -> None:
         _check(self.lib.sclap_profile_enable(self.h, 1 if on else 0))
@@ -317,6 +326,19 @@ def bounds(total_w: int, max_w: int, k: int, eps: tuple[int, int] = (3, 100), f:
     return lmax.value, W.value, U.value
 
 
+def server_footprint(n: int, m: int, k: int, weighted_edges: bool = False, nw_bytes: int = 0) -> tuple[int, int]:
+    """(input bytes, footprint bytes) a server charges for a job on a graph
+    of n nodes and m stored entries (host math only)."""
+    c = Csr()
+    c.n, c.m = n, m
+    c.ew = 1 if weighted_edges else None   # only the presence of the arrays matters
+    c.nw = 1 if nw_bytes else None
+    c.nw_bytes = nw_bytes
+    inp, fp = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().sclap_server_footprint(ctypes.byref(c), k, ctypes.byref(inp), ctypes.byref(fp)))
+    return inp.value, fp.value
+
+
 def validate(ctx: Context, g: DeviceGraph, stream=None) -> int:
     """Returns OK, ENOTSYM or EINVAL (no exception)."""
     c = g.csr()
@@ -427,13 +449,13 @@ class Server:
         # the server copies the graph on a stream of its own
         torch.cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
-        _check(self.ctx.lib.sclap_server_submit(self.h, ctypes.byref(job), ctypes.byref(t)))
+        _check(self.ctx.lib.sclap_submit(self.h, ctypes.byref(job), ctypes.byref(t)))
         self._keep[t.value] = part_out
         return t.value
 
     def poll(self, ticket: int) -> Optional[dict]:
         r = JobResult()
-        rc = self.ctx.lib.sclap_server_poll(self.h, ticket, ctypes.byref(r))
+        rc = self.ctx.lib.sclap_poll(self.h, ticket, ctypes.byref(r))
         if rc == EAGAIN:
             return None
         _check(rc)
@@ -441,7 +463,7 @@ class Server:
 
     def wait(self, ticket: int) -> dict:
         r = JobResult()
-        _check(self.ctx.lib.sclap_server_wait(self.h, ticket, ctypes.byref(r)))
+        _check(self.ctx.lib.sclap_wait(self.h, ticket, ctypes.byref(r)))
         return self._res(ticket, r)
 
     def _res(self, ticket: int, r: JobResult) -> dict:

@@ -153,7 +153,17 @@ int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t e
 
 extern "C" {
 
-const char* sclap_last_error(void) { return last_error_cstr(); }
+const char* sclap_last_error(const sclap_ctx* ctx) {
+  (void)ctx;  // the message is kept per thread
+  return last_error_cstr();
+}
+
+int sclap_trim(sclap_ctx* ctx) {
+  if (!ctx) return fail(SCLAP_EINVAL, "ctx is NULL");
+  SCLAP_HIP(hipSetDevice(ctx->c.device));
+  ctx_trim(&ctx->c);
+  return SCLAP_OK;
+}
 
 int sclap_create(sclap_ctx** out, int device) {
   if (!out) return fail(SCLAP_EINVAL, "out is NULL");

@@ -70,6 +70,7 @@ struct DevSlot {
   int32_t* conn;          // refine: n x conn_k block connections conn(v, b), or nullptr
   int32_t last_round;     // no LP round of this stage follows (its moves need no bookkeeping)
   int32_t ident;          // first clustering round of a level: lab(v) = v, so a neighbour's label is its id
+  uint32_t* err;          // set nonzero when an LDS hash table of the round fills up (the round fails)
 };
 
 // Refinement with block connections kept per node: the first round of a

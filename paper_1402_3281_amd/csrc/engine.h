@@ -92,6 +92,7 @@ struct Ctx {
   // freed device blocks kept for later allocations on the same stream
   std::vector<CachedBlock> cache;
   size_t cache_bytes = 0;
+  size_t cache_limit = (size_t)96 << 30;  // bytes kept cached at most
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
@@ -150,6 +151,27 @@ void job_release_levels(Job* j, hipStream_t st);
 
 // One fused LP round over the given jobs (all in ST_COARSEN or ST_REFINE).
 int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st);
+
+// Upper bounds of the context scratch a fused round sizes by its total node
+// count and by its slots' stored entries, with the 1/4 growth margin of
+// Scratch::ensure: degree bins (4 B) and their rows (8 B) for each of kBins
+// bins, hub own/best rows (16 B), rated list, old blocks and big movers
+// (12 B), contended keys (8 B) and their sort/scan buffers (28 B, plus sort
+// space), hub layout rows (20 B), binning and tile-admission scans; per
+// stored entry the staged and pooled (label, sum) pairs of hub rows (16 B per
+// pair, at most 1.5 pairs per entry) and the hub chunk x part matrix.
+constexpr int64_t kRoundBytesPerNode = 320;
+constexpr int64_t kRoundBytesPerEntry = 40;
+// Temporaries of contracting a level, per stored entry: the key cache (8 B),
+// the cross keys before and after sorting and their sums (at most one per
+// undirected edge, 8 B each), weights (4 B each), sort space, and the sorted
+// mirror of the coarse edges.
+constexpr int64_t kContractBytesPerEntry = 48;
+
+// Served jobs: device bytes of a job's input copy, and an upper bound of
+// everything the job holds at once on the device (see server.hip).
+int64_t input_bytes_of(const sclap_csr& g);
+int64_t footprint_of(const sclap_csr& g, int32_t k);
 // Contract level cur of a job into level cur + 1.
 int contract_level(Ctx* c, Job* j, int i, int drop_isolated, hipStream_t st);
 // Fused initial partition of the jobs' current (coarsest) levels.

@@ -56,8 +56,6 @@ size_t alloc_class(size_t bytes) {
   const size_t step = (size_t)1 << (lg - 3);
   return (bytes + step - 1) / step * step;
 }
-
-constexpr size_t kCacheLimit = (size_t)96 << 30;  // bytes a context keeps cached at most
 }  // namespace
 
 CtxScope::CtxScope(Ctx* c) : prev(tls_ctx) { tls_ctx = c; }
@@ -125,10 +123,10 @@ void dfree(void* p, hipStream_t st) {
     if (it != g_size.end()) {
       bytes = it->second.bytes;
       if (c && it->second.device != c->device) c = nullptr;
-      if (!c || c->cache_bytes + bytes > kCacheLimit) g_size.erase(it);
+      if (!c || c->cache_bytes + bytes > c->cache_limit) g_size.erase(it);
     }
   }
-  if (c && bytes && c->cache_bytes + bytes <= kCacheLimit) {
+  if (c && bytes && c->cache_bytes + bytes <= c->cache_limit) {
     c->cache.push_back({p, bytes, st});
     c->cache_bytes += bytes;
     return;
@@ -336,6 +334,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   bool tiny_graph = false;  // a binned slot with fewer than 32 entries (degree <= 64 in the 64-lane bin)
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
+  uint32_t* table_err = (uint32_t*)((char*)c->small.p + 256) + 17;
   bool any_build = false, any_cached = false, any_tile = false, any_other = false, any_binned = false;
   bool any_plain = false;  // a slot rated from the bins (no block connections)
   int tile_kmax = 0;
@@ -356,6 +355,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.flag_cur = j->fcur;
     d.flag_next = j->fnext;
     d.ctr = ctr + (size_t)s * CTR_N;
+    d.err = table_err;
     d.n = L.n;
     d.m = L.m;
     d.nbase = N;
@@ -414,17 +414,21 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_gkeys.ensure((size_t)hub_stage * sizeof(int2), st));
     SCLAP_TRY(c->hub_gvals.ensure((size_t)hub_stage * sizeof(int2), st));
     SCLAP_TRY(c->hub_pbase.ensure((size_t)hub_parts * sizeof(int64_t), st));
-    if (c->hub_parts_cap < hub_parts) {
+    if (c->hub_parts_cap < hub_parts || !c->hub_ptot.p) {
+      // the capacity is only valid with its buffer: a failed allocation
+      // leaves hub_ptot empty, and the next round must not take the old
+      // capacity for a buffer that no longer exists
+      c->hub_parts_cap = 0;
       SCLAP_TRY(c->hub_ptot.ensure((size_t)hub_parts * sizeof(uint32_t), st));
+      SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, (int64_t)(c->hub_ptot.bytes / sizeof(uint32_t)), 0, st));
       c->hub_parts_cap = (int64_t)(c->hub_ptot.bytes / sizeof(uint32_t));
-      SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, c->hub_parts_cap, 0, st));
     }
   }
-  if (c->hub_own.bytes < Nz * sizeof(int64_t)) {
+  if (c->hub_own.bytes < Nz * sizeof(int64_t) || !c->hub_own.p) {
     SCLAP_TRY(c->hub_own.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
   }
-  if (c->hub_best.bytes < Nz * sizeof(int64_t)) {
+  if (c->hub_best.bytes < Nz * sizeof(int64_t) || !c->hub_best.p) {
     SCLAP_TRY(c->hub_best.ensure(Nz * sizeof(int64_t), st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
   }
@@ -439,7 +443,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   // Per-round counters (zeroed together with the slot counters after them):
   // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and label
   // parts, [13] refinement movers, [15] big movers, [16] contended set too
-  // large for the one-workgroup path, [24..25] hub pair pool cursor (u64).  The binning results live in c->binmeta:
+  // large for the one-workgroup path, [17] an LDS hash table filled up,
+  // [24..25] hub pair pool cursor (u64).  The binning results live in c->binmeta:
   // u32 [0..8] bin counts, [14] rated; u64 at byte 128: visits per bin.
   // Clustering rounds of the same jobs on the same levels rate the same
   // nodes, so their bins are reused.
@@ -537,12 +542,16 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));
   const uint32_t* hs = (const uint32_t*)c->pin;
-  if (hs[10]) {
-    // a hub label part beyond its LDS table (or a layout beyond its sizes):
-    // the part counters may be left nonzero, so they are cleared
+  if (hs[10] || hs[17]) {
+    // a hub label part beyond its LDS table, a layout beyond its sizes, or a
+    // hash table that filled up: the counters that are kept zero between
+    // rounds may be left nonzero, so they are cleared before the error
     if (c->hub_parts_cap > 0) SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, c->hub_parts_cap, 0, st));
+    SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
+    SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
     (void)hipStreamSynchronize(st);
-    return fail(SCLAP_EHIP, "hub rating: a label part exceeds its table");
+    return fail(SCLAP_EHIP, hs[10] ? "hub rating: a label part exceeds its table"
+                                   : "rating or admission: an LDS hash table filled up");
   }
   if (hs[16]) {
     // contended set too large for one workgroup: device-wide sort and scan,
@@ -829,8 +838,10 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
   std::vector<IpSlot> hs(cnt);
   std::vector<int32_t*> scratch(cnt, nullptr);
   int64_t* states = nullptr;
-  SCLAP_TRY(dalloc_t(&states, (size_t)cnt * 4, st));
-  SCLAP_TRY(fill_i64(states, (int64_t)cnt * 4, 0, st));
+  // 4 words of search state per slot, then the claim-table error flag
+  SCLAP_TRY(dalloc_t(&states, (size_t)cnt * 4 + 1, st));
+  SCLAP_TRY(fill_i64(states, (int64_t)cnt * 4 + 1, 0, st));
+  uint32_t* ip_err = (uint32_t*)(states + (size_t)cnt * 4);
   for (int s = 0; s < cnt; ++s) {
     Job* j = jobs[s];
     const Level& L = j->lv[j->cur];
@@ -851,6 +862,7 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
     x.claim = scratch[s] + 2 * nn;
     x.cnt = scratch[s] + 3 * nn;
     x.state = states + 4 * s;
+    x.err = ip_err;
     SCLAP_TRY(fill_i32(x.part, n, -1, st));
     SCLAP_TRY(fill_i32(x.pos, n, -1, st));
     SCLAP_TRY(fill_i32(x.claim, n, INT32_MAX, st));
@@ -868,8 +880,13 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
   } else {
     SCLAP_TRY(initial_partition((const IpSlot*)c->ip_slots.p, cnt, max_n, 0, 0, st));
   }
+  SCLAP_TRY(ctx_ensure_pin(c, 64));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, ip_err, 4, hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  const uint32_t err = *(const uint32_t*)c->pin;
   for (int s = 0; s < cnt; ++s) dfree(scratch[s], st);
   dfree(states, st);
+  if (err) return fail(SCLAP_EHIP, "initial partition: the LDS claim table filled up");
   return SCLAP_OK;
 }
 

@@ -599,10 +599,14 @@ __device__ __forceinline__ void rate_upto(const DevSlot* __restrict__ S, int ns,
   else rate_group_body<D, ONE>(S, ns, list, info, cnt, bid, nblk);
 }
 
-// Insert (t, w) into an open-addressing table (keys -1 = empty).
-__device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t mask, int32_t t, int32_t w) {
+// Insert (t, w) into an open-addressing table (keys -1 = empty).  Tables
+// are sized for twice the distinct keys they can receive, so the probe ends
+// well before it has seen every slot; if it ever did, *err is set (the round
+// fails) instead of probing forever.
+__device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t mask, int32_t t, int32_t w,
+                                          uint32_t* err) {
   uint32_t h = hash32((uint32_t)t) & mask;
-  for (;;) {
+  for (uint32_t probes = 0; probes <= mask; ++probes) {
     const int32_t prev = atomicCAS(&keys[h], -1, t);
     if (prev == -1 || prev == t) {
       atomicAdd(&vals[h], w);
@@ -610,6 +614,7 @@ __device__ __forceinline__ void table_add(int32_t* keys, int32_t* vals, uint32_t
     }
     h = (h + 1) & mask;
   }
+  atomicOr(err, 1u);
 }
 
 __device__ __forceinline__ uint32_t table_size(int64_t d, int64_t nlabels) {
@@ -660,7 +665,7 @@ __device__ __forceinline__ void table_fill(const int32_t* __restrict__ col, cons
                                            const int32_t* __restrict__ lab, int64_t row0, int first, int d, int step,
                                            int32_t own, int32_t lo, int32_t hi, int32_t* keys, int32_t* vals,
                                            uint32_t mask, int32_t (&nb)[B], int32_t (&wt)[B], int64_t& my_own,
-                                           bool& foreign) {
+                                           bool& foreign, uint32_t* err) {
   for (int base = 0; base < d; base += step * B) {
     int32_t tt[B], cw[B];
 #pragma unroll
@@ -688,7 +693,7 @@ __device__ __forceinline__ void table_fill(const int32_t* __restrict__ col, cons
       }
       foreign = true;
       if (tq < lo || tq > hi) continue;
-      table_add(keys, vals, mask, tq, cw[q]);
+      table_add(keys, vals, mask, tq, cw[q], err);
     }
   }
 }
@@ -779,8 +784,7 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
     int64_t my_own = 0;
     bool foreign = false;
     table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, lane, d, kWave, own, lo, hi, keys, vals, tsz - 1,
-                  p.nb, p.wt, my_own,
-                  foreign);
+                  p.nb, p.wt, my_own, foreign, sl.err);
     for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
     const bool boundary = __ballot(foreign) != 0;
     wave_sync();
@@ -877,8 +881,7 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     int64_t my_own = 0;
     bool foreign = false;
     table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask,
-                  p.nb, p.wt, my_own,
-                  foreign);
+                  p.nb, p.wt, my_own, foreign, sl.err);
     const int64_t conn_own = block_reduce(my_own, red->conn, OpAdd64());
     const int boundary = block_reduce(foreign ? 1 : 0, red->flag, OpOr());
     const bool own_ok = own_allowed(sl, own);
@@ -1127,8 +1130,13 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
         }
         foreign = true;
         if (dir_blocked(sl, tq, own)) continue;
+        // at most kHubChunk distinct labels in a table of 2 x kHubChunk slots
         uint32_t h = hash32((uint32_t)tq) & (kHubTable - 1);
-        for (;;) {
+        for (uint32_t probes = 0;; ++probes) {
+          if (probes == (uint32_t)kHubTable) {
+            *L.overflow = 1;
+            break;
+          }
           const int32_t prev = atomicCAS(&keys[h], -1, tq);
           if (prev == -1 || prev == tq) {
             if (prev == -1) ulist[atomicAdd(&s_used, 1u)] = h;
@@ -1175,9 +1183,12 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
 #pragma unroll
       for (int q = 0; q < PT; ++q) {
         const uint32_t p = threadIdx.x * PT + q;
-        if (p <= P) loff[p] = run;
+        if (p < P) loff[p] = run;
         run += mine[q];
       }
+      // the total: the last thread's running sum covers every part, also
+      // when P = kHubMaxParts (its index is past the threads' entries)
+      if (threadIdx.x == NT - 1) loff[P] = run;
     }
     __syncthreads();
     // chunk x part matrix: staged offsets and each part's reserved range
@@ -1307,7 +1318,11 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
           const uint32_t hh = hash32((uint32_t)pr.x);
           if (((hh >> 12) & (Q - 1)) != q) continue;
           uint32_t h = hh & mask;
-          for (;;) {
+          for (uint32_t probes = 0;; ++probes) {
+            if (probes > mask) {
+              *L.overflow = 1;
+              break;
+            }
             const int32_t prev = atomicCAS(&keys[h], -1, pr.x);
             if (prev == -1 || prev == pr.x) {
               if (prev == -1) atomicAdd(&s_used, 1u);
@@ -1374,11 +1389,13 @@ constexpr unsigned long long kEmpty = ~0ull;
 constexpr uint32_t kCountLabel = 0xFFFFFFFFu;  // key label used for per-slot counters
 
 // Returns whether the key was new to the table; a key found there is marked
-// hot (hot may be null).
+// hot (hot may be null).  The flush rule below keeps the table at most 3/4
+// full; a probe over every slot sets *err (the round fails) instead of
+// probing forever.
 __device__ __forceinline__ bool agg_add(unsigned long long* hk, long long* hv, uint32_t mask, unsigned long long key,
-                                        long long val, uint8_t* hot = nullptr) {
+                                        long long val, uint8_t* hot, uint32_t* err) {
   uint32_t h = hash32((uint32_t)key ^ (uint32_t)(key >> 32) * 0x9E3779B1u) & mask;
-  for (;;) {
+  for (uint32_t probes = 0; probes <= mask; ++probes) {
     // a slot that already holds the key needs no compare-and-swap
     unsigned long long prev = hk[h];
     if (prev == kEmpty) prev = atomicCAS(&hk[h], kEmpty, key);
@@ -1389,6 +1406,8 @@ __device__ __forceinline__ bool agg_add(unsigned long long* hk, long long* hv, u
     }
     h = (h + 1) & mask;
   }
+  atomicOr(err, 1u);
+  return false;
 }
 
 constexpr int kAggNodes = 512;    // nodes per workgroup iteration
@@ -1531,7 +1550,8 @@ __global__ void __launch_bounds__(256) k_incoming(const DevSlot* __restrict__ S,
 #pragma unroll
     for (int it = 0; it < IT; ++it)
       if (ok[it] && t[it] != own[it] && !tile_admission(S[sv[it]]))
-        ins += agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it], hot);
+        ins += agg_add(hk, hv, kIncTable - 1, ((unsigned long long)sv[it] << 32) | (uint32_t)t[it], cv[it], hot,
+                       S[0].err);
     agg_step<kIncTable>(hk, hv, hot, &ctr, ins, base + kAggNodes >= e, kAggNodes, hot_seen,
                         [&](unsigned long long k, long long x) { gadd64(S[ONE ? 0 : (k >> 32)].inc, (uint32_t)k, x); });
   }
@@ -1855,7 +1875,7 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
       const unsigned long long ks = (unsigned long long)s << 32;
       if (admitted && cv != 0) {
         if (alone) gst(sl.W, own, gld(sl.W, own) - cv);  // no other change of W(own) here
-        else ins += agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv, hot);
+        else ins += agg_add(hk, hv, kApplyTable - 1, ks | (uint32_t)own, -cv, hot, S[0].err);
       }
       // moved count: carried by the wave while its slot does not change
       const int s0 = __shfl(s, 0);

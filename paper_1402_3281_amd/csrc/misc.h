@@ -75,6 +75,7 @@ struct IpSlot {
   int32_t* claim;  // n scratch, pre-filled with INT32_MAX
   int32_t* cnt;    // n scratch
   int64_t* state;  // 4: head, tail, next seed, yielded (zero before the first launch)
+  uint32_t* err;   // set nonzero if the LDS claim table filled up (the partition fails)
 };
 // One workgroup per slot; see k_ip_bfs for allow_yield / big_entries.
 // max_n: the largest n over the slots (graphs of up to 2^18 nodes keep

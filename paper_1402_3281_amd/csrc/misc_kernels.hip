@@ -849,11 +849,18 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
             re1[q] = sl.rp[uq[q] + 1];
           }
         }
+        // at most kIpFastEntries keys in 2 x kIpFastEntries slots: a probe
+        // ends long before it has seen every slot (else the partition fails)
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           if (!hq[q]) continue;
           uint32_t h = hash32((uint32_t)uq[q]) & (kIpClaimSlots - 1);
-          for (;;) {
+          for (int probes = 0;; ++probes) {
+            if (probes == kIpClaimSlots) {
+              atomicOr(sl.err, 1u);
+              hq[q] = false;
+              break;
+            }
             const int32_t prev = atomicCAS(&ckey[h], -1, uq[q]);
             if (prev == -1 || prev == uq[q]) {
               atomicMin(&cval[h], (int32_t)(i0 + q));
@@ -873,8 +880,9 @@ __global__ void __launch_bounds__(kIpThreads) k_ip_bfs(const IpSlot* __restrict_
           ch[q] = false;
           if (hq[q]) {
             uint32_t h = hash32((uint32_t)uq[q]) & (kIpClaimSlots - 1);
-            while (ckey[h] != uq[q]) h = (h + 1) & (kIpClaimSlots - 1);
-            ch[q] = cval[h] == (int32_t)(i0 + q);
+            for (int probes = 0; ckey[h] != uq[q] && probes < kIpClaimSlots; ++probes)
+              h = (h + 1) & (kIpClaimSlots - 1);
+            ch[q] = ckey[h] == uq[q] && cval[h] == (int32_t)(i0 + q);
           }
           mine += ch[q] ? 1 : 0;
         }

@@ -1,11 +1,13 @@
 // server.hip -- served partition jobs with continuous batching.
 //
-// A worker thread owns a context of its own (scratch, stream).  Submitted
-// jobs are copied to device memory owned by the server and queued.  Between
-// executor steps the worker admits queued jobs in arrival order while the
-// sum of the footprints of the admitted jobs stays within the HBM budget,
-// then advances every admitted job by one step: one fused LP round over all
-// jobs at an LP stage, their contractions, initial partitions and finishing.
+// A worker thread owns a context of its own (scratch, stream).  A submitted
+// job is charged its device footprint against the HBM budget (submission
+// waits until it fits beside the queued and running jobs), copied to device
+// memory owned by the server and queued.  Between executor steps the worker
+// admits queued jobs in arrival order up to max_active, then advances every
+// admitted job by one step: one fused LP round over all jobs at an LP stage,
+// their contractions, initial partitions and finishing.  A job's charge is
+// returned when it completes.
 // Jobs that arrive while others run therefore share the following launches.
 // Every step is exact per job, so a served result equals the same job run
 // alone.
@@ -51,17 +53,44 @@ struct ServedJob {
   sclap_job_result res{};
 };
 
-// Device bytes a job may hold at once: its input copy, a hierarchy of at
-// most two weighted copies of the input, the LP state of a level (with the
-// block connections of refinement, n x k int32 for k <= kConnMaxK) and the
-// initial-partition scratch.
+}  // namespace
+
+namespace sclap {
+// Device bytes of a job's input copy.
+int64_t input_bytes_of(const sclap_csr& g) {
+  const int64_t n = g.n, m = g.m;
+  return 8 * (n + 1) + 4 * m + (g.ew ? 4 * m : 0) + (g.nw ? (int64_t)g.nw_bytes * n : 0);
+}
+
+// Device bytes a job may hold at once, as an upper bound:
+//   - its input copy;
+//   - the hierarchy: at most two weighted copies of the input (every level
+//     has at most the nodes and entries of the one below it, and each
+//     contraction shrinks the node count by at least 5%, so the levels above
+//     level 1 sum to less than another copy): 8 (n + 1) + 8 m + 8 n + 4 n each;
+//   - the LP state of a level: labels, desires, admitted flags, label or
+//     block weights and incoming sums, the two rated-set bitmaps (48 B per
+//     node), and the block connections of refinement (n x k int32 for
+//     k <= kConnMaxK);
+//   - its share of the context scratch that every fused round sizes by the
+//     total node count of the round: kRoundBytesPerNode per node (degree
+//     bins and rows, rated list, movers, contended keys, hub rows, tile
+//     admission) and kRoundBytesPerEntry per stored entry (the staged and
+//     pooled (label, sum) pairs of hub rows);
+//   - the temporaries of a contraction: kContractBytesPerEntry per stored
+//     entry of the contracted level (key cache, two key arrays, sums, sort
+//     space, mirror) and the initial-partition scratch (16 B per node).
 int64_t footprint_of(const sclap_csr& g, int32_t k) {
   const int64_t n = g.n, m = g.m;
-  const int64_t input = 8 * (n + 1) + 4 * m + (g.ew ? 4 * m : 0) + (g.nw ? (int64_t)g.nw_bytes * n : 0);
   const int64_t hierarchy = 2 * (8 * (n + 1) + 8 * m + 8 * n + 4 * n);
   const int64_t conn = k <= kConnMaxK ? 4 * n * (int64_t)k : 0;
-  return input + hierarchy + 48 * n + conn + 4096;
+  const int64_t scratch = kRoundBytesPerNode * n + kRoundBytesPerEntry * m;
+  const int64_t contraction = kContractBytesPerEntry * m + 16 * n;
+  return input_bytes_of(g) + hierarchy + 48 * n + conn + scratch + contraction + 65536;
 }
+}  // namespace sclap
+
+namespace {
 
 void free_input(ServedJob* sj, hipStream_t st) {
   dfree(sj->rp, st);
@@ -112,13 +141,11 @@ void sclap_server::run() {
       std::unique_lock<std::mutex> lk(mu);
       work_cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
       if (stop && queue.empty() && active.empty()) break;
-      while (!queue.empty() && (int32_t)(active.size() + admit.size()) < max_active &&
-             in_use + queue.front()->footprint <= budget) {
-        ServedJob* sj = queue.front();
+      // every queued job's footprint is charged from its submission on, so
+      // admission only waits for a free slot
+      while (!queue.empty() && (int32_t)(active.size() + admit.size()) < max_active) {
+        admit.push_back(queue.front());
         queue.pop_front();
-        in_use += sj->footprint;
-        peak = std::max(peak, in_use);
-        admit.push_back(sj);
       }
     }
     for (ServedJob* sj : admit) {
@@ -161,6 +188,9 @@ void sclap_server::run() {
         free_input(sj, stream);
       }
       (void)hipStreamSynchronize(stream);
+      // freed blocks beyond the context's cache limit go back to HIP; the
+      // cache is outside the budget, so it is kept small
+      if (ctx.cache_bytes > ctx.cache_limit / 2) ctx_trim(&ctx);
       const double t = now_ms();
       std::lock_guard<std::mutex> lk(mu);
       for (ServedJob* sj : finished) {
@@ -194,6 +224,9 @@ int sclap_server_create(sclap_ctx* ctx, int64_t hbm_budget_bytes, int32_t max_ac
   s->budget = hbm_budget_bytes;
   s->max_active = max_active;
   s->ctx.device = dev;
+  // freed device blocks cached by the worker are not part of any job's
+  // footprint: at most 1/16 of the budget (and 8 GiB)
+  s->ctx.cache_limit = (size_t)std::min<int64_t>(hbm_budget_bytes / 16, (int64_t)8 << 30);
   if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) != hipSuccess) {
     delete s;
@@ -216,6 +249,15 @@ int sclap_server_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticke
   if (sj->footprint > srv->budget) {
     delete sj;
     return fail(SCLAP_EBUDGET, "job larger than the server's memory budget");
+  }
+  {
+    // the job's whole footprint counts against the budget from now on (its
+    // input copy is made here): wait while it does not fit beside the jobs
+    // queued and running; a job alone always fits
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->done_cv.wait(lk, [&] { return srv->in_use + sj->footprint <= srv->budget; });
+    srv->in_use += sj->footprint;
+    srv->peak = std::max(srv->peak, srv->in_use);
   }
   sj->k = job->k;
   sj->eps_num = job->eps_num;
@@ -245,6 +287,11 @@ int sclap_server_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticke
     if (rc != SCLAP_OK) {
       free_input(sj, st);
       (void)hipStreamSynchronize(st);
+      {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->in_use -= sj->footprint;
+      }
+      srv->done_cv.notify_all();
       delete sj;
       return fail(rc, "copying the job's graph failed");
     }
@@ -290,6 +337,23 @@ int sclap_server_poll(sclap_server* srv, uint64_t ticket, sclap_job_result* res)
 int sclap_server_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res) {
   if (!srv) return fail(SCLAP_EINVAL, "NULL server");
   return take_result(srv, ticket, res, true);
+}
+
+int sclap_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticket) {
+  return sclap_server_submit(srv, job, ticket);
+}
+int sclap_poll(sclap_server* srv, uint64_t ticket, sclap_job_result* res) {
+  return sclap_server_poll(srv, ticket, res);
+}
+int sclap_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res) {
+  return sclap_server_wait(srv, ticket, res);
+}
+
+int sclap_server_footprint(const sclap_csr* g, int32_t k, int64_t* input_bytes, int64_t* footprint_bytes) {
+  if (!g || k < 1 || g->n < 0 || g->m < 0) return fail(SCLAP_EINVAL, "bad argument");
+  if (input_bytes) *input_bytes = input_bytes_of(*g);
+  if (footprint_bytes) *footprint_bytes = footprint_of(*g, k);
+  return SCLAP_OK;
 }
 
 int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double* jobs_per_s, int64_t* completed,

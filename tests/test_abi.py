@@ -50,3 +50,32 @@ def test_bounds_golden_via_abi():
         sc.bounds(10, 1, 0)
     with pytest.raises(sc.SclapError):
         sc.bounds(10, 1, 2, eps=(1, 0))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsclap.so not built")
+def test_server_footprint_bounds():
+    """The bytes a server charges for a job cover what the job holds on the
+    device at once: the input copy, two weighted hierarchy copies, the LP
+    state with refinement's block connections, the per-node and per-entry
+    scratch of the fused rounds (degree bins 9 x (4 + 8) B, hub rows 16 B,
+    rated list and movers 12 B, contended keys and their buffers 36 B per
+    node; staged hub pairs 16 B x 1.5 per entry) and a contraction's
+    temporaries (key cache 8 B per entry and four 8 B arrays per undirected
+    edge)."""
+    import paper_1402_3281_amd as sc
+
+    for n, m, k, ew, nwb in ((1 << 10, 16 << 10, 2, False, 0), (1 << 20, 32 << 20, 64, False, 0),
+                             (1 << 16, 1 << 20, 128, True, 8), (5, 0, 3, False, 4), (0, 0, 1, False, 0)):
+        inp, fp = sc.server_footprint(n, m, k, ew, nwb)
+        assert inp == 8 * (n + 1) + 4 * m + (4 * m if ew else 0) + nwb * n
+        hierarchy = 2 * (8 * (n + 1) + 8 * m + 12 * n)
+        conn = 4 * n * k if k <= 64 else 0
+        round_scratch = n * (9 * 12 + 16 + 12 + 36) + int(1.5 * 16 * m)
+        contraction = 8 * m + 4 * 8 * (m // 2)
+        assert fp >= inp + hierarchy + 48 * n + conn + round_scratch + contraction, (n, m, k)
+    # monotone in the graph size and in k up to the block-connection limit
+    a = sc.server_footprint(1000, 8000, 4)[1]
+    assert sc.server_footprint(2000, 8000, 4)[1] > a and sc.server_footprint(1000, 16000, 4)[1] > a
+    assert sc.server_footprint(1000, 8000, 8)[1] > a
+    with pytest.raises(sc.SclapError):
+        sc.server_footprint(10, 10, 0)

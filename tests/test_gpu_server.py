@@ -33,10 +33,9 @@ def test_served_equals_alone(sc, ctx):
     graphs = [s.make() for s in specs]
     devs = [sc.DeviceGraph.from_host(g) for g in graphs]
     parts = [torch.full((g.n,), -1, dtype=torch.int32, device="cuda") for g in graphs]
-    # a budget of about two of the largest jobs (a job holds about 20 B per
-    # edge, 100 B per node and 4 B per node and block of refinement), so
-    # admission waits for retirements
-    budget = 2 * max(20 * g.m + 100 * g.n + 4 * g.n * s.k + 8192 for g, s in zip(graphs, specs))
+    # a budget of about two of the largest jobs, so that admission (and the
+    # submission of input copies) waits for retirements
+    budget = 2 * max(sc.server_footprint(g.n, g.m, s.k)[1] for g, s in zip(graphs, specs))
     srv = sc.Server(ctx, hbm_budget_bytes=budget, max_active=8)
     try:
         tickets = [srv.submit(d, s.k, p) for d, s, p in zip(devs, specs, parts)]
@@ -92,5 +91,28 @@ def test_budget_rejects_oversized_job(sc, ctx):
         with pytest.raises(sc.SclapError) as e:
             srv.submit(d, 4, p)
         assert e.value.code == sc.EBUDGET
+    finally:
+        srv.close()
+
+
+def test_budget_of_one_job_runs_them_in_turn(sc, ctx):
+    """A budget that holds the largest job and little else: submissions wait
+    while the queued input copies would not fit, every job still completes,
+    and each equals the oracle's partition of it alone."""
+    specs = graphgen.serve_specs(count=6, seed=27, lg_lo=9, lg_hi=13)
+    graphs = [s.make() for s in specs]
+    devs = [sc.DeviceGraph.from_host(g) for g in graphs]
+    parts = [torch.full((g.n,), -1, dtype=torch.int32, device="cuda") for g in graphs]
+    budget = max(sc.server_footprint(g.n, g.m, s.k)[1] for g, s in zip(graphs, specs)) + 4096
+    srv = sc.Server(ctx, hbm_budget_bytes=budget, max_active=4)
+    try:
+        tickets = [srv.submit(d, s.k, p) for d, s, p in zip(devs, specs, parts)]
+        results = [srv.wait(t) for t in tickets]
+        for g, s, p, r in zip(graphs, specs, parts, results):
+            assert r["status"] == sc.OK, g.name
+            want_part, want = oracle.partition(g, s.k)
+            assert np.array_equal(p.cpu().numpy(), want_part), g.name
+            assert r["cut"] == want["cut"], g.name
+        assert srv.stats()["peak_bytes"] <= budget
     finally:
         srv.close()
