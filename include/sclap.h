@@ -212,6 +212,22 @@ int sclap_refine(sclap_ctx* ctx, const sclap_csr* g, int32_t k, int64_t lmax, co
 int sclap_cut(sclap_ctx* ctx, const sclap_csr* g, const int32_t* part, int32_t k, int64_t* cut_out,
               int64_t* block_w_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the cut
+ * and, if block_w_out is not NULL, the block weights of sclap_cut, written
+ * to DEVICE memory the caller owns (cut_out: 1 int64, block_w_out: k int64)
+ * on `stream`, with no host synchronisation and no allocation of any kind.
+ * The cut's per-workgroup partial sums use a fixed device array of the
+ * library (64 KiB, 8192 entries, enough for any edge count; one copy per
+ * GPU, kept until the process ends, its address looked up by sclap_create
+ * or by the first call on a device).  k is at most 4096 when block weights
+ * are asked for (SCLAP_EINVAL otherwise).  Calls that overlap on one GPU
+ * (on different streams, or from several threads) share that array and
+ * race; calls in order on one stream do not.  Node weights are read as
+ * given (nw_bytes 4 or 8, NULL for unit weights). */
+int sclap_cut_noalloc(const sclap_csr* g, const int32_t* part, int32_t k, int64_t* cut_out, int64_t* block_w_out,
+                      void* stream);
+
 /* ---- multilevel partition (Section 1 scheme; Section 3.1) ----------------- */
 
 /* Bounds from the whole input; degree-0 nodes set aside; coarsen by

@@ -120,6 +120,7 @@ SIGNATURES = {
     "sclap_initial_partition": (ctypes.c_int, [_vp, _P(Csr), _i32, _i32, _vp, _vp]),
     "sclap_refine": (ctypes.c_int, [_vp, _P(Csr), _i32, _i64, _P(LpParams), _vp, _P(RoundStats), _vp]),
     "sclap_cut": (ctypes.c_int, [_vp, _P(Csr), _vp, _i32, _P(_i64), _vp, _vp]),
+    "sclap_cut_noalloc": (ctypes.c_int, [_P(Csr), _vp, _i32, _vp, _vp, _vp]),
     "sclap_partition": (ctypes.c_int, [_vp, _P(Csr), _i32, _i64, _i64, _P(MlParams), _vp, _P(Stats), _vp]),
     "sclap_partition_batch": (ctypes.c_int, [_vp, _i32, _P(Csr), _vp, _i64, _i64, _P(MlParams), _vp, _P(Stats),
                                              _vp]),
@@ -394,6 +395,15 @@ def cut(ctx: Context, g, part: torch.Tensor, k: int, stream=None) -> tuple[int, 
     c = g.csr()
     _check(ctx.lib.sclap_cut(ctx.h, ctypes.byref(c), _ptr(part), k, ctypes.byref(cv), bw, _stream(stream)))
     return cv.value, list(bw)
+
+
+def cut_noalloc(g, part: torch.Tensor, k: int, cut_out: torch.Tensor, block_w_out: Optional[torch.Tensor] = None,
+                stream=None) -> None:
+    """Cut (and block weights) into caller-owned device tensors (cut_out: 1
+    int64, block_w_out: k int64), without any allocation by the library."""
+    c = g.csr()
+    _check(load_library().sclap_cut_noalloc(ctypes.byref(c), _ptr(part), k, _ptr(cut_out), _ptr(block_w_out),
+                                            _stream(stream)))
 
 
 def ml_params(f: int = 14, lp_rounds: int = 10, refine_rounds: int = 10, direction_rule: int = 1,

@@ -11,6 +11,7 @@
 
 namespace sclap {
 const char* last_error_cstr();
+int noalloc_setup(int device);
 }
 
 using namespace sclap;
@@ -183,6 +184,8 @@ int sclap_create(sclap_ctx** out, int device) {
     (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
   }
   for (auto& e : x->c.ev) SCLAP_HIP(hipEventCreate(&e));
+  // the allocation-free entry point's fixed scratch on this device
+  SCLAP_TRY(noalloc_setup(device));
   *out = x.release();
   return SCLAP_OK;
 }

@@ -20,6 +20,12 @@ int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st
 int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);
 int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st);
 int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, int64_t* W, hipStream_t st);
+// Block weights from node weights as the caller gives them (nw_bytes 4 or 8,
+// nw NULL for unit weights) into W (k entries, zeroed here by a kernel);
+// k at most kBlockWeightsLdsK.  Allocates nothing.
+constexpr int32_t kBlockWeightsLdsK = 4096;
+int block_weights_raw(const int32_t* part, const void* nw, int nw_bytes, int64_t n, int32_t k, int64_t* W,
+                      hipStream_t st);
 // Workgroup partial sums cut_edges needs for m entries.
 int cut_partials(int64_t m);
 // *out = the cut: sum of w over the undirected edges (entries u < v of the

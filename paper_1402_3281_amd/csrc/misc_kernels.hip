@@ -170,6 +170,37 @@ __global__ void __launch_bounds__(256) k_block_weights(const int32_t* __restrict
       if (hist[b]) atomicAdd((unsigned long long*)&W[b], hist[b]);
 }
 
+// The same from the caller's node weights as given (int32, int64 or NULL
+// for unit weights), without a widened copy.
+__global__ void __launch_bounds__(256) k_block_weights_raw(const int32_t* __restrict__ part,
+                                                           const void* __restrict__ nw, int bytes, int64_t n,
+                                                           int32_t k, int64_t* __restrict__ W) {
+  extern __shared__ unsigned long long hist[];
+  for (int b = threadIdx.x; b < k; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int32_t b = part[v];
+    if (b < 0) continue;
+    const int64_t c = !nw ? 1 : bytes == 4 ? (int64_t)((const int32_t*)nw)[v] : ((const int64_t*)nw)[v];
+    atomicAdd(&hist[b], (unsigned long long)c);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < k; b += blockDim.x)
+    if (hist[b]) atomicAdd((unsigned long long*)&W[b], hist[b]);
+}
+
+int block_weights_raw(const int32_t* part, const void* nw, int nw_bytes, int64_t n, int32_t k, int64_t* W,
+                      hipStream_t st) {
+  if (k > kBlockWeightsLdsK) return fail(SCLAP_EINVAL, "block_weights_raw: k above the LDS histogram");
+  SCLAP_TRY(fill_i64(W, k, 0, st));
+  if (n <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_block_weights_raw, dim3(grid1(n, 1024)), dim3(256), (size_t)k * 8, st, part, nw, nw_bytes, n,
+                     k, W);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
 int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, int64_t* W, hipStream_t st) {
   SCLAP_TRY(fill_i64(W, k, 0, st));
   if (n <= 0) return SCLAP_OK;
