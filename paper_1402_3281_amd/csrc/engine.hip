@@ -536,7 +536,12 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     any_big = any_big || (r && jobs[s]->lv[jobs[s]->cur].hubs > 0);  // rows above 4096 entries
   }
   int32_t* big = any_big ? bigm : nullptr;
-  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, small + 16, st));
+  // measurement of the marking kernels: events around them, and the mover
+  // entries they walk (u64 at words 20..21 of the round counters)
+  unsigned long long* mark_entries = c->profile ? (unsigned long long*)(small + 20) : nullptr;
+  hipEvent_t* mark_ev = c->profile ? c->ev + kRateGroups + 3 : nullptr;
+  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, small + 16, st,
+                         mark_ev, mark_entries));
   const size_t rd = 256 + (size_t)ns * CTR_N * sizeof(int64_t);
   SCLAP_TRY(ctx_ensure_pin(c, rd + 512));
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
@@ -573,7 +578,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                     (const int64_t*)c->prefix.p, st));
     SCLAP_TRY(launch_contended_add(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                    (const int64_t*)c->prefix.p, st));
-    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, nullptr, st));
+    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, nullptr, st,
+                           mark_ev, mark_entries));
     SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
   }
@@ -615,6 +621,31 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     c->prof_round_ms += b2;
     c->prof_rounds += 1;
     for (int s = 0; s < ns; ++s) c->prof_rate_visits += sctr[(size_t)s * CTR_N + CTR_VISITS];
+    if (any_refine) {
+      // marking group (kMarkGroup): per rated position its id and old block
+      // (8 B); per mover its row offsets and new block (20 B); per entry of
+      // a mover's row the neighbour id and its rated-set flag (5 B), and,
+      // when the round's moves are added to the block connections, the
+      // edge weight (weighted levels) and two 4-byte read-modify-writes
+      float mm = 0;
+      SCLAP_HIP(hipEventElapsedTime(&mm, c->ev[kRateGroups + 3], c->ev[kRateGroups + 4]));
+      const uint64_t ent = *(const unsigned long long*)((const char*)c->pin + 80);
+      int64_t movers = 0;
+      bool push = false;
+      for (int s = 0; s < ns; ++s) {
+        const DevSlot& d = c->pin_slots[s];
+        if (d.mode != MODE_REFINE) continue;
+        const int64_t mv = sctr[(size_t)s * CTR_N + CTR_MOVED];
+        movers += mv;
+        push = push || (d.conn && !d.last_round && mv * kConnPushDiv <= d.n);
+      }
+      c->prof_k_ms[kMarkGroup] += mm;
+      c->prof_k_group_launches[kMarkGroup] += 1;
+      c->prof_k_nodes[kMarkGroup] += movers;
+      c->prof_k_visits[kMarkGroup] += (int64_t)ent;
+      c->prof_k_bytes[kMarkGroup] += 8.0 * hm[14] + 20.0 * (double)movers +
+                                     (double)ent * (5.0 + (push ? 16.0 + (weighted ? 4.0 : 0.0) : 0.0));
+    }
   }
   // move the slot counters to the front of the staging buffer; a clustering
   // round rates every node of degree > 0, so its edge visits are the level's m
@@ -679,10 +710,10 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   const int64_t mx = c->pin[0];
   const size_t mz = (size_t)std::max<int64_t>(mx, 1);
   // unit edge weights: the sums are the run lengths of the sorted keys;
-  // weighted keys of at most 32 bits carry their weight in the low half of
-  // one 64-bit item (one key-only sort instead of key-value pairs)
+  // weighted keys of at most kPackedKeyBits bits carry their weight in the
+  // low half of one 64-bit item (one key-only sort instead of key-value pairs)
   const bool unit = F.ew == nullptr;
-  const bool packed = !unit && 2 * bits <= 32;
+  const bool packed = !unit && 2 * bits <= kPackedKeyBits;
   uint64_t *k1 = nullptr, *k2 = nullptr;
   int32_t *v1 = nullptr, *v2 = nullptr;
   SCLAP_TRY(dalloc_t(&k1, mz, st));
@@ -724,7 +755,7 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   k2 = nullptr;
   dfree(v2, st);
   v2 = nullptr;
-  const bool mpacked = 2 * bits <= 32;
+  const bool mpacked = 2 * bits <= kPackedKeyBits;
   const size_t hz = (size_t)std::max<int64_t>(mh, 1);
   uint64_t *mk = nullptr, *mks = nullptr;
   int32_t *mw = nullptr, *mws = nullptr;

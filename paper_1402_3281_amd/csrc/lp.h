@@ -46,6 +46,9 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 // Rating launches: bins 0-4 (k_rate_small), 5-6 (k_rate_mid), 7 (k_rate_large),
 // 8 (hub kernels, only if `hubs`).  evs (may be NULL): 5 events around them.
 constexpr int kRateGroups = 5;
+// Measurement group of the refinement marking kernels (k_mark, k_mark_big),
+// after the rating groups in the profile arrays.
+constexpr int kMarkGroup = kRateGroups;
 // max_deg: no binned node has a larger degree (the launches of bins above
 // it are left out).  *groups (may be NULL): bit g set when launch group g
 // (the intervals between evs[g] and evs[g + 1]) ran a kernel.
@@ -88,9 +91,11 @@ int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated
 // (mold, -1: stayed) and then marks the movers' neighbours (updating block
 // connections) for every refinement slot.  big == NULL: no row has more than
 // 4096 entries (no grid-wide walk is launched).
+// mark_ev (may be NULL): two events recorded around the marking kernels;
+// mark_entries (may be NULL): receives the number of mover entries walked.
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
                  int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
-                 hipStream_t st);
+                 hipStream_t st, hipEvent_t* mark_ev = nullptr, unsigned long long* mark_entries = nullptr);
 // Admission and application of the moves of refinement slots with at most
 // kConnMaxK blocks, by binning tiles (roff: the rated-list offsets of the
 // tiles from launch_bin's scratch, see bin_rated_offsets; kmax: the largest
@@ -115,8 +120,18 @@ int launch_tile_admission(const DevSlot* S, int ns, const int32_t* rated, const 
 const uint32_t* bin_rated_offsets(void* scratch, int64_t T);
 
 // Library primitives (rocPRIM) used as steps: sorts, scans, reductions.
+//
+// The radix sort sorts 1024 < n <= 2^20 keys by block sorts and merges, and
+// its merge comparison masks bits [begin_bit, end_bit) with a shift by
+// end_bit that is undefined at 64 (on the device the mask then covers the
+// low 32 bits, and the merged keys come out unsorted).  Sorts over a range
+// that starts above bit 0 must therefore end below bit 64: packed items
+// (key << 32 | weight, sorted by bits [32, 32 + key bits)) take keys of at
+// most kPackedKeyBits bits, and prim_sort_keys rejects such a range.
+constexpr int kPackedKeyBits = 30;
 size_t prim_sort_keys_bytes(size_t n);
-// Sort by bits [begin_bit, end_bit) of the 64-bit keys.
+// Sort by bits [begin_bit, end_bit) of the 64-bit keys (end_bit < 64 when
+// begin_bit > 0).
 int prim_sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, size_t n, int end_bit,
                    hipStream_t st, int begin_bit = 0);
 size_t prim_sort_pairs_bytes(size_t n);

@@ -27,6 +27,9 @@ size_t prim_sort_keys_bytes(size_t n) {
 int prim_sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, size_t n, int end_bit,
                    hipStream_t st, int begin_bit) {
   if (n == 0) return SCLAP_OK;
+  // the merge path's bit mask is wrong for ranges that end at bit 64 and
+  // start above bit 0 (see lp.h)
+  if (begin_bit > 0 && end_bit >= 64) return fail(SCLAP_EINVAL, "radix sort: bit range [b, 64) with b > 0");
   PRIM_CALL(rocprim::radix_sort_keys(tmp, tmp_bytes, in, out, n, (unsigned)begin_bit, (unsigned)end_bit, st));
   return SCLAP_OK;
 }
