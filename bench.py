@@ -30,11 +30,25 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 RATE_KERNELS = ["k_rate_tiny (degree 1-32)", "k_rate_small (degree 33-128)", "k_rate_mid (degree 129-1024)",
-                "k_rate_large (degree 1025-4096)", "hub path (6 kernels, degree > 4096)"]
+                "k_rate_large (degree 1025-4096)", "hub path (6 kernels, degree > 4096)",
+                "k_mark + k_mark_big (refinement marking)"]
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
+
+
+def host_info() -> dict:
+    """The host the CPU baseline ran on: logical CPUs and model name."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def kernel_source_digest() -> str:
@@ -77,13 +91,17 @@ def copy_calibration(mbytes: int) -> int:
 
 
 def roofline(prof: dict, workload: str) -> tuple[dict, list]:
-    """Roofline of the dominant rating kernel: algorithmic bytes per launch
-    (4 B neighbour id + 4 B neighbour label [+ 4 B edge weight] per edge visit,
-    no label bytes in a level's first clustering round, whose labels are the ids;
-    32 B per rated node) / mean launch duration from HIP events.  A launch is
-    a round in which the group's kernels ran (groups with no node in their
-    degree range are left out of a round)."""
-    dom = max(range(4), key=lambda b: prof["kernels"][b]["ms"])
+    """Roofline of the dominant launch group (the one with the most device
+    time over the step, among the five rating groups and the refinement
+    marking kernels): algorithmic bytes per launch / mean launch duration from
+    HIP events.  Rating: 4 B neighbour id + 4 B neighbour label [+ 4 B edge
+    weight] per edge visit, no label bytes in a level's first clustering
+    round, whose labels are the ids; 32 B per rated node.  Marking: 8 B per
+    rated position, 20 B per mover, 5 B per entry of a mover's row plus 16 B
+    [+ 4 B edge weight] in rounds that update the block connections.  A
+    launch is a round in which the group's kernels ran."""
+    groups = range(len(prof["kernels"]))
+    dom = max(groups, key=lambda b: prof["kernels"][b]["ms"])
     kd = prof["kernels"][dom]
     launches = max(kd["launches"], 1)
     avg_ms = kd["ms"] / launches
@@ -92,7 +110,7 @@ def roofline(prof: dict, workload: str) -> tuple[dict, list]:
     per_kernel = [{"kernel": RATE_KERNELS[b], "launches": prof["kernels"][b]["launches"],
                    "ms_per_launch": prof["kernels"][b]["ms"] / max(prof["kernels"][b]["launches"], 1),
                    "GBps": (prof["kernels"][b]["bytes"] / (prof["kernels"][b]["ms"] * 1e-3) / 1e9)
-                   if prof["kernels"][b]["ms"] > 0 else 0.0} for b in range(5)]
+                   if prof["kernels"][b]["ms"] > 0 else 0.0} for b in groups]
     traffic = traffic_for(RATE_KERNELS[dom], workload)
     rl = {"bound": "hbm", "kernel": RATE_KERNELS[dom], "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -190,8 +208,8 @@ def run_two_graphs(args) -> int:
             rounds += r.rounds
         ct = time.perf_counter() - t1
         cpu = {"value": cv / ct, "unit": "edge visits/s", "cores": 1, "kind": "oracle",
-               "sample": "oracle level-0 clustering (10 LP rounds) of both graphs, single thread, gcc -O2: "
-                         f"{rounds} rounds, {cv} visits in {ct:.1f}s"}
+               "sample": "oracle level-0 clustering of both graphs, exactly 10 LP rounds each (no stop rule), "
+                         f"single thread, gcc -O2: {rounds} rounds, {cv} visits in {ct:.1f}s", **host_info()}
 
     line = base_line(
         "SCLaP edge visits/s (multilevel partition, clustering + refinement rounds)", visits / elapsed,
@@ -279,7 +297,7 @@ def run_batch(args) -> int:
         ct = time.perf_counter() - t1
         cpu = {"value": done / ct, "unit": "graphs/s", "cores": 1, "kind": "oracle",
                "sample": f"oracle partition of the first {done} graphs of the batch, one after the other, single "
-                         f"thread; blocks equal to the batched GPU blocks: {equal}"}
+                         f"thread; blocks equal to the batched GPU blocks: {equal}", **host_info()}
 
     line = base_line(
         "graphs/s, mixed graphs partitioned batched (every executor step fused over all graphs)",
@@ -407,7 +425,8 @@ def run_serve(args) -> int:
             done += 1
         ct = time.perf_counter() - t1
         cpu = {"value": done / ct, "unit": "jobs/s", "cores": 1, "kind": "oracle",
-               "sample": f"oracle partition of the first {done} jobs of the stream, one after the other, single thread"}
+               "sample": f"oracle partition of the first {done} jobs of the stream, one after the other, single thread",
+               **host_info()}
 
     line = base_line(
         "jobs/s, served Poisson stream of partition jobs (continuous batching under an HBM budget)",
@@ -499,7 +518,8 @@ def run_large(args) -> int:
         r = oracle.cluster(oracle.OGraph.of(g), U, 1, 0, 1)
         ct = time.perf_counter() - t1
         cpu = {"value": r.visits / ct, "unit": "edge visits/s", "cores": 1, "kind": "oracle",
-               "sample": f"oracle clustering round 1 on level 0, single thread: {r.visits} visits in {ct:.1f}s"}
+               "sample": f"oracle clustering round 1 on level 0, single thread: {r.visits} visits in {ct:.1f}s",
+               **host_info()}
 
     line = base_line(
         "SCLaP edge visits/s (multilevel partition, clustering + refinement rounds)", visits / elapsed,

@@ -319,16 +319,20 @@ int sclap_profile_enable(sclap_ctx* ctx, int32_t on);
  * visits and nodes rated, whole-round device ms and rounds. */
 int sclap_profile_read(sclap_ctx* ctx, double* rate_ms, int64_t* rate_launches, int64_t* visits, int64_t* nodes,
                        double* round_ms, int64_t* rounds);
-/* Per rating launch group (0: degree 1-32, one thread per node; 1: degree
+/* Per launch group (0: rating, degree 1-32, one thread per node; 1: degree
  * 33-128, 64 lanes per node or one wave with an LDS table; 2: degree
  * 129-1024; 3: degree 1025-4096, one workgroup with an LDS table; 4: the
- * multi-workgroup hub path), `count` entries each (any pointer may be NULL):
- * device ms, algorithmic bytes (4 B neighbour id + 4 B neighbour label, not
- * read in the first clustering round of a level, where labels are node ids [+ 4 B
- * edge weight] per visit, 32 B per rated node), edge visits and nodes, summed
- * over rounds, and launches = rounds in which the group's kernels ran (a
- * group is left out when no node of the round falls in its degree range).
- * *rounds = rating rounds profiled. */
+ * multi-workgroup hub path; 5: the refinement marking kernels, which add the
+ * neighbours of moved nodes to the next rated set and move their edge
+ * weights between block connections), `count` entries each (any pointer may
+ * be NULL): device ms; algorithmic bytes (rating: 4 B neighbour id + 4 B
+ * neighbour label, not read in the first clustering round of a level, where
+ * labels are node ids [+ 4 B edge weight] per visit, 32 B per rated node;
+ * marking: 8 B per rated position, 20 B per mover, per entry of a mover's
+ * row 5 B, plus 16 B of block-connection updates [+ 4 B edge weight] in
+ * rounds that update them); edge visits (marking: mover entries) and nodes
+ * (marking: movers), summed over rounds; and launches = rounds in which the
+ * group's kernels ran.  *rounds = LP rounds profiled. */
 int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
                           int64_t* launches, int64_t* rounds);
 

@@ -212,7 +212,7 @@ class Context:
                                            ctypes.byref(nodes), ctypes.byref(rnd_ms), ctypes.byref(rounds)))
         out = {"rate_ms": ms.value, "rate_launches": la.value, "visits": vis.value, "nodes": nodes.value,
                "round_ms": rnd_ms.value, "rounds": rounds.value}
-        K = 5
+        K = 6  # five rating groups and the refinement marking kernels
         kms, kb = (ctypes.c_double * K)(), (ctypes.c_double * K)()
         kv, kn = (ctypes.c_int64 * K)(), (ctypes.c_int64 * K)()
         kl, kr = (ctypes.c_int64 * K)(), ctypes.c_int64()

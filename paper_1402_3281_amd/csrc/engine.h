@@ -109,7 +109,9 @@ struct Ctx {
   size_t pin_slots_cap = 0;
   // optional timing of the rating kernels (per degree bin) and LP rounds
   bool profile = false;
-  hipEvent_t ev[kBins + 3];       // [0..kBins] rating kernels, [kBins+1], [kBins+2] whole round
+  // [0..kRateGroups] rating launch groups, [kRateGroups+1], [kRateGroups+2]
+  // the whole round, [kRateGroups+3], [kRateGroups+4] the marking kernels
+  hipEvent_t ev[kBins + 3];
   double prof_rate_ms = 0;         // sum over rounds of the whole rating step
   int64_t prof_rate_launches = 0;
   int64_t prof_rate_visits = 0;

@@ -2054,7 +2054,8 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
                                               const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
                                               const int32_t* __restrict__ mold,
                                               int32_t* __restrict__ big, uint32_t* __restrict__ big_cnt,
-                                              const uint32_t* __restrict__ skip) {
+                                              const uint32_t* __restrict__ skip,
+                                              unsigned long long* __restrict__ entries) {
   __shared__ int32_t s_ex[4][kWave];
   __shared__ int64_t s_e0[4][kWave];
   __shared__ int64_t s_ab[4][kWave];
@@ -2085,6 +2086,12 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
         d = gld(sl->rp, v + 1) - e0;
         mover_blocks(*sl, oa, v, a, b);
       }
+    }
+    if (entries) {
+      // measurement only: the entries of the movers' rows, one add per wave
+      uint64_t wd = (uint64_t)d;
+      for (int off = 32; off > 0; off >>= 1) wd += __shfl_xor(wd, off);
+      if (lane_id() == 0 && wd) atomicAdd(entries, (unsigned long long)wd);
     }
     {
       const int32_t ds = d > 0 && d <= kWave ? (int32_t)d : 0;
@@ -2740,11 +2747,14 @@ int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const
 
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
                  int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
-                 hipStream_t st) {
+                 hipStream_t st, hipEvent_t* mark_ev, unsigned long long* mark_entries) {
   if (run_apply) LAUNCH(k_apply, grid_for(N, kAggNodes, kAggGrid), 256, S, ns, rated, rcnt, mold, skip);
   if (any_refine) {
-    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, skip);
+    if (mark_ev) SCLAP_HIP(hipEventRecord(mark_ev[0], st));
+    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, skip,
+           mark_entries);
     if (big) LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, skip);
+    if (mark_ev) SCLAP_HIP(hipEventRecord(mark_ev[1], st));
   }
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
