@@ -1,21 +1,24 @@
 """Benchmark of the SCLaP multilevel partitioner on one MI355X.
 
-Default workload (one step): partition an R-MAT graph (scale 22, edge factor
-16, a/b/c/d = .57/.19/.19/.05, 4.19M nodes) and a 2D random geometric graph
-(2^22 nodes, average degree 10) into k = 16 blocks, eps = 3/100, f = 14,
-coarsening to <= 5000 k = 80,000 nodes, 10 LP rounds per level, LP refinement
-on every level.  Inputs are generated on the host, copied to the device before
-timing, and stay resident.  value = edge visits (clustering + refinement
-rounds, both graphs) per second of the whole step (contraction, initial
-partition and projection included).  The JSON line carries the HBM roofline
-of the dominant rating kernel and the CPU oracle as a reported baseline.
+Default workload (`--workload large`, one step): partition an R-MAT graph of
+scale 26 (edge factor 16, a/b/c/d = .57/.19/.19/.05, 67.1M nodes, 2.1G
+directed entries after symmetrisation and de-duplication) into k = 32 blocks,
+eps = 3/100, f = 14, coarsening to at most max(60k, n/(60k)) nodes, 10 LP
+rounds per level, LP refinement on every level.  The input is generated on the
+host, copied to the device before timing, and stays resident.  value = edge
+visits (clustering + refinement rounds) per second of the whole step
+(contraction, initial partition and projection included).  The returned blocks
+are checked on the host (cut and block weights recomputed, every block within
+L_max).  The JSON line carries the HBM roofline of the dominant rating kernel
+group and the CPU oracle as a reported baseline.
 
 Other workloads (`--workload`):
-  batch  512 mixed graphs, batched (every step fused over all graphs) versus
-         plain (one graph after the other); graphs/s.
-  serve  served Poisson stream of partition jobs under an HBM budget versus
-         plain; p50/p99 latency and jobs/s.
-  large  one R-MAT graph of scale 26, k = 32, with result properties checked.
+  two-graphs  R-MAT scale 22 and a 2D random geometric graph of 2^22 nodes
+              (average degree 10), k = 16, coarsening to <= 5000 k nodes.
+  batch       512 mixed graphs, batched (every step fused over all graphs)
+              versus plain (one graph after the other); graphs/s.
+  serve       served Poisson stream of partition jobs under an HBM budget
+              versus plain; p50/p99 latency and jobs/s.
 """
 from __future__ import annotations
 
@@ -545,9 +548,9 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="two-graphs", choices=("two-graphs", "batch", "serve", "large"),
-                    help="two-graphs: R-MAT s22 + RGG 2^22, k=16 (default); batch: 512 mixed graphs batched vs "
-                         "plain; serve: Poisson stream of jobs; large: R-MAT s26, k=32")
+    ap.add_argument("--workload", default="large", choices=("large", "two-graphs", "batch", "serve"),
+                    help="large: R-MAT s26, k=32 (default); two-graphs: R-MAT s22 + RGG 2^22, k=16; batch: 512 "
+                         "mixed graphs batched vs plain; serve: Poisson stream of jobs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scale", type=int, default=0, help="R-MAT scale (two-graphs: 22, large: 26)")
     ap.add_argument("--graphs", type=int, default=512, help="batch size (batch)")
@@ -565,7 +568,7 @@ def main() -> int:
         return copy_calibration(args.calib_copy_mb)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the partitioner's multi-GPU path is "
-              "not built; see the sharding notes in DESIGN.md.", file=sys.stderr)
+              "not built.", file=sys.stderr)
         return 2
     if args.workload == "two-graphs":
         args.scale = args.scale or 22
