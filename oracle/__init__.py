@@ -14,18 +14,28 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = [os.path.join(_HERE, "sclap_oracle.c"), os.path.join(_HERE, "seq_sclap.c")]
+_SRCS = [os.path.join(_HERE, "sclap_oracle.c"), os.path.join(_HERE, "sclap_extensions.c"),
+         os.path.join(_HERE, "seq_sclap.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MAXLEV = 64
 MAXR = 64
+MAXCYC = 16
 
 OK, EINVAL, ENOMEM, EOVERFLOW = 0, -1, -2, -3
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return any(os.path.getmtime(f) > t for f in _SRCS + [os.path.join(_HERE, "sclap_oracle.h")])
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc -O2 (single-threaded, no OpenMP)."""
-    if force or not os.path.exists(_LIB):
+    """Compile the oracle with gcc -O2 (single-threaded, no OpenMP); with
+    force=False only when the library is missing or older than a source."""
+    if force or _stale():
         subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-o", _LIB] + _SRCS)
     return _LIB
 
@@ -76,6 +86,30 @@ class Stats(ctypes.Structure):
         return d
 
 
+class MLX(ctypes.Structure):
+    """Options of the Section 4 extensions (all zero: the plain scheme)."""
+    _fields_ = [
+        ("vcycles", ctypes.c_int32), ("subrounds", ctypes.c_int32), ("ensemble", ctypes.c_int32),
+        ("pad", ctypes.c_int32), ("delta_num", ctypes.c_int64), ("delta_den", ctypes.c_int64),
+    ]
+
+
+class Cycles(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int32), ("best", ctypes.c_int32),
+        ("cut", ctypes.c_int64 * MAXCYC), ("max_block", ctypes.c_int64 * MAXCYC),
+        ("visits", ctypes.c_int64 * MAXCYC), ("levels", ctypes.c_int32 * MAXCYC),
+        ("lmax", (ctypes.c_int64 * MAXLEV) * MAXCYC),
+    ]
+
+    def to_dict(self) -> dict:
+        c = self.cycles
+        return {"cycles": c, "best": self.best, "cut": [self.cut[i] for i in range(c)],
+                "max_block": [self.max_block[i] for i in range(c)], "visits": [self.visits[i] for i in range(c)],
+                "levels": [self.levels[i] for i in range(c)],
+                "lmax": [[self.lmax[i][j] for j in range(self.levels[i])] for i in range(c)]}
+
+
 _lib = None
 _i64p = ctypes.c_void_p
 
@@ -116,6 +150,27 @@ def _load():
         lib.orc_partition.argtypes = [P(_G), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                       _i64p, P(Stats)]
+        lib.orc_rate_ext.restype = ctypes.c_int64
+        lib.orc_rate_ext.argtypes = [P(_G), _i64p, _i64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_int32, _i64p, _i64p, _i64p, _i64p]
+        lib.orc_cluster_ext.restype = ctypes.c_int32
+        lib.orc_cluster_ext.argtypes = [P(_G), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        _i64p, ctypes.c_int32, _i64p, _i64p, _i64p, P(ctypes.c_int64)]
+        lib.orc_member_labels.restype = None
+        lib.orc_member_labels.argtypes = [ctypes.c_int64, ctypes.c_int32, _i64p]
+        lib.orc_overlay.restype = ctypes.c_int64
+        lib.orc_overlay.argtypes = [ctypes.c_int64, _i64p, _i64p]
+        lib.orc_ensemble.restype = ctypes.c_int32
+        lib.orc_ensemble.argtypes = [P(_G), ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, _i64p, ctypes.c_int32, _i64p, _i64p, P(ctypes.c_int64)]
+        lib.orc_level_lmax.restype = ctypes.c_int64
+        lib.orc_level_lmax.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                       ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int64]
+        lib.orc_partition_ext.restype = ctypes.c_int
+        lib.orc_partition_ext.argtypes = [P(_G), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                          P(MLX), _i64p, P(Stats), P(Cycles)]
         lib.seq_partition.restype = ctypes.c_int
         lib.seq_partition.argtypes = [P(_G), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _i64p, P(Stats)]
@@ -281,6 +336,86 @@ def partition(g, k: int, eps: tuple[int, int] = (3, 100), f: int = 14, lp_rounds
     if rc:
         raise RuntimeError(f"orc_partition: {rc}")
     return part, st.to_dict()
+
+
+def rate_ext(g, lab, Wt, cap: int, rnd: int, dir_rule: int = 1, vblk=None, lblk=None, active=None):
+    """Clustering rating with the respect filter and an active mask; returns
+    (desire, visits); visits is -1 if a cluster lies outside its block."""
+    g = OGraph.of(g)
+    lab = np.ascontiguousarray(lab, np.int32)
+    Wt = np.ascontiguousarray(Wt, np.int64)
+    vblk = None if vblk is None else np.ascontiguousarray(vblk, np.int32)
+    lblk = None if lblk is None else np.ascontiguousarray(lblk, np.int32)
+    active = None if active is None else np.ascontiguousarray(active, np.uint8)
+    desire = np.empty(g.n, np.int32)
+    vis = _load().orc_rate_ext(ctypes.byref(g.s), _ptr(lab), _ptr(Wt), Wt.shape[0], cap, rnd, dir_rule,
+                               _ptr(vblk), _ptr(lblk), _ptr(active), _ptr(desire))
+    return desire, int(vis)
+
+
+def cluster_ext(g, U: int, max_rounds: int = 10, stop_rule: int = 0, dir_rule: int = 1, vblk=None,
+                subrounds: int = 0, lab0=None) -> ClusterResult:
+    g = OGraph.of(g)
+    vblk = None if vblk is None else np.ascontiguousarray(vblk, np.int32)
+    lab0 = None if lab0 is None else np.ascontiguousarray(lab0, np.int32)
+    lab = np.empty(g.n, np.int32)
+    moved = np.zeros(max(max_rounds, 1), np.int64)
+    visits = ctypes.c_int64()
+    r = _load().orc_cluster_ext(ctypes.byref(g.s), U, max_rounds, stop_rule, dir_rule, _ptr(vblk), subrounds,
+                                _ptr(lab0), _ptr(lab), _ptr(moved), ctypes.byref(visits))
+    if r < 0:
+        raise AssertionError("orc_cluster_ext: a cluster left its block")
+    return ClusterResult(lab, int(r), [int(x) for x in moved[:r]], int(visits.value))
+
+
+def member_labels(n: int, e: int) -> np.ndarray:
+    lab0 = np.empty(n, np.int32)
+    _load().orc_member_labels(n, e, _ptr(lab0))
+    return lab0
+
+
+def overlay(O, C) -> tuple[np.ndarray, int]:
+    O = np.array(O, np.int32)
+    C = np.ascontiguousarray(C, np.int32)
+    c = _load().orc_overlay(O.shape[0], _ptr(O), _ptr(C))
+    return O, int(c)
+
+
+def ensemble(g, U: int, members: int, max_rounds: int = 10, stop_rule: int = 1, dir_rule: int = 1, vblk=None,
+             subrounds: int = 0) -> ClusterResult:
+    g = OGraph.of(g)
+    vblk = None if vblk is None else np.ascontiguousarray(vblk, np.int32)
+    lab = np.empty(g.n, np.int32)
+    moved = np.zeros(max(max_rounds, 1), np.int64)
+    visits = ctypes.c_int64()
+    r = _load().orc_ensemble(ctypes.byref(g.s), U, max_rounds, stop_rule, dir_rule, members, _ptr(vblk),
+                             subrounds, _ptr(lab), _ptr(moved), ctypes.byref(visits))
+    if r < 0:
+        raise AssertionError("orc_ensemble: a cluster left its block")
+    return ClusterResult(lab, int(r), [int(x) for x in moved[:r]], int(visits.value))
+
+
+def level_lmax(C: int, k: int, eps: tuple[int, int], delta: tuple[int, int], q: int, i: int, lmax: int) -> int:
+    """L_max on level i of q levels with extra imbalance delta (Section 4)."""
+    return int(_load().orc_level_lmax(C, k, eps[0], eps[1], delta[0], delta[1], q, i, lmax))
+
+
+def partition_ext(g, k: int, eps: tuple[int, int] = (3, 100), f: int = 14, lp_rounds: int = 10,
+                  ref_rounds: int = 10, threshold: int = 0, dir_rule: int = 1, vcycles: int = 1,
+                  subrounds: int = 0, ensemble: int = 1, delta: tuple[int, int] = (0, 1)):
+    """Multilevel partition with the Section 4 extensions; returns (part,
+    stats of the last cycle with the returned partition's cut, per-cycle
+    results)."""
+    g = OGraph.of(g)
+    part = np.empty(g.n, np.int32)
+    st = Stats()
+    cy = Cycles()
+    x = MLX(vcycles, subrounds, ensemble, 0, delta[0], delta[1])
+    rc = _load().orc_partition_ext(ctypes.byref(g.s), k, eps[0], eps[1], f, lp_rounds, ref_rounds, threshold,
+                                   dir_rule, ctypes.byref(x), _ptr(part), ctypes.byref(st), ctypes.byref(cy))
+    if rc:
+        raise RuntimeError(f"orc_partition_ext: {rc}")
+    return part, st.to_dict(), cy.to_dict()
 
 
 def seq_partition(g, k: int, eps: tuple[int, int] = (3, 100), f: int = 14, lp_rounds: int = 10,

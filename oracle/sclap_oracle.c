@@ -27,49 +27,10 @@
  * All arithmetic is integer.  Node weights are int64, edge weights int32
  * (NULL means unit), ratings accumulate in int64.
  */
-#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXLEV 64
-#define ORC_MAXR 64
-
-enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_EOVERFLOW = -3 };
-
-typedef struct orc_graph {
-  int64_t n;
-  int64_t m;            /* directed entries */
-  const int64_t* rp;    /* n + 1 */
-  const int32_t* col;   /* m */
-  const int32_t* ew;    /* m, or NULL for unit edge weights */
-  const int64_t* nw;    /* n, or NULL for unit node weights */
-} orc_graph;
-
-typedef struct orc_owned {
-  int64_t n, m;
-  int64_t* rp;
-  int32_t* col;
-  int32_t* ew;
-  int64_t* nw;
-} orc_owned;
-
-typedef struct orc_stats {
-  int32_t levels;                       /* graphs in the hierarchy, level 0 = input without isolated nodes */
-  int32_t pad;
-  int64_t n_level[ORC_MAXLEV];
-  int64_t m_level[ORC_MAXLEV];
-  int32_t rounds_c[ORC_MAXLEV];         /* clustering rounds run on level i */
-  int32_t rounds_r[ORC_MAXLEV];         /* refinement rounds run on level i */
-  int64_t moved_c[ORC_MAXLEV][ORC_MAXR];
-  int64_t moved_r[ORC_MAXLEV][ORC_MAXR];
-  int64_t visits_c[ORC_MAXLEV];         /* coarsening edge visits on level i */
-  int64_t visits_r[ORC_MAXLEV];         /* refinement edge visits on level i */
-  int64_t lmax, W, U, threshold;
-  int64_t n_isolated;
-  int64_t ip_cut;                       /* cut of the initial partition (coarsest level) */
-  int64_t cut;
-  int64_t max_block;
-} orc_stats;
+#include "sclap_oracle.h"
 
 static inline int64_t node_w(const orc_graph* g, int64_t v) { return g->nw ? g->nw[v] : 1; }
 static inline int64_t edge_w(const orc_graph* g, int64_t e) { return g->ew ? (int64_t)g->ew[e] : 1; }

@@ -12,48 +12,10 @@
  * Section 4 / Appendix B.2 (two FIFO queues and two bit vectors) picks the
  * nodes of later rounds.
  */
-#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXLEV 64
-#define ORC_MAXR 64
-
-typedef struct orc_graph {
-  int64_t n, m;
-  const int64_t* rp;
-  const int32_t* col;
-  const int32_t* ew;
-  const int64_t* nw;
-} orc_graph;
-
-typedef struct orc_owned {
-  int64_t n, m;
-  int64_t* rp;
-  int32_t* col;
-  int32_t* ew;
-  int64_t* nw;
-} orc_owned;
-
-typedef struct orc_stats {
-  int32_t levels, pad;
-  int64_t n_level[ORC_MAXLEV];
-  int64_t m_level[ORC_MAXLEV];
-  int32_t rounds_c[ORC_MAXLEV];
-  int32_t rounds_r[ORC_MAXLEV];
-  int64_t moved_c[ORC_MAXLEV][ORC_MAXR];
-  int64_t moved_r[ORC_MAXLEV][ORC_MAXR];
-  int64_t visits_c[ORC_MAXLEV];
-  int64_t visits_r[ORC_MAXLEV];
-  int64_t lmax, W, U, threshold, n_isolated, ip_cut, cut, max_block;
-} orc_stats;
-
-int orc_bounds(int64_t, int64_t, int32_t, int64_t, int64_t, int32_t, int64_t*, int64_t*, int64_t*);
-int orc_contract(const orc_graph*, const int32_t*, int32_t, int32_t*, orc_owned*);
-void orc_owned_free(orc_owned*);
-void orc_initial_partition(const orc_graph*, int32_t, int32_t, int32_t*);
-int64_t orc_cut(const orc_graph*, const int32_t*, int32_t, int64_t*);
-void orc_place_isolated(const int64_t*, int64_t, const uint8_t*, int32_t, const int64_t*, int32_t*);
+#include "sclap_oracle.h"
 
 static inline int64_t nwt(const orc_graph* g, int64_t v) { return g->nw ? g->nw[v] : 1; }
 static inline int64_t ewt(const orc_graph* g, int64_t e) { return g->ew ? (int64_t)g->ew[e] : 1; }

@@ -21,6 +21,5 @@ def _built_cpu_libs():
 
     if not os.path.exists(os.path.join(ROOT, "graphgen", "libgraphgen.so")):
         graphgen.build()
-    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
-        oracle.build()
+    oracle.build(force=False)  # rebuilt when a source is newer than the library
     yield
