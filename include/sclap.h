@@ -57,6 +57,9 @@ extern "C" {
 
 #define SCLAP_MAX_LEVELS 64
 #define SCLAP_MAX_ROUNDS 64
+#define SCLAP_MAX_CYCLES 16
+#define SCLAP_MAX_SUBROUNDS 16
+#define SCLAP_MAX_ENSEMBLE 64
 
 typedef struct sclap_ctx sclap_ctx;
 typedef struct sclap_graph sclap_graph;
@@ -81,7 +84,12 @@ typedef struct sclap_lp_params {
   int32_t stop_rule;      /* 0: exactly max_rounds rounds; 1: stop after round r >= 2 when
                              20 * (moved_r + moved_{r-1}) < n */
   int32_t direction_rule; /* 1: odd rounds move down, even rounds up (default); 0: no rule */
-  int32_t reserved;
+  int32_t subrounds;      /* Section 4 node ordering by increasing degree: with S >= 2, every round
+                             is S sub-rounds; sub-round s rates the nodes of degree class s (0 below
+                             degree 4, else floor(log4 degree), at most S - 1) from the labels and
+                             weights the previous sub-round left, and admits their moves; the
+                             direction rule follows the round.  0 or 1: synchronous rounds.
+                             At most SCLAP_MAX_SUBROUNDS. */
 } sclap_lp_params;
 
 /* Per-call round statistics (edge visits = sum of the degrees of the nodes
@@ -101,6 +109,23 @@ typedef struct sclap_ml_params {
   int32_t refine_rounds;   /* l during uncoarsening (0 = no refinement) */
   int32_t direction_rule;  /* as in sclap_lp_params */
   int64_t threshold;       /* stop coarsening at <= threshold nodes; <= 0: max(60k, n/(60k)) */
+  /* Section 4 extensions; all zero gives the plain scheme. */
+  int32_t vcycles;         /* iterated multilevel cycles (Section 4; Appendix B.1), 0 or 1: one;
+                              cycle c >= 2 starts from the best partition so far, clusters every
+                              level within its blocks (no cut edge is contracted) and takes those
+                              blocks on its coarsest level instead of an initial partition.  The
+                              result is the best cycle's partition: blocks within L_max first,
+                              then the smaller cut, ties to the earlier cycle.  <= SCLAP_MAX_CYCLES */
+  int32_t subrounds;       /* degree-ordered sub-rounds of every clustering round (see
+                              sclap_lp_params); 0 or 1: none */
+  int32_t ensemble;        /* clusterings overlaid on every coarsening level (Section 4, ensemble
+                              clusterings), 0 or 1: one.  Member e >= 1 starts from the labels
+                              (a_e v + b_e) mod n (sclap_cluster_ext); the overlay puts two nodes
+                              together iff every member does.  <= SCLAP_MAX_ENSEMBLE */
+  int32_t reserved;
+  int64_t delta_num;       /* extra imbalance delta = delta_num / delta_den on the coarse levels of */
+  int64_t delta_den;       /* the first cycle (Section 4): level i of q refines against
+                              floor((1 + eps + delta / (q - i)) ceil(c(V) / k)); 0: none */
 } sclap_ml_params;
 
 /* Multilevel statistics.  Level 0 is the input without its degree-0 nodes. */
@@ -125,6 +150,14 @@ typedef struct sclap_stats {
   double ms_initial;
   double ms_refine;
   double ms_total;         /* wall time of the call */
+  /* iterated cycles: the per-level fields above describe the last cycle;
+     cut and max_block are the returned (best) partition's */
+  int32_t cycles;
+  int32_t best_cycle;
+  int64_t cycle_cut[SCLAP_MAX_CYCLES];
+  int64_t cycle_max_block[SCLAP_MAX_CYCLES];
+  int64_t cycle_visits[SCLAP_MAX_CYCLES];  /* clustering + refinement edge visits of the cycle */
+  int32_t cycle_levels[SCLAP_MAX_CYCLES];
 } sclap_stats;
 
 /* ---- context ------------------------------------------------------------ */
@@ -161,6 +194,30 @@ int sclap_bounds(int64_t total_w, int64_t max_w, int32_t k, int64_t eps_num, int
  * *n_clusters the number of distinct labels; st (may be NULL) the rounds. */
 int sclap_cluster(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_params* p,
                   int32_t* labels_out, int64_t* n_clusters, sclap_round_stats* st, void* stream);
+
+/* Clustering with the Section 4 extensions.
+ * blocks (device, n, or NULL): a partition to respect (Appendix B.1): a node
+ *   only joins clusters that lie inside its own block, so no cluster takes
+ *   nodes of two blocks and contracting keeps every cut edge of the
+ *   partition.  Edge visits count each node's neighbours in its own block.
+ * member (>= 0): the ensemble member whose initial labels are used: member 0
+ *   starts from the node ids, member e >= 1 from (a_e v + b_e) mod n, where
+ *   a_e is the first value from (2654435761 e) mod n upward (cyclically,
+ *   skipping 0) that is coprime to n, and b_e = (2246822519 e) mod n.
+ * p->subrounds: degree-ordered sub-rounds (see sclap_lp_params).
+ * Otherwise as sclap_cluster. */
+int sclap_cluster_ext(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_params* p,
+                      const int32_t* blocks, int32_t member, int32_t* labels_out, int64_t* n_clusters,
+                      sclap_round_stats* st, void* stream);
+
+/* Overlay of two clusterings (Section 4, ensemble clusterings): nodes u, v
+ * share a cluster of the result iff overlay_inout(u) == overlay_inout(v) and
+ * labels(u) == labels(v).  Clusters are numbered 0, 1, ... in the order in
+ * which a pass over the nodes in increasing id first meets them.
+ * overlay_inout and labels: device, n, values in [0, n).  *n_clusters (may be
+ * NULL) receives the cluster count. */
+int sclap_overlay(sclap_ctx* ctx, int64_t n, int32_t* overlay_inout, const int32_t* labels,
+                  int64_t* n_clusters, void* stream);
 
 /* ---- cluster contraction (Section 3.1, Figure 2) -------------------------- */
 
@@ -301,8 +358,12 @@ int sclap_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
  * which bounds everything the job holds at once: the input copy, two
  * weighted copies of the hierarchy, the LP state of a level with the block
  * connections of refinement, its share of the context scratch of the fused
- * rounds, and the temporaries of a contraction. */
-int sclap_server_footprint(const sclap_csr* g, int32_t k, int64_t* input_bytes, int64_t* footprint_bytes);
+ * rounds, and the temporaries of a contraction, plus what the Section 4
+ * extensions of p (may be NULL: none) add: the best partition and the level
+ * without cut edges of iterated cycles, the degree classes of sub-rounds, the
+ * overlay of an ensemble. */
+int sclap_server_footprint(const sclap_csr* g, int32_t k, const sclap_ml_params* p, int64_t* input_bytes,
+                           int64_t* footprint_bytes);
 /* Latency percentiles over completed jobs and throughput since creation. */
 int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double* jobs_per_s,
                        int64_t* completed, int64_t* peak_bytes);

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsclap.so")
 
 MAX_LEVELS = 64
 MAX_ROUNDS = 64
+MAX_CYCLES = 16
 
 OK, EINVAL, ENOTSYM, EOVERFLOW, ENOMEM, EHIP, EBUDGET, ENOTFOUND, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7, -8
 
@@ -39,7 +40,7 @@ class Csr(ctypes.Structure):
 
 class LpParams(ctypes.Structure):
     _fields_ = [("max_rounds", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
-                ("direction_rule", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("direction_rule", ctypes.c_int32), ("subrounds", ctypes.c_int32)]
 
 
 class RoundStats(ctypes.Structure):
@@ -53,7 +54,9 @@ class RoundStats(ctypes.Structure):
 
 class MlParams(ctypes.Structure):
     _fields_ = [("f", ctypes.c_int32), ("lp_rounds", ctypes.c_int32), ("refine_rounds", ctypes.c_int32),
-                ("direction_rule", ctypes.c_int32), ("threshold", ctypes.c_int64)]
+                ("direction_rule", ctypes.c_int32), ("threshold", ctypes.c_int64),
+                ("vcycles", ctypes.c_int32), ("subrounds", ctypes.c_int32), ("ensemble", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("delta_num", ctypes.c_int64), ("delta_den", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -69,6 +72,9 @@ class Stats(ctypes.Structure):
         ("max_block", ctypes.c_int64),
         ("ms_cluster", ctypes.c_double), ("ms_contract", ctypes.c_double), ("ms_initial", ctypes.c_double),
         ("ms_refine", ctypes.c_double), ("ms_total", ctypes.c_double),
+        ("cycles", ctypes.c_int32), ("best_cycle", ctypes.c_int32),
+        ("cycle_cut", ctypes.c_int64 * MAX_CYCLES), ("cycle_max_block", ctypes.c_int64 * MAX_CYCLES),
+        ("cycle_visits", ctypes.c_int64 * MAX_CYCLES), ("cycle_levels", ctypes.c_int32 * MAX_CYCLES),
     ]
 
     def to_dict(self) -> dict:
@@ -88,6 +94,11 @@ class Stats(ctypes.Structure):
             d[f] = getattr(self, f)
         d["ms"] = {"cluster": self.ms_cluster, "contract": self.ms_contract, "initial": self.ms_initial,
                    "refine": self.ms_refine, "total": self.ms_total}
+        c = self.cycles
+        d["cycles"] = {"cycles": c, "best": self.best_cycle, "cut": [self.cycle_cut[i] for i in range(c)],
+                       "max_block": [self.cycle_max_block[i] for i in range(c)],
+                       "visits": [self.cycle_visits[i] for i in range(c)],
+                       "levels": [self.cycle_levels[i] for i in range(c)]}
         return d
 
 
@@ -113,6 +124,9 @@ SIGNATURES = {
     "sclap_validate": (ctypes.c_int, [_vp, _P(Csr), _vp]),
     "sclap_bounds": (ctypes.c_int, [_i64, _i64, _i32, _i64, _i64, _i32, _P(_i64), _P(_i64), _P(_i64)]),
     "sclap_cluster": (ctypes.c_int, [_vp, _P(Csr), _i64, _P(LpParams), _vp, _P(_i64), _P(RoundStats), _vp]),
+    "sclap_cluster_ext": (ctypes.c_int, [_vp, _P(Csr), _i64, _P(LpParams), _vp, _i32, _vp, _P(_i64),
+                                         _P(RoundStats), _vp]),
+    "sclap_overlay": (ctypes.c_int, [_vp, _i64, _vp, _vp, _P(_i64), _vp]),
     "sclap_contract": (ctypes.c_int, [_vp, _P(Csr), _vp, _i32, _vp, _P(_vp), _vp]),
     "sclap_graph_view": (ctypes.c_int, [_vp, _P(Csr)]),
     "sclap_graph_free": (ctypes.c_int, [_vp]),
@@ -131,7 +145,7 @@ SIGNATURES = {
     "sclap_submit": (ctypes.c_int, [_vp, _P(Job), _P(_u64)]),
     "sclap_poll": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
     "sclap_wait": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
-    "sclap_server_footprint": (ctypes.c_int, [_P(Csr), _i32, _P(_i64), _P(_i64)]),
+    "sclap_server_footprint": (ctypes.c_int, [_P(Csr), _i32, _P(MlParams), _P(_i64), _P(_i64)]),
     "sclap_server_stats": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double),
                                           _P(_i64), _P(_i64)]),
     "sclap_server_destroy": (ctypes.c_int, [_vp]),
@@ -327,7 +341,8 @@ def bounds(total_w: int, max_w: int, k: int, eps: tuple[int, int] = (3, 100), f:
     return lmax.value, W.value, U.value
 
 
-def server_footprint(n: int, m: int, k: int, weighted_edges: bool = False, nw_bytes: int = 0) -> tuple[int, int]:
+def server_footprint(n: int, m: int, k: int, weighted_edges: bool = False, nw_bytes: int = 0,
+                     params: Optional[MlParams] = None) -> tuple[int, int]:
     """(input bytes, footprint bytes) a server charges for a job on a graph
     of n nodes and m stored entries (host math only)."""
     c = Csr()
@@ -336,7 +351,8 @@ def server_footprint(n: int, m: int, k: int, weighted_edges: bool = False, nw_by
     c.nw = 1 if nw_bytes else None
     c.nw_bytes = nw_bytes
     inp, fp = ctypes.c_int64(), ctypes.c_int64()
-    _check(load_library().sclap_server_footprint(ctypes.byref(c), k, ctypes.byref(inp), ctypes.byref(fp)))
+    _check(load_library().sclap_server_footprint(ctypes.byref(c), k, None if params is None else ctypes.byref(params),
+                                                 ctypes.byref(inp), ctypes.byref(fp)))
     return inp.value, fp.value
 
 
@@ -347,17 +363,33 @@ def validate(ctx: Context, g: DeviceGraph, stream=None) -> int:
 
 
 def cluster(ctx: Context, g: DeviceGraph, U: int, max_rounds: int = 10, stop_rule: int = 0,
-            direction_rule: int = 1, stream=None, labels_out: Optional[torch.Tensor] = None):
-    """Size-constrained label propagation; returns (labels, n_clusters, round stats)."""
+            direction_rule: int = 1, stream=None, labels_out: Optional[torch.Tensor] = None, subrounds: int = 0,
+            blocks: Optional[torch.Tensor] = None, member: int = 0):
+    """Size-constrained label propagation; returns (labels, n_clusters, round
+    stats).  blocks / member / subrounds select the Section 4 extensions
+    (sclap_cluster_ext); without them sclap_cluster runs."""
     labels = labels_out if labels_out is not None else torch.empty(max(g.n, 1), dtype=torch.int32,
                                                                      device=g.row_ptr.device)
-    p = LpParams(max_rounds, stop_rule, direction_rule, 0)
+    p = LpParams(max_rounds, stop_rule, direction_rule, subrounds)
     nc = ctypes.c_int64()
     rs = RoundStats()
     c = g.csr()
-    _check(ctx.lib.sclap_cluster(ctx.h, ctypes.byref(c), U, ctypes.byref(p), _ptr(labels), ctypes.byref(nc),
-                                 ctypes.byref(rs), _stream(stream)))
+    if blocks is None and member == 0 and subrounds <= 1:
+        _check(ctx.lib.sclap_cluster(ctx.h, ctypes.byref(c), U, ctypes.byref(p), _ptr(labels), ctypes.byref(nc),
+                                     ctypes.byref(rs), _stream(stream)))
+    else:
+        _check(ctx.lib.sclap_cluster_ext(ctx.h, ctypes.byref(c), U, ctypes.byref(p), _ptr(blocks), member,
+                                         _ptr(labels), ctypes.byref(nc), ctypes.byref(rs), _stream(stream)))
     return labels[:g.n], nc.value, rs.to_dict()
+
+
+def overlay(ctx: Context, overlay_inout: torch.Tensor, labels: torch.Tensor, stream=None) -> int:
+    """Overlay of two clusterings in place on overlay_inout (numbered by first
+    occurrence); returns the cluster count."""
+    nc = ctypes.c_int64()
+    _check(ctx.lib.sclap_overlay(ctx.h, int(overlay_inout.shape[0]), _ptr(overlay_inout), _ptr(labels),
+                                 ctypes.byref(nc), _stream(stream)))
+    return nc.value
 
 
 def contract(ctx: Context, g: DeviceGraph, labels: torch.Tensor, drop_isolated: bool = False, stream=None):
@@ -407,16 +439,20 @@ def cut_noalloc(g, part: torch.Tensor, k: int, cut_out: torch.Tensor, block_w_ou
 
 
 def ml_params(f: int = 14, lp_rounds: int = 10, refine_rounds: int = 10, direction_rule: int = 1,
-              threshold: int = 0) -> MlParams:
-    return MlParams(f, lp_rounds, refine_rounds, direction_rule, threshold)
+              threshold: int = 0, vcycles: int = 0, subrounds: int = 0, ensemble: int = 0,
+              delta: tuple[int, int] = (0, 1)) -> MlParams:
+    return MlParams(f, lp_rounds, refine_rounds, direction_rule, threshold, vcycles, subrounds, ensemble, 0,
+                    delta[0], delta[1])
 
 
 def partition(ctx: Context, g: DeviceGraph, k: int, eps: tuple[int, int] = (3, 100), f: int = 14,
               lp_rounds: int = 10, refine_rounds: int = 10, direction_rule: int = 1, threshold: int = 0,
-              stream=None, part_out: Optional[torch.Tensor] = None):
-    """Multilevel partition; returns (part tensor, stats dict)."""
+              stream=None, part_out: Optional[torch.Tensor] = None, vcycles: int = 0, subrounds: int = 0,
+              ensemble: int = 0, delta: tuple[int, int] = (0, 1)):
+    """Multilevel partition; returns (part tensor, stats dict).  vcycles,
+    subrounds, ensemble and delta select the Section 4 extensions."""
     part = part_out if part_out is not None else torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
-    p = ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold)
+    p = ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold, vcycles, subrounds, ensemble, delta)
     st = Stats()
     c = g.csr()
     _check(ctx.lib.sclap_partition(ctx.h, ctypes.byref(c), k, eps[0], eps[1], ctypes.byref(p), _ptr(part),
@@ -426,7 +462,8 @@ def partition(ctx: Context, g: DeviceGraph, k: int, eps: tuple[int, int] = (3, 1
 
 def partition_batch(ctx: Context, graphs: Sequence[DeviceGraph], ks: Sequence[int], eps: tuple[int, int] = (3, 100),
                     f: int = 14, lp_rounds: int = 10, refine_rounds: int = 10, direction_rule: int = 1,
-                    threshold: int = 0, stream=None, parts_out: Optional[list] = None):
+                    threshold: int = 0, stream=None, parts_out: Optional[list] = None, vcycles: int = 0,
+                    subrounds: int = 0, ensemble: int = 0, delta: tuple[int, int] = (0, 1)):
     """Partition many graphs in fused launches; returns (parts, stats list)."""
     G = len(graphs)
     csrs = (Csr * max(G, 1))(*[g.csr() for g in graphs])
@@ -435,7 +472,7 @@ def partition_batch(ctx: Context, graphs: Sequence[DeviceGraph], ks: Sequence[in
         torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in graphs]
     pptr = (ctypes.c_void_p * max(G, 1))(*[p.data_ptr() for p in parts])
     sts = (Stats * max(G, 1))()
-    p = ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold)
+    p = ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold, vcycles, subrounds, ensemble, delta)
     _check(ctx.lib.sclap_partition_batch(ctx.h, G, csrs, karr, eps[0], eps[1], ctypes.byref(p), pptr, sts,
                                          _stream(stream)))
     return [parts[i][:graphs[i].n] for i in range(G)], [sts[i].to_dict() for i in range(G)]
@@ -453,9 +490,11 @@ class Server:
 
     def submit(self, g: DeviceGraph, k: int, part_out: torch.Tensor, eps: tuple[int, int] = (3, 100),
                f: int = 14, lp_rounds: int = 10, refine_rounds: int = 10, direction_rule: int = 1,
-               threshold: int = 0) -> int:
-        job = Job(g.csr(), k, 0, eps[0], eps[1], ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold),
-                  _ptr(part_out))
+               threshold: int = 0, vcycles: int = 0, subrounds: int = 0, ensemble: int = 0,
+               delta: tuple[int, int] = (0, 1)) -> int:
+        job = Job(g.csr(), k, 0, eps[0], eps[1],
+                  ml_params(f, lp_rounds, refine_rounds, direction_rule, threshold, vcycles, subrounds, ensemble,
+                            delta), _ptr(part_out))
         # the server copies the graph on a stream of its own
         torch.cuda.current_stream().synchronize()
         t = ctypes.c_uint64()

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "ext.h"
 
 namespace sclap {
 const char* last_error_cstr();
@@ -40,6 +41,7 @@ static int check_lp(const sclap_lp_params* p) {
   if (!p) return fail(SCLAP_EINVAL, "params are NULL");
   if (p->max_rounds < 1 || p->max_rounds > SCLAP_MAX_ROUNDS) return fail(SCLAP_EINVAL, "max_rounds out of range");
   if (p->stop_rule != 0 && p->stop_rule != 1) return fail(SCLAP_EINVAL, "stop_rule must be 0 or 1");
+  if (p->subrounds < 0 || p->subrounds > SCLAP_MAX_SUBROUNDS) return fail(SCLAP_EINVAL, "subrounds out of range");
   return SCLAP_OK;
 }
 
@@ -96,8 +98,20 @@ int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t e
   if (p->lp_rounds < 1 || p->lp_rounds > SCLAP_MAX_ROUNDS || p->refine_rounds < 0 ||
       p->refine_rounds > SCLAP_MAX_ROUNDS)
     return fail(SCLAP_EINVAL, "rounds out of range");
+  if (p->vcycles < 0 || p->vcycles > SCLAP_MAX_CYCLES) return fail(SCLAP_EINVAL, "vcycles out of range");
+  if (p->subrounds < 0 || p->subrounds > SCLAP_MAX_SUBROUNDS) return fail(SCLAP_EINVAL, "subrounds out of range");
+  if (p->ensemble < 0 || p->ensemble > SCLAP_MAX_ENSEMBLE) return fail(SCLAP_EINVAL, "ensemble out of range");
+  if (p->delta_num < 0 || (p->delta_num > 0 && p->delta_den < 1))
+    return fail(SCLAP_EINVAL, "extra imbalance: delta_num >= 0 and delta_den >= 1 required");
   if (g->n > 0 && !part_out) return fail(SCLAP_EINVAL, "part_out is NULL");
   j->t_start = now_ms();
+  j->vcycles = std::max<int32_t>(p->vcycles, 1);
+  j->subrounds = p->subrounds;
+  j->members = std::max<int32_t>(p->ensemble, 1);
+  j->delta_num = p->delta_num;
+  j->delta_den = p->delta_num > 0 ? p->delta_den : 1;
+  j->eps_num = eps_num;
+  j->eps_den = eps_den;
   j->kind = JOB_PARTITION;
   j->k = k;
   j->lp_rounds = p->lp_rounds;
@@ -118,6 +132,9 @@ int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t e
     j->st.threshold = j->threshold;
     j->st.levels = 1;
     j->st.rounds_r[0] = std::min<int32_t>(j->ref_rounds, 2);
+    // every cycle of an empty graph is the same: the first is kept
+    j->st.cycles = 1;
+    j->st.cycle_levels[0] = 1;
     j->st.ms_total = now_ms() - j->t_start;
     j->stage = ST_DONE;
     return SCLAP_OK;
@@ -244,8 +261,40 @@ int sclap_validate(sclap_ctx* ctx, const sclap_csr* g, void* stream) {
   return SCLAP_OK;
 }
 
+static int cluster_impl(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_params* p,
+                        const int32_t* blocks, int32_t member, int32_t* labels_out, int64_t* n_clusters,
+                        sclap_round_stats* rs, void* stream);
+
 int sclap_cluster(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_params* p, int32_t* labels_out,
                   int64_t* n_clusters, sclap_round_stats* rs, void* stream) {
+  return cluster_impl(ctx, g, U, p, nullptr, 0, labels_out, n_clusters, rs, stream);
+}
+
+int sclap_cluster_ext(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_params* p,
+                      const int32_t* blocks, int32_t member, int32_t* labels_out, int64_t* n_clusters,
+                      sclap_round_stats* rs, void* stream) {
+  if (member < 0) return fail(SCLAP_EINVAL, "member must be >= 0");
+  return cluster_impl(ctx, g, U, p, blocks, member, labels_out, n_clusters, rs, stream);
+}
+
+int sclap_overlay(sclap_ctx* ctx, int64_t n, int32_t* overlay_inout, const int32_t* labels, int64_t* n_clusters,
+                  void* stream) {
+  if (!ctx) return fail(SCLAP_EINVAL, "ctx is NULL");
+  if (n < 0 || n >= ((int64_t)1 << 31)) return fail(SCLAP_EINVAL, "n out of range");
+  if (n > 0 && (!overlay_inout || !labels)) return fail(SCLAP_EINVAL, "NULL labels");
+  Ctx* c = &ctx->c;
+  CtxScope scope(c);
+  hipStream_t st = as_stream(stream);
+  int64_t cnt = 0;
+  int rc = overlay_labels(c, overlay_inout, labels, n, &cnt, st);
+  if (rc == SCLAP_OK && n_clusters) *n_clusters = cnt;
+  (void)hipStreamSynchronize(st);
+  return rc;
+}
+
+static int cluster_impl(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_params* p,
+                        const int32_t* blocks, int32_t member, int32_t* labels_out, int64_t* n_clusters,
+                        sclap_round_stats* rs, void* stream) {
   if (!ctx) return fail(SCLAP_EINVAL, "ctx is NULL");
   SCLAP_TRY(check_csr(g));
   SCLAP_TRY(check_lp(p));
@@ -271,10 +320,13 @@ int sclap_cluster(sclap_ctx* ctx, const sclap_csr* g, int64_t U, const sclap_lp_
   j.lp_rounds = p->max_rounds;
   j.stop_rule = p->stop_rule;
   j.dir_rule = p->direction_rule;
+  j.subrounds = p->subrounds;
+  j.member = member;
   j.part_out = labels_out;
   j.t_start = now_ms();
   std::memset(&j.rst, 0, sizeof(j.rst));
   int rc = job_set_input(c, &j, g, st);
+  j.lv[0].blk = const_cast<int32_t*>(blocks);  // the caller's; not owned
   if (rc == SCLAP_OK) rc = level_totals(c, &j, &j.lv[0], nullptr, nullptr, st);
   if (rc == SCLAP_OK) rc = job_begin_cluster(c, &j, st);
   if (rc == SCLAP_OK) {

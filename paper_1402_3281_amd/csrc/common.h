@@ -70,6 +70,8 @@ struct DevSlot {
   int32_t* conn;          // refine: n x conn_k block connections conn(v, b), or nullptr
   int32_t last_round;     // no LP round of this stage follows (its moves need no bookkeeping)
   int32_t ident;          // first clustering round of a level: lab(v) = v, so a neighbour's label is its id
+  int32_t sub;            // degree-ordered sub-rounds: the degree class rated in this step
+  const uint8_t* cls;     // ... the degree class of every node, or nullptr (every node is rated)
   uint32_t* err;          // set nonzero when an LDS hash table of the round fills up (the round fails)
 };
 

@@ -31,6 +31,8 @@ struct Level {
   int32_t* own_ew = nullptr;
   int64_t* own_nw = nullptr;
   int32_t* coarse_of = nullptr;  // n: map to the next coarser level
+  int32_t* blk = nullptr;        // n: blocks of the partition the clustering respects, or nullptr
+  bool blk_owned = false;
   int rows_sorted = 0;
   int64_t n_active = 0;          // nodes of degree > 0
   int64_t max_deg = 0;
@@ -71,6 +73,23 @@ struct Job {
   int32_t* conn = nullptr;         // refine: n x k block connections (k <= kConnMaxK)
   bool conn_stale = false;         // the last round's moves were not added to conn
   int64_t nlabels = 0;
+  // extensions (Section 4)
+  int32_t vcycles = 1, cycle = 0;        // iterated multilevel cycles; the current one
+  int32_t subrounds = 0, sub = 0;        // degree-ordered sub-rounds per round; the current one
+  int64_t sub_moved = 0, sub_visits = 0; // sums over the sub-rounds of the current round
+  int32_t members = 1, member = 0;       // ensemble clusterings per level; the current one
+  int64_t delta_num = 0, delta_den = 1;  // extra imbalance on coarse levels of the first cycle
+  int64_t eps_num = 3, eps_den = 100;
+  int64_t lmax_cur = 0;                  // refinement bound of the level being refined
+  uint8_t* cls = nullptr;                // degree classes of the level being clustered (subrounds >= 2)
+  Level flt;                             // that level without the cut edges of its blocks
+  bool flt_on = false;
+  int32_t* ovl = nullptr;                // overlay of the members clustered so far
+  bool wt_clusters = true;               // Wt holds the weights of the clusters of lab
+  int32_t* best = nullptr;               // best partition of the input so far (several cycles)
+  int64_t best_cut = 0, best_over = 0;
+  int32_t best_cycle = 0;
+  int64_t lp_gen = 0;                    // changes whenever the rated node set may change
   // outputs
   int32_t* part_out = nullptr;     // caller buffer (level-0 blocks / labels)
   sclap_stats st{};
@@ -149,6 +168,8 @@ int job_begin_cluster(Ctx* c, Job* j, hipStream_t st);
 // Start refinement on level cur with blocks in `part` (owned by the job).
 int job_begin_refine(Ctx* c, Job* j, int32_t* part, bool owned, hipStream_t st);
 void job_release_lp(Job* j, hipStream_t st, bool keep_lab);
+// Frees the respect graph and degree classes of the level being clustered.
+void job_release_ext(Job* j, hipStream_t st);
 void job_release_levels(Job* j, hipStream_t st);
 
 // One fused LP round over the given jobs (all in ST_COARSEN or ST_REFINE).
@@ -173,7 +194,7 @@ constexpr int64_t kContractBytesPerEntry = 48;
 // Served jobs: device bytes of a job's input copy, and an upper bound of
 // everything the job holds at once on the device (see server.hip).
 int64_t input_bytes_of(const sclap_csr& g);
-int64_t footprint_of(const sclap_csr& g, int32_t k);
+int64_t footprint_of(const sclap_csr& g, int32_t k, const sclap_ml_params* p);
 // Contract level cur of a job into level cur + 1.
 int contract_level(Ctx* c, Job* j, int i, int drop_isolated, hipStream_t st);
 // Fused initial partition of the jobs' current (coarsest) levels.

@@ -15,6 +15,7 @@
 #include <unordered_map>
 
 #include "engine.h"
+#include "ext.h"
 
 namespace sclap {
 
@@ -253,22 +254,48 @@ static void level_free(Level& L, hipStream_t st) {
   dfree(L.own_ew, st);
   dfree(L.own_nw, st);
   dfree(L.coarse_of, st);
+  if (L.blk_owned) dfree(L.blk, st);
   L.own_rp = nullptr;
   L.own_col = nullptr;
   L.own_ew = nullptr;
   L.own_nw = nullptr;
   L.coarse_of = nullptr;
+  L.blk = nullptr;
+  L.blk_owned = false;
+}
+
+void job_release_ext(Job* j, hipStream_t st) {
+  if (j->flt_on) level_free(j->flt, st);
+  j->flt = Level();
+  j->flt_on = false;
+  dfree(j->cls, st);
+  j->cls = nullptr;
 }
 
 void job_release_levels(Job* j, hipStream_t st) {
   for (auto& L : j->lv) level_free(L, st);
+  job_release_ext(j, st);
+  dfree(j->ovl, st);
+  j->ovl = nullptr;
+  dfree(j->best, st);
+  j->best = nullptr;
 }
 
 int job_begin_cluster(Ctx* c, Job* j, hipStream_t st) {
-  (void)c;
   Level& L = j->lv[j->cur];
   const int64_t n = L.n;
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  if (L.blk && !j->flt_on) {
+    // clustering that respects the level's blocks rates the level without
+    // its cut edges (built once per level, shared by the ensemble members)
+    SCLAP_TRY(build_respect_graph(c, L, L.blk, &j->flt, st));
+    j->flt_on = true;
+    SCLAP_TRY(level_totals(c, j, &j->flt, nullptr, nullptr, st));
+  }
+  if (j->subrounds > 1 && !j->cls) {
+    SCLAP_TRY(dalloc_t(&j->cls, nn, st));
+    SCLAP_TRY(degree_classes(L.rp, n, j->subrounds, j->cls, st));
+  }
   if (j->kind == JOB_CLUSTER) {
     j->lab = j->part_out;
     j->lab_owned = false;
@@ -281,9 +308,15 @@ int job_begin_cluster(Ctx* c, Job* j, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&j->Wt, nn, st));
   SCLAP_TRY(dalloc_t(&j->inc, nn, st));
   SCLAP_TRY(fill_i64(j->inc, n, 0, st));
-  SCLAP_TRY(init_cluster(j->lab, j->desire, j->Wt, L.nw, n, st));
+  if (j->member == 0) SCLAP_TRY(init_cluster(j->lab, j->desire, j->Wt, L.nw, n, st));
+  else SCLAP_TRY(begin_member_labels(c, j, st));
   j->nlabels = n;
   j->round = 1;
+  j->sub = 0;
+  j->sub_moved = 0;
+  j->sub_visits = 0;
+  j->lp_gen += 1;
+  j->wt_clusters = true;
   j->moved_prev = 0;
   j->n_stop = (j->cur == 0 && j->kind == JOB_PARTITION) ? L.n_active : L.n;
   j->stage = ST_COARSEN;
@@ -315,8 +348,14 @@ int job_begin_refine(Ctx* c, Job* j, int32_t* part, bool owned, hipStream_t st) 
   SCLAP_TRY(fill_u8(j->fcur, n, 0, st));
   SCLAP_TRY(copy_i32(part, j->desire, n, st));
   SCLAP_TRY(block_weights(part, L.nw, n, j->k, j->Wt, st));
+  // extra imbalance on the coarse levels of the first cycle (Section 4)
+  j->lmax_cur = j->kind == JOB_PARTITION && j->cycle == 0
+                    ? level_lmax(j->total_w, j->k, j->eps_num, j->eps_den, j->delta_num, j->delta_den,
+                                 j->st.levels, j->cur, j->lmax)
+                    : j->lmax;
   j->nlabels = j->k;
   j->round = 1;
+  j->lp_gen += 1;
   j->zero_streak = 0;
   j->stage = ST_REFINE;
   return SCLAP_OK;
@@ -340,7 +379,9 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   int tile_kmax = 0;
   for (int s = 0; s < ns; ++s) {
     Job* j = jobs[s];
-    const Level& L = j->lv[j->cur];
+    const bool refine = j->stage == ST_REFINE;
+    // a clustering that respects a partition rates the level without its cut edges
+    const Level& L = !refine && j->flt_on ? j->flt : j->lv[j->cur];
     DevSlot& d = c->pin_slots[s];
     std::memset(&d, 0, sizeof(d));
     d.rp = L.rp;
@@ -362,11 +403,14 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.tbase = T_bin;
     d.nlabels = j->nlabels;
     d.lbase = Lt;
-    const bool refine = j->stage == ST_REFINE;
-    d.cap = refine ? j->lmax : j->U;
+    d.cap = refine ? j->lmax_cur : j->U;
     d.round = j->round;
     d.mode = refine ? MODE_REFINE : MODE_CLUSTER;
-    d.ident = !refine && j->round == 1 ? 1 : 0;  // clustering starts from lab(v) = v
+    // clustering starts from lab(v) = v (ensemble member 0, before any move)
+    d.ident = !refine && j->round == 1 && j->sub == 0 && j->member == 0 ? 1 : 0;
+    // degree-ordered sub-rounds rate the nodes of one degree class
+    d.cls = !refine && j->subrounds > 1 ? j->cls : nullptr;
+    d.sub = j->sub;
     d.dir_rule = j->dir_rule;
     d.use_flags = refine && j->round > 1;
     d.conn = refine ? j->conn : nullptr;
@@ -458,7 +502,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   std::vector<std::pair<const void*, int>> sig;
   bool all_cluster = true;
   for (int s = 0; s < ns; ++s) {
-    sig.emplace_back(jobs[s], jobs[s]->cur);
+    sig.emplace_back(jobs[s], (int)jobs[s]->lp_gen);
     all_cluster = all_cluster && jobs[s]->stage == ST_COARSEN;
   }
   const bool reuse_bins = all_cluster && c->bin_sig_valid && sig == c->bin_sig && c->bin_cap_used == bin_cap;
@@ -650,8 +694,11 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   // move the slot counters to the front of the staging buffer; a clustering
   // round rates every node of degree > 0, so its edge visits are the level's m
   std::memmove(c->pin, sctr, (size_t)ns * CTR_N * sizeof(int64_t));
-  for (int s = 0; s < ns; ++s)
-    if (jobs[s]->stage == ST_COARSEN) c->pin[(size_t)s * CTR_N + CTR_VISITS] = jobs[s]->lv[jobs[s]->cur].m;
+  for (int s = 0; s < ns; ++s) {
+    const Job* j = jobs[s];
+    if (j->stage == ST_COARSEN && j->subrounds <= 1)
+      c->pin[(size_t)s * CTR_N + CTR_VISITS] = j->flt_on ? j->flt.m : j->lv[j->cur].m;
+  }
   return SCLAP_OK;
 }
 
@@ -684,7 +731,7 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&F.coarse_of, nn, st));
   SCLAP_TRY(dalloc_t(&C.own_nw, (size_t)std::max<int64_t>(nc, 1), st));
   // after a clustering of this level, the label weights are the cluster weights
-  const int64_t* Wl = (j->Wt && j->nlabels == n && j->kind == JOB_PARTITION) ? j->Wt : nullptr;
+  const int64_t* Wl = (j->wt_clusters && j->Wt && j->nlabels == n && j->kind == JOB_PARTITION) ? j->Wt : nullptr;
   SCLAP_TRY(contract_coarse_of(j->lab, F.rp, F.nw, n, drop, cid, F.coarse_of, C.own_nw, nc, used, Wl, st));
   dfree(used, st);
   dfree(cid, st);
@@ -797,6 +844,12 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   C.col = C.own_col;
   C.ew = C.own_ew;
   C.nw = C.own_nw;
+  if (F.blk) {
+    // a coarse node takes the block its members share
+    SCLAP_TRY(dalloc_t(&C.blk, (size_t)std::max<int64_t>(nc, 1), st));
+    C.blk_owned = true;
+    SCLAP_TRY(blocks_up(F.coarse_of, F.blk, n, C.blk, st));
+  }
   j->lv.push_back(C);
   if (overflow) return fail(SCLAP_EOVERFLOW, "coarse edge weight exceeds int32");
   return SCLAP_OK;
@@ -1012,10 +1065,57 @@ static int after_refine_level(Ctx* c, Job* j, hipStream_t st) {
   return job_begin_refine(c, j, pf, owned, st);
 }
 
-static int start_ip_or_refine(Ctx* c, Job* j, std::vector<Job*>& ipq) {
-  (void)c;
+// Later cycles (Section 4, iterated multilevel algorithms): the coarsest
+// level keeps the blocks of the cycle's start partition (same cut and block
+// weights), with no initial partitioning.
+static int start_from_blocks(Ctx* c, Job* j, hipStream_t st) {
+  Level& L = j->lv[j->cur];
+  int32_t* part = nullptr;
+  bool owned = false;
+  SCLAP_TRY(alloc_part(j, j->cur, &part, &owned, st));
+  SCLAP_TRY(copy_i32(L.blk, part, L.n, st));
+  // on the input level the degree-0 nodes wait for their placement
+  if (j->cur == 0) SCLAP_TRY(clear_isolated(L.rp, L.n, part, st));
+  j->st.ip_cut = read_cut(c, L, part, st);
+  if (j->ref_rounds > 0) return job_begin_refine(c, j, part, owned, st);
+  j->lab = part;
+  j->lab_owned = owned;
+  return after_refine_level(c, j, st);
+}
+
+static int start_ip_or_refine(Ctx* c, Job* j, std::vector<Job*>& ipq, hipStream_t st) {
+  if (j->cycle > 0) return start_from_blocks(c, j, st);
   j->stage = ST_IP;
   ipq.push_back(j);
+  return SCLAP_OK;
+}
+
+// After a clustering of the current level: the next ensemble member, or the
+// contraction of the members' overlay (Section 4, ensemble clusterings).
+static int after_member(Ctx* c, Job* j, hipStream_t st) {
+  if (j->members <= 1) {
+    j->stage = ST_CONTRACT;
+    return SCLAP_OK;
+  }
+  const int64_t n = j->lv[j->cur].n;
+  if (j->member == 0) {
+    j->ovl = j->lab;  // the overlay starts as the first member's clustering
+    j->lab = nullptr;
+    j->lab_owned = false;
+  } else {
+    SCLAP_TRY(overlay_labels(c, j->ovl, j->lab, n, nullptr, st));
+  }
+  job_release_lp(j, st, false);
+  if (j->member + 1 < j->members) {
+    j->member += 1;
+    return job_begin_cluster(c, j, st);
+  }
+  j->lab = j->ovl;
+  j->lab_owned = true;
+  j->ovl = nullptr;
+  j->wt_clusters = false;  // the overlay's cluster weights are summed by the contraction
+  j->member = 0;
+  j->stage = ST_CONTRACT;
   return SCLAP_OK;
 }
 
@@ -1023,6 +1123,7 @@ static int after_contract(Ctx* c, Job* j, std::vector<Job*>& ipq, hipStream_t st
   // level cur was just contracted into cur + 1
   const int64_t n_prev = j->cur == 0 ? j->lv[0].n_active : j->lv[j->cur].n;
   job_release_lp(j, st, false);
+  job_release_ext(j, st);
   j->cur += 1;
   Level& L = j->lv[j->cur];
   SCLAP_TRY(level_totals(c, j, &L, nullptr, nullptr, st));
@@ -1031,7 +1132,78 @@ static int after_contract(Ctx* c, Job* j, std::vector<Job*>& ipq, hipStream_t st
   j->st.m_level[j->cur] = L.m;
   const bool stall = 20 * (n_prev - L.n) < n_prev;
   if (L.n > j->threshold && !stall && j->cur + 1 < SCLAP_MAX_LEVELS) return job_begin_cluster(c, j, st);
-  return start_ip_or_refine(c, j, ipq);
+  return start_ip_or_refine(c, j, ipq, st);
+}
+
+// Iterated multilevel algorithms (Section 4; Appendix B.1): the next cycle
+// starts from the best partition so far, clustering every level within its
+// blocks.  Per-level statistics describe the last cycle.
+static int begin_next_cycle(Ctx* c, Job* j, hipStream_t st) {
+  j->cycle += 1;
+  sclap_stats& S = j->st;
+  S.levels = 1;
+  for (int i = 1; i < SCLAP_MAX_LEVELS; ++i) {
+    S.n_level[i] = 0;
+    S.m_level[i] = 0;
+  }
+  std::memset(S.rounds_c, 0, sizeof(S.rounds_c));
+  std::memset(S.rounds_r, 0, sizeof(S.rounds_r));
+  std::memset(S.moved_c, 0, sizeof(S.moved_c));
+  std::memset(S.moved_r, 0, sizeof(S.moved_r));
+  std::memset(S.visits_c, 0, sizeof(S.visits_c));
+  std::memset(S.visits_r, 0, sizeof(S.visits_r));
+  S.ip_cut = 0;
+  // the coarse levels of the last cycle are gone; level 0 is contracted anew
+  for (size_t i = 1; i < j->lv.size(); ++i) level_free(j->lv[i], st);
+  j->lv.resize(1);
+  Level& L0 = j->lv[0];
+  dfree(L0.coarse_of, st);
+  L0.coarse_of = nullptr;
+  L0.blk = j->best;
+  L0.blk_owned = false;
+  j->cur = 0;
+  j->member = 0;
+  if (L0.n_active > j->threshold) return job_begin_cluster(c, j, st);
+  return start_from_blocks(c, j, st);
+}
+
+// After the cut of a cycle's partition (part_out): keep it if it is the best
+// so far (blocks within L_max first, then the smaller cut; ties keep the
+// earlier cycle), then start the next cycle or finish with the best.
+static int after_cycle(Ctx* c, Job* j, hipStream_t st) {
+  sclap_stats& S = j->st;
+  const int cy = j->cycle;
+  int64_t vis = 0;
+  for (int i = 0; i < S.levels; ++i) vis += S.visits_c[i] + S.visits_r[i];
+  const int64_t cut = S.cut, mb = S.max_block;
+  if (cy < SCLAP_MAX_CYCLES) {
+    S.cycle_cut[cy] = cut;
+    S.cycle_max_block[cy] = mb;
+    S.cycle_visits[cy] = vis;
+    S.cycle_levels[cy] = S.levels;
+  }
+  S.cycles = cy + 1;
+  const int64_t over = mb > j->lmax ? 1 : 0;
+  if (cy == 0 || over < j->best_over || (over == j->best_over && cut < j->best_cut)) {
+    j->best_over = over;
+    j->best_cut = cut;
+    j->best_cycle = cy;
+    if (j->vcycles > 1) {
+      const int64_t n = j->lv[0].n;
+      if (!j->best) SCLAP_TRY(dalloc_t(&j->best, (size_t)std::max<int64_t>(n, 1), st));
+      SCLAP_TRY(copy_i32(j->part_out, j->best, n, st));
+    }
+  }
+  S.best_cycle = j->best_cycle;
+  S.cut = j->best_cut;
+  S.max_block = S.cycle_max_block[j->best_cycle];
+  if (cy + 1 < j->vcycles) return begin_next_cycle(c, j, st);
+  if (j->best_cycle != cy) SCLAP_TRY(copy_i32(j->best, j->part_out, j->lv[0].n, st));
+  dfree(j->best, st);
+  j->best = nullptr;
+  j->lv[0].blk = nullptr;
+  j->stage = ST_DONE;
+  return SCLAP_OK;
 }
 
 // One step of the executor: one fused LP round over every job at an LP
@@ -1057,19 +1229,41 @@ int step_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st, bool* all_done_ou
       const int r = j->round;
       if (j->stage == ST_COARSEN) {
         j->st.ms_cluster += dt;
-        j->st.moved_c[j->cur][r - 1] = moved;
-        j->st.visits_c[j->cur] += visits;
-        j->rst.moved[r - 1] = moved;
-        j->rst.visits += visits;
         j->rst.ms += dt;
+        int64_t mv = moved, vs = visits;
+        if (j->subrounds > 1) {
+          // a round is its sub-rounds, one degree class each (Section 4 node order)
+          j->sub_moved += moved;
+          j->sub_visits += visits;
+          j->lp_gen += 1;
+          if (j->sub + 1 < j->subrounds) {
+            j->sub += 1;
+            continue;
+          }
+          mv = j->sub_moved;
+          vs = j->sub_visits;
+          j->sub = 0;
+          j->sub_moved = 0;
+          j->sub_visits = 0;
+        }
+        // ensemble members add up per round (moves) and per level (visits)
+        j->st.moved_c[j->cur][r - 1] += mv;
+        j->st.visits_c[j->cur] += vs;
+        j->rst.moved[r - 1] = mv;
+        j->rst.visits += vs;
         bool done = r >= j->lp_rounds;
-        if (j->stop_rule == 1 && r >= 2 && 20 * (moved + j->moved_prev) < j->n_stop) done = true;
-        j->moved_prev = moved;
+        if (j->stop_rule == 1 && r >= 2 && 20 * (mv + j->moved_prev) < j->n_stop) done = true;
+        j->moved_prev = mv;
         if (done) {
-          j->st.rounds_c[j->cur] = r;
+          j->st.rounds_c[j->cur] = std::max(j->st.rounds_c[j->cur], r);
           j->rst.rounds = r;
-          j->stage = j->kind == JOB_CLUSTER ? ST_DONE : ST_CONTRACT;
-          if (j->kind == JOB_CLUSTER) job_release_lp(j, st, true);
+          if (j->kind == JOB_CLUSTER) {
+            j->stage = ST_DONE;
+            job_release_lp(j, st, true);
+            job_release_ext(j, st);
+          } else {
+            SCLAP_TRY(after_member(c, j, st));
+          }
         } else {
           j->round = r + 1;
         }
@@ -1140,7 +1334,7 @@ int step_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st, bool* all_done_ou
   for (Job* j : jobs) {
     if (j->stage == ST_FINISH) {
       SCLAP_TRY(finish_partition(c, j, st));
-      j->stage = ST_DONE;
+      SCLAP_TRY(after_cycle(c, j, st));
     }
     if (j->stage == ST_DONE && j->st.ms_total == 0) j->st.ms_total = now_ms() - j->t_start;
     if (j->stage != ST_DONE && j->stage != ST_ERROR) all_done = false;

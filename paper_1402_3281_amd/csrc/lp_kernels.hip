@@ -84,7 +84,8 @@ struct BinOf {
 template <bool ONE>
 __device__ __forceinline__ BinOf bin_node(const DevSlot& sl, int64_t v) {
   BinOf r{false, 0, 0, 0, v};
-  if (v < sl.n && sl.round > 0 && (!sl.use_flags || gld(sl.flag_cur, v))) {
+  if (v < sl.n && sl.round > 0 && (!sl.use_flags || gld(sl.flag_cur, v)) &&
+      (!sl.cls || (int32_t)gld(sl.cls, v) == sl.sub)) {
     r.e0 = gld(sl.rp, v);
     r.d = gld(sl.rp, v + 1) - r.e0;
     r.take = r.d > 0;

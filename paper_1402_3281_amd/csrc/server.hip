@@ -79,14 +79,23 @@ int64_t input_bytes_of(const sclap_csr& g) {
 //     pooled (label, sum) pairs of hub rows);
 //   - the temporaries of a contraction: kContractBytesPerEntry per stored
 //     entry of the contracted level (key cache, two key arrays, sums, sort
-//     space, mirror) and the initial-partition scratch (16 B per node).
-int64_t footprint_of(const sclap_csr& g, int32_t k) {
+//     space, mirror) and the initial-partition scratch (16 B per node);
+//   - with the Section 4 extensions: the best partition of iterated cycles
+//     (4 B per node), the level without the cut edges that a later cycle's
+//     clustering rates (8 (n + 1) + 8 m) and its filter scratch (2 B per
+//     entry), the degree classes of sub-rounds (1 B per node), and an
+//     ensemble's overlay with its sort and scans (48 B per node).
+int64_t footprint_of(const sclap_csr& g, int32_t k, const sclap_ml_params* p) {
   const int64_t n = g.n, m = g.m;
   const int64_t hierarchy = 2 * (8 * (n + 1) + 8 * m + 8 * n + 4 * n);
   const int64_t conn = k <= kConnMaxK ? 4 * n * (int64_t)k : 0;
   const int64_t scratch = kRoundBytesPerNode * n + kRoundBytesPerEntry * m;
   const int64_t contraction = kContractBytesPerEntry * m + 16 * n;
-  return input_bytes_of(g) + hierarchy + 48 * n + conn + scratch + contraction + 65536;
+  int64_t ext = 0;
+  if (p && p->vcycles > 1) ext += 4 * n + 8 * (n + 1) + 8 * m + 2 * m + 4096;
+  if (p && p->subrounds > 1) ext += n;
+  if (p && p->ensemble > 1) ext += 48 * n;
+  return input_bytes_of(g) + hierarchy + 48 * n + conn + scratch + contraction + ext + 65536;
 }
 }  // namespace sclap
 
@@ -245,7 +254,7 @@ int sclap_server_submit(sclap_server* srv, const sclap_job* job, uint64_t* ticke
     return fail(SCLAP_EINVAL, "bad job");
   if (g.nw && g.nw_bytes != 4 && g.nw_bytes != 8) return fail(SCLAP_EINVAL, "nw_bytes must be 4 or 8");
   ServedJob* sj = new ServedJob();
-  sj->footprint = footprint_of(g, job->k);
+  sj->footprint = footprint_of(g, job->k, &job->params);
   if (sj->footprint > srv->budget) {
     delete sj;
     return fail(SCLAP_EBUDGET, "job larger than the server's memory budget");
@@ -349,10 +358,11 @@ int sclap_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res) {
   return sclap_server_wait(srv, ticket, res);
 }
 
-int sclap_server_footprint(const sclap_csr* g, int32_t k, int64_t* input_bytes, int64_t* footprint_bytes) {
+int sclap_server_footprint(const sclap_csr* g, int32_t k, const sclap_ml_params* p, int64_t* input_bytes,
+                           int64_t* footprint_bytes) {
   if (!g || k < 1 || g->n < 0 || g->m < 0) return fail(SCLAP_EINVAL, "bad argument");
   if (input_bytes) *input_bytes = input_bytes_of(*g);
-  if (footprint_bytes) *footprint_bytes = footprint_of(*g, k);
+  if (footprint_bytes) *footprint_bytes = footprint_of(*g, k, p);
   return SCLAP_OK;
 }
 
