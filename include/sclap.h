@@ -364,10 +364,17 @@ int sclap_wait(sclap_server* srv, uint64_t ticket, sclap_job_result* res);
  * overlay of an ensemble. */
 int sclap_server_footprint(const sclap_csr* g, int32_t k, const sclap_ml_params* p, int64_t* input_bytes,
                            int64_t* footprint_bytes);
-/* Latency percentiles over completed jobs and throughput since creation. */
+/* Latency percentiles over completed jobs and throughput since creation;
+ * peak_bytes: the most footprint bytes charged at once; peak_active: the most
+ * jobs admitted to the device at once.  Any output may be NULL. */
 int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double* jobs_per_s,
-                       int64_t* completed, int64_t* peak_bytes);
+                       int64_t* completed, int64_t* peak_bytes, int64_t* peak_active);
 /* Finishes every queued and running job, then frees the server. */
+/* Hold (hold != 0) or release admission: while held, submitted jobs queue
+ * (their footprints are charged) and no queued job is admitted to the
+ * device; jobs already admitted run on.  Releasing admits queued jobs up to
+ * max_active at once, for callers that submit a group of requests together. */
+int sclap_server_hold(sclap_server* srv, int32_t hold);
 int sclap_server_destroy(sclap_server* srv);
 
 /* ---- measurement ------------------------------------------------------------ */
@@ -396,6 +403,15 @@ int sclap_profile_read(sclap_ctx* ctx, double* rate_ms, int64_t* rate_launches, 
  * group's kernels ran.  *rounds = LP rounds profiled. */
 int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
                           int64_t* launches, int64_t* rounds);
+
+/* Counts of the paths the LP rounds of a context (or of a server's context)
+ * took since it was created, always kept: out[0] rounds, out[1] rounds fused
+ * over more than one job, out[2] binning scans done device-wide (more than
+ * one workgroup's worth of tiles), out[3] device-wide contended admissions
+ * (more contended movers than one workgroup sorts), out[4] rounds with rows
+ * above 4096 entries (the hub path).  count: entries wanted (at most 5). */
+int sclap_path_counters(sclap_ctx* ctx, int32_t count, int64_t* out);
+int sclap_server_path_counters(sclap_server* srv, int32_t count, int64_t* out);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsclap.so")
 MAX_LEVELS = 64
 MAX_ROUNDS = 64
 MAX_CYCLES = 16
+PATH_COUNTERS = ("rounds", "multi_job_rounds", "device_wide_bin_scans", "device_wide_contended", "hub_rounds")
 
 OK, EINVAL, ENOTSYM, EOVERFLOW, ENOMEM, EHIP, EBUDGET, ENOTFOUND, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7, -8
 
@@ -147,9 +148,12 @@ SIGNATURES = {
     "sclap_wait": (ctypes.c_int, [_vp, _u64, _P(JobResult)]),
     "sclap_server_footprint": (ctypes.c_int, [_P(Csr), _i32, _P(MlParams), _P(_i64), _P(_i64)]),
     "sclap_server_stats": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_double), _P(ctypes.c_double),
-                                          _P(_i64), _P(_i64)]),
+                                          _P(_i64), _P(_i64), _P(_i64)]),
     "sclap_server_destroy": (ctypes.c_int, [_vp]),
+    "sclap_server_hold": (ctypes.c_int, [_vp, _i32]),
     "sclap_profile_enable": (ctypes.c_int, [_vp, _i32]),
+    "sclap_path_counters": (ctypes.c_int, [_vp, _i32, _P(_i64)]),
+    "sclap_server_path_counters": (ctypes.c_int, [_vp, _i32, _P(_i64)]),
     "sclap_profile_read": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(_i64), _P(_i64), _P(_i64),
                                           _P(ctypes.c_double), _P(_i64)]),
     "sclap_profile_kernels": (ctypes.c_int, [_vp, _i32, _P(ctypes.c_double), _P(ctypes.c_double), _P(_i64),
@@ -215,6 +219,12 @@ class Context:
     def trim(self) -> None:
         """Return the device blocks the context keeps cached to HIP."""
         _check(self.lib.sclap_trim(self.h))
+
+    def path_counters(self) -> dict:
+        """Paths the LP rounds of this context took since its creation."""
+        out = (ctypes.c_int64 * 5)()
+        _check(self.lib.sclap_path_counters(self.h, 5, out))
+        return dict(zip(PATH_COUNTERS, list(out)))
 
     def profile(self, on: bool = True) -> None:
         _check(self.lib.sclap_profile_enable(self.h, 1 if on else 0))
@@ -522,11 +532,21 @@ class Server:
 
     def stats(self) -> dict:
         p50, p99, jps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        done, peak = ctypes.c_int64(), ctypes.c_int64()
+        done, peak, pa = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(self.ctx.lib.sclap_server_stats(self.h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(jps),
-                                               ctypes.byref(done), ctypes.byref(peak)))
+                                               ctypes.byref(done), ctypes.byref(peak), ctypes.byref(pa)))
         return {"p50_ms": p50.value, "p99_ms": p99.value, "jobs_per_s": jps.value, "completed": done.value,
-                "peak_bytes": peak.value}
+                "peak_bytes": peak.value, "peak_active": pa.value}
+
+    def hold(self, on: bool = True) -> None:
+        """Hold (or release) admission of queued jobs."""
+        _check(self.ctx.lib.sclap_server_hold(self.h, 1 if on else 0))
+
+    def path_counters(self) -> dict:
+        """Paths the LP rounds of the server's context took since its creation."""
+        out = (ctypes.c_int64 * 5)()
+        _check(self.ctx.lib.sclap_server_path_counters(self.h, 5, out))
+        return dict(zip(PATH_COUNTERS, list(out)))
 
     def close(self) -> None:
         if self.h:

@@ -152,6 +152,8 @@ int setup_partition_job(Ctx* c, Job* j, const sclap_csr* g, int32_t k, int64_t e
     const int64_t a = 60 * (int64_t)k, b = g->n / (60 * (int64_t)k);
     j->threshold = a > b ? a : b;
   }
+  // level 0: the input without its degree-0 nodes
+  SCLAP_TRY(job_compact_input(c, j, st));
   Level& L = j->lv[0];
   j->st.lmax = j->lmax;
   j->st.W = j->W;
@@ -632,6 +634,12 @@ int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* byt
     if (launches) launches[b] = c.prof_k_group_launches[b];
   }
   if (rounds) *rounds = c.prof_k_launches;
+  return SCLAP_OK;
+}
+
+int sclap_path_counters(sclap_ctx* ctx, int32_t count, int64_t* out) {
+  if (!ctx || count < 0 || (count > 0 && !out)) return fail(SCLAP_EINVAL, "bad argument");
+  for (int i = 0; i < count && i < kPathCounters; ++i) out[i] = ctx->c.path_ctr[i].load(std::memory_order_relaxed);
   return SCLAP_OK;
 }
 

@@ -70,6 +70,7 @@ struct DevSlot {
   int32_t* conn;          // refine: n x conn_k block connections conn(v, b), or nullptr
   int32_t last_round;     // no LP round of this stage follows (its moves need no bookkeeping)
   int32_t ident;          // first clustering round of a level: lab(v) = v, so a neighbour's label is its id
+  int32_t all_elig;       // ident round on a level with 2 max c(v) <= cap: every candidate is eligible
   int32_t sub;            // degree-ordered sub-rounds: the degree class rated in this step
   const uint8_t* cls;     // ... the degree class of every node, or nullptr (every node is rated)
   uint32_t* err;          // set nonzero when an LDS hash table of the round fills up (the round fails)
@@ -94,9 +95,10 @@ enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_STALE = 3, CTR_N
 //   0: 1..8       8 lanes per node        5: 129..512    one wave, 1024-entry LDS table
 //   1: 9..16      16 lanes per node       6: 513..1024   one workgroup, 2048-entry LDS table
 //   2: 17..32     32 lanes per node       7: 1025..4096  one workgroup, 8192-entry LDS table
-//   3: 33..64     one wave per node       8: > 4096      several workgroups, global table
+//   3: 33..64     one wave, 128-entry LDS 8: > 4096      several workgroups, global table
 //   4: 65..128    one wave, 256-entry LDS table
 constexpr int kBins = 9;
+constexpr int kPathCounters = 5;
 constexpr int64_t kBinBlock = 4096;
 
 constexpr int kHubChunk = 2048;      // entries per workgroup in the multi-workgroup path

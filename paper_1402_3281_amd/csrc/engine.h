@@ -11,6 +11,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <vector>
 
 #include "common.h"
@@ -36,6 +37,7 @@ struct Level {
   int rows_sorted = 0;
   int64_t n_active = 0;          // nodes of degree > 0
   int64_t max_deg = 0;
+  int64_t max_w = 0;             // largest node weight
   // sizes of the hub rating path on this level (degree > kBinBlock)
   int64_t hubs = 0;
   int64_t hub_stage = 0;         // staged pair slots
@@ -90,6 +92,12 @@ struct Job {
   int64_t best_cut = 0, best_over = 0;
   int32_t best_cycle = 0;
   int64_t lp_gen = 0;                    // changes whenever the rated node set may change
+  // Partitions of inputs with degree-0 nodes work on the input without them
+  // (level 0, its nodes numbered in id order); `input` is the caller's graph
+  // (with widened node weights) and act maps level-0 nodes to input ids.
+  bool compact = false;
+  Level input;
+  int32_t* act = nullptr;
   // outputs
   int32_t* part_out = nullptr;     // caller buffer (level-0 blocks / labels)
   sclap_stats st{};
@@ -143,6 +151,10 @@ struct Ctx {
   int64_t prof_k_nodes[kBins] = {};
   int64_t prof_k_launches = 0;     // rounds profiled
   int64_t prof_k_group_launches[kBins] = {};  // rounds in which the group's kernels ran
+  // Which paths the LP rounds took (kept always, read by sclap_path_counters):
+  // [0] rounds, [1] rounds over more than one job, [2] device-wide binning
+  // scans, [3] device-wide contended admissions, [4] rounds with a hub row
+  std::atomic<int64_t> path_ctr[kPathCounters] = {};
 };
 
 int ctx_ensure_pin(Ctx* c, size_t bytes);
@@ -161,6 +173,9 @@ int ctx_ensure_slots(Ctx* c, size_t count);
 
 // Prepare a job's level 0 from the caller's CSR (widens node weights).
 int job_set_input(Ctx* c, Job* j, const sclap_csr* g, hipStream_t st);
+// Partitions: make level 0 the input without its degree-0 nodes (after
+// level_totals of the input; nothing to do without such nodes).
+int job_compact_input(Ctx* c, Job* j, hipStream_t st);
 // Compute per-level totals (n_active, hub table needs); returns via sync.
 int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipStream_t st);
 // Start clustering on level cur (labels = node ids).

@@ -208,6 +208,38 @@ int job_set_input(Ctx* c, Job* j, const sclap_csr* g, hipStream_t st) {
   return SCLAP_OK;
 }
 
+int job_compact_input(Ctx* c, Job* j, hipStream_t st) {
+  Level& L = j->lv[0];
+  const int64_t n = L.n, m = L.m, n0 = L.n_active;
+  if (n0 == n || n0 == 0) return SCLAP_OK;
+  int32_t *f = nullptr, *rank = nullptr;
+  SCLAP_TRY(dalloc_t(&f, (size_t)n, st));
+  SCLAP_TRY(dalloc_t(&rank, (size_t)n, st));
+  SCLAP_TRY(active_flags(L.rp, n, f, st));
+  const size_t sb = prim_exscan_i32_bytes((size_t)n);
+  SCLAP_TRY(c->prim.ensure(sb, st));
+  SCLAP_TRY(prim_exscan_i32(c->prim.p, sb, f, rank, (size_t)n, st));
+  dfree(f, st);
+  Level C;
+  C.n = n0;
+  C.m = m;
+  C.rows_sorted = L.rows_sorted;
+  SCLAP_TRY(dalloc_t(&C.own_rp, (size_t)n0 + 1, st));
+  SCLAP_TRY(dalloc_t(&C.own_col, (size_t)std::max<int64_t>(m, 1), st));
+  SCLAP_TRY(dalloc_t(&C.own_nw, (size_t)n0, st));
+  SCLAP_TRY(dalloc_t(&j->act, (size_t)n0, st));
+  SCLAP_TRY(compact_graph(L.rp, L.col, L.nw, rank, n, m, n0, C.own_rp, C.own_col, C.own_nw, j->act, st));
+  dfree(rank, st);
+  C.rp = C.own_rp;
+  C.col = C.own_col;
+  C.ew = L.ew;  // entries keep their places
+  C.nw = C.own_nw;
+  j->input = L;
+  j->lv[0] = C;
+  j->compact = true;
+  return level_totals(c, j, &j->lv[0], nullptr, nullptr, st);
+}
+
 int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipStream_t st) {
   SCLAP_TRY(c->small.ensure(256, st));
   unsigned long long* d = (unsigned long long*)c->small.p;
@@ -225,6 +257,7 @@ int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipSt
   L->hub_parts_r = c->pin[7];
   L->hub_mat_r = c->pin[8];
   L->max_deg = c->pin[9];
+  L->max_w = c->pin[1];
   return SCLAP_OK;
 }
 
@@ -274,6 +307,9 @@ void job_release_ext(Job* j, hipStream_t st) {
 
 void job_release_levels(Job* j, hipStream_t st) {
   for (auto& L : j->lv) level_free(L, st);
+  level_free(j->input, st);
+  dfree(j->act, st);
+  j->act = nullptr;
   job_release_ext(j, st);
   dfree(j->ovl, st);
   j->ovl = nullptr;
@@ -408,6 +444,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     d.mode = refine ? MODE_REFINE : MODE_CLUSTER;
     // clustering starts from lab(v) = v (ensemble member 0, before any move)
     d.ident = !refine && j->round == 1 && j->sub == 0 && j->member == 0 ? 1 : 0;
+    // in that round W(t) = c(t), so with 2 max c <= U no candidate is ineligible
+    d.all_elig = d.ident && 2 * L.max_w <= j->U ? 1 : 0;
     // degree-ordered sub-rounds rate the nodes of one degree class
     d.cls = !refine && j->subrounds > 1 ? j->cls : nullptr;
     d.sub = j->sub;
@@ -508,6 +546,10 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   const bool reuse_bins = all_cluster && c->bin_sig_valid && sig == c->bin_sig && c->bin_cap_used == bin_cap;
 
   if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kRateGroups + 1], st));
+  c->path_ctr[0].fetch_add(1, std::memory_order_relaxed);
+  if (ns > 1) c->path_ctr[1].fetch_add(1, std::memory_order_relaxed);
+  if (!reuse_bins && bin_scan_device_wide(T_bin)) c->path_ctr[2].fetch_add(1, std::memory_order_relaxed);
+  if (hubs) c->path_ctr[4].fetch_add(1, std::memory_order_relaxed);
   uint64_t* binfo = (uint64_t*)c->binfo.p;
   if (!reuse_bins) {
     const size_t bsb = bin_scratch_bytes(T_bin);
@@ -605,6 +647,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (hs[16]) {
     // contended set too large for one workgroup: device-wide sort and scan,
     // then the apply step that was skipped
+    c->path_ctr[3].fetch_add(1, std::memory_order_relaxed);
     const uint32_t cc = hs[9];
     SCLAP_TRY(c->ckeys2.ensure((size_t)cc * 8, st));
     SCLAP_TRY(c->tkey.ensure((size_t)cc * 4, st));
@@ -988,9 +1031,10 @@ static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, hipStream_t
   return c->pin[0];
 }
 
-// Allocate the block array of level i (level 0 writes the caller's buffer).
+// Allocate the block array of level i (level 0 writes the caller's buffer,
+// unless level 0 is the input without its degree-0 nodes).
 static int alloc_part(Job* j, int i, int32_t** out, bool* owned, hipStream_t st) {
-  if (i == 0 && j->part_out) {
+  if (i == 0 && j->part_out && !j->compact) {
     *out = j->part_out;
     *owned = false;
     return SCLAP_OK;
@@ -1000,9 +1044,17 @@ static int alloc_part(Job* j, int i, int32_t** out, bool* owned, hipStream_t st)
 }
 
 static int finish_partition(Ctx* c, Job* j, hipStream_t st) {
-  Level& L = j->lv[0];
+  // the caller's graph: level 0, or the input that level 0 compacts
+  Level& L = j->compact ? j->input : j->lv[0];
   int32_t* part = j->part_out;
   const int64_t k = j->k;
+  if (j->compact) {
+    // level 0's blocks go to their input nodes; the degree-0 nodes wait
+    SCLAP_TRY(fill_i32(part, L.n, -1, st));
+    SCLAP_TRY(scatter_i32(j->act, j->lab, j->lv[0].n, part, st));
+    dfree(j->lab, st);
+    j->lab = nullptr;
+  }
   int64_t* B = nullptr;
   SCLAP_TRY(dalloc_t(&B, (size_t)k, st));
   if (j->st.n_isolated > 0) {
@@ -1074,8 +1126,6 @@ static int start_from_blocks(Ctx* c, Job* j, hipStream_t st) {
   bool owned = false;
   SCLAP_TRY(alloc_part(j, j->cur, &part, &owned, st));
   SCLAP_TRY(copy_i32(L.blk, part, L.n, st));
-  // on the input level the degree-0 nodes wait for their placement
-  if (j->cur == 0) SCLAP_TRY(clear_isolated(L.rp, L.n, part, st));
   j->st.ip_cut = read_cut(c, L, part, st);
   if (j->ref_rounds > 0) return job_begin_refine(c, j, part, owned, st);
   j->lab = part;
@@ -1159,8 +1209,17 @@ static int begin_next_cycle(Ctx* c, Job* j, hipStream_t st) {
   Level& L0 = j->lv[0];
   dfree(L0.coarse_of, st);
   L0.coarse_of = nullptr;
-  L0.blk = j->best;
-  L0.blk_owned = false;
+  if (j->compact) {
+    // level 0 numbers only the input's nodes of degree > 0
+    if (!L0.blk_owned) {
+      SCLAP_TRY(dalloc_t(&L0.blk, (size_t)L0.n, st));
+      L0.blk_owned = true;
+    }
+    SCLAP_TRY(gather_i32(j->act, j->best, L0.n, L0.blk, st));
+  } else {
+    L0.blk = j->best;
+    L0.blk_owned = false;
+  }
   j->cur = 0;
   j->member = 0;
   if (L0.n_active > j->threshold) return job_begin_cluster(c, j, st);
@@ -1189,7 +1248,7 @@ static int after_cycle(Ctx* c, Job* j, hipStream_t st) {
     j->best_cut = cut;
     j->best_cycle = cy;
     if (j->vcycles > 1) {
-      const int64_t n = j->lv[0].n;
+      const int64_t n = j->compact ? j->input.n : j->lv[0].n;
       if (!j->best) SCLAP_TRY(dalloc_t(&j->best, (size_t)std::max<int64_t>(n, 1), st));
       SCLAP_TRY(copy_i32(j->part_out, j->best, n, st));
     }
@@ -1198,10 +1257,13 @@ static int after_cycle(Ctx* c, Job* j, hipStream_t st) {
   S.cut = j->best_cut;
   S.max_block = S.cycle_max_block[j->best_cycle];
   if (cy + 1 < j->vcycles) return begin_next_cycle(c, j, st);
-  if (j->best_cycle != cy) SCLAP_TRY(copy_i32(j->best, j->part_out, j->lv[0].n, st));
+  const int64_t n_in = j->compact ? j->input.n : j->lv[0].n;
+  if (j->best_cycle != cy) SCLAP_TRY(copy_i32(j->best, j->part_out, n_in, st));
   dfree(j->best, st);
   j->best = nullptr;
+  if (j->lv[0].blk_owned) dfree(j->lv[0].blk, st);
   j->lv[0].blk = nullptr;
+  j->lv[0].blk_owned = false;
   j->stage = ST_DONE;
   return SCLAP_OK;
 }

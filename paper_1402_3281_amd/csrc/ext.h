@@ -26,8 +26,6 @@ int filter_rows(const int64_t* rp, int64_t n, int64_t m, const uint64_t* kw, con
 
 // bc(cof(v)) = bf(v) for every v with cof(v) >= 0.
 int blocks_up(const int32_t* cof, const int32_t* bf, int64_t n, int32_t* bc, hipStream_t st);
-// part(v) = -1 for the nodes of degree 0 (set aside until they are placed).
-int clear_isolated(const int64_t* rp, int64_t n, int32_t* part, hipStream_t st);
 // Degree class of every node for S sub-rounds: 0 below degree 4, else
 // floor(log4(degree)), at most S - 1.
 int degree_classes(const int64_t* rp, int64_t n, int S, uint8_t* cls, hipStream_t st);
@@ -38,12 +36,6 @@ int init_member(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, in
                 hipStream_t st);
 // f(v) = 1 for the nodes of degree > 0.
 int active_flags(const int64_t* rp, int64_t n, int32_t* f, hipStream_t st);
-// Member labels on the input level of a partition, whose n - n0 degree-0
-// nodes are set aside: the member permutation of n0 applied to the rank of
-// each other node (rank: exclusive scan of active_flags); the degree-0 nodes
-// take n0, n0 + 1, ... in id order.
-int init_member_ranked(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, const int64_t* rp,
-                       const int32_t* rank, int64_t n, int64_t n0, int32_t e, hipStream_t st);
 
 int overlay_keys(const int32_t* O, const int32_t* C, int64_t n, int bits, uint64_t* keys, int32_t* vals,
                  hipStream_t st);

@@ -55,23 +55,10 @@ int build_respect_graph(Ctx* c, const Level& L, const int32_t* blk, Level* F, hi
 }
 
 int begin_member_labels(Ctx* c, Job* j, hipStream_t st) {
+  (void)c;
+  // a partition's level 0 already numbers only the input's nodes of degree > 0
   const Level& L = j->lv[j->cur];
-  const int64_t n = L.n;
-  // the input level of a partition numbers only its nodes of degree > 0
-  if (j->kind == JOB_PARTITION && j->cur == 0 && L.n_active < n) {
-    int32_t *f = nullptr, *rank = nullptr;
-    SCLAP_TRY(dalloc_t(&f, (size_t)std::max<int64_t>(n, 1), st));
-    SCLAP_TRY(dalloc_t(&rank, (size_t)std::max<int64_t>(n, 1), st));
-    SCLAP_TRY(active_flags(L.rp, n, f, st));
-    const size_t sb = prim_exscan_i32_bytes((size_t)n);
-    SCLAP_TRY(c->prim.ensure(sb, st));
-    SCLAP_TRY(prim_exscan_i32(c->prim.p, sb, f, rank, (size_t)n, st));
-    SCLAP_TRY(init_member_ranked(j->lab, j->desire, j->Wt, L.nw, L.rp, rank, n, L.n_active, j->member, st));
-    dfree(f, st);
-    dfree(rank, st);
-    return SCLAP_OK;
-  }
-  return init_member(j->lab, j->desire, j->Wt, L.nw, n, j->member, st);
+  return init_member(j->lab, j->desire, j->Wt, L.nw, L.n, j->member, st);
 }
 
 int overlay_labels(Ctx* c, int32_t* O, const int32_t* C, int64_t n, int64_t* count, hipStream_t st) {

@@ -159,20 +159,6 @@ int blocks_up(const int32_t* cof, const int32_t* bf, int64_t n, int32_t* bc, hip
   return SCLAP_OK;
 }
 
-__global__ void __launch_bounds__(256) k_clear_isolated(const int64_t* __restrict__ rp, int64_t n,
-                                                        int32_t* __restrict__ part) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    if (rp[v + 1] == rp[v]) part[v] = -1;
-}
-
-int clear_isolated(const int64_t* rp, int64_t n, int32_t* part, hipStream_t st) {
-  if (n <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_clear_isolated, dim3(ext_grid(n)), dim3(256), 0, st, rp, n, part);
-  SCLAP_HIP(hipGetLastError());
-  return SCLAP_OK;
-}
-
 // Class 0 below degree 4, else floor(log4(degree)), at most S - 1.
 __global__ void __launch_bounds__(256) k_deg_class(const int64_t* __restrict__ rp, int64_t n, int S,
                                                    uint8_t* __restrict__ cls) {
@@ -205,26 +191,6 @@ __global__ void __launch_bounds__(256) k_init_member(int32_t* __restrict__ lab, 
   }
 }
 
-// The input level of a partition: its degree-0 nodes are set aside, and the
-// others are numbered 0 .. n0 - 1 in id order (rank = exclusive count of
-// nodes of degree > 0 before v).  Member labels permute that numbering; the
-// set-aside nodes take the labels n0, n0 + 1, ... in id order (no neighbour
-// ever carries them).
-__global__ void __launch_bounds__(256) k_init_member_ranked(int32_t* __restrict__ lab, int32_t* __restrict__ desire,
-                                                            int64_t* __restrict__ W, const int64_t* __restrict__ nw,
-                                                            const int64_t* __restrict__ rp,
-                                                            const int32_t* __restrict__ rank, int64_t n, int64_t n0,
-                                                            uint64_t a, uint64_t b) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const int64_t r = rank[v];
-    const int32_t p = rp[v + 1] > rp[v] ? (int32_t)((a * (uint64_t)r + b) % (uint64_t)n0) : (int32_t)(n0 + (v - r));
-    lab[v] = p;
-    desire[v] = p;
-    W[p] = nw[v];
-  }
-}
-
 __global__ void __launch_bounds__(256) k_active_flags(const int64_t* __restrict__ rp, int64_t n,
                                                       int32_t* __restrict__ f) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -235,17 +201,6 @@ __global__ void __launch_bounds__(256) k_active_flags(const int64_t* __restrict_
 int active_flags(const int64_t* rp, int64_t n, int32_t* f, hipStream_t st) {
   if (n <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_active_flags, dim3(ext_grid(n)), dim3(256), 0, st, rp, n, f);
-  SCLAP_HIP(hipGetLastError());
-  return SCLAP_OK;
-}
-
-int init_member_ranked(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, const int64_t* rp,
-                       const int32_t* rank, int64_t n, int64_t n0, int32_t e, hipStream_t st) {
-  if (n <= 0) return SCLAP_OK;
-  int64_t a = 1, b = 0;
-  member_affine(n0, e, &a, &b);
-  hipLaunchKernelGGL(k_init_member_ranked, dim3(ext_grid(n)), dim3(256), 0, st, lab, desire, W, nw, rp, rank, n, n0,
-                     (uint64_t)a, (uint64_t)b);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -37,6 +37,9 @@ struct HubLayout {
 // Stores the round's slot descriptors (host_slots, ns entries; pinned or
 // pageable host memory, free for reuse on return) in S and zeroes zero[0,
 // nzero) on stream st, in one launch when ns is small.
+// Whether binning T tiles scans device-wide (rocPRIM) instead of in one workgroup.
+bool bin_scan_device_wide(int64_t T);
+
 int round_begin(const DevSlot* host_slots, int ns, DevSlot* S, uint32_t* zero, int64_t nzero, hipStream_t st);
 int64_t bin_tiles(int64_t n);
 size_t bin_scratch_bytes(int64_t T);

@@ -212,6 +212,8 @@ __global__ void __launch_bounds__(kBinTile) k_bin_write(const DevSlot* __restric
 constexpr int kScan1Threads = 1024;
 constexpr int64_t kScan1Rows = 64 * kScan1Threads;
 
+bool bin_scan_device_wide(int64_t T) { return T > 0 && (int64_t)kBinRows * T + 1 > kScan1Rows; }
+
 __device__ void bin_totals(const DevSlot* __restrict__ S, int ns, int64_t T, const uint32_t* __restrict__ off,
                            const int64_t* __restrict__ voff, uint32_t* __restrict__ bin_cnt,
                            unsigned long long* __restrict__ bin_visits, uint32_t* __restrict__ rated_cnt);
@@ -707,6 +709,49 @@ __device__ __forceinline__ void dir_interval(const DevSlot& sl, int32_t own, int
   hi = down ? own - 1 : INT32_MAX;
 }
 
+// First clustering round of a level (labels = node ids, weights W(t) = c(t)):
+// no row repeats a neighbour, so conn(v, u) = w(v, u) for each neighbour u,
+// and no neighbour carries the own label (conn 0).  The best candidate is the
+// direction-allowed eligible neighbour of largest weight, ties to the
+// smallest id: a maximum of pack_key(w, u) over the row, with no table.  This
+// thread takes entries first, first + step, ..., B at a time, the first B
+// already loaded (nb, wt).  W(u) is read only when the slot's level does not
+// make every candidate eligible.
+template <int B>
+__device__ __forceinline__ uint64_t ident_best(const DevSlot& sl, int64_t row0, int first, int d, int step,
+                                               int32_t lo, int32_t hi, int64_t cv, int32_t (&nb)[B],
+                                               int32_t (&wt)[B]) {
+  uint64_t best = 0;
+  for (int base = 0; base < d; base += step * B) {
+    int32_t t[B], w[B];
+    bool in[B];
+    int64_t wu[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      t[q] = nb[q];
+      w[q] = wt[q];
+      in[q] = base + first + q * step < d && t[q] >= lo && t[q] <= hi;
+      wu[q] = (in[q] && !sl.all_elig) ? gld(sl.W, t[q]) : 0;
+    }
+    const int nbase = base + step * B;
+    if (nbase < d) {
+#pragma unroll
+      for (int q = 0; q < B; ++q) {
+        const int ee = nbase + first + q * step;
+        const int64_t ec = row0 + (ee < d ? ee : d - 1);
+        nb[q] = gld(sl.col, ec);
+        wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const uint64_t k = (in[q] && (sl.all_elig || wu[q] + cv <= sl.cap)) ? pack_key(w[q], t[q]) : 0ull;
+      best = best > k ? best : k;
+    }
+  }
+  return best;
+}
+
 // Best eligible candidate among the table slots first, first + step, ...
 // below tsz (keys -1 = empty).  C slots per thread are read at a time and
 // their W lookups are issued together, so that a thread waits for one round
@@ -776,6 +821,19 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
     const int64_t cv = p.cv;
     int32_t lo, hi;
     dir_interval(sl, own, lo, hi);
+    if (sl.ident) {
+      // first clustering round: a maximum over the row, no table
+      uint64_t best = ident_best<B>(sl, e0, lane, d, kWave, lo, hi, cv, p.nb, p.wt);
+      p.u = un;
+      p.x = xn;
+      if (has_next) pre_row<B, ONE>(p, S, ns, lane, kWave);
+      for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(best, off);
+        best = best > o ? best : o;
+      }
+      if (lane == 0) gst(sl.desire, v, best ? key_label(best) : own);
+      continue;
+    }
     const uint32_t tsz = table_size(d, sl.nlabels);
     for (uint32_t j = lane; j < tsz; j += kWave) {
       keys[j] = -1;
@@ -784,8 +842,8 @@ __device__ __forceinline__ void rate_wave_body(const DevSlot* __restrict__ S, in
     wave_sync();
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, lane, d, kWave, own, lo, hi, keys, vals, tsz - 1,
-                  p.nb, p.wt, my_own, foreign, sl.err);
+    table_fill<B>(sl.col, sl.ew, sl.lab, e0, lane, d, kWave, own, lo, hi, keys, vals, tsz - 1, p.nb, p.wt, my_own,
+                  foreign, sl.err);
     for (int off = 32; off > 0; off >>= 1) my_own += __shfl_xor(my_own, off);
     const bool boundary = __ballot(foreign) != 0;
     wave_sync();
@@ -872,6 +930,17 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     const int64_t cv = p.cv;
     int32_t lo, hi;
     dir_interval(sl, own, lo, hi);
+    if (sl.ident) {
+      // first clustering round: a maximum over the row, no table
+      uint64_t best = ident_best<B>(sl, e0, threadIdx.x, d, NT, lo, hi, cv, p.nb, p.wt);
+      p.u = un;
+      p.x = xn;
+      if (has_next) pre_row<B, ONE>(p, S, ns, threadIdx.x, NT);
+      best = block_reduce(best, red->best, OpMax64());
+      if (threadIdx.x == 0) gst(sl.desire, v, best ? key_label(best) : own);
+      __syncthreads();
+      continue;
+    }
     const uint32_t tsz = table_size(d, sl.nlabels);
     const uint32_t mask = tsz - 1;
     for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
@@ -881,8 +950,8 @@ __device__ __forceinline__ void rate_block_body(const DevSlot* __restrict__ S, i
     __syncthreads();
     int64_t my_own = 0;
     bool foreign = false;
-    table_fill<B>(sl.col, sl.ew, sl.ident ? nullptr : sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask,
-                  p.nb, p.wt, my_own, foreign, sl.err);
+    table_fill<B>(sl.col, sl.ew, sl.lab, e0, threadIdx.x, d, NT, own, lo, hi, keys, vals, mask, p.nb, p.wt, my_own,
+                  foreign, sl.err);
     const int64_t conn_own = block_reduce(my_own, red->conn, OpAdd64());
     const int boundary = block_reduce(foreign ? 1 : 0, red->flag, OpOr());
     const bool own_ok = own_allowed(sl, own);
@@ -938,7 +1007,7 @@ __global__ void __launch_bounds__(256) k_rate_small(const DevSlot* __restrict__ 
   const int32_t* list = bins + b * bin_cap;
   const uint64_t* info = binfo + b * bin_cap;
   const uint32_t cnt = bin_cnt[b];
-  if (b == 3) rate_group_body<64, ONE>(S, ns, list, info, cnt, bid, nblk);
+  if (b == 3) rate_wave_body<128, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
   else rate_wave_body<256, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
 }
 
@@ -1102,6 +1171,28 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
     const int64_t e_begin = (int64_t)lc * kHubChunk;
     const int64_t e_end = e_begin + kHubChunk < d ? e_begin + kHubChunk : d;
     const int32_t own = gld(sl.lab, v);
+    if (sl.ident) {
+      // first clustering round: the chunk's best neighbour (a maximum, see
+      // ident_best) goes straight to the hub's best; nothing is staged
+      int32_t lo, hi;
+      dir_interval(sl, own, lo, hi);
+      const int64_t cv = gld(sl.nw, v);
+      uint64_t best = 0;
+      for (int64_t e = e_begin + threadIdx.x; e < e_end; e += NT) {
+        const int32_t t = gld(sl.col, row0 + e);
+        const int32_t w = sl.ew ? gld(sl.ew, row0 + e) : 1;
+        if (t < lo || t > hi) continue;
+        if (!sl.all_elig && gld(sl.W, t) + cv > sl.cap) continue;
+        const uint64_t k = pack_key(w, t);
+        best = best > k ? best : k;
+      }
+      best = block_reduce(best, reinterpret_cast<uint64_t*>(redi), OpMax64());
+      uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (2 * P + 1);
+      for (uint32_t p = threadIdx.x; p < 2 * P + 1; p += NT) mat_loff[p] = 0u;
+      if (threadIdx.x == 0 && best) atomicMax(&L.best[i], (unsigned long long)best);
+      __syncthreads();
+      continue;
+    }
     for (uint32_t p = threadIdx.x; p < P; p += NT) cur[p] = 0;
     if (threadIdx.x == 0) s_used = 0;
     __syncthreads();
@@ -1120,7 +1211,7 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
         wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tt[q] = sl.ident ? nb[q] : gld(sl.lab, nb[q]);
+      for (int q = 0; q < 8; ++q) tt[q] = gld(sl.lab, nb[q]);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int32_t tq = tt[q];

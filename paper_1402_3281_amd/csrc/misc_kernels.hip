@@ -141,6 +141,67 @@ __global__ void __launch_bounds__(256) k_copy_i32(const int32_t* __restrict__ a,
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) b[v] = a[v];
 }
 
+// The input without its degree-0 nodes: node i of the compacted graph is
+// input node act(i), ids kept in increasing order (rank(v): the nodes of
+// degree > 0 before v).  Degree-0 nodes own no entries, so the entries keep
+// their places and the row offsets are the input's at the kept nodes.
+__global__ void __launch_bounds__(256) k_compact_rows(const int64_t* __restrict__ rp, const int64_t* __restrict__ nw,
+                                                      const int32_t* __restrict__ rank, int64_t n, int64_t m,
+                                                      int64_t n0, int64_t* __restrict__ rp0,
+                                                      int64_t* __restrict__ nw0, int32_t* __restrict__ act) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t e0 = rp[v];
+    if (rp[v + 1] == e0) continue;
+    const int32_t i = rank[v];
+    rp0[i] = e0;
+    nw0[i] = nw[v];
+    act[i] = (int32_t)v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) rp0[n0] = m;
+}
+
+__global__ void __launch_bounds__(256) k_compact_col(const int32_t* __restrict__ col, const int32_t* __restrict__ rank,
+                                                     int64_t m, int32_t* __restrict__ col0) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) col0[e] = rank[col[e]];
+}
+
+int compact_graph(const int64_t* rp, const int32_t* col, const int64_t* nw, const int32_t* rank, int64_t n,
+                  int64_t m, int64_t n0, int64_t* rp0, int32_t* col0, int64_t* nw0, int32_t* act, hipStream_t st) {
+  if (n <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_compact_rows, dim3(grid1(n)), dim3(256), 0, st, rp, nw, rank, n, m, n0, rp0, nw0, act);
+  if (m > 0) hipLaunchKernelGGL(k_compact_col, dim3(grid1(m)), dim3(256), 0, st, col, rank, m, col0);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+__global__ void __launch_bounds__(256) k_gather_i32(const int32_t* __restrict__ idx, const int32_t* __restrict__ src,
+                                                    int64_t n, int32_t* __restrict__ dst) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[idx[i]];
+}
+
+__global__ void __launch_bounds__(256) k_scatter_i32(const int32_t* __restrict__ idx, const int32_t* __restrict__ src,
+                                                     int64_t n, int32_t* __restrict__ dst) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[idx[i]] = src[i];
+}
+
+int gather_i32(const int32_t* idx, const int32_t* src, int64_t n, int32_t* dst, hipStream_t st) {
+  if (n <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_gather_i32, dim3(grid1(n)), dim3(256), 0, st, idx, src, n, dst);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
+int scatter_i32(const int32_t* idx, const int32_t* src, int64_t n, int32_t* dst, hipStream_t st) {
+  if (n <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_scatter_i32, dim3(grid1(n)), dim3(256), 0, st, idx, src, n, dst);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
 int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st) {
   if (n <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_copy_i32, dim3(grid1(n)), dim3(256), 0, st, a, b, n);

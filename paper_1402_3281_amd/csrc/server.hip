@@ -80,6 +80,8 @@ int64_t input_bytes_of(const sclap_csr& g) {
 //   - the temporaries of a contraction: kContractBytesPerEntry per stored
 //     entry of the contracted level (key cache, two key arrays, sums, sort
 //     space, mirror) and the initial-partition scratch (16 B per node);
+//   - level 0, the input without its degree-0 nodes: row offsets, renumbered
+//     columns, node weights, input ids and the renumbering scratch;
 //   - with the Section 4 extensions: the best partition of iterated cycles
 //     (4 B per node), the level without the cut edges that a later cycle's
 //     clustering rates (8 (n + 1) + 8 m) and its filter scratch (2 B per
@@ -91,7 +93,8 @@ int64_t footprint_of(const sclap_csr& g, int32_t k, const sclap_ml_params* p) {
   const int64_t conn = k <= kConnMaxK ? 4 * n * (int64_t)k : 0;
   const int64_t scratch = kRoundBytesPerNode * n + kRoundBytesPerEntry * m;
   const int64_t contraction = kContractBytesPerEntry * m + 16 * n;
-  int64_t ext = 0;
+  // the input without its degree-0 nodes (level 0) and its renumbering
+  int64_t ext = 8 * (n + 1) + 4 * m + 8 * n + 12 * n;
   if (p && p->vcycles > 1) ext += 4 * n + 8 * (n + 1) + 8 * m + 2 * m + 4096;
   if (p && p->subrounds > 1) ext += n;
   if (p && p->ensemble > 1) ext += 48 * n;
@@ -123,6 +126,7 @@ struct sclap_server {
   int64_t in_use = 0;
   int64_t peak = 0;
   int32_t max_active = 64;
+  int64_t peak_active = 0;        // most jobs on the device at once (under mu)
   std::mutex mu;
   std::mutex upload_mu;
   std::condition_variable work_cv;
@@ -133,6 +137,7 @@ struct sclap_server {
   std::vector<double> latencies;
   uint64_t next_ticket = 1;
   bool stop = false;
+  bool hold = false;              // admission held: queued jobs wait (under mu)
   std::thread worker;
   double t_first_submit = -1;
   double t_last_done = 0;
@@ -148,11 +153,11 @@ void sclap_server::run() {
     std::vector<ServedJob*> admit;
     {
       std::unique_lock<std::mutex> lk(mu);
-      work_cv.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+      work_cv.wait(lk, [&] { return stop || (!hold && !queue.empty()) || !active.empty(); });
       if (stop && queue.empty() && active.empty()) break;
       // every queued job's footprint is charged from its submission on, so
       // admission only waits for a free slot
-      while (!queue.empty() && (int32_t)(active.size() + admit.size()) < max_active) {
+      while (!hold && !queue.empty() && (int32_t)(active.size() + admit.size()) < max_active) {
         admit.push_back(queue.front());
         queue.pop_front();
       }
@@ -167,6 +172,10 @@ void sclap_server::run() {
         sj->job.status = rc;
       }
       active.push_back(sj);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      peak_active = std::max<int64_t>(peak_active, (int64_t)active.size());
     }
     std::vector<Job*> js;
     for (ServedJob* sj : active) js.push_back(&sj->job);
@@ -366,8 +375,14 @@ int sclap_server_footprint(const sclap_csr* g, int32_t k, const sclap_ml_params*
   return SCLAP_OK;
 }
 
+int sclap_server_path_counters(sclap_server* srv, int32_t count, int64_t* out) {
+  if (!srv || count < 0 || (count > 0 && !out)) return fail(SCLAP_EINVAL, "bad argument");
+  for (int i = 0; i < count && i < kPathCounters; ++i) out[i] = srv->ctx.path_ctr[i].load(std::memory_order_relaxed);
+  return SCLAP_OK;
+}
+
 int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double* jobs_per_s, int64_t* completed,
-                       int64_t* peak_bytes) {
+                       int64_t* peak_bytes, int64_t* peak_active) {
   if (!srv) return fail(SCLAP_EINVAL, "NULL server");
   std::lock_guard<std::mutex> lk(srv->mu);
   std::vector<double> l = srv->latencies;
@@ -383,6 +398,17 @@ int sclap_server_stats(sclap_server* srv, double* p50_ms, double* p99_ms, double
   if (jobs_per_s) *jobs_per_s = (srv->completed > 0 && span > 0) ? srv->completed / (span * 1e-3) : 0.0;
   if (completed) *completed = srv->completed;
   if (peak_bytes) *peak_bytes = srv->peak;
+  if (peak_active) *peak_active = srv->peak_active;
+  return SCLAP_OK;
+}
+
+int sclap_server_hold(sclap_server* srv, int32_t hold) {
+  if (!srv) return fail(SCLAP_EINVAL, "NULL server");
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->hold = hold != 0;
+  }
+  srv->work_cv.notify_all();
   return SCLAP_OK;
 }
 
