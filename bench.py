@@ -19,6 +19,9 @@ Other workloads (`--workload`):
               versus plain (one graph after the other); graphs/s.
   serve       served Poisson stream of partition jobs under an HBM budget
               versus plain; p50/p99 latency and jobs/s.
+  extensions  the Section 4 extensions (V-cycles, sub-rounds, ensembles,
+              extra coarse imbalance) on the scale-22 graphs: time, edge
+              visits/s and cut per configuration.
 """
 from __future__ import annotations
 
@@ -73,7 +76,7 @@ def traffic_for(kernel: str, workload: str):
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if t.get("source_digest") != kernel_source_digest() or t.get("workload", "two-graphs-s22") != workload:
+    if t.get("source_digest") != kernel_source_digest() or t.get("workload") != workload:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k.get("bytes_per_launch")
@@ -125,6 +128,107 @@ def roofline(prof: dict, workload: str) -> tuple[dict, list]:
         rl["traffic_GBps"] = traffic / (avg_ms * 1e-3) / 1e9
         rl["traffic_frac"] = rl["traffic_GBps"] / HBM_PEAK_GBS
     return rl, per_kernel
+
+
+# Kernels of each launch group (the roofline groups above), and the kernels
+# of an LP round as a whole, for the rocprofv3 counter summaries.
+GROUP_KERNELS = [["k_rate_tiny", "k_rate_b32"], ["k_rate_small"], ["k_rate_mid"], ["k_rate_large"],
+                 ["k_hub_prep", "k_hub_chunk", "k_hub_alloc", "k_hub_scatter", "k_hub_part", "k_hub_final"],
+                 ["k_mark", "k_mark_big"]]
+ROUND_KERNELS = {k for g in GROUP_KERNELS for k in g} | {
+    "k_round_begin", "k_bin_count", "k_bin_write", "k_bin_scan1", "k_bin_totals", "k_conn_build", "k_conn_zero_hubs",
+    "k_rate_cached", "k_incoming", "k_decide", "k_fold", "k_contended_small", "k_contended_split", "k_contended_mark",
+    "k_contended_add", "k_ta_sums", "k_ta_scan_small", "k_ta_admit", "k_ta_reduce", "k_apply"}
+
+
+def short_kernel_name(name: str) -> str:
+    """sclap::k_rate_mid<true>(...) -> k_rate_mid; library kernels keep a
+    short form of their name."""
+    base = name.split("(")[0].replace("void ", "").strip()
+    if "rocprim" in base:
+        return "rocprim " + base.split("detail::")[-1].split("<")[0]
+    return base.split("::")[-1].split("<")[0]
+
+
+def summarize_counters(a) -> int:
+    """Summary of rocprofv3 runs of the same bench command: the kernel trace
+    (durations), a FETCH_SIZE and a WRITE_SIZE counter run, and the two
+    counter runs of a plain device copy of --calib-copy-mb MiB (the scale of
+    each counter).  Writes profiles/traffic.json (HBM bytes per launch of
+    every roofline group, for the current kernel sources) and prints a
+    markdown table."""
+    import csv
+    import glob
+
+    def rows(d, what):
+        fs = glob.glob(os.path.join(d, "**", f"*{what}.csv"), recursive=True)
+        if not fs:
+            raise SystemExit(f"no *{what}.csv under {d}")
+        return list(csv.DictReader(open(fs[0])))
+
+    def per_kernel(d, what):
+        out = {}
+        for r in rows(d, what):
+            k = short_kernel_name(r["Kernel_Name"])
+            out.setdefault(k, [0, 0.0])
+            out[k][0] += 1
+            out[k][1] += float(r["Counter_Value"])
+        return out
+
+    copy_bytes = a.calib_copy_mb * (1 << 20)
+    cf = [float(r["Counter_Value"]) for r in rows(a.calib_fetch, "counter_collection")
+          if "copyBuffer" in r["Kernel_Name"]]
+    cw = [float(r["Counter_Value"]) for r in rows(a.calib_write, "counter_collection")
+          if "copyBuffer" in r["Kernel_Name"]]
+    f_factor = copy_bytes / (sum(cf) / len(cf) * 1024.0)
+    w_factor = copy_bytes / (sum(cw) / len(cw) * 1024.0)
+    fetch = per_kernel(a.fetch, "counter_collection")
+    write = per_kernel(a.write, "counter_collection")
+    dur = {}
+    for r in rows(a.trace, "kernel_trace"):
+        k = short_kernel_name(r["Kernel_Name"])
+        dur.setdefault(k, [0, 0.0])
+        dur[k][0] += 1
+        dur[k][1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+    # the bench's JSON line among the lines the profiled run printed
+    line = next(json.loads(x) for x in reversed(open(a.bench_line).read().splitlines()) if x.startswith("{"))
+    launches = [rk["launches"] for rk in line["rating_kernels"]]
+
+    def agg(names):
+        fb = sum(fetch.get(k, [0, 0.0])[1] for k in names) * 1024.0 * f_factor
+        wb = sum(write.get(k, [0, 0.0])[1] for k in names) * 1024.0 * w_factor
+        ms = sum(dur.get(k, [0, 0.0])[1] for k in names)
+        nd = sum(dur.get(k, [0, 0.0])[0] for k in names)
+        return fb, wb, ms, nd
+
+    groups = {}
+    print("| kernels | dispatches | fetched GB | written GB | kernel ms | GB/s | of 8 TB/s |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+
+    def row(label, names):
+        fb, wb, ms, nd = agg(names)
+        rate = (fb + wb) / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        print(f"| {label} | {nd} | {fb / 1e9:.2f} | {wb / 1e9:.2f} | {ms:.2f} | {rate:.0f} | "
+              f"{100.0 * rate / HBM_PEAK_GBS:.1f}% |")
+        return fb, wb, ms, nd
+
+    for i, names in enumerate(GROUP_KERNELS):
+        fb, wb, ms, nd = row(RATE_KERNELS[i], names)
+        la = max(launches[i] * a.partitions, 1)
+        groups[RATE_KERNELS[i]] = {"dispatches": nd, "fetch_bytes_per_launch": fb / la,
+                                   "write_bytes_per_launch": wb / la, "bytes_per_launch": (fb + wb) / la,
+                                   "kernels": names}
+    row("LP rounds (all round kernels)", sorted(ROUND_KERNELS))
+    others = sorted(k for k in dur if k not in ROUND_KERNELS)
+    row("everything else (contraction, initial partition, cut, copies)", others)
+    row("rocPRIM (contraction sorts, reductions, scans)", [k for k in others if k.startswith("rocprim")])
+    if a.write_traffic:
+        out = {"workload": a.workload, "source_digest": kernel_source_digest(),
+               "digest_files": ["paper_1402_3281_amd/csrc/common.h", "paper_1402_3281_amd/csrc/lp_kernels.hip"],
+               "calibration": {"copy_bytes": copy_bytes, "fetch_factor": f_factor, "write_factor": w_factor},
+               "partitions": a.partitions, "kernels": groups}
+        json.dump(out, open(os.path.join(ROOT, "profiles", "traffic.json"), "w"), indent=1)
+    return 0
 
 
 def profiled(ctx, fn):
@@ -229,6 +333,78 @@ def run_two_graphs(args) -> int:
         "roofline": rl,
         "cpu_baseline": cpu,
     })
+    print(json.dumps(line), flush=True)
+    ctx.close()
+    return 0
+
+
+# --------------------------------------------------------------------------
+# The Section 4 extensions on R-MAT s22 + RGG 2^22
+
+EXT_CONFIGS = [
+    ("plain", {}),
+    ("V2 (2 V-cycles)", {"vcycles": 2}),
+    ("V3 (3 V-cycles)", {"vcycles": 3}),
+    ("S4 (4 degree-ordered sub-rounds)", {"subrounds": 4}),
+    ("E3 (3-member ensemble)", {"ensemble": 3}),
+    ("B (extra coarse imbalance 1/10)", {"delta": (1, 10)}),
+    ("V3/B/S4", {"vcycles": 3, "delta": (1, 10), "subrounds": 4}),
+]
+
+
+def run_extensions(args) -> int:
+    """Every extension configuration partitions both graphs `steps` times
+    after `warmup` untimed runs; reported per configuration: time per
+    step, edge visits/s and the cuts against the plain scheme's.  value: the
+    edge visits/s of three V-cycles (the paper's V configuration)."""
+    import torch
+
+    import graphgen
+    import paper_1402_3281_amd as sc
+
+    k, thr, scale = 16, 80000, args.scale
+    t0 = time.time()
+    graphs = [graphgen.rmat(scale, 16, seed=1), graphgen.rgg(1 << scale, 10.0, seed=1)]
+    log(f"generated inputs in {time.time() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    devs = [sc.DeviceGraph.from_host(g, rows_sorted=True) for g in graphs]
+    parts = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in graphs]
+    ctx = sc.Context(0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    plain_cuts = None
+    for name, kw in EXT_CONFIGS:
+        def step():
+            return [sc.partition(ctx, d, k, threshold=thr, stream=stream, part_out=p, **kw)[1]
+                    for d, p in zip(devs, parts)]
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        visits, sts = 0, []
+        for _ in range(args.steps):
+            sts = step()
+            visits += sum(sum(s["cycles"]["visits"]) for s in sts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        cuts = [s["cut"] for s in sts]
+        if plain_cuts is None:
+            plain_cuts = cuts
+        row = {"config": name, "params": {a: list(b) if isinstance(b, tuple) else b for a, b in kw.items()},
+               "ms_per_step": el * 1000.0 / args.steps, "visits_per_s": visits / el, "cuts": cuts,
+               "cut_vs_plain": [c / p for c, p in zip(cuts, plain_cuts)],
+               "max_block_le_lmax": [s["max_block"] <= s["lmax"] for s in sts],
+               "cycle_cuts": [s["cycles"]["cut"] for s in sts]}
+        rows.append(row)
+        log(f"{name}: {row['ms_per_step']:.1f} ms, cuts {cuts}")
+    v3 = next(r for r in rows if r["config"].startswith("V3 "))
+    line = base_line("SCLaP edge visits/s (multilevel partition with three V-cycles)", v3["visits_per_s"],
+                     "edge visits/s", args.steps, args.warmup, v3["ms_per_step"],
+                     {"workload": f"rmat-s{scale}-ef16 + rgg-2^{scale}-d10, k=16, eps=3/100, f=14, coarsen to <= "
+                                  f"{thr}, 10 LP rounds per level, LP refinement on every level; Section 4 "
+                                  "extensions", "k": k, "graphs": [{"name": g.name, "n": g.n, "m": g.m} for g in graphs]})
+    line["configs"] = rows
     print(json.dumps(line), flush=True)
     ctx.close()
     return 0
@@ -548,7 +724,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="large", choices=("large", "two-graphs", "batch", "serve"),
+    ap.add_argument("--workload", default="large", choices=("large", "two-graphs", "batch", "serve", "extensions"),
                     help="large: R-MAT s26, k=32 (default); two-graphs: R-MAT s22 + RGG 2^22, k=16; batch: 512 "
                          "mixed graphs batched vs plain; serve: Poisson stream of jobs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -563,7 +739,17 @@ def main() -> int:
     ap.add_argument("--max-active", type=int, default=256, help="jobs on the device at once (serve)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--summarize", action="store_true",
+                    help="summarise rocprofv3 runs (--trace, --fetch, --write, --calib-fetch, --calib-write, "
+                         "--bench-line) instead of running")
+    for opt in ("--trace", "--fetch", "--write", "--calib-fetch", "--calib-write", "--bench-line"):
+        ap.add_argument(opt, default="")
+    ap.add_argument("--partitions", type=int, default=2, help="partition steps in each profiled run (summarize)")
+    ap.add_argument("--write-traffic", action="store_true", help="write profiles/traffic.json (summarize)")
     args = ap.parse_args()
+    if args.summarize:
+        args.calib_copy_mb = args.calib_copy_mb or 1024
+        return summarize_counters(args)
     if args.calib_copy_mb:
         return copy_calibration(args.calib_copy_mb)
     if args.gpus != 1:
@@ -575,6 +761,9 @@ def main() -> int:
         return run_two_graphs(args)
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "extensions":
+        args.scale = args.scale or 22
+        return run_extensions(args)
     if args.workload == "serve":
         return run_serve(args)
     args.scale = args.scale or 26
