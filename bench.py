@@ -452,6 +452,13 @@ def run_batch(args) -> int:
         log(f"{name}: {dt * 1e3:.1f} ms per pass over the batch")
         return dt, out
 
+    tune = None
+    if not args.no_autotune:
+        # the degree bins' bounds, tuned on the batch's largest graph (untimed setup)
+        big = max(range(len(graphs)), key=lambda i: graphs[i].m)
+        _, _, U = sc.bounds(graphs[big].n, 1, ks[big], (3, 100), 14)
+        tune = ctx.autotune(devs[big], U, rounds=3, stream=stream)
+        log(f"autotuned bin bounds {tune}")
     tp, sts_p = timed(plain, "plain")
     tb, sts_b = timed(batched, "batched")
     same = all(torch.equal(a[:g.n], b[:g.n]) for a, b, g in zip(plain_parts, batch_parts, graphs))
@@ -492,6 +499,7 @@ def run_batch(args) -> int:
         "identical_results": bool(same),
         "sclap_round_visits_per_s": round_rate(prof),
         "rating_kernels": per_kernel,
+        "autotune": tune,
         "roofline": rl,
         "cpu_baseline": cpu,
     })
@@ -646,6 +654,12 @@ def run_large(args) -> int:
     part = torch.empty(g.n, dtype=torch.int32, device="cuda")
     ctx = sc.Context(0)
     stream = torch.cuda.current_stream()
+    tune = None
+    if not args.no_autotune:
+        # the degree bins' bounds, picked by timing clustering rounds (untimed setup)
+        _, _, U = sc.bounds(g.n, 1, k, (3, 100), 14)
+        tune = ctx.autotune(dev, U, rounds=3, stream=stream)
+        log(f"autotuned bin bounds {tune}")
 
     def step():
         return sc.partition(ctx, dev, k, stream=stream, part_out=part)[1]
@@ -710,6 +724,7 @@ def run_large(args) -> int:
         "sclap_round_visits_per_s": round_rate(prof),
         "phase_ms": st["ms"],
         "properties": props,
+        "autotune": tune,
         "rating_kernels": per_kernel,
         "roofline": rl,
         "cpu_baseline": cpu,
@@ -728,6 +743,7 @@ def main() -> int:
                     help="large: R-MAT s26, k=32 (default); two-graphs: R-MAT s22 + RGG 2^22, k=16; batch: 512 "
                          "mixed graphs batched vs plain; serve: Poisson stream of jobs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default degree-bin bounds (large, batch)")
     ap.add_argument("--scale", type=int, default=0, help="R-MAT scale (two-graphs: 22, large: 26)")
     ap.add_argument("--graphs", type=int, default=512, help="batch size (batch)")
     ap.add_argument("--jobs", type=int, default=10000, help="jobs in the served stream (serve)")

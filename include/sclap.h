@@ -404,6 +404,28 @@ int sclap_profile_read(sclap_ctx* ctx, double* rate_ms, int64_t* rate_launches, 
 int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* bytes, int64_t* visits, int64_t* nodes,
                           int64_t* launches, int64_t* rounds);
 
+/* ---- tuning of the degree bins (clustering rounds) ------------------------ */
+
+/* Nodes of degree 1..32 are rated one thread per node (unit weights) and
+ * nodes of degree above 4096 by the hub path; degrees in between go to bins
+ * 3..7, whose kernels are: bin 3 one wave with a 128-slot LDS table, bin 4
+ * one wave with 256 slots, bin 5 one wave with 1024, bin 6 one workgroup with
+ * 2048, bin 7 one workgroup with 8192.  hi[0..3] are the largest degrees of
+ * bins 3..6: 32 <= hi[0] <= 64, hi[0] <= hi[1] <= 128, hi[1] <= hi[2] <= 512,
+ * hi[2] <= hi[3] <= 1024 (default 64, 128, 512, 1024).  The bounds change
+ * only which kernel rates a node, never the result; they apply to the
+ * clustering rounds of the context's later calls. */
+int sclap_set_bin_bounds(sclap_ctx* ctx, const int32_t* hi);
+int sclap_get_bin_bounds(sclap_ctx* ctx, int32_t* hi);
+/* Autotuner: times `rounds` clustering rounds of g under cap U (no stop
+ * rule; the best of two runs) with the default bounds and with each of a
+ * grid of candidate bounds (hi[0] in {32, 64}, hi[1] in {64, 128}, hi[2] in
+ * {128, 256, 512}, hi[3] in {512, 1024}, rising), keeps the fastest in the
+ * context and returns it in hi_out (4 entries, may be NULL) with its time
+ * and the default bounds' time in ms (may be NULL).  Synchronous. */
+int sclap_autotune(sclap_ctx* ctx, const sclap_csr* g, int64_t U, int32_t rounds, int32_t* hi_out, double* best_ms,
+                   double* default_ms, void* stream);
+
 /* Counts of the paths the LP rounds of a context (or of a server's context)
  * took since it was created, always kept: out[0] rounds, out[1] rounds fused
  * over more than one job, out[2] binning scans done device-wide (more than

@@ -153,6 +153,10 @@ SIGNATURES = {
     "sclap_server_hold": (ctypes.c_int, [_vp, _i32]),
     "sclap_profile_enable": (ctypes.c_int, [_vp, _i32]),
     "sclap_path_counters": (ctypes.c_int, [_vp, _i32, _P(_i64)]),
+    "sclap_set_bin_bounds": (ctypes.c_int, [_vp, _P(_i32)]),
+    "sclap_get_bin_bounds": (ctypes.c_int, [_vp, _P(_i32)]),
+    "sclap_autotune": (ctypes.c_int, [_vp, _P(Csr), _i64, _i32, _P(_i32), _P(ctypes.c_double),
+                                      _P(ctypes.c_double), _vp]),
     "sclap_server_path_counters": (ctypes.c_int, [_vp, _i32, _P(_i64)]),
     "sclap_profile_read": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(_i64), _P(_i64), _P(_i64),
                                           _P(ctypes.c_double), _P(_i64)]),
@@ -219,6 +223,26 @@ class Context:
     def trim(self) -> None:
         """Return the device blocks the context keeps cached to HIP."""
         _check(self.lib.sclap_trim(self.h))
+
+    def bin_bounds(self) -> list:
+        """Largest degrees of the rating bins 3..6 of clustering rounds."""
+        hi = (ctypes.c_int32 * 4)()
+        _check(self.lib.sclap_get_bin_bounds(self.h, hi))
+        return list(hi)
+
+    def set_bin_bounds(self, hi) -> None:
+        arr = (ctypes.c_int32 * 4)(*hi)
+        _check(self.lib.sclap_set_bin_bounds(self.h, arr))
+
+    def autotune(self, g: "DeviceGraph", U: int, rounds: int = 3, stream=None) -> dict:
+        """Time clustering rounds of g under candidate bin bounds and keep the
+        fastest; returns the bounds and the times (ms)."""
+        hi = (ctypes.c_int32 * 4)()
+        bms, dms = ctypes.c_double(), ctypes.c_double()
+        c = g.csr()
+        _check(self.lib.sclap_autotune(self.h, ctypes.byref(c), U, rounds, hi, ctypes.byref(bms), ctypes.byref(dms),
+                                       _stream(stream)))
+        return {"bounds": list(hi), "ms": bms.value, "default_ms": dms.value}
 
     def path_counters(self) -> dict:
         """Paths the LP rounds of this context took since its creation."""

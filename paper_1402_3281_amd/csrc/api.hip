@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -634,6 +635,90 @@ int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* byt
     if (launches) launches[b] = c.prof_k_group_launches[b];
   }
   if (rounds) *rounds = c.prof_k_launches;
+  return SCLAP_OK;
+}
+
+static bool valid_bin_bounds(const int32_t* hi) {
+  int32_t lo = 32;
+  for (int q = 0; q < 4; ++q) {
+    if (hi[q] < lo || hi[q] > kBinHiCap[q]) return false;
+    lo = hi[q];
+  }
+  return true;
+}
+
+int sclap_set_bin_bounds(sclap_ctx* ctx, const int32_t* hi) {
+  if (!ctx || !hi) return fail(SCLAP_EINVAL, "NULL argument");
+  if (!valid_bin_bounds(hi)) return fail(SCLAP_EINVAL, "bin bounds must rise from 32 and stay within 64/128/512/1024");
+  for (int q = 0; q < 4; ++q) ctx->c.tune_hi[q] = hi[q];
+  return SCLAP_OK;
+}
+
+int sclap_get_bin_bounds(sclap_ctx* ctx, int32_t* hi) {
+  if (!ctx || !hi) return fail(SCLAP_EINVAL, "NULL argument");
+  for (int q = 0; q < 4; ++q) hi[q] = ctx->c.tune_hi[q];
+  return SCLAP_OK;
+}
+
+int sclap_autotune(sclap_ctx* ctx, const sclap_csr* g, int64_t U, int32_t rounds, int32_t* hi_out, double* best_ms,
+                   double* default_ms, void* stream) {
+  if (!ctx) return fail(SCLAP_EINVAL, "ctx is NULL");
+  SCLAP_TRY(check_csr(g));
+  if (rounds < 1 || rounds > SCLAP_MAX_ROUNDS) return fail(SCLAP_EINVAL, "rounds out of range");
+  Ctx* c = &ctx->c;
+  int32_t* lab = nullptr;
+  {
+    CtxScope scope(c);
+    SCLAP_TRY(dalloc_t(&lab, (size_t)std::max<int64_t>(g->n, 1), as_stream(stream)));
+  }
+  // candidate bounds of bins 3..6: each bin may start where the one below
+  // ends; the kernels' capacities cap them
+  std::vector<std::array<int32_t, 4>> cand;
+  for (int32_t h0 : {32, 64})
+    for (int32_t h1 : {64, 128})
+      for (int32_t h2 : {128, 256, 512})
+        for (int32_t h3 : {512, 1024})
+          if (h1 >= h0 && h2 >= h1 && h3 >= h2) cand.push_back({h0, h1, h2, h3});
+  sclap_lp_params p{rounds, 0, 1, 0};
+  const std::array<int32_t, 4> saved{c->tune_hi[0], c->tune_hi[1], c->tune_hi[2], c->tune_hi[3]};
+  auto time_it = [&](const std::array<int32_t, 4>& hi, double* ms) -> int {
+    for (int q = 0; q < 4; ++q) c->tune_hi[q] = hi[q];
+    double best = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      const double t0 = now_ms();
+      SCLAP_TRY(cluster_impl(ctx, g, U, &p, nullptr, 0, lab, nullptr, nullptr, stream));
+      best = std::min(best, now_ms() - t0);
+    }
+    *ms = best;
+    return SCLAP_OK;
+  };
+  int rc = SCLAP_OK;
+  double dms = 0, bms = 1e300;
+  std::array<int32_t, 4> best{kBinHiDefault[0], kBinHiDefault[1], kBinHiDefault[2], kBinHiDefault[3]};
+  rc = time_it(best, &dms);
+  bms = dms;
+  for (size_t i = 0; rc == SCLAP_OK && i < cand.size(); ++i) {
+    double ms = 0;
+    rc = time_it(cand[i], &ms);
+    if (rc == SCLAP_OK && ms < bms) {
+      bms = ms;
+      best = cand[i];
+    }
+  }
+  {
+    CtxScope scope(c);
+    dfree(lab, as_stream(stream));
+    (void)hipStreamSynchronize(as_stream(stream));
+  }
+  if (rc != SCLAP_OK) {
+    for (int q = 0; q < 4; ++q) c->tune_hi[q] = saved[q];
+    return rc;
+  }
+  for (int q = 0; q < 4; ++q) c->tune_hi[q] = best[q];
+  if (hi_out)
+    for (int q = 0; q < 4; ++q) hi_out[q] = best[q];
+  if (best_ms) *best_ms = bms;
+  if (default_ms) *default_ms = dms;
   return SCLAP_OK;
 }
 

@@ -71,6 +71,7 @@ struct DevSlot {
   int32_t last_round;     // no LP round of this stage follows (its moves need no bookkeeping)
   int32_t ident;          // first clustering round of a level: lab(v) = v, so a neighbour's label is its id
   int32_t all_elig;       // ident round on a level with 2 max c(v) <= cap: every candidate is eligible
+  int32_t bin_hi[4];      // largest degree of bins 3..6 (see bin_of; tuned for clustering slots)
   int32_t sub;            // degree-ordered sub-rounds: the degree class rated in this step
   const uint8_t* cls;     // ... the degree class of every node, or nullptr (every node is rated)
   uint32_t* err;          // set nonzero when an LDS hash table of the round fills up (the round fails)
@@ -98,6 +99,12 @@ enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_STALE = 3, CTR_N
 //   3: 33..64     one wave, 128-entry LDS 8: > 4096      several workgroups, global table
 //   4: 65..128    one wave, 256-entry LDS table
 constexpr int kBins = 9;
+// Default upper degree bounds of bins 3..6, and the most each bin's kernel
+// takes (its table holds twice the degree): bin 3 one wave with 128 slots,
+// bin 4 one wave with 256, bin 5 one wave with 1024, bin 6 one workgroup with
+// 2048.  The lower bound of bin 3 (33) and of the hub bin (4097) are fixed.
+constexpr int32_t kBinHiDefault[4] = {64, 128, 512, 1024};
+constexpr int32_t kBinHiCap[4] = {64, 128, 512, 1024};
 constexpr int kPathCounters = 5;
 constexpr int64_t kBinBlock = 4096;
 

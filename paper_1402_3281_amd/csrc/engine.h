@@ -116,6 +116,8 @@ struct CachedBlock {
 struct Ctx {
   int device = 0;
   int cu_count = 256;
+  // upper degree bounds of bins 3..6 for clustering rounds (sclap_autotune)
+  int32_t tune_hi[4] = {kBinHiDefault[0], kBinHiDefault[1], kBinHiDefault[2], kBinHiDefault[3]};
   // freed device blocks kept for later allocations on the same stream
   std::vector<CachedBlock> cache;
   size_t cache_bytes = 0;

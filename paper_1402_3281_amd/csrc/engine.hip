@@ -234,10 +234,22 @@ int job_compact_input(Ctx* c, Job* j, hipStream_t st) {
   C.col = C.own_col;
   C.ew = L.ew;  // entries keep their places
   C.nw = C.own_nw;
+  // the totals carry over (no sync): degrees are unchanged, and a node's
+  // degree never exceeds n0 - 1, so the hub layout sizes are the same; the
+  // largest weight may only shrink, which keeps the input's a valid bound
+  C.n_active = n0;
+  C.max_deg = L.max_deg;
+  C.max_w = L.max_w;
+  C.hubs = L.hubs;
+  C.hub_stage = L.hub_stage;
+  C.hub_parts_c = L.hub_parts_c;
+  C.hub_mat_c = L.hub_mat_c;
+  C.hub_parts_r = L.hub_parts_r;
+  C.hub_mat_r = L.hub_mat_r;
   j->input = L;
   j->lv[0] = C;
   j->compact = true;
-  return level_totals(c, j, &j->lv[0], nullptr, nullptr, st);
+  return SCLAP_OK;
 }
 
 int level_totals(Ctx* c, Job* j, Level* L, int64_t* sum_w, int64_t* max_w, hipStream_t st) {
@@ -406,6 +418,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   SCLAP_TRY(ctx_ensure_slots(c, (size_t)ns));
   int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0, max_tiles = 0;
   int64_t bin_max_deg = 0;  // largest degree of a slot whose nodes go to the bins
+  int32_t lo5 = kBinHiCap[1], lo7 = kBinHiCap[3];  // smallest lower bounds of bins 5 and 7 over the slots
   bool tiny_graph = false;  // a binned slot with fewer than 32 entries (degree <= 64 in the 64-lane bin)
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
@@ -449,6 +462,11 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     // degree-ordered sub-rounds rate the nodes of one degree class
     d.cls = !refine && j->subrounds > 1 ? j->cls : nullptr;
     d.sub = j->sub;
+    // degree bins: tuned bounds for clustering, the defaults for refinement
+    const int32_t* hi = refine ? kBinHiDefault : c->tune_hi;
+    for (int q = 0; q < 4; ++q) d.bin_hi[q] = hi[q];
+    lo5 = std::min(lo5, d.bin_hi[1]);
+    lo7 = std::min(lo7, d.bin_hi[3]);
     d.dir_rule = j->dir_rule;
     d.use_flags = refine && j->round > 1;
     d.conn = refine ? j->conn : nullptr;
@@ -591,7 +609,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     // (binned nodes of CONN_BUILD slots are rated here too, and again, with
     // the same result, from their new rows below)
     SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights,
-                          tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, st,
+                          tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, lo5, lo7, st,
                           c->profile ? c->ev : nullptr, &groups));
   } else {
     // every binned slot builds its block connections and is rated from them

@@ -45,9 +45,12 @@ __device__ __forceinline__ void wave_sync() {
 // entries from the row start.
 constexpr int64_t kThreadMinM = 32;
 
-__device__ __forceinline__ int bin_of(int64_t d, int64_t m) {
+// Degree bin of a node: fixed bounds up to 32 and from 4097 on; between them
+// the slot's bounds hi[0..3] (at most the kernels' capacities kBinHiCap,
+// each at least the one before) split degrees 33..4096 into bins 3..7.
+__device__ __forceinline__ int bin_of(int64_t d, int64_t m, const int32_t* hi) {
   if (m < kThreadMinM && d <= 64) return 3;
-  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= 64 ? 3 : d <= 128 ? 4 : d <= 512 ? 5 : d <= 1024 ? 6
+  return d <= 8 ? 0 : d <= 16 ? 1 : d <= 32 ? 2 : d <= hi[0] ? 3 : d <= hi[1] ? 4 : d <= hi[2] ? 5 : d <= hi[3] ? 6
        : d <= kBinBlock ? 7 : 8;
 }
 
@@ -90,7 +93,7 @@ __device__ __forceinline__ BinOf bin_node(const DevSlot& sl, int64_t v) {
     r.d = gld(sl.rp, v + 1) - r.e0;
     r.take = r.d > 0;
     // rated from the block connections: the rated list only
-    r.b = sl.conn_mode == CONN_RATE ? kBins : bin_of(r.d, sl.m);
+    r.b = sl.conn_mode == CONN_RATE ? kBins : bin_of(r.d, sl.m, sl.bin_hi);
   }
   return r;
 }
@@ -2702,9 +2705,11 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, hipStream_t st, hipEvent_t* evs, unsigned* groups) {
+                int64_t max_deg, int32_t lo5, int32_t lo7, hipStream_t st, hipEvent_t* evs, unsigned* groups) {
   const unsigned G = grid_for(n_hint, 64, 2048);
-  if (groups) *groups = 1u | (max_deg > 32 ? 2u : 0u) | (max_deg > 128 ? 4u : 0u) | (max_deg > 1024 ? 8u : 0u) |
+  // bins 5-6 hold degrees above lo5, bin 7 degrees above lo7 (the smallest
+  // such bounds over the slots)
+  if (groups) *groups = 1u | (max_deg > 32 ? 2u : 0u) | (max_deg > lo5 ? 4u : 0u) | (max_deg > lo7 ? 8u : 0u) |
                         (hubs ? 16u : 0u);
   auto rec = [&](int i) {
     if (evs) (void)hipEventRecord(evs[i], st);
@@ -2716,9 +2721,9 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
   rec(1);
   if (max_deg > 32) LAUNCH(k_rate_small, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(2);
-  if (max_deg > 128) LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
+  if (max_deg > lo5) LAUNCH(k_rate_mid, 2 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G);
   rec(3);
-  if (max_deg > 1024) LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
+  if (max_deg > lo7) LAUNCH(k_rate_large, G, 512, S, ns, bins + 7 * bin_cap, binfo + 7 * bin_cap, bin_cnt + 7);
   rec(4);
   if (hubs) {
     const int32_t* hb = bins + 8 * bin_cap;
