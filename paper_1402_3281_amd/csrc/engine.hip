@@ -212,14 +212,17 @@ int job_compact_input(Ctx* c, Job* j, hipStream_t st) {
   Level& L = j->lv[0];
   const int64_t n = L.n, m = L.m, n0 = L.n_active;
   if (n0 == n || n0 == 0) return SCLAP_OK;
-  int32_t *f = nullptr, *rank = nullptr;
-  SCLAP_TRY(dalloc_t(&f, (size_t)n, st));
-  SCLAP_TRY(dalloc_t(&rank, (size_t)n, st));
-  SCLAP_TRY(active_flags(L.rp, n, f, st));
-  const size_t sb = prim_exscan_i32_bytes((size_t)n);
+  const int64_t W = (n + 63) / 64;
+  uint64_t* words = nullptr;
+  int32_t *wcnt = nullptr, *wpre = nullptr;
+  SCLAP_TRY(dalloc_t(&words, (size_t)W, st));
+  SCLAP_TRY(dalloc_t(&wcnt, (size_t)W, st));
+  SCLAP_TRY(dalloc_t(&wpre, (size_t)W, st));
+  SCLAP_TRY(active_words(L.rp, n, words, wcnt, st));
+  const size_t sb = prim_exscan_i32_bytes((size_t)W);
   SCLAP_TRY(c->prim.ensure(sb, st));
-  SCLAP_TRY(prim_exscan_i32(c->prim.p, sb, f, rank, (size_t)n, st));
-  dfree(f, st);
+  SCLAP_TRY(prim_exscan_i32(c->prim.p, sb, wcnt, wpre, (size_t)W, st));
+  dfree(wcnt, st);
   Level C;
   C.n = n0;
   C.m = m;
@@ -228,8 +231,9 @@ int job_compact_input(Ctx* c, Job* j, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&C.own_col, (size_t)std::max<int64_t>(m, 1), st));
   SCLAP_TRY(dalloc_t(&C.own_nw, (size_t)n0, st));
   SCLAP_TRY(dalloc_t(&j->act, (size_t)n0, st));
-  SCLAP_TRY(compact_graph(L.rp, L.col, L.nw, rank, n, m, n0, C.own_rp, C.own_col, C.own_nw, j->act, st));
-  dfree(rank, st);
+  SCLAP_TRY(compact_graph(L.rp, L.col, L.nw, words, wpre, n, m, n0, C.own_rp, C.own_col, C.own_nw, j->act, st));
+  dfree(words, st);
+  dfree(wpre, st);
   C.rp = C.own_rp;
   C.col = C.own_col;
   C.ew = L.ew;  // entries keep their places
@@ -419,6 +423,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   int64_t N = 0, Lt = 0, T_bin = 0, hub_stage = 0, hub_parts = 0, hub_mat = 0, max_tiles = 0;
   int64_t bin_max_deg = 0;  // largest degree of a slot whose nodes go to the bins
   int32_t lo5 = kBinHiCap[1], lo7 = kBinHiCap[3];  // smallest lower bounds of bins 5 and 7 over the slots
+  bool hubs_ident = true;   // every slot with hubs is in its first clustering round
   bool tiny_graph = false;  // a binned slot with fewer than 32 entries (degree <= 64 in the 64-lane bin)
   SCLAP_TRY(c->small.ensure(512 + (size_t)ns * CTR_N * sizeof(int64_t) + 4096, st));
   int64_t* ctr = (int64_t*)((char*)c->small.p + 512);
@@ -467,6 +472,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     for (int q = 0; q < 4; ++q) d.bin_hi[q] = hi[q];
     lo5 = std::min(lo5, d.bin_hi[1]);
     lo7 = std::min(lo7, d.bin_hi[3]);
+    if (L.hubs > 0 && !d.ident) hubs_ident = false;
     d.dir_rule = j->dir_rule;
     d.use_flags = refine && j->round > 1;
     d.conn = refine ? j->conn : nullptr;
@@ -587,7 +593,9 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     hub.chunk_hub = (uint32_t*)c->hub_maps.p;
     hub.part_hub = hub.chunk_hub + map_cap;
     hub.map_cap = (int64_t)map_cap;
+    SCLAP_TRY(c->hub_keep.ensure(64, st));
     hub.totals = small + 11;
+    hub.totals_kept = (uint32_t*)c->hub_keep.p;
     hub.pool_cursor = (unsigned long long*)(small + 24);
     hub.part_total = (uint32_t*)c->hub_ptot.p;
     hub.part_base = (int64_t*)c->hub_pbase.p;
@@ -609,11 +617,14 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     // (binned nodes of CONN_BUILD slots are rated here too, and again, with
     // the same result, from their new rows below)
     SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights,
-                          tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, lo5, lo7, st,
+                          tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, lo5, lo7, hubs_ident,
+                          reuse_bins && c->hub_keep_valid, st,
                           c->profile ? c->ev : nullptr, &groups));
+    c->hub_keep_valid = hubs;
   } else {
     // every binned slot builds its block connections and is rated from them
     if (any_binned && hubs) SCLAP_TRY(launch_hub_prep(S, ns, bins, bin_cap, meta, hub, st));
+    c->hub_keep_valid = false;
     if (c->profile)
       for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));
   }

@@ -34,8 +34,6 @@ int degree_classes(const int64_t* rp, int64_t n, int S, uint8_t* cls, hipStream_
 void member_affine(int64_t n, int32_t e, int64_t* a, int64_t* b);
 int init_member(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, int32_t e,
                 hipStream_t st);
-// f(v) = 1 for the nodes of degree > 0.
-int active_flags(const int64_t* rp, int64_t n, int32_t* f, hipStream_t st);
 
 int overlay_keys(const int32_t* O, const int32_t* C, int64_t n, int bits, uint64_t* keys, int32_t* vals,
                  hipStream_t st);

@@ -191,20 +191,6 @@ __global__ void __launch_bounds__(256) k_init_member(int32_t* __restrict__ lab, 
   }
 }
 
-__global__ void __launch_bounds__(256) k_active_flags(const int64_t* __restrict__ rp, int64_t n,
-                                                      int32_t* __restrict__ f) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    f[v] = rp[v + 1] > rp[v] ? 1 : 0;
-}
-
-int active_flags(const int64_t* rp, int64_t n, int32_t* f, hipStream_t st) {
-  if (n <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_active_flags, dim3(ext_grid(n)), dim3(256), 0, st, rp, n, f);
-  SCLAP_HIP(hipGetLastError());
-  return SCLAP_OK;
-}
-
 static int64_t gcd_i64(int64_t a, int64_t b) {
   while (b) {
     const int64_t t = a % b;

@@ -16,6 +16,7 @@ struct HubLayout {
   uint32_t* part_hub;     // map_cap: hub of every part
   int64_t map_cap;
   uint32_t* totals;       // 2: chunks, parts
+  uint32_t* totals_kept;  // 2: the same, kept between rounds (the layout is reused with the bins)
   unsigned long long* pool_cursor;  // 1
   uint32_t* part_total;   // parts_cap: pairs of every part (kept 0)
   int64_t* part_base;     // parts_cap: segment of every part in the pool
@@ -57,7 +58,8 @@ constexpr int kMarkGroup = kRateGroups;
 // (the intervals between evs[g] and evs[g + 1]) ran a kernel.
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, int32_t lo5, int32_t lo7, hipStream_t st, hipEvent_t* evs, unsigned* groups);
+                int64_t max_deg, int32_t lo5, int32_t lo7, bool hubs_ident, bool hub_layout_kept, hipStream_t st,
+                hipEvent_t* evs, unsigned* groups);
 // Small contended sets resolved on the device (admission, then the admitted
 // weight added to each target's W); sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,

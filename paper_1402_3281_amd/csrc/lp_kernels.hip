@@ -1135,9 +1135,20 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
   if (threadIdx.x == 0) {
     L.totals[0] = carry_c;
     L.totals[1] = carry_p;
+    L.totals_kept[0] = carry_c;
+    L.totals_kept[1] = carry_p;
     if ((int64_t)carry_c * kHubChunk > L.stage_cap || carry_m > L.mat_cap || carry_p > L.parts_cap)
       *L.overflow = 1;
   }
+}
+
+// A clustering round whose bins are the previous round's keeps that round's
+// hub layout (it depends on the hubs, their degrees and the label count
+// only); the round's counters were zeroed, so the totals are restored.
+__global__ void k_hub_reuse(HubLayout L) {
+  L.totals[0] = L.totals_kept[0];
+  L.totals[1] = L.totals_kept[1];
+  *L.pool_cursor = 0;
 }
 
 constexpr int kHubChunkThreads = 512;
@@ -2705,7 +2716,8 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, int32_t lo5, int32_t lo7, hipStream_t st, hipEvent_t* evs, unsigned* groups) {
+                int64_t max_deg, int32_t lo5, int32_t lo7, bool hubs_ident, bool hub_layout_kept, hipStream_t st,
+                hipEvent_t* evs, unsigned* groups) {
   const unsigned G = grid_for(n_hint, 64, 2048);
   // bins 5-6 hold degrees above lo5, bin 7 degrees above lo7 (the smallest
   // such bounds over the slots)
@@ -2728,11 +2740,15 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
   if (hubs) {
     const int32_t* hb = bins + 8 * bin_cap;
     const uint32_t* hc = bin_cnt + 8;
-    LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub);
+    if (hub_layout_kept) hipLaunchKernelGGL(k_hub_reuse, dim3(1), dim3(1), 0, st, hub);
+    else LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub);
     LAUNCH(k_hub_chunk, G, kHubChunkThreads, S, ns, hb, hub);
-    hipLaunchKernelGGL(k_hub_alloc, dim3(G), dim3(256), 0, st, hub);
-    hipLaunchKernelGGL(k_hub_scatter, dim3(G), dim3(256), 0, st, hub);
-    LAUNCH(k_hub_part, G, 256, S, ns, hb, hub);
+    if (!hubs_ident) {
+      // (first clustering rounds stage no pairs: their chunks went to the hubs' best directly)
+      hipLaunchKernelGGL(k_hub_alloc, dim3(G), dim3(256), 0, st, hub);
+      hipLaunchKernelGGL(k_hub_scatter, dim3(G), dim3(256), 0, st, hub);
+      LAUNCH(k_hub_part, G, 256, S, ns, hb, hub);
+    }
     LAUNCH(k_hub_final, 64, 256, S, ns, hb, hc, hub);
   }
   rec(5);

@@ -19,12 +19,16 @@ int graph_totals(const int64_t* rp, const int64_t* nw, int64_t n, int64_t k, uns
 int widen_nw(const void* src, int bytes, int64_t n, int64_t* dst, hipStream_t st);
 int init_cluster(int32_t* lab, int32_t* desire, int64_t* W, const int64_t* nw, int64_t n, hipStream_t st);
 int copy_i32(const int32_t* a, int32_t* b, int64_t n, hipStream_t st);
-// The input without its degree-0 nodes (n0 of the n nodes have degree > 0;
-// rank: exclusive scan of their flags): row offsets rp0 (n0 + 1), columns
-// col0 (m, renumbered), node weights nw0 (n0) and act (n0: input id of each
-// compacted node).  Entries keep their order, so edge weights are shared.
-int compact_graph(const int64_t* rp, const int32_t* col, const int64_t* nw, const int32_t* rank, int64_t n,
-                  int64_t m, int64_t n0, int64_t* rp0, int32_t* col0, int64_t* nw0, int32_t* act, hipStream_t st);
+// The nodes of degree > 0 as one 64-bit mask per 64 ids (words, ceil(n/64))
+// and the masks' popcounts (wcnt); wpre below is the exclusive scan of wcnt.
+int active_words(const int64_t* rp, int64_t n, uint64_t* words, int32_t* wcnt, hipStream_t st);
+// The input without its degree-0 nodes (n0 of the n nodes have degree > 0):
+// row offsets rp0 (n0 + 1), columns col0 (m, renumbered), node weights nw0
+// (n0) and act (n0: input id of each compacted node).  Entries keep their
+// order, so edge weights are shared.
+int compact_graph(const int64_t* rp, const int32_t* col, const int64_t* nw, const uint64_t* words,
+                  const int32_t* wpre, int64_t n, int64_t m, int64_t n0, int64_t* rp0, int32_t* col0, int64_t* nw0,
+                  int32_t* act, hipStream_t st);
 // dst(i) = src(idx(i)) and dst(idx(i)) = src(i), i < n.
 int gather_i32(const int32_t* idx, const int32_t* src, int64_t n, int32_t* dst, hipStream_t st);
 int scatter_i32(const int32_t* idx, const int32_t* src, int64_t n, int32_t* dst, hipStream_t st);
