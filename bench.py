@@ -223,7 +223,7 @@ def summarize_counters(a) -> int:
     row("everything else (contraction, initial partition, cut, copies)", others)
     row("rocPRIM (contraction sorts, reductions, scans)", [k for k in others if k.startswith("rocprim")])
     if a.write_traffic:
-        out = {"workload": a.workload, "source_digest": kernel_source_digest(),
+        out = {"workload": a.traffic_key, "source_digest": kernel_source_digest(),
                "digest_files": ["paper_1402_3281_amd/csrc/common.h", "paper_1402_3281_amd/csrc/lp_kernels.hip"],
                "calibration": {"copy_bytes": copy_bytes, "fetch_factor": f_factor, "write_factor": w_factor},
                "partitions": a.partitions, "kernels": groups}
@@ -762,6 +762,8 @@ def main() -> int:
         ap.add_argument(opt, default="")
     ap.add_argument("--partitions", type=int, default=2, help="partition steps in each profiled run (summarize)")
     ap.add_argument("--write-traffic", action="store_true", help="write profiles/traffic.json (summarize)")
+    ap.add_argument("--traffic-key", default="rmat-s26",
+                    help="workload key the bytes in profiles/traffic.json belong to (summarize)")
     args = ap.parse_args()
     if args.summarize:
         args.calib_copy_mb = args.calib_copy_mb or 1024
