@@ -584,3 +584,29 @@ def test_empty_and_edgeless_stop_rules():
     assert part.size == 0
     assert (st["levels"], st["rounds_c"], st["rounds_r"]) == (1, [0], [2])
     assert (st["lmax"], st["W"], st["U"], st["cut"], st["threshold"]) == (0, 0, 0, 0, 240)
+
+
+def test_place_isolated_against_greedy():
+    """Brute force against the plain greedy rule (each isolated node, in id
+    order, into the currently lightest block, ties to the smallest id) on
+    unit weights: the fill by intervals in block order reaches the same
+    largest block, and the same block weights whenever the level is reached
+    exactly; it may leave the last block with a deficit below the level."""
+    rng = random.Random(5)
+    exact = 0
+    for t in range(2000):
+        k = rng.randint(1, 9)
+        B = np.array([rng.randint(0, 20) for _ in range(k)], np.int64)
+        ni = rng.randint(0, 40)
+        part = oracle.place_isolated(None, np.ones(ni, np.uint8), k, B)
+        W = B.copy()
+        np.add.at(W, part, 1)
+        G = B.copy()
+        for _ in range(ni):
+            G[int(np.argmin(G))] += 1
+        assert W.sum() == G.sum() and W.max() == G.max(), (B, ni)
+        lam = int(W.max()) if ni else 0
+        if ni and int(np.maximum(0, lam - B).sum()) == ni:
+            assert W.tolist() == G.tolist(), (B, ni)
+            exact += 1
+    assert exact > 100
