@@ -537,7 +537,9 @@ int sclap_cut(sclap_ctx* ctx, const sclap_csr* g, const int32_t* part, int32_t k
   SCLAP_TRY(c->small.ensure(256, st));
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
   SCLAP_TRY(c->cutbuf.ensure((size_t)cut_partials(g->m) * 8, st));
-  SCLAP_TRY(cut_edges(g->row_ptr, g->col, g->ew, part, g->n, g->m, d, (int64_t*)c->cutbuf.p, st));
+  const int32_t* trow = nullptr;
+  SCLAP_TRY(ctx_tile_rows(c, g->row_ptr, g->n, g->m, &trow, st));
+  SCLAP_TRY(cut_edges(g->row_ptr, g->col, g->ew, part, g->n, g->m, d, (int64_t*)c->cutbuf.p, st, trow));
   SCLAP_TRY(ctx_ensure_pin(c, 64 + (size_t)k * 8));
   SCLAP_HIP(hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st));
   SCLAP_HIP(hipStreamSynchronize(st));

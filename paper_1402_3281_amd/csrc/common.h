@@ -74,6 +74,7 @@ struct DevSlot {
   int32_t bin_hi[4];      // largest degree of bins 3..6 (see bin_of; tuned for clustering slots)
   int32_t sub;            // degree-ordered sub-rounds: the degree class rated in this step
   const uint8_t* cls;     // ... the degree class of every node, or nullptr (every node is rated)
+  const uint8_t* lab8;    // CONN_BUILD slots: lab as one byte per node (blocks < 256), or nullptr
   uint32_t* err;          // set nonzero when an LDS hash table of the round fills up (the round fails)
 };
 

@@ -125,7 +125,7 @@ struct Ctx {
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
-  Scratch hub_P, hub_ptot, hub_pbase, hub_mat, binscr, cutbuf, tadm, hub_keep;
+  Scratch hub_P, hub_ptot, hub_pbase, hub_mat, binscr, cutbuf, tadm, hub_keep, trows, part8, lab8;
   // jobs and levels whose nodes the current bins hold (clustering rounds only)
   std::vector<std::pair<const void*, int>> bin_sig;
   bool bin_sig_valid = false;
@@ -172,6 +172,9 @@ struct CtxScope {
 void ctx_trim(Ctx* c);
 // Frees every scratch buffer, the pinned staging and the events of c.
 void ctx_release(Ctx* c, hipStream_t st);
+// The tile-row table (misc.h) of a graph, built in the context's scratch;
+// *out stays NULL for an empty graph.  Valid until the next call on c.
+int ctx_tile_rows(Ctx* c, const int64_t* rp, int64_t n, int64_t m, const int32_t** out, hipStream_t st);
 int ctx_ensure_slots(Ctx* c, size_t count);
 
 // Prepare a job's level 0 from the caller's CSR (widens node weights).

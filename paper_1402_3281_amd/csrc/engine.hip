@@ -160,13 +160,22 @@ int ctx_ensure_pin(Ctx* c, size_t bytes) {
   return SCLAP_OK;
 }
 
+int ctx_tile_rows(Ctx* c, const int64_t* rp, int64_t n, int64_t m, const int32_t** out, hipStream_t st) {
+  *out = nullptr;
+  if (n <= 0 || m <= 0) return SCLAP_OK;
+  SCLAP_TRY(c->trows.ensure((size_t)tile_rows_len(m) * sizeof(int32_t), st));
+  SCLAP_TRY(tile_rows(rp, n, m, (int32_t*)c->trows.p, st));
+  *out = (const int32_t*)c->trows.p;
+  return SCLAP_OK;
+}
+
 void ctx_release(Ctx* c, hipStream_t st) {
   ctx_trim(c);
   Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
                     &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_pbase, &c->hub_mat,
-                    &c->binscr, &c->cutbuf, &c->tadm};
+                    &c->binscr, &c->cutbuf, &c->tadm, &c->hub_keep, &c->trows, &c->part8, &c->lab8};
   c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
   (void)hipStreamSynchronize(st);
@@ -231,9 +240,12 @@ int job_compact_input(Ctx* c, Job* j, hipStream_t st) {
   SCLAP_TRY(dalloc_t(&C.own_col, (size_t)std::max<int64_t>(m, 1), st));
   SCLAP_TRY(dalloc_t(&C.own_nw, (size_t)n0, st));
   SCLAP_TRY(dalloc_t(&j->act, (size_t)n0, st));
-  SCLAP_TRY(compact_graph(L.rp, L.col, L.nw, words, wpre, n, m, n0, C.own_rp, C.own_col, C.own_nw, j->act, st));
+  uint8_t* rec = nullptr;
+  SCLAP_TRY(dalloc_t(&rec, (size_t)compact_rec_bytes(n), st));
+  SCLAP_TRY(compact_graph(L.rp, L.col, L.nw, words, wpre, n, m, n0, C.own_rp, C.own_col, C.own_nw, j->act, rec, st));
   dfree(words, st);
   dfree(wpre, st);
+  dfree(rec, st);
   C.rp = C.own_rp;
   C.col = C.own_col;
   C.ew = L.ew;  // entries keep their places
@@ -504,6 +516,23 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   }
   if (N >= ((int64_t)1 << 31) || Lt >= ((int64_t)1 << 32))
     return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
+  if (any_build) {
+    // slots that build block connections gather their neighbours' blocks
+    // from a byte copy of the blocks (a quarter of the bytes to cache)
+    int64_t bytes = 0;
+    for (int s = 0; s < ns; ++s)
+      if (c->pin_slots[s].conn_mode == CONN_BUILD) bytes += (c->pin_slots[s].n + 255) / 256 * 256;
+    SCLAP_TRY(c->lab8.ensure((size_t)std::max<int64_t>(bytes, 256), st));
+    int64_t off = 0;
+    for (int s = 0; s < ns; ++s) {
+      DevSlot& d = c->pin_slots[s];
+      if (d.conn_mode != CONN_BUILD) continue;
+      uint8_t* b = (uint8_t*)c->lab8.p + off;
+      SCLAP_TRY(narrow_u8(d.lab, d.n, b, st));
+      d.lab8 = b;
+      off += (d.n + 255) / 256 * 256;
+    }
+  }
   const size_t Nz = (size_t)std::max<int64_t>(N, 1);
   SCLAP_TRY(c->bins.ensure(kBins * Nz * sizeof(int32_t), st));
   SCLAP_TRY(c->binfo.ensure(kBins * Nz * sizeof(uint64_t), st));
@@ -817,8 +846,10 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   SCLAP_TRY(fill_i64(tcnt, (int64_t)T + 1, 0, st));
   uint64_t* kcache = nullptr;
   SCLAP_TRY(dalloc_t(&kcache, (size_t)std::max<int64_t>(F.m, 1), st));
+  const int32_t* trow = nullptr;
+  SCLAP_TRY(ctx_tile_rows(c, F.rp, n, F.m, &trow, st));
   SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, kcache,
-                           st));
+                           st, 0, trow));
   {
     const size_t sb = prim_exscan_i64_bytes((size_t)T + 1);
     SCLAP_TRY(c->prim.ensure(sb, st));
@@ -1049,11 +1080,20 @@ int ip_jobs(Ctx* c, std::vector<Job*>& jobs, std::vector<int32_t*>& parts, hipSt
 // ---------------------------------------------------------------------------
 // Executor.
 // ---------------------------------------------------------------------------
-static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, hipStream_t st) {
+static int64_t read_cut(Ctx* c, const Level& L, const int32_t* part, int32_t k, hipStream_t st) {
   if (c->small.ensure(256, st) != SCLAP_OK) return -1;
   unsigned long long* d = (unsigned long long*)((char*)c->small.p + 128);
   if (c->cutbuf.ensure((size_t)cut_partials(L.m) * 8, st) != SCLAP_OK) return -1;
-  if (cut_edges(L.rp, L.col, L.ew, part, L.n, L.m, d, (int64_t*)c->cutbuf.p, st) != SCLAP_OK) return -1;
+  const int32_t* trow = nullptr;
+  if (ctx_tile_rows(c, L.rp, L.n, L.m, &trow, st) != SCLAP_OK) return -1;
+  // with k <= 256 the blocks are gathered from a byte copy of the partition
+  const uint8_t* part8 = nullptr;
+  if (k <= 256 && L.n > 0 && L.m > 0) {
+    if (c->part8.ensure((size_t)L.n, st) != SCLAP_OK) return -1;
+    if (narrow_u8(part, L.n, (uint8_t*)c->part8.p, st) != SCLAP_OK) return -1;
+    part8 = (const uint8_t*)c->part8.p;
+  }
+  if (cut_edges(L.rp, L.col, L.ew, part, L.n, L.m, d, (int64_t*)c->cutbuf.p, st, trow, part8) != SCLAP_OK) return -1;
   if (ctx_ensure_pin(c, 64) != SCLAP_OK) return -1;
   if (hipMemcpyAsync(c->pin, d, 8, hipMemcpyDeviceToHost, st) != hipSuccess) return -1;
   if (hipStreamSynchronize(st) != hipSuccess) return -1;
@@ -1103,7 +1143,7 @@ static int finish_partition(Ctx* c, Job* j, hipStream_t st) {
     dfree(last, st);
   }
   SCLAP_TRY(block_weights(part, L.nw, L.n, j->k, B, st));
-  const int64_t cut = read_cut(c, L, part, st);
+  const int64_t cut = read_cut(c, L, part, j->k, st);
   if (cut < 0) return fail(SCLAP_EHIP, "cut");
   SCLAP_TRY(ctx_ensure_pin(c, (size_t)k * 8));
   SCLAP_HIP(hipMemcpyAsync(c->pin, B, (size_t)k * 8, hipMemcpyDeviceToHost, st));
@@ -1155,7 +1195,7 @@ static int start_from_blocks(Ctx* c, Job* j, hipStream_t st) {
   bool owned = false;
   SCLAP_TRY(alloc_part(j, j->cur, &part, &owned, st));
   SCLAP_TRY(copy_i32(L.blk, part, L.n, st));
-  j->st.ip_cut = read_cut(c, L, part, st);
+  j->st.ip_cut = read_cut(c, L, part, j->k, st);
   if (j->ref_rounds > 0) return job_begin_refine(c, j, part, owned, st);
   j->lab = part;
   j->lab_owned = owned;
@@ -1409,7 +1449,7 @@ int step_jobs(Ctx* c, std::vector<Job*>& jobs, hipStream_t st, bool* all_done_ou
     for (size_t s = 0; s < ipq.size(); ++s) {
       Job* j = ipq[s];
       j->st.ms_initial += dt;
-      j->st.ip_cut = read_cut(c, j->lv[j->cur], parts[s], st);
+      j->st.ip_cut = read_cut(c, j->lv[j->cur], parts[s], j->k, st);
       if (j->ref_rounds > 0) {
         SCLAP_TRY(job_begin_refine(c, j, parts[s], owned[s], st));
       } else {

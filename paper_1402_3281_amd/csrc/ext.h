@@ -17,7 +17,7 @@ int64_t filter_tiles(int64_t m);
 // kw, wpre: 32 * filter_tiles(m) entries; tcnt: filter_tiles(m) + 1 (the last
 // left for the caller to zero).
 int filter_mark(const int64_t* rp, const int32_t* col, const int32_t* blk, int64_t n, int64_t m, uint64_t* kw,
-                uint32_t* wpre, int64_t* tcnt, hipStream_t st);
+                uint32_t* wpre, int64_t* tcnt, const int32_t* trow, hipStream_t st);
 // toff: exclusive scan of tcnt (T + 1 entries).
 int filter_place(const int32_t* col, const int32_t* ew, int64_t m, const uint64_t* kw, const uint32_t* wpre,
                  const int64_t* toff, int32_t* col2, int32_t* ew2, hipStream_t st);

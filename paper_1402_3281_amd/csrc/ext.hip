@@ -29,7 +29,9 @@ int build_respect_graph(Ctx* c, const Level& L, const int32_t* blk, Level* F, hi
   SCLAP_TRY(dalloc_t(&tcnt, (size_t)T + 1, st));
   SCLAP_TRY(dalloc_t(&toff, (size_t)T + 1, st));
   SCLAP_TRY(fill_i64(tcnt + T, 1, 0, st));
-  SCLAP_TRY(filter_mark(L.rp, L.col, blk, n, m, kw, wpre, tcnt, st));
+  const int32_t* trow = nullptr;
+  SCLAP_TRY(ctx_tile_rows(c, L.rp, n, m, &trow, st));
+  SCLAP_TRY(filter_mark(L.rp, L.col, blk, n, m, kw, wpre, tcnt, trow, st));
   const size_t sb = prim_exscan_i64_bytes((size_t)T + 1);
   SCLAP_TRY(c->prim.ensure(sb, st));
   SCLAP_TRY(prim_exscan_i64(c->prim.p, sb, tcnt, toff, (size_t)T + 1, st));

@@ -42,13 +42,13 @@ int64_t filter_tiles(int64_t m) { return (m + kEpb - 1) / kEpb; }
 __global__ void __launch_bounds__(256) k_filter_mark(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                      const int32_t* __restrict__ blk, int64_t n, int64_t m,
                                                      uint64_t* __restrict__ kw, uint32_t* __restrict__ wpre,
-                                                     int64_t* __restrict__ tcnt) {
+                                                     int64_t* __restrict__ tcnt, const int32_t* __restrict__ trow) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   __shared__ uint32_t s_pc[kEpb / kWave];
   const int w = threadIdx.x / kWave;
   for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < m; E0 += (int64_t)gridDim.x * kEpb) {
-    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
+    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds, trow);
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const int64_t e = E0 + j * 256 + threadIdx.x;
@@ -113,11 +113,11 @@ __global__ void __launch_bounds__(256) k_filter_rows(const int64_t* __restrict__
 }
 
 int filter_mark(const int64_t* rp, const int32_t* col, const int32_t* blk, int64_t n, int64_t m, uint64_t* kw,
-                uint32_t* wpre, int64_t* tcnt, hipStream_t st) {
+                uint32_t* wpre, int64_t* tcnt, const int32_t* trow, hipStream_t st) {
   const int64_t T = filter_tiles(m);
   if (T == 0) return SCLAP_OK;
   const unsigned G = (unsigned)(T < 8192 ? T : 8192);
-  hipLaunchKernelGGL(k_filter_mark, dim3(G), dim3(256), 0, st, rp, col, blk, n, m, kw, wpre, tcnt);
+  hipLaunchKernelGGL(k_filter_mark, dim3(G), dim3(256), 0, st, rp, col, blk, n, m, kw, wpre, tcnt, trow);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -2468,8 +2468,14 @@ __device__ __forceinline__ void conn_build_group(const DevSlot* __restrict__ S, 
           nb[q] = gld(sl.col, ec);
           w[q] = sl.ew ? gld(sl.ew, ec) : 1;
         }
+// the blocks of the neighbours, from the byte copy when there is one
+        if (sl.lab8) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) t[q] = gld(sl.lab, nb[q]);
+          for (int q = 0; q < B; ++q) t[q] = (int32_t)gld(sl.lab8, nb[q]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < B; ++q) t[q] = gld(sl.lab, nb[q]);
+        }
 #pragma unroll
         for (int q = 0; q < B; ++q)
           if (e + q * G < d && (uint32_t)t[q] < (uint32_t)K) atomicAdd(&my[t[q]], w[q]);
@@ -2511,8 +2517,13 @@ __device__ __forceinline__ void conn_build_hubs(const DevSlot* __restrict__ S, i
         nb[q] = gld(sl.col, ec);
         w[q] = sl.ew ? gld(sl.ew, ec) : 1;
       }
+      if (sl.lab8) {
 #pragma unroll
-      for (int q = 0; q < B; ++q) t[q] = gld(sl.lab, nb[q]);
+        for (int q = 0; q < B; ++q) t[q] = (int32_t)gld(sl.lab8, nb[q]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < B; ++q) t[q] = gld(sl.lab, nb[q]);
+      }
 #pragma unroll
       for (int q = 0; q < B; ++q)
         if (e + q * kWave < c1 && (uint32_t)t[q] < (uint32_t)K) atomicAdd(&row[t[q]], w[q]);
@@ -2539,22 +2550,23 @@ __global__ void __launch_bounds__(256) k_conn_zero_hubs(const DevSlot* __restric
   }
 }
 
-// Blocks [b * nblk, (b + 1) * nblk) serve bin b (0-7); blocks from 8 * nblk
-// the hub chunks (when `hubs`).
+// Blocks [0, hblk) serve the hub chunks (when `hubs`; dispatched first, as
+// they hold the most entries), blocks hblk + [b * nblk, (b + 1) * nblk) bin b
+// (0-7).
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_conn_build(const DevSlot* __restrict__ S, int ns,
                                                     const int32_t* __restrict__ bins,
                                                     const uint64_t* __restrict__ binfo, int64_t bin_cap,
-                                                    const uint32_t* __restrict__ bin_cnt, uint32_t nblk, int hubs,
-                                                    HubLayout L) {
+                                                    const uint32_t* __restrict__ bin_cnt, uint32_t nblk,
+                                                    uint32_t hblk, HubLayout L) {
   __shared__ int32_t rows[4][8 * kConnMaxK];
   const int w = threadIdx.x / kWave;
-  const uint32_t b = blockIdx.x / nblk, bid = blockIdx.x % nblk;
-  const uint32_t wid = bid * 4 + w, nw = nblk * 4;
-  if (b == 8) {
-    if (hubs && !*L.overflow) conn_build_hubs<ONE>(S, ns, bins + 8 * bin_cap, L, wid, nw, rows[w]);
+  if (blockIdx.x < hblk) {
+    if (!*L.overflow) conn_build_hubs<ONE>(S, ns, bins + 8 * bin_cap, L, blockIdx.x * 4 + w, hblk * 4, rows[w]);
     return;
   }
+  const uint32_t b = (blockIdx.x - hblk) / nblk, bid = (blockIdx.x - hblk) % nblk;
+  const uint32_t wid = bid * 4 + w, nw = nblk * 4;
   const int32_t* list = bins + b * bin_cap;
   const uint64_t* info = binfo + b * bin_cap;
   const uint32_t cnt = bin_cnt[b];
@@ -2805,8 +2817,10 @@ int launch_hub_prep(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_c
 int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                       const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, hipStream_t st) {
   const unsigned G = grid_for(n_hint, 256, 1024);
+  // the hub chunks get a full grid of their own (2048 entries per wave)
+  const unsigned H = hubs ? 2048u : 0u;
   if (hubs) LAUNCH(k_conn_zero_hubs, 64, 256, S, ns, bins + 8 * bin_cap, bin_cnt + 8);
-  LAUNCH(k_conn_build, 9 * G, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G, hubs ? 1 : 0, hub);
+  LAUNCH(k_conn_build, 8 * G + H, 256, S, ns, bins, binfo, bin_cap, bin_cnt, G, H, hub);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

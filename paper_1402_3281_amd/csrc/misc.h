@@ -26,9 +26,11 @@ int active_words(const int64_t* rp, int64_t n, uint64_t* words, int32_t* wcnt, h
 // row offsets rp0 (n0 + 1), columns col0 (m, renumbered), node weights nw0
 // (n0) and act (n0: input id of each compacted node).  Entries keep their
 // order, so edge weights are shared.
+// rec: compact_rec_bytes(n) bytes of scratch (16-byte aligned).
+int64_t compact_rec_bytes(int64_t n);
 int compact_graph(const int64_t* rp, const int32_t* col, const int64_t* nw, const uint64_t* words,
                   const int32_t* wpre, int64_t n, int64_t m, int64_t n0, int64_t* rp0, int32_t* col0, int64_t* nw0,
-                  int32_t* act, hipStream_t st);
+                  int32_t* act, void* rec, hipStream_t st);
 // dst(i) = src(idx(i)) and dst(idx(i)) = src(i), i < n.
 int gather_i32(const int32_t* idx, const int32_t* src, int64_t n, int32_t* dst, hipStream_t st);
 int scatter_i32(const int32_t* idx, const int32_t* src, int64_t n, int32_t* dst, hipStream_t st);
@@ -44,7 +46,18 @@ int cut_partials(int64_t m);
 // *out = the cut: sum of w over the undirected edges (entries u < v of the
 // symmetric graph) joining different blocks.
 int cut_edges(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
-              unsigned long long* out, int64_t* partial, hipStream_t st);
+              unsigned long long* out, int64_t* partial, hipStream_t st, const int32_t* trow = nullptr,
+              const uint8_t* part8 = nullptr);
+// b(v) = a(v) as one byte (blocks of a partition with k <= 256): the cut
+// then gathers the blocks from a quarter of the bytes (part8 above, used
+// instead of part when not NULL).
+int narrow_u8(const int32_t* a, int64_t n, uint8_t* b, hipStream_t st);
+// The tile-row table of the edge-centric kernels (tile_rows_len(m) int32
+// entries): entry t is the row holding entry t * 2048 of the graph, the last
+// is n - 1.  The edge-centric launchers take it as trow; without it (NULL)
+// every tile searches the row offsets for its rows.
+int64_t tile_rows_len(int64_t m);
+int tile_rows(const int64_t* rp, int64_t n, int64_t m, int32_t* trow, hipStream_t st);
 
 int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, int32_t* used, hipStream_t st);
 // coarse_of and coarse node weights; with W (label weights of the labels in
@@ -63,7 +76,7 @@ int cross_tiles(int64_t m);
 // packed (2 bits <= 32): keys hold key << 32 | weight.
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   uint64_t* kcache, hipStream_t st, int packed = 0);
+                   uint64_t* kcache, hipStream_t st, int packed = 0, const int32_t* trow = nullptr);
 // The reduced upper entries (ukeys x * 2^bits + y with x < y, ascending; aggs
 // their weights, m of them) mirrored to keys y * 2^bits + x with int32
 // weights in mw (packed: key << 32 | weight in mkeys, mw unused); *overflow

@@ -186,13 +186,51 @@ __global__ void __launch_bounds__(256) k_compact_rows(const int64_t* __restrict_
   if (blockIdx.x == 0 && threadIdx.x == 0) rp0[n0] = m;
 }
 
-__global__ void __launch_bounds__(256) k_compact_col(const int32_t* __restrict__ col,
-                                                     const uint64_t* __restrict__ words,
-                                                     const int32_t* __restrict__ wpre, int64_t m,
-                                                     int32_t* __restrict__ col0) {
+// A 64-id mask and the count before it in one 16-byte record, so renaming
+// a column costs one gather.
+struct alignas(16) RankRec {
+  uint64_t mask;
+  int32_t pre;
+  int32_t pad;
+};
+
+__global__ void __launch_bounds__(256) k_pack_ranks(const uint64_t* __restrict__ words,
+                                                    const int32_t* __restrict__ wpre, int64_t W,
+                                                    RankRec* __restrict__ rec) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride)
-    col0[e] = rank_of(words, wpre, col[e]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < W; i += stride) {
+    RankRec r;
+    r.mask = words[i];
+    r.pre = wpre[i];
+    r.pad = 0;
+    rec[i] = r;
+  }
+}
+
+// Tiles of 2048 entries, 8 per thread: the tile's column loads, then its
+// record gathers, are in flight together.
+__global__ void __launch_bounds__(256) k_compact_col(const int32_t* __restrict__ col,
+                                                     const RankRec* __restrict__ rec, int64_t m,
+                                                     int32_t* __restrict__ col0) {
+  constexpr int kPer = 8;
+  for (int64_t E0 = (int64_t)blockIdx.x * (256 * kPer); E0 < m; E0 += (int64_t)gridDim.x * (256 * kPer)) {
+    int32_t c[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      c[j] = e < m ? col[e] : 0;
+    }
+    RankRec r[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) r[j] = rec[c[j] >> 6];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      const int bit = c[j] & 63;
+      const uint64_t below = bit ? (r[j].mask & ((1ull << bit) - 1ull)) : 0ull;
+      if (e < m) col0[e] = r[j].pre + __popcll(below);
+    }
+  }
 }
 
 int active_words(const int64_t* rp, int64_t n, uint64_t* words, int32_t* wcnt, hipStream_t st) {
@@ -202,12 +240,20 @@ int active_words(const int64_t* rp, int64_t n, uint64_t* words, int32_t* wcnt, h
   return SCLAP_OK;
 }
 
+int64_t compact_rec_bytes(int64_t n) { return ((n + 63) / 64) * (int64_t)sizeof(RankRec); }
+
 int compact_graph(const int64_t* rp, const int32_t* col, const int64_t* nw, const uint64_t* words,
                   const int32_t* wpre, int64_t n, int64_t m, int64_t n0, int64_t* rp0, int32_t* col0, int64_t* nw0,
-                  int32_t* act, hipStream_t st) {
+                  int32_t* act, void* rec, hipStream_t st) {
   if (n <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_compact_rows, dim3(grid1(n)), dim3(256), 0, st, rp, nw, words, wpre, n, m, n0, rp0, nw0, act);
-  if (m > 0) hipLaunchKernelGGL(k_compact_col, dim3(grid1(m)), dim3(256), 0, st, col, words, wpre, m, col0);
+  const int64_t W = (n + 63) / 64;
+  if (m > 0) {
+    hipLaunchKernelGGL(k_pack_ranks, dim3(grid1(W)), dim3(256), 0, st, words, wpre, W, (RankRec*)rec);
+    const int64_t tiles = (m + 2047) / 2048;
+    const unsigned G = (unsigned)(tiles < 16384 ? tiles : 16384);
+    hipLaunchKernelGGL(k_compact_col, dim3(G), dim3(256), 0, st, col, (const RankRec*)rec, m, col0);
+  }
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
@@ -311,22 +357,30 @@ int block_weights(const int32_t* part, const int64_t* nw, int64_t n, int32_t k, 
 // Cut: sum of w(u, v) over the entries with u < v and part(u) != part(v) (one
 // per undirected edge of the symmetric graph).  Nodes with part -1 have no
 // entries.
+template <typename P>
 __global__ void __launch_bounds__(256) k_cut(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                             const int32_t* __restrict__ ew, const int32_t* __restrict__ part,
-                                             int64_t n, int64_t m, int64_t* __restrict__ partial) {
+                                             const int32_t* __restrict__ ew, const P* __restrict__ part,
+                                             int64_t n, int64_t m, int64_t* __restrict__ partial,
+                                             const int32_t* __restrict__ trow) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   int64_t acc = 0;
   for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < m; E0 += (int64_t)gridDim.x * kEpb) {
-    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
+    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds, trow);
+    // the tile's columns first, so their loads are in flight together
+    int32_t v[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      v[j] = e < r.e1 ? col[e] : -1;
+    }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
       const int64_t e = E0 + j * 256 + threadIdx.x;
       if (e >= r.e1) continue;
       const int64_t u = edge_row(rp, r, s_rp, e);
-      const int32_t v = col[e];
       // each undirected edge once: its entry with u < v (the graph is symmetric)
-      if (u < v && part[u] != part[v]) acc += ew ? ew[e] : 1;
+      if (u < v[j] && part[u] != part[v[j]]) acc += ew ? ew[e] : 1;
     }
   }
   __shared__ int64_t red[4];
@@ -356,15 +410,51 @@ static inline unsigned grid_edges(int64_t m) {
 
 
 
+// The tile-row table of edges.h: one thread per row writes the tile starts
+// that fall in its row; each tile start lies in exactly one non-empty row.
+__global__ void __launch_bounds__(256) k_tile_rows(const int64_t* __restrict__ rp, int64_t n, int64_t m,
+                                                   int32_t* __restrict__ trow) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int64_t a = rp[v], b = rp[v + 1];
+    for (int64_t t = (a + kEpb - 1) / kEpb; t * kEpb < b; ++t) trow[t] = (int32_t)v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) trow[(m + kEpb - 1) / kEpb] = (int32_t)(n - 1);
+}
+
+int64_t tile_rows_len(int64_t m) { return (m + kEpb - 1) / kEpb + 1; }
+
+int tile_rows(const int64_t* rp, int64_t n, int64_t m, int32_t* trow, hipStream_t st) {
+  if (n <= 0 || m <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_tile_rows, dim3(grid1(n)), dim3(256), 0, st, rp, n, m, trow);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
 int cut_partials(int64_t m) { return (int)grid_edges(m); }
 
+__global__ void __launch_bounds__(256) k_narrow_u8(const int32_t* __restrict__ a, int64_t n,
+                                                   uint8_t* __restrict__ b) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) b[v] = (uint8_t)a[v];
+}
+
+int narrow_u8(const int32_t* a, int64_t n, uint8_t* b, hipStream_t st) {
+  if (n <= 0) return SCLAP_OK;
+  hipLaunchKernelGGL(k_narrow_u8, dim3(grid1(n)), dim3(256), 0, st, a, n, b);
+  SCLAP_HIP(hipGetLastError());
+  return SCLAP_OK;
+}
+
 int cut_edges(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* part, int64_t n, int64_t m,
-              unsigned long long* out, int64_t* partial, hipStream_t st) {
+              unsigned long long* out, int64_t* partial, hipStream_t st, const int32_t* trow,
+              const uint8_t* part8) {
   SCLAP_TRY(fill_t((uint64_t*)out, 1, (uint64_t)0, st));
   if (n <= 0 || m <= 0) return SCLAP_OK;
   // per-workgroup partial sums, added by one workgroup
   const unsigned G = grid_edges(m);
-  hipLaunchKernelGGL(k_cut, dim3(G), dim3(256), 0, st, rp, col, ew, part, n, m, partial);
+  if (part8) hipLaunchKernelGGL(k_cut<uint8_t>, dim3(G), dim3(256), 0, st, rp, col, ew, part8, n, m, partial, trow);
+  else hipLaunchKernelGGL(k_cut<int32_t>, dim3(G), dim3(256), 0, st, rp, col, ew, part, n, m, partial, trow);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)G, out);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
@@ -411,7 +501,8 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
                                                int64_t n, int64_t m, int bits, int mode,
                                                int64_t* __restrict__ tcnt, const int64_t* __restrict__ toff,
                                                uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                               uint64_t* __restrict__ kcache, int packed) {
+                                               uint64_t* __restrict__ kcache, int packed,
+                                               const int32_t* __restrict__ trow) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   __shared__ uint32_t s_cnt[4][kItems];
@@ -425,7 +516,13 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
     uint32_t rank[kItems];
     if (mode == 0) {
       // the key of every entry joining two coarse nodes, kSame otherwise
-      const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds);
+      const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds, trow);
+      int32_t vv[kItems];
+#pragma unroll
+      for (int j = 0; j < kItems; ++j) {
+        const int64_t e = E0 + j * 256 + threadIdx.x;
+        vv[j] = e < r.e1 ? col[e] : -1;
+      }
 #pragma unroll
       for (int j = 0; j < kItems; ++j) {
         const int64_t e = E0 + j * 256 + threadIdx.x;
@@ -436,7 +533,7 @@ __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, c
         // ids are gathered), keyed by the coarse pair in ascending order;
         // the mirror is added after the reduction
         const int64_t u = edge_row(rp, r, s_rp, e);
-        const int32_t v = col[e];
+        const int32_t v = vv[j];
         if (u < v) {
           const int32_t x = cof[u], y = cof[v];
           if (x != y) {
@@ -639,10 +736,10 @@ int cross_tiles(int64_t m) { return (int)((m + kEpb - 1) / kEpb); }
 
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
                    int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   uint64_t* kcache, hipStream_t st, int packed) {
+                   uint64_t* kcache, hipStream_t st, int packed, const int32_t* trow) {
   if (n <= 0 || m <= 0) return SCLAP_OK;
   hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
-                     keys, vals, kcache, packed);
+                     keys, vals, kcache, packed, trow);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
