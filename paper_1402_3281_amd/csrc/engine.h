@@ -206,10 +206,10 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st);
 // pair, at most 1.5 pairs per entry) and the hub chunk x part matrix.
 constexpr int64_t kRoundBytesPerNode = 320;
 constexpr int64_t kRoundBytesPerEntry = 40;
-// Temporaries of contracting a level, per stored entry: the key cache (8 B),
-// the cross keys before and after sorting and their sums (at most one per
-// undirected edge, 8 B each), weights (4 B each), sort space, and the sorted
-// mirror of the coarse edges.
+// Temporaries of contracting a level, per stored entry: the cross keys as
+// emitted (room for every entry, 8 B, and 4 B weights), their sorted copy
+// and sums (at most one per undirected edge, 8 B each, weights 4 B), sort
+// space, and the sorted mirror of the coarse edges.
 constexpr int64_t kContractBytesPerEntry = 48;
 
 // Served jobs: device bytes of a job's input copy, and an upper bound of

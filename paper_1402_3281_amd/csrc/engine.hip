@@ -838,45 +838,29 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   dfree(cid, st);
   const int bits = bits_for(nc);
   SCLAP_TRY(c->small.ensure(256, st));
-  // cross entries per tile, their exclusive scan (entry T = the total)
-  const int T = cross_tiles(F.m);
-  int64_t *tcnt = nullptr, *toff = nullptr;
-  SCLAP_TRY(dalloc_t(&tcnt, (size_t)T + 1, st));
-  SCLAP_TRY(dalloc_t(&toff, (size_t)T + 1, st));
-  SCLAP_TRY(fill_i64(tcnt, (int64_t)T + 1, 0, st));
-  uint64_t* kcache = nullptr;
-  SCLAP_TRY(dalloc_t(&kcache, (size_t)std::max<int64_t>(F.m, 1), st));
-  const int32_t* trow = nullptr;
-  SCLAP_TRY(ctx_tile_rows(c, F.rp, n, F.m, &trow, st));
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 0, tcnt, nullptr, nullptr, nullptr, kcache,
-                           st, 0, trow));
-  {
-    const size_t sb = prim_exscan_i64_bytes((size_t)T + 1);
-    SCLAP_TRY(c->prim.ensure(sb, st));
-    SCLAP_TRY(prim_exscan_i64(c->prim.p, sb, tcnt, toff, (size_t)T + 1, st));
-  }
-  SCLAP_HIP(hipMemcpyAsync(c->pin, toff + T, 8, hipMemcpyDeviceToHost, st));
-  SCLAP_HIP(hipStreamSynchronize(st));
-  const int64_t mx = c->pin[0];
-  const size_t mz = (size_t)std::max<int64_t>(mx, 1);
   // unit edge weights: the sums are the run lengths of the sorted keys;
   // weighted keys of at most kPackedKeyBits bits carry their weight in the
   // low half of one 64-bit item (one key-only sort instead of key-value pairs)
   const bool unit = F.ew == nullptr;
   const bool packed = !unit && 2 * bits <= kPackedKeyBits;
+  // the cross entries (one per undirected edge, at most m/2 of the m
+  // entries of a symmetric graph; room for m), then their count
+  const size_t cz = (size_t)std::max<int64_t>(F.m, 1);
   uint64_t *k1 = nullptr, *k2 = nullptr;
   int32_t *v1 = nullptr, *v2 = nullptr;
-  SCLAP_TRY(dalloc_t(&k1, mz, st));
+  SCLAP_TRY(dalloc_t(&k1, cz, st));
+  if (!unit && !packed) SCLAP_TRY(dalloc_t(&v1, cz, st));
+  unsigned long long* cursor = (unsigned long long*)((char*)c->small.p + 96);
+  const int32_t* trow = nullptr;
+  SCLAP_TRY(ctx_tile_rows(c, F.rp, n, F.m, &trow, st));
+  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, cursor, k1, v1, packed ? 1 : 0, trow, st));
+  SCLAP_HIP(hipMemcpyAsync(c->pin, cursor, 8, hipMemcpyDeviceToHost, st));
+  SCLAP_HIP(hipStreamSynchronize(st));
+  const int64_t mx = c->pin[0];
+  if (mx < 0 || mx > F.m) return fail(SCLAP_EHIP, "contraction: cross entry count out of range");
+  const size_t mz = (size_t)std::max<int64_t>(mx, 1);
   SCLAP_TRY(dalloc_t(&k2, mz, st));
-  if (!unit && !packed) {
-    SCLAP_TRY(dalloc_t(&v1, mz, st));
-    SCLAP_TRY(dalloc_t(&v2, mz, st));
-  }
-  SCLAP_TRY(contract_cross(F.rp, F.col, F.ew, F.coarse_of, n, F.m, bits, 1, tcnt, toff, k1, v1, kcache, st,
-                           packed ? 1 : 0));
-  dfree(kcache, st);
-  dfree(tcnt, st);
-  dfree(toff, st);
+  if (!unit && !packed) SCLAP_TRY(dalloc_t(&v2, mz, st));
   const size_t tb = unit     ? std::max(prim_sort_keys_bytes(mz), prim_rle_bytes(mz))
                     : packed ? std::max(prim_sort_keys_bytes(mz), prim_reduce_packed_bytes(mz))
                              : std::max(prim_sort_pairs_bytes(mz), prim_reduce_by_key_bytes(mz));
@@ -920,8 +904,10 @@ int contract_level(Ctx* c, Job* j, int i, int drop, hipStream_t st) {
   if (mh > 0) {
     const size_t tb2 = mpacked ? prim_sort_keys_bytes(hz) : prim_sort_pairs_bytes(hz);
     SCLAP_TRY(c->prim.ensure(tb2, st));
-    if (mpacked) SCLAP_TRY(prim_sort_keys(c->prim.p, tb2, mk, mks, (size_t)mh, 32 + 2 * bits, st, 32));
-    else SCLAP_TRY(prim_sort_pairs(c->prim.p, tb2, mk, mks, mw, mws, (size_t)mh, 2 * bits, st));
+    // the mirror keys y * 2^bits + x come in ascending (x, y) order, so a
+    // stable sort by y alone leaves every row's x ascending
+    if (mpacked) SCLAP_TRY(prim_sort_keys(c->prim.p, tb2, mk, mks, (size_t)mh, 32 + 2 * bits, st, 32 + bits));
+    else SCLAP_TRY(prim_sort_pairs(c->prim.p, tb2, mk, mks, mw, mws, (size_t)mh, 2 * bits, st, bits));
   }
   dfree(mk, st);
   dfree(mw, st);

@@ -140,8 +140,9 @@ size_t prim_sort_keys_bytes(size_t n);
 int prim_sort_keys(void* tmp, size_t tmp_bytes, const uint64_t* in, uint64_t* out, size_t n, int end_bit,
                    hipStream_t st, int begin_bit = 0);
 size_t prim_sort_pairs_bytes(size_t n);
+// Stable by the keys' bits [begin_bit, end_bit) (end_bit < 64 when begin_bit > 0).
 int prim_sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
-                    int32_t* vout, size_t n, int end_bit, hipStream_t st);
+                    int32_t* vout, size_t n, int end_bit, hipStream_t st, int begin_bit = 0);
 size_t prim_scan_by_key_bytes(size_t n);
 int prim_scan_by_key(void* tmp, size_t tmp_bytes, const uint32_t* keys, const int64_t* in, int64_t* out, size_t n,
                      hipStream_t st);

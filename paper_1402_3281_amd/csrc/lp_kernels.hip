@@ -1160,8 +1160,9 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
   __shared__ int32_t keys[kHubTable];
   __shared__ int32_t vals[kHubTable];
   __shared__ uint32_t ulist[kHubChunk];  // used table slots (low 16 bits) | rank in their part << 16
+  // pairs per part, then (scanned in place) the part's first staged pair; one
+  // array for both keeps the workgroup within a third of the CU's LDS
   __shared__ uint32_t loff[kHubMaxParts + 1];
-  __shared__ uint32_t cur[kHubMaxParts];
   __shared__ int64_t redi[8];
   __shared__ int redo[8];
   __shared__ uint32_t s_wsum[8];
@@ -1207,17 +1208,19 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
       __syncthreads();
       continue;
     }
-    for (uint32_t p = threadIdx.x; p < P; p += NT) cur[p] = 0;
+    for (uint32_t p = threadIdx.x; p < P; p += NT) loff[p] = 0;
     if (threadIdx.x == 0) s_used = 0;
     __syncthreads();
     // aggregate the chunk's entries by label, listing every slot taken
     int64_t my_own = 0;
     bool foreign = false;
-    for (int64_t e = e_begin + threadIdx.x; e < e_end; e += (int64_t)NT * 8) {
-      int32_t nb[8], wt[8], tt[8];
-      bool ok[8];
+    // a chunk is one pass: QC entries per thread, their loads in flight together
+    constexpr int QC = kHubChunk / NT;
+    for (int64_t e = e_begin + threadIdx.x; e < e_end; e += (int64_t)NT * QC) {
+      int32_t nb[QC], wt[QC], tt[QC];
+      bool ok[QC];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < QC; ++q) {
         const int64_t ee = e + (int64_t)q * NT;
         ok[q] = ee < e_end;
         const int64_t ec = row0 + (ok[q] ? ee : e_end - 1);
@@ -1225,9 +1228,9 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
         wt[q] = sl.ew ? gld(sl.ew, ec) : 1;
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) tt[q] = gld(sl.lab, nb[q]);
+      for (int q = 0; q < QC; ++q) tt[q] = gld(sl.lab, nb[q]);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < QC; ++q) {
         const int32_t tq = tt[q];
         if (!ok[q]) continue;
         if (tq == own) {
@@ -1263,18 +1266,19 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
     // label part of every pair and its rank within the part
     for (uint32_t k = threadIdx.x; k < nu; k += NT) {
       const uint32_t h = ulist[k];
-      const uint32_t r = atomicAdd(&cur[hub_part_of(keys[h], P)], 1u);
+      const uint32_t r = atomicAdd(&loff[hub_part_of(keys[h], P)], 1u);
       ulist[k] = h | (r << 16);
     }
     __syncthreads();
     {
-      // exclusive scan of cur[0..P) into loff[0..P]
+      // exclusive scan of the counts loff[0..P) in place, total in loff[P]
+      // (every thread reads and writes only its own PT entries)
       constexpr int PT = kHubMaxParts / NT;
       uint32_t mine[PT], tot = 0;
 #pragma unroll
       for (int q = 0; q < PT; ++q) {
         const uint32_t p = threadIdx.x * PT + q;
-        mine[q] = p < P ? cur[p] : 0u;
+        mine[q] = p < P ? loff[p] : 0u;
         tot += mine[q];
       }
       uint32_t incl = tot;
@@ -1303,7 +1307,7 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
     for (uint32_t p = threadIdx.x; p <= P; p += NT) {
       mat_loff[p] = loff[p];
       if (p < P) {
-        const uint32_t k = cur[p];
+        const uint32_t k = loff[p + 1] - loff[p];
         mat_pos[p] = k ? atomicAdd(&L.part_total[L.part_off[i] + p], k) : 0u;
       }
     }

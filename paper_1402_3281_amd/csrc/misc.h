@@ -65,18 +65,15 @@ int contract_flag(const int32_t* lab, const int64_t* rp, int64_t n, int drop, in
 int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw, int64_t n, int drop,
                        const int32_t* cid, int32_t* cof, int64_t* cnw, int64_t nc, const int32_t* used,
                        const int64_t* W, hipStream_t st);
-// Entry tiles of the edge-centric contraction kernels (m entries).
-int cross_tiles(int64_t m);
-// mode 0: per tile, the entries (u, v) with u < v whose ends lie in coarse
-// nodes x != y (one per undirected edge of the symmetric graph) -> tcnt[tile],
-// and every entry's key min(x, y) * 2^bits + max(x, y) (~0 for the other
-// entries) -> kcache (m);
-// mode 1: the keys and weights (vals may be NULL: not written) of those
-// entries from toff[tile] on (exclusive scan of tcnt), read from kcache;
-// packed (2 bits <= 32): keys hold key << 32 | weight.
+// The entries (u, v) with u < v whose ends lie in coarse nodes x != y (one
+// per undirected edge of the symmetric graph) as keys
+// min(x, y) * 2^bits + max(x, y), with their weights in vals (NULL: not
+// written), in no particular order; *cursor (device, zeroed here) ends as
+// their count, and keys/vals need room for every entry with u < v (at most
+// m); packed (2 bits <= 32): keys hold key << 32 | weight.
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
-                   int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   uint64_t* kcache, hipStream_t st, int packed = 0, const int32_t* trow = nullptr);
+                   int64_t m, int bits, unsigned long long* cursor, uint64_t* keys, int32_t* vals, int packed,
+                   const int32_t* trow, hipStream_t st);
 // The reduced upper entries (ukeys x * 2^bits + y with x < y, ascending; aggs
 // their weights, m of them) mirrored to keys y * 2^bits + x with int32
 // weights in mw (packed: key << 32 | weight in mkeys, mw unused); *overflow

@@ -491,97 +491,82 @@ __global__ void __launch_bounds__(256) k_coarse_of(const int32_t* __restrict__ l
   }
 }
 
-// Count (mode 0) or emit (mode 1) the entries that join different coarse
-// nodes, as keys x * 2^b + y with their weights.  Tile t holds the entries
-// [t * kEpb, (t + 1) * kEpb): mode 0 writes its count to tcnt[t], mode 1
-// writes its keys from position toff[t] on (an exclusive scan of tcnt), so
-// no counter is shared between workgroups.
+// Emit the entries that join different coarse nodes, as keys
+// min(x, y) * 2^b + max(x, y) with their weights, in one pass: each tile of
+// kEpb entries reserves its range of the output with one atomic on *cursor
+// and writes its keys there in entry order.  The tiles' ranges come in
+// scheduling order, which the sort that follows makes irrelevant: the
+// reduction sums the weights of equal keys.
 __global__ void __launch_bounds__(256) k_cross(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const int32_t* __restrict__ ew, const int32_t* __restrict__ cof,
-                                               int64_t n, int64_t m, int bits, int mode,
-                                               int64_t* __restrict__ tcnt, const int64_t* __restrict__ toff,
-                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                               uint64_t* __restrict__ kcache, int packed,
+                                               int64_t n, int64_t m, int bits, unsigned long long* __restrict__ cursor,
+                                               uint64_t* __restrict__ keys, int32_t* __restrict__ vals, int packed,
                                                const int32_t* __restrict__ trow) {
   __shared__ int64_t s_rp[kRpLds];
   __shared__ int64_t s_bounds[3];
   __shared__ uint32_t s_cnt[4][kItems];
+  __shared__ unsigned long long s_base;
   constexpr uint64_t kSame = ~0ull;
   const int w = threadIdx.x / kWave;
   const uint64_t lt = (1ull << lane()) - 1ull;
-  const int64_t ntiles = (m + kEpb - 1) / kEpb;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t E0 = t * kEpb;
+  for (int64_t E0 = (int64_t)blockIdx.x * kEpb; E0 < m; E0 += (int64_t)gridDim.x * kEpb) {
+    const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds, trow);
+    int32_t vv[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      vv[j] = e < r.e1 ? col[e] : -1;
+    }
     uint64_t kk[kItems];
-    uint32_t rank[kItems];
-    if (mode == 0) {
-      // the key of every entry joining two coarse nodes, kSame otherwise
-      const EdgeRange r = edge_range(rp, n, m, E0, s_rp, s_bounds, trow);
-      int32_t vv[kItems];
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const int64_t e = E0 + j * 256 + threadIdx.x;
-        vv[j] = e < r.e1 ? col[e] : -1;
-      }
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const int64_t e = E0 + j * 256 + threadIdx.x;
-        kk[j] = kSame;
-        if (e >= r.e1) continue;
-        // the graph is symmetric with equal weights: the entry (u, v) with
-        // u < v stands for its undirected edge (only its endpoints' coarse
-        // ids are gathered), keyed by the coarse pair in ascending order;
-        // the mirror is added after the reduction
-        const int64_t u = edge_row(rp, r, s_rp, e);
-        const int32_t v = vv[j];
-        if (u < v) {
-          const int32_t x = cof[u], y = cof[v];
-          if (x != y) {
-            const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
-            kk[j] = ((uint64_t)(uint32_t)lo << bits) | (uint64_t)(uint32_t)hi;
-          }
+    for (int j = 0; j < kItems; ++j) {
+      const int64_t e = E0 + j * 256 + threadIdx.x;
+      kk[j] = kSame;
+      if (e >= r.e1) continue;
+      // the graph is symmetric with equal weights: the entry (u, v) with
+      // u < v stands for its undirected edge (only its endpoints' coarse
+      // ids are gathered), keyed by the coarse pair in ascending order;
+      // the mirror is added after the reduction
+      const int64_t u = edge_row(rp, r, s_rp, e);
+      const int32_t v = vv[j];
+      if (u < v) {
+        const int32_t x = cof[u], y = cof[v];
+        if (x != y) {
+          const int32_t lo = x < y ? x : y, hi = x < y ? y : x;
+          kk[j] = ((uint64_t)(uint32_t)lo << bits) | (uint64_t)(uint32_t)hi;
         }
-        kcache[e] = kk[j];
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        const int64_t e = E0 + j * 256 + threadIdx.x;
-        kk[j] = e < m ? kcache[e] : kSame;
       }
     }
     // ranks: entry-slot j of wave w takes the places after every earlier
     // slot of the tile and the same slot of earlier waves
+    uint32_t rank[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-      const uint64_t b = __ballot(kk[j] != kSame);
-      rank[j] = (uint32_t)__popcll(b & lt);
-      if (lane() == 0) s_cnt[w][j] = (uint32_t)__popcll(b);
+      const uint64_t bl = __ballot(kk[j] != kSame);
+      rank[j] = (uint32_t)__popcll(bl & lt);
+      if (lane() == 0) s_cnt[w][j] = (uint32_t)__popcll(bl);
     }
     __syncthreads();
-    if (mode == 0) {
-      if (threadIdx.x == 0) {
-        int64_t total = 0;
-        for (int j = 0; j < kItems; ++j) total += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
-        tcnt[t] = total;
-      }
-    } else {
-      int64_t base = toff[t];
+    if (threadIdx.x == 0) {
+      unsigned long long total = 0;
+      for (int j = 0; j < kItems; ++j) total += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
+      s_base = total ? atomicAdd(cursor, total) : 0ull;
+    }
+    __syncthreads();
+    int64_t base = (int64_t)s_base;
 #pragma unroll
-      for (int j = 0; j < kItems; ++j) {
-        int64_t before = 0;
-        for (int q = 0; q < w; ++q) before += s_cnt[q][j];
-        if (kk[j] != kSame) {
-          const int64_t pos = base + before + rank[j];
-          const int32_t wgt = ew ? ew[E0 + j * 256 + threadIdx.x] : 1;
-          // packed: key << 32 | weight in one item (keys of at most 32 bits)
-          keys[pos] = packed ? (kk[j] << 32) | (uint32_t)wgt : kk[j];
-          if (vals) vals[pos] = wgt;
-        }
-        base += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
+    for (int j = 0; j < kItems; ++j) {
+      int64_t before = 0;
+      for (int q = 0; q < w; ++q) before += s_cnt[q][j];
+      if (kk[j] != kSame) {
+        const int64_t pos = base + before + rank[j];
+        const int32_t wgt = ew ? ew[E0 + j * 256 + threadIdx.x] : 1;
+        // packed: key << 32 | weight in one item (keys of at most 32 bits)
+        keys[pos] = packed ? (kk[j] << 32) | (uint32_t)wgt : kk[j];
+        if (vals) vals[pos] = wgt;
       }
+      base += s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
     }
-    __syncthreads();
   }
 }
 
@@ -732,14 +717,13 @@ int contract_coarse_of(const int32_t* lab, const int64_t* rp, const int64_t* nw,
   return SCLAP_OK;
 }
 
-int cross_tiles(int64_t m) { return (int)((m + kEpb - 1) / kEpb); }
-
 int contract_cross(const int64_t* rp, const int32_t* col, const int32_t* ew, const int32_t* cof, int64_t n,
-                   int64_t m, int bits, int mode, int64_t* tcnt, const int64_t* toff, uint64_t* keys, int32_t* vals,
-                   uint64_t* kcache, hipStream_t st, int packed, const int32_t* trow) {
+                   int64_t m, int bits, unsigned long long* cursor, uint64_t* keys, int32_t* vals, int packed,
+                   const int32_t* trow, hipStream_t st) {
+  SCLAP_TRY(fill_t((uint64_t*)cursor, 1, (uint64_t)0, st));
   if (n <= 0 || m <= 0) return SCLAP_OK;
-  hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, mode, tcnt, toff,
-                     keys, vals, kcache, packed, trow);
+  hipLaunchKernelGGL(k_cross, dim3(grid_edges(m)), dim3(256), 0, st, rp, col, ew, cof, n, m, bits, cursor, keys, vals,
+                     packed, trow);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -42,9 +42,11 @@ size_t prim_sort_pairs_bytes(size_t n) {
 }
 
 int prim_sort_pairs(void* tmp, size_t tmp_bytes, const uint64_t* kin, uint64_t* kout, const int32_t* vin,
-                    int32_t* vout, size_t n, int end_bit, hipStream_t st) {
+                    int32_t* vout, size_t n, int end_bit, hipStream_t st, int begin_bit) {
   if (n == 0) return SCLAP_OK;
-  PRIM_CALL(rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, n, 0, (unsigned)end_bit, st));
+  if (begin_bit > 0 && end_bit >= 64) return fail(SCLAP_EINVAL, "radix sort: bit range [b, 64) with b > 0");
+  PRIM_CALL(rocprim::radix_sort_pairs(tmp, tmp_bytes, kin, kout, vin, vout, n, (unsigned)begin_bit, (unsigned)end_bit,
+                                      st));
   return SCLAP_OK;
 }
 

@@ -78,8 +78,8 @@ int64_t input_bytes_of(const sclap_csr& g) {
 //     admission) and kRoundBytesPerEntry per stored entry (the staged and
 //     pooled (label, sum) pairs of hub rows);
 //   - the temporaries of a contraction: kContractBytesPerEntry per stored
-//     entry of the contracted level (key cache, two key arrays, sums, sort
-//     space, mirror) and the initial-partition scratch (16 B per node);
+//     entry of the contracted level (two key arrays, sums, sort space,
+//     mirror) and the initial-partition scratch (16 B per node);
 //   - level 0, the input without its degree-0 nodes: row offsets, renumbered
 //     columns, node weights, input ids and the renumbering scratch;
 //   - with the Section 4 extensions: the best partition of iterated cycles
