@@ -2591,12 +2591,23 @@ template <bool ONE>
 __global__ void __launch_bounds__(256) k_rate_cached(const DevSlot* __restrict__ S, int ns,
                                                      const int32_t* __restrict__ rated,
                                                      const uint32_t* __restrict__ rcnt) {
+  // a group of G lanes per rated node: lane g reads the 16-byte pieces g,
+  // g + G, ... of the node's row, so the rows of consecutive rated nodes are
+  // read as consecutive bytes; a row whose column count is not a multiple
+  // of 4 is scanned by the group's first lane
+  constexpr int G = 8;
   const uint32_t cnt = *rcnt;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
-    const int64_t u = gld(rated, i);
+  const uint32_t lane = lane_id();
+  const int g = (int)(lane & (G - 1));
+  const uint32_t ngroups = gridDim.x * blockDim.x / G;
+  const uint32_t first = (blockIdx.x * blockDim.x + threadIdx.x - lane) / G;  // the wave's first group
+  for (uint32_t i0 = first; i0 < cnt; i0 += ngroups) {
+    const uint32_t i = i0 + lane / G;
+    const bool valid = i < cnt;
+    const int64_t u = gld(rated, valid ? i : cnt - 1);
     const DevSlot& sl = S[SLOT(u)];
-    if (sl.conn_mode == CONN_NONE) continue;  // CONN_BUILD rows were just built
+    // CONN_NONE slots are rated from the bins; CONN_BUILD rows were just built
+    const bool act = valid && sl.conn_mode != CONN_NONE;
     const int64_t v = u - sl.nbase;
     const int K = sl.conn_k;
     const int32_t own = gld(sl.lab, v);
@@ -2605,7 +2616,7 @@ __global__ void __launch_bounds__(256) k_rate_cached(const DevSlot* __restrict__
     int32_t lo, hi;
     dir_interval(sl, own, lo, hi);
     const bool own_ok = own_allowed(sl, own);
-    const int64_t conn_own = (uint32_t)own < (uint32_t)K ? gld(row, own) : 0;
+    const int64_t conn_own = act && (uint32_t)own < (uint32_t)K ? gld(row, own) : 0;
     bool foreign = false;
     uint64_t best = 0;
     auto consider = [&](int t, int64_t c) {
@@ -2618,25 +2629,39 @@ __global__ void __launch_bounds__(256) k_rate_cached(const DevSlot* __restrict__
         best = best > k ? best : k;
       }
     };
-    if ((K & 3) == 0) {
-      // rows of a multiple of 4 columns are 16-byte aligned
-      const int4* row4 = (const int4*)row;
-      for (int t = 0; t < K; t += 4) {
-        const int4 q = row4[t >> 2];
-        consider(t, q.x);
-        consider(t + 1, q.y);
-        consider(t + 2, q.z);
-        consider(t + 3, q.w);
+    if (act) {
+      if ((K & 3) == 0) {
+        // rows of a multiple of 4 columns are 16-byte aligned
+        const int4* row4 = (const int4*)row;
+        for (int t = 4 * g; t < K; t += 4 * G) {
+          const int4 q = row4[t >> 2];
+          consider(t, q.x);
+          consider(t + 1, q.y);
+          consider(t + 2, q.z);
+          consider(t + 3, q.w);
+        }
+      } else if (g == 0) {
+        for (int t = 0; t < K; ++t) consider(t, gld(row, t));
       }
-    } else {
-      for (int t = 0; t < K; ++t) consider(t, gld(row, t));
     }
-    if (own_ok) {
-      const uint64_t ok = pack_key(conn_own, own);
-      best = best > ok ? best : ok;
+    // the group's best candidate (a maximum) and whether any lane saw a
+    // foreign block
+    int any = foreign ? 1 : 0;
+    for (int off = 1; off < G; off <<= 1) {
+      const uint32_t lo32 = __shfl_xor((uint32_t)best, off);
+      const uint32_t hi32 = __shfl_xor((uint32_t)(best >> 32), off);
+      const uint64_t o = ((uint64_t)hi32 << 32) | lo32;
+      best = best > o ? best : o;
+      any |= __shfl_xor(any, off);
     }
-    gst(sl.desire, v, best ? key_label(best) : own);
-    if (foreign) gst(sl.flag_next, v, (uint8_t)1);
+    if (act && g == 0) {
+      if (own_ok) {
+        const uint64_t ok = pack_key(conn_own, own);
+        best = best > ok ? best : ok;
+      }
+      gst(sl.desire, v, best ? key_label(best) : own);
+      if (any) gst(sl.flag_next, v, (uint8_t)1);
+    }
   }
 }
 
@@ -2831,7 +2856,7 @@ int launch_conn_build(const DevSlot* S, int ns, const int32_t* bins, const uint6
 
 int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt,
                        hipStream_t st) {
-  LAUNCH(k_rate_cached, grid_for(N, 256, 4096), 256, S, ns, rated, rcnt);
+  LAUNCH(k_rate_cached, grid_for(N, 32, 8192), 256, S, ns, rated, rcnt);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }
