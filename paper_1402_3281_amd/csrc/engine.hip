@@ -579,6 +579,7 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and label
   // parts, [13] refinement movers, [15] big movers, [16] contended set too
   // large for the one-workgroup path, [17] an LDS hash table filled up,
+  // [18] movers with rows above 65536 entries,
   // [24..25] hub pair pool cursor (u64).  The binning results live in c->binmeta:
   // u32 [0..8] bin counts, [14] rated; u64 at byte 128: visits per bin.
   // Clustering rounds of the same jobs on the same levels rate the same
@@ -684,8 +685,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   // entries they walk (u64 at words 20..21 of the round counters)
   unsigned long long* mark_entries = c->profile ? (unsigned long long*)(small + 20) : nullptr;
   hipEvent_t* mark_ev = c->profile ? c->ev + kRateGroups + 3 : nullptr;
-  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, small + 16, st,
-                         mark_ev, mark_entries));
+  SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, small + 18, (int64_t)Nz, any_other,
+                         any_refine, small + 16, st, mark_ev, mark_entries));
   const size_t rd = 256 + (size_t)ns * CTR_N * sizeof(int64_t);
   SCLAP_TRY(ctx_ensure_pin(c, rd + 512));
   SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
@@ -723,8 +724,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
                                     (const int64_t*)c->prefix.p, st));
     SCLAP_TRY(launch_contended_add(S, ns, (const uint64_t*)c->ckeys2.p, cc, node_bits,
                                    (const int64_t*)c->prefix.p, st));
-    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, any_other, any_refine, nullptr, st,
-                           mark_ev, mark_entries));
+    SCLAP_TRY(launch_apply(S, ns, N, rated, meta + 14, mold, big, small + 15, small + 18, (int64_t)Nz, any_other,
+                           any_refine, nullptr, st, mark_ev, mark_entries));
     SCLAP_HIP(hipMemcpyAsync(c->pin, small, rd, hipMemcpyDeviceToHost, st));
     SCLAP_HIP(hipStreamSynchronize(st));
   }

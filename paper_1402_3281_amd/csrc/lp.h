@@ -95,12 +95,15 @@ int launch_rate_cached(const DevSlot* S, int ns, int64_t N, const int32_t* rated
 // refinement writes the old block of every admitted mover by rated position
 // (mold, -1: stayed) and then marks the movers' neighbours (updating block
 // connections) for every refinement slot.  big == NULL: no row has more than
-// 4096 entries (no grid-wide walk is launched).
+// 4096 entries (no walk of long rows is launched); else big (big_cap entries)
+// lists the movers with longer rows, counted by big_cnt from its front and,
+// above 65536 entries, by huge_cnt from its back.
 // mark_ev (may be NULL): two events recorded around the marking kernels;
 // mark_entries (may be NULL): receives the number of mover entries walked.
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
-                 int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
-                 hipStream_t st, hipEvent_t* mark_ev = nullptr, unsigned long long* mark_entries = nullptr);
+                 int32_t* big, uint32_t* big_cnt, uint32_t* huge_cnt, int64_t big_cap, bool run_apply,
+                 bool any_refine, const uint32_t* skip, hipStream_t st, hipEvent_t* mark_ev = nullptr,
+                 unsigned long long* mark_entries = nullptr);
 // Admission and application of the moves of refinement slots with at most
 // kConnMaxK blocks, by binning tiles (roff: the rated-list offsets of the
 // tiles from launch_bin's scratch, see bin_rated_offsets; kmax: the largest

@@ -2031,8 +2031,10 @@ __global__ void __launch_bounds__(256) k_apply(const DevSlot* __restrict__ S, in
 // block a to block b moves w from conn(v, a) to conn(v, b).  Each wave takes
 // 64 movers; rows of up to 64 entries are walked by their lane, rows of up
 // to kMarkBig entries by the whole wave; longer rows are listed (by mover
-// index) and walked by all workgroups together (k_mark_big).
+// index) for k_mark_big: rows of up to kMarkHuge entries are walked by one
+// workgroup each, longer ones by all workgroups together.
 constexpr int64_t kMarkBig = 4096;
+constexpr int64_t kMarkHuge = 65536;
 
 __device__ __forceinline__ void conn_add(int32_t* conn, int64_t i, int32_t v) {
   __hip_atomic_fetch_add((SCLAP_GLOBAL int*)(conn + i), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2164,6 +2166,7 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
                                               const int32_t* __restrict__ rated, const uint32_t* __restrict__ rcnt,
                                               const int32_t* __restrict__ mold,
                                               int32_t* __restrict__ big, uint32_t* __restrict__ big_cnt,
+                                              uint32_t* __restrict__ huge_cnt, int64_t big_cap,
                                               const uint32_t* __restrict__ skip,
                                               unsigned long long* __restrict__ entries) {
   __shared__ int32_t s_ex[4][kWave];
@@ -2227,7 +2230,12 @@ __global__ void __launch_bounds__(256) k_mark(const DevSlot* __restrict__ S, int
       }
     }
     // without a big list (no row above kMarkBig) the wave walks every row
-    if (big && d > kMarkBig) big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
+    // rows above kMarkBig go to the big list from its front, rows above
+    // kMarkHuge from its back (the two counts add up to at most big_cap)
+    if (big && d > kMarkBig) {
+      if (d > kMarkHuge) big[big_cap - 1 - (int64_t)atomicAdd(huge_cnt, 1u)] = (int32_t)i;
+      else big[atomicAdd(big_cnt, 1u)] = (int32_t)i;
+    }
     uint64_t mid = __ballot(d > kWave && (d <= kMarkBig || !big));
     while (mid) {
       const int l = __ffsll((unsigned long long)mid) - 1;
@@ -2244,12 +2252,26 @@ template <bool ONE>
 __global__ void __launch_bounds__(256) k_mark_big(const DevSlot* __restrict__ S, int ns,
                                                   const int32_t* __restrict__ rated, const int32_t* __restrict__ mold,
                                                   const int32_t* __restrict__ big, const uint32_t* __restrict__ big_cnt,
+                                                  const uint32_t* __restrict__ huge_cnt, int64_t big_cap,
                                                   const uint32_t* __restrict__ skip) {
   if (skip && *skip) return;
+  // rows of up to kMarkHuge entries: one workgroup each
   const uint32_t cnt = *big_cnt;
+  for (uint32_t k = blockIdx.x; k < cnt; k += gridDim.x) {
+    const uint32_t mi = (uint32_t)big[k];
+    const int64_t u = rated[mi];
+    const DevSlot& sl = S[SLOT(u)];
+    const int64_t v = u - sl.nbase;
+    int32_t a, b;
+    mover_blocks(sl, mold[mi], v, a, b);
+    const int64_t e0 = sl.rp[v], e1 = sl.rp[v + 1];
+    mark_row<4>(sl, e0, (int64_t)threadIdx.x, e1 - e0, (int)blockDim.x, a, b);
+  }
+  // longer rows: every workgroup takes a share of each
+  const uint32_t hc = *huge_cnt;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (uint32_t i = 0; i < cnt; ++i) {
-    const uint32_t mi = (uint32_t)big[i];
+  for (uint32_t k = 0; k < hc; ++k) {
+    const uint32_t mi = (uint32_t)big[big_cap - 1 - (int64_t)k];
     const int64_t u = rated[mi];
     const DevSlot& sl = S[SLOT(u)];
     const int64_t v = u - sl.nbase;
@@ -2902,14 +2924,15 @@ int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const
 }
 
 int launch_apply(const DevSlot* S, int ns, int64_t N, const int32_t* rated, const uint32_t* rcnt, int32_t* mold,
-                 int32_t* big, uint32_t* big_cnt, bool run_apply, bool any_refine, const uint32_t* skip,
-                 hipStream_t st, hipEvent_t* mark_ev, unsigned long long* mark_entries) {
+                 int32_t* big, uint32_t* big_cnt, uint32_t* huge_cnt, int64_t big_cap, bool run_apply,
+                 bool any_refine, const uint32_t* skip, hipStream_t st, hipEvent_t* mark_ev,
+                 unsigned long long* mark_entries) {
   if (run_apply) LAUNCH(k_apply, grid_for(N, kAggNodes, kAggGrid), 256, S, ns, rated, rcnt, mold, skip);
   if (any_refine) {
     if (mark_ev) SCLAP_HIP(hipEventRecord(mark_ev[0], st));
-    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, skip,
-           mark_entries);
-    if (big) LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, skip);
+    LAUNCH(k_mark, grid_for(N, 256 * kWave / 4, 2048), 256, S, ns, rated, rcnt, mold, big, big_cnt, huge_cnt,
+           big_cap, skip, mark_entries);
+    if (big) LAUNCH(k_mark_big, 1024, 256, S, ns, rated, mold, big, big_cnt, huge_cnt, big_cap, skip);
     if (mark_ev) SCLAP_HIP(hipEventRecord(mark_ev[1], st));
   }
   SCLAP_HIP(hipGetLastError());
