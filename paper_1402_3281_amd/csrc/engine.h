@@ -123,9 +123,9 @@ struct Ctx {
   size_t cache_bytes = 0;
   size_t cache_limit = (size_t)96 << 30;  // bytes kept cached at most
   // scratch reused by every step
-  Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys, hub_gvals;
+  Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
-  Scratch hub_P, hub_ptot, hub_pbase, hub_mat, binscr, cutbuf, tadm, hub_keep, trows, part8, lab8;
+  Scratch hub_P, hub_ptot, hub_mat, binscr, cutbuf, tadm, hub_keep, trows, part8, lab8;
   // jobs and levels whose nodes the current bins hold (clustering rounds only)
   std::vector<std::pair<const void*, int>> bin_sig;
   bool bin_sig_valid = false;
@@ -202,8 +202,9 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st);
 // bins, hub own/best rows (16 B), rated list, old blocks and big movers
 // (12 B), contended keys (8 B) and their sort/scan buffers (28 B, plus sort
 // space), hub layout rows (20 B), binning and tile-admission scans; per
-// stored entry the staged and pooled (label, sum) pairs of hub rows (16 B per
-// pair, at most 1.5 pairs per entry) and the hub chunk x part matrix.
+// stored entry the staged (label, sum) pairs of hub rows (8 B per pair, room
+// for a whole chunk of pairs per chunk of entries) and the hub chunk x part
+// matrix.
 constexpr int64_t kRoundBytesPerNode = 320;
 constexpr int64_t kRoundBytesPerEntry = 40;
 // Temporaries of contracting a level, per stored entry: the cross keys as

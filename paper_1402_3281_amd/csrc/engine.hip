@@ -172,9 +172,9 @@ int ctx_tile_rows(Ctx* c, const int64_t* rp, int64_t n, int64_t m, const int32_t
 void ctx_release(Ctx* c, hipStream_t st) {
   ctx_trim(c);
   Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
-                    &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->hub_gvals, &c->step_ctr, &c->small,
+                    &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
-                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_pbase, &c->hub_mat,
+                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_mat,
                     &c->binscr, &c->cutbuf, &c->tadm, &c->hub_keep, &c->trows, &c->part8, &c->lab8};
   c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
@@ -547,8 +547,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_maps.ensure(2 * map_cap * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_mat.ensure((size_t)std::max<int64_t>(hub_mat, 1) * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_gkeys.ensure((size_t)hub_stage * sizeof(int2), st));
-    SCLAP_TRY(c->hub_gvals.ensure((size_t)hub_stage * sizeof(int2), st));
-    SCLAP_TRY(c->hub_pbase.ensure((size_t)hub_parts * sizeof(int64_t), st));
     if (c->hub_parts_cap < hub_parts || !c->hub_ptot.p) {
       // the capacity is only valid with its buffer: a failed allocation
       // leaves hub_ptot empty, and the next round must not take the old
@@ -579,8 +577,8 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   // u32 [9] contended, [10] hub overflow, [11..12] hub chunks and label
   // parts, [13] refinement movers, [15] big movers, [16] contended set too
   // large for the one-workgroup path, [17] an LDS hash table filled up,
-  // [18] movers with rows above 65536 entries,
-  // [24..25] hub pair pool cursor (u64).  The binning results live in c->binmeta:
+  // [18] movers with rows above 65536 entries, [20..21] mover entries
+  // walked (u64, measurement only).  The binning results live in c->binmeta:
   // u32 [0..8] bin counts, [14] rated; u64 at byte 128: visits per bin.
   // Clustering rounds of the same jobs on the same levels rate the same
   // nodes, so their bins are reused.
@@ -626,14 +624,11 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_keep.ensure(64, st));
     hub.totals = small + 11;
     hub.totals_kept = (uint32_t*)c->hub_keep.p;
-    hub.pool_cursor = (unsigned long long*)(small + 24);
     hub.part_total = (uint32_t*)c->hub_ptot.p;
-    hub.part_base = (int64_t*)c->hub_pbase.p;
     hub.parts_cap = hub_parts;
     hub.mat = (uint32_t*)c->hub_mat.p;
     hub.mat_cap = hub_mat;
     hub.stage = (int2*)c->hub_gkeys.p;
-    hub.pool = (int2*)c->hub_gvals.p;
     hub.stage_cap = hub_stage;
     hub.own = (int64_t*)c->hub_own.p;
     hub.best = (unsigned long long*)c->hub_best.p;

@@ -17,14 +17,11 @@ struct HubLayout {
   int64_t map_cap;
   uint32_t* totals;       // 2: chunks, parts
   uint32_t* totals_kept;  // 2: the same, kept between rounds (the layout is reused with the bins)
-  unsigned long long* pool_cursor;  // 1
   uint32_t* part_total;   // parts_cap: pairs of every part (kept 0)
-  int64_t* part_base;     // parts_cap: segment of every part in the pool
   int64_t parts_cap;
-  uint32_t* mat;          // mat_cap: per chunk, staged part offsets (P + 1) and reservations (P)
+  uint32_t* mat;          // mat_cap: per chunk, the first staged pair of each part (P + 1)
   int64_t mat_cap;
-  int2* stage;            // stage_cap: (label, weight sum) pairs, kHubChunk per chunk
-  int2* pool;             // stage_cap: the same pairs grouped by part
+  int2* stage;            // stage_cap: (label, weight sum) pairs, kHubChunk per chunk, grouped by part
   int64_t stage_cap;
   int64_t* own;           // hubs: own-label connection (kept 0)
   unsigned long long* best;  // hubs: best foreign candidate key (kept 0)

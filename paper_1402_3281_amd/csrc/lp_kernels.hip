@@ -1046,13 +1046,12 @@ __global__ void __launch_bounds__(512) k_rate_large(const DevSlot* __restrict__ 
 //   prep     per hub: chunks of kHubChunk entries, label parts (a power of
 //            two, about kHubPartLabels distinct labels each), offsets
 //   chunk    per chunk: labels aggregated in an LDS table; the chunk's
-//            (label, sum) pairs are staged grouped by part, and every part
-//            reserves its range with one atomic on the part's counter
-//   alloc    per part: its segment of the pair pool (block scan + one
-//            atomic per workgroup)
-//   scatter  per chunk: staged pairs copied into their parts' segments
-//   part     per part: pairs aggregated in LDS; the best eligible label of
-//            the part, combined per hub with an integer maximum
+//            (label, sum) pairs are staged grouped by part (the part's first
+//            pair noted in the hub's chunk x part matrix), and every part's
+//            pair count is summed with one atomic per chunk
+//   part     per part: the part's pairs, read from every chunk of its hub,
+//            aggregated in LDS; the best eligible label of the part,
+//            combined per hub with an integer maximum
 //   final    per hub: the own label against the best foreign one.
 // Every label of a hub falls in exactly one part, so the per-part sums are
 // the node's connections.
@@ -1081,7 +1080,6 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
     carry_c = 0;
     carry_p = 0;
     carry_m = 0;
-    *L.pool_cursor = 0;
   }
   __syncthreads();
   for (uint32_t base = 0; base < cnt; base += blockDim.x) {
@@ -1095,7 +1093,7 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
       const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
       nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
       np = hub_parts(d, sl.nlabels);
-      nm = (int64_t)nc * (2 * np + 1);
+      nm = (int64_t)nc * (np + 1);
       L.hub_P[i] = np;
     }
     sc[threadIdx.x] = nc;
@@ -1148,7 +1146,6 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
 __global__ void k_hub_reuse(HubLayout L) {
   L.totals[0] = L.totals_kept[0];
   L.totals[1] = L.totals_kept[1];
-  *L.pool_cursor = 0;
 }
 
 constexpr int kHubChunkThreads = 512;
@@ -1202,8 +1199,8 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
         best = best > k ? best : k;
       }
       best = block_reduce(best, reinterpret_cast<uint64_t*>(redi), OpMax64());
-      uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (2 * P + 1);
-      for (uint32_t p = threadIdx.x; p < 2 * P + 1; p += NT) mat_loff[p] = 0u;
+      uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (P + 1);
+      for (uint32_t p = threadIdx.x; p <= P; p += NT) mat_loff[p] = 0u;
       if (threadIdx.x == 0 && best) atomicMax(&L.best[i], (unsigned long long)best);
       __syncthreads();
       continue;
@@ -1301,14 +1298,14 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
       if (threadIdx.x == NT - 1) loff[P] = run;
     }
     __syncthreads();
-    // chunk x part matrix: staged offsets and each part's reserved range
-    uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (2 * P + 1);
-    uint32_t* mat_pos = mat_loff + P + 1;
+    // chunk x part matrix: the part offsets of the staged pairs; each part's
+    // pair count
+    uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (P + 1);
     for (uint32_t p = threadIdx.x; p <= P; p += NT) {
       mat_loff[p] = loff[p];
       if (p < P) {
         const uint32_t k = loff[p + 1] - loff[p];
-        mat_pos[p] = k ? atomicAdd(&L.part_total[L.part_off[i] + p], k) : 0u;
+        if (k) atomicAdd(&L.part_total[L.part_off[i] + p], k);
       }
     }
     // staged pairs grouped by part; the used slots are cleared
@@ -1325,64 +1322,17 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
   }
 }
 
-// Segment of every part in the pair pool.
-__global__ void __launch_bounds__(256) k_hub_alloc(HubLayout L) {
-  __shared__ uint64_t s_w[4];
-  __shared__ uint64_t s_base;
-  if (*L.overflow) return;
-  const uint32_t nparts = L.totals[1];
-  const int w = threadIdx.x / kWave;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < nparts; base += gridDim.x * blockDim.x) {
-    const uint32_t g = base + threadIdx.x;
-    const uint64_t t = g < nparts ? L.part_total[g] : 0;
-    uint64_t incl = t;
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint64_t o = __shfl_up(incl, off);
-      if ((int)lane_id() >= off) incl += o;
-    }
-    if (lane_id() == kWave - 1) s_w[w] = incl;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint64_t tot = 0;
-      for (int k = 0; k < 4; ++k) {
-        const uint64_t x = s_w[k];
-        s_w[k] = tot;
-        tot += x;
-      }
-      s_base = tot ? atomicAdd(L.pool_cursor, (unsigned long long)tot) : 0;
-    }
-    __syncthreads();
-    if (g < nparts) L.part_base[g] = (int64_t)(s_base + s_w[w] + incl - t);
-    __syncthreads();
-  }
-}
-
-// Staged pairs of every chunk into their parts' segments.
-__global__ void __launch_bounds__(256) k_hub_scatter(HubLayout L) {
-  if (*L.overflow) return;
-  const uint32_t nchunks = L.totals[0];
-  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const uint32_t i = L.chunk_hub[c];
-    const uint32_t lc = c - L.chunk_off[i];
-    const uint32_t P = L.hub_P[i];
-    const uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (2 * P + 1);
-    const uint32_t* mat_pos = mat_loff + P + 1;
-    const int64_t* pbase = L.part_base + L.part_off[i];
-    const uint32_t tot = mat_loff[P];
-    const int2* stage = L.stage + (int64_t)c * kHubChunk;
-    for (uint32_t j = threadIdx.x; j < tot; j += blockDim.x) {
-      const int2 pr = stage[j];
-      const uint32_t p = hub_part_of(pr.x, P);
-      L.pool[pbase[p] + mat_pos[p] + (j - mat_loff[p])] = pr;
-    }
-  }
-}
-
-// Best eligible label of every part; the part's counter is reset.  A part
-// whose distinct labels would overfill the LDS table is taken in Q passes,
-// each over the labels of one residue of a further hash (Q doubles until the
-// passes fit), so any label distribution is handled exactly.
+// Best eligible label of every part; the part's counter is reset.  The
+// part's pairs are read where its hub's chunks staged them: for hubs of up
+// to kHubFlat chunks, the workgroup's threads stride over the part's pairs
+// of all chunks in a row (each finds its chunk by binary search over the
+// prefix of the chunks' pair counts in LDS); larger hubs take a thread per
+// chunk.  A part whose distinct labels would overfill the LDS table is taken
+// in Q passes, each over the labels of one residue of a further hash (Q
+// doubles until the passes fit), so any label distribution is handled
+// exactly.
 constexpr uint32_t kHubMaxPasses = 64;
+constexpr uint32_t kHubFlat = 512;
 
 template <bool ONE>
 __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S, int ns,
@@ -1391,8 +1341,13 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
   __shared__ int32_t vals[kHubPartTable];
   __shared__ uint32_t s_used;
   __shared__ uint64_t red64[8];
+  __shared__ uint32_t s_beg[kHubFlat];      // first pair of the part in each chunk's stage
+  __shared__ uint32_t s_pre[kHubFlat + 1];  // exclusive prefix of the chunks' pair counts
+  __shared__ uint32_t s_wsum[4];
+  constexpr uint32_t NT = 256;
   if (*L.overflow) return;
   const uint32_t nparts = L.totals[1];
+  const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
   for (uint32_t g = blockIdx.x; g < nparts; g += gridDim.x) {
     const uint32_t i = L.part_hub[g];
     const int64_t u = list[i];
@@ -1403,7 +1358,46 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
     const int64_t conn_own = L.own[i];
     const bool own_ok = own_allowed(sl, own);
     const uint32_t len = L.part_total[g];
-    const int2* seg = L.pool + L.part_base[g];
+    const uint32_t P = L.hub_P[i];
+    const uint32_t pp = g - L.part_off[i];
+    const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
+    const uint32_t nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
+    const uint32_t* mat = L.mat + L.mat_off[i];
+    const int2* stage0 = L.stage + (int64_t)L.chunk_off[i] * kHubChunk;
+    const bool flat = nc <= kHubFlat;
+    if (flat) {
+      // two chunks per thread: their pair counts, scanned across the workgroup
+      uint32_t c2[2], tot = 0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const uint32_t lc = 2 * threadIdx.x + q;
+        c2[q] = 0;
+        if (lc < nc) {
+          const uint32_t* ml = mat + (int64_t)lc * (P + 1);
+          const uint32_t b0 = ml[pp];
+          s_beg[lc] = b0;
+          c2[q] = ml[pp + 1] - b0;
+        }
+        tot += c2[q];
+      }
+      uint32_t incl = tot;
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if ((int)lane >= off) incl += o;
+      }
+      if (lane == kWave - 1) s_wsum[wave] = incl;
+      __syncthreads();
+      uint32_t run = incl - tot;
+      for (uint32_t k = 0; k < wave; ++k) run += s_wsum[k];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const uint32_t lc = 2 * threadIdx.x + q;
+        if (lc < nc) s_pre[lc] = run;
+        run += c2[q];
+      }
+      if (threadIdx.x == NT - 1) s_pre[nc] = run;
+      __syncthreads();
+    }
     uint64_t best = 0;
     for (uint32_t Q = 1;; Q <<= 1) {
       if (Q > kHubMaxPasses) {
@@ -1417,16 +1411,16 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
       bool fits = true;
       best = 0;
       for (uint32_t q = 0; q < Q && fits; ++q) {
-        for (uint32_t j = threadIdx.x; j < tsz; j += blockDim.x) {
+        for (uint32_t j = threadIdx.x; j < tsz; j += NT) {
           keys[j] = -1;
           vals[j] = 0;
         }
         if (threadIdx.x == 0) s_used = 0;
         __syncthreads();
-        for (uint32_t j = threadIdx.x; j < len; j += blockDim.x) {
-          const int2 pr = seg[j];
+        // false once the table is too full for this pass (more passes follow)
+        auto insert = [&](int2 pr) -> bool {
           const uint32_t hh = hash32((uint32_t)pr.x);
-          if (((hh >> 12) & (Q - 1)) != q) continue;
+          if (((hh >> 12) & (Q - 1)) != q) return true;
           uint32_t h = hh & mask;
           for (uint32_t probes = 0;; ++probes) {
             if (probes > mask) {
@@ -1441,12 +1435,32 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
             }
             h = (h + 1) & mask;
           }
-          if (s_used > (uint32_t)kHubPartFill) break;  // table too full: more passes
+          return s_used <= (uint32_t)kHubPartFill;
+        };
+        if (flat) {
+          const uint32_t total = s_pre[nc];
+          for (uint32_t x = threadIdx.x; x < total; x += NT) {
+            uint32_t lo = 0, hi = nc - 1;  // the last chunk whose pairs start at or before x
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi + 1) >> 1;
+              if (s_pre[mid] <= x) lo = mid;
+              else hi = mid - 1;
+            }
+            if (!insert(stage0[(int64_t)lo * kHubChunk + s_beg[lo] + (x - s_pre[lo])])) break;
+          }
+        } else {
+          bool go = true;
+          for (uint32_t lc = threadIdx.x; lc < nc && go; lc += NT) {
+            const uint32_t* ml = mat + (int64_t)lc * (P + 1);
+            const uint32_t s0 = ml[pp], s1 = ml[pp + 1];
+            const int2* st = stage0 + (int64_t)lc * kHubChunk;
+            for (uint32_t j = s0; j < s1 && go; ++j) go = insert(st[j]);
+          }
         }
         __syncthreads();
         fits = s_used <= (uint32_t)kHubPartFill;
         if (fits) {
-          uint64_t b = scan_table<8>(sl, keys, vals, tsz, threadIdx.x, blockDim.x, own_ok, conn_own, own, cv);
+          uint64_t b = scan_table<8>(sl, keys, vals, tsz, threadIdx.x, NT, own_ok, conn_own, own, cv);
           b = block_reduce(b, red64, OpMax64());
           best = best > b ? best : b;
         }
@@ -2808,8 +2822,6 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
     LAUNCH(k_hub_chunk, G, kHubChunkThreads, S, ns, hb, hub);
     if (!hubs_ident) {
       // (first clustering rounds stage no pairs: their chunks went to the hubs' best directly)
-      hipLaunchKernelGGL(k_hub_alloc, dim3(G), dim3(256), 0, st, hub);
-      hipLaunchKernelGGL(k_hub_scatter, dim3(G), dim3(256), 0, st, hub);
       LAUNCH(k_hub_part, G, 256, S, ns, hb, hub);
     }
     LAUNCH(k_hub_final, 64, 256, S, ns, hb, hc, hub);

@@ -64,9 +64,9 @@ __global__ void __launch_bounds__(256) k_graph_totals(const int64_t* __restrict_
       acc[3] += nc * kHubChunk;
       acc[4] += 1;
       acc[5] += pc;
-      acc[6] += nc * (2 * pc + 1);
+      acc[6] += nc * (pc + 1);
       acc[7] += pr;
-      acc[8] += nc * (2 * pr + 1);
+      acc[8] += nc * (pr + 1);
     }
   }
   // wave, then workgroup combination: one atomic per workgroup and counter

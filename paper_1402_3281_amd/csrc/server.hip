@@ -75,8 +75,8 @@ int64_t input_bytes_of(const sclap_csr& g) {
 //   - its share of the context scratch that every fused round sizes by the
 //     total node count of the round: kRoundBytesPerNode per node (degree
 //     bins and rows, rated list, movers, contended keys, hub rows, tile
-//     admission) and kRoundBytesPerEntry per stored entry (the staged and
-//     pooled (label, sum) pairs of hub rows);
+//     admission) and kRoundBytesPerEntry per stored entry (the staged
+//     (label, sum) pairs of hub rows);
 //   - the temporaries of a contraction: kContractBytesPerEntry per stored
 //     entry of the contracted level (two key arrays, sums, sort space,
 //     mirror) and the initial-partition scratch (16 B per node);
