@@ -747,7 +747,7 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=0, help="R-MAT scale (two-graphs: 22, large: 26)")
     ap.add_argument("--graphs", type=int, default=512, help="batch size (batch)")
     ap.add_argument("--jobs", type=int, default=10000, help="jobs in the served stream (serve)")
-    ap.add_argument("--pool", type=int, default=128, help="distinct graphs the served jobs draw from (serve)")
+    ap.add_argument("--pool", type=int, default=1024, help="distinct graphs the served jobs draw from (serve)")
     ap.add_argument("--plain-jobs", type=int, default=1000, help="jobs run one by one for comparison (serve)")
     ap.add_argument("--capacity-jobs", type=int, default=2000, help="jobs of the closed-loop capacity run (serve)")
     ap.add_argument("--rate", type=float, default=0.0, help="arrival rate in jobs/s (serve; default 0.8 x capacity)")

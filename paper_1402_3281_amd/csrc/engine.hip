@@ -516,17 +516,23 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   }
   if (N >= ((int64_t)1 << 31) || Lt >= ((int64_t)1 << 32))
     return fail(SCLAP_EINVAL, "fused round larger than 2^31 nodes");
-  if (any_build) {
-    // slots that build block connections gather their neighbours' blocks
-    // from a byte copy of the blocks (a quarter of the bytes to cache)
+  // slots of at least kLab8Nodes nodes that build block connections gather
+  // their neighbours' blocks from a byte copy of the blocks (a quarter of the
+  // bytes to cache); smaller levels' blocks stay in the caches anyway, and a
+  // batch of many small graphs would pay a launch per slot
+  constexpr int64_t kLab8Nodes = (int64_t)1 << 20;
+  auto wants_lab8 = [&](const DevSlot& d) { return d.conn_mode == CONN_BUILD && d.n >= kLab8Nodes; };
+  bool any_lab8 = false;
+  for (int s = 0; s < ns; ++s) any_lab8 = any_lab8 || wants_lab8(c->pin_slots[s]);
+  if (any_lab8) {
     int64_t bytes = 0;
     for (int s = 0; s < ns; ++s)
-      if (c->pin_slots[s].conn_mode == CONN_BUILD) bytes += (c->pin_slots[s].n + 255) / 256 * 256;
+      if (wants_lab8(c->pin_slots[s])) bytes += (c->pin_slots[s].n + 255) / 256 * 256;
     SCLAP_TRY(c->lab8.ensure((size_t)std::max<int64_t>(bytes, 256), st));
     int64_t off = 0;
     for (int s = 0; s < ns; ++s) {
       DevSlot& d = c->pin_slots[s];
-      if (d.conn_mode != CONN_BUILD) continue;
+      if (!wants_lab8(d)) continue;
       uint8_t* b = (uint8_t*)c->lab8.p + off;
       SCLAP_TRY(narrow_u8(d.lab, d.n, b, st));
       d.lab8 = b;
