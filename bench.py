@@ -35,9 +35,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-RATE_KERNELS = ["k_rate_tiny (degree 1-32)", "k_rate_small (degree 33-128)", "k_rate_mid (degree 129-1024)",
-                "k_rate_large (degree 1025-4096)", "hub path (6 kernels, degree > 4096)",
-                "k_mark + k_mark_big (refinement marking)"]
+RATE_KERNELS = ["k_rate_tiny + k_rate_b32 (degree 1-32)", "k_rate_small (bins 3-4, degree 33-128 by default)",
+                "k_rate_mid (bins 5-6, degree 129-1024 by default)", "k_rate_large (bin 7, degree up to 4096)",
+                "hub path (degree > 4096)", "k_mark + k_mark_big (refinement marking)"]
 
 
 def log(msg: str) -> None:
@@ -133,7 +133,7 @@ def roofline(prof: dict, workload: str) -> tuple[dict, list]:
 # Kernels of each launch group (the roofline groups above), and the kernels
 # of an LP round as a whole, for the rocprofv3 counter summaries.
 GROUP_KERNELS = [["k_rate_tiny", "k_rate_b32"], ["k_rate_small"], ["k_rate_mid"], ["k_rate_large"],
-                 ["k_hub_prep", "k_hub_chunk", "k_hub_alloc", "k_hub_scatter", "k_hub_part", "k_hub_final"],
+                 ["k_hub_prep", "k_hub_reuse", "k_hub_chunk", "k_hub_part", "k_hub_final"],
                  ["k_mark", "k_mark_big"]]
 ROUND_KERNELS = {k for g in GROUP_KERNELS for k in g} | {
     "k_round_begin", "k_bin_count", "k_bin_write", "k_bin_scan1", "k_bin_totals", "k_conn_build", "k_conn_zero_hubs",

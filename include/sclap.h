@@ -409,10 +409,11 @@ int sclap_profile_kernels(sclap_ctx* ctx, int32_t count, double* ms, double* byt
 /* Nodes of degree 1..32 are rated one thread per node (unit weights) and
  * nodes of degree above 4096 by the hub path; degrees in between go to bins
  * 3..7, whose kernels are: bin 3 one wave with a 128-slot LDS table, bin 4
- * one wave with 256 slots, bin 5 one wave with 1024, bin 6 one workgroup with
- * 2048, bin 7 one workgroup with 8192.  hi[0..3] are the largest degrees of
- * bins 3..6: 32 <= hi[0] <= 64, hi[0] <= hi[1] <= 128, hi[1] <= hi[2] <= 512,
- * hi[2] <= hi[3] <= 1024 (default 64, 128, 512, 1024).  The bounds change
+ * one wave with 256 slots, bin 5 one wave with 1024, bin 6 one workgroup of
+ * 256 threads with up to 4096, bin 7 one workgroup of 512 with up to 8192.
+ * hi[0..3] are the largest degrees of bins 3..6: 32 <= hi[0] <= 64,
+ * hi[0] <= hi[1] <= 128, hi[1] <= hi[2] <= 512, hi[2] <= hi[3] <= 2048
+ * (default 64, 128, 512, 1024).  The bounds change
  * only which kernel rates a node, never the result; they apply to the
  * clustering rounds of the context's later calls. */
 int sclap_set_bin_bounds(sclap_ctx* ctx, const int32_t* hi);
@@ -420,7 +421,7 @@ int sclap_get_bin_bounds(sclap_ctx* ctx, int32_t* hi);
 /* Autotuner: times `rounds` clustering rounds of g under cap U (no stop
  * rule; the best of two runs) with the default bounds and with each of a
  * grid of candidate bounds (hi[0] in {32, 64}, hi[1] in {64, 128}, hi[2] in
- * {128, 256, 512}, hi[3] in {512, 1024}, rising), keeps the fastest in the
+ * {128, 256, 512}, hi[3] in {512, 1024, 2048}, rising), keeps the fastest in the
  * context and returns it in hi_out (4 entries, may be NULL) with its time
  * and the default bounds' time in ms (may be NULL).  Synchronous. */
 int sclap_autotune(sclap_ctx* ctx, const sclap_csr* g, int64_t U, int32_t rounds, int32_t* hi_out, double* best_ms,

@@ -679,7 +679,7 @@ int sclap_autotune(sclap_ctx* ctx, const sclap_csr* g, int64_t U, int32_t rounds
   for (int32_t h0 : {32, 64})
     for (int32_t h1 : {64, 128})
       for (int32_t h2 : {128, 256, 512})
-        for (int32_t h3 : {512, 1024})
+        for (int32_t h3 : {512, 1024, 2048})
           if (h1 >= h0 && h2 >= h1 && h3 >= h2) cand.push_back({h0, h1, h2, h3});
   sclap_lp_params p{rounds, 0, 1, 0};
   const std::array<int32_t, 4> saved{c->tune_hi[0], c->tune_hi[1], c->tune_hi[2], c->tune_hi[3]};

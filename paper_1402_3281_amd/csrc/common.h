@@ -95,17 +95,19 @@ enum : int { CTR_MOVED = 0, CTR_VISITS = 1, CTR_MOVERS = 2, CTR_STALE = 3, CTR_N
 
 // Degree bins of the rating kernels:
 //   0: 1..8       8 lanes per node        5: 129..512    one wave, 1024-entry LDS table
-//   1: 9..16      16 lanes per node       6: 513..1024   one workgroup, 2048-entry LDS table
+//   1: 9..16      16 lanes per node       6: 513..1024   one workgroup of 256, LDS table of up to 4096
 //   2: 17..32     32 lanes per node       7: 1025..4096  one workgroup, 8192-entry LDS table
 //   3: 33..64     one wave, 128-entry LDS 8: > 4096      several workgroups, global table
 //   4: 65..128    one wave, 256-entry LDS table
 constexpr int kBins = 9;
 // Default upper degree bounds of bins 3..6, and the most each bin's kernel
 // takes (its table holds twice the degree): bin 3 one wave with 128 slots,
-// bin 4 one wave with 256, bin 5 one wave with 1024, bin 6 one workgroup with
-// 2048.  The lower bound of bin 3 (33) and of the hub bin (4097) are fixed.
+// bin 4 one wave with 256, bin 5 one wave with 1024, bin 6 one workgroup of
+// 256 threads with 4096 (bin 7 takes the rest up to 4096 with workgroups of
+// 512 and 8192 slots).  The lower bound of bin 3 (33) and of the hub bin
+// (4097) are fixed.
 constexpr int32_t kBinHiDefault[4] = {64, 128, 512, 1024};
-constexpr int32_t kBinHiCap[4] = {64, 128, 512, 1024};
+constexpr int32_t kBinHiCap[4] = {64, 128, 512, 2048};
 constexpr int kPathCounters = 5;
 constexpr int64_t kBinBlock = 4096;
 

@@ -1019,16 +1019,16 @@ __global__ void __launch_bounds__(256) k_rate_mid(const DevSlot* __restrict__ S,
                                                   const int32_t* __restrict__ bins,
                                                   const uint64_t* __restrict__ binfo, int64_t bin_cap,
                                                   const uint32_t* __restrict__ bin_cnt, uint32_t nblk) {
-  // bin 5: four wave tables of 2 x 1024; bin 6: one table of 2 x 2048 and
-  // the reduction scratch after it (32 KB in all: five workgroups per CU)
-  __shared__ __align__(16) int32_t lds[8 * 1024];
+  // bin 5: four wave tables of 2 x 1024; bin 6: one table of 2 x 4096 and
+  // the reduction scratch after it (32.9 KB in all: four workgroups per CU)
+  __shared__ __align__(16) int32_t lds[8 * 1024 + sizeof(BlockRed) / sizeof(int32_t)];
   const uint32_t b = 5 + blockIdx.x / nblk, bid = blockIdx.x % nblk;
   const int32_t* list = bins + b * bin_cap;
   const uint64_t* info = binfo + b * bin_cap;
   const uint32_t cnt = bin_cnt[b];
   if (b == 5) rate_wave_body<1024, ONE>(S, ns, list, info, cnt, bid, nblk, lds);
-  else rate_block_body<2048, 256, ONE>(S, ns, list, info, cnt, bid, nblk, lds,
-                                        reinterpret_cast<BlockRed*>(lds + 2 * 2048));
+  else rate_block_body<4096, 256, ONE>(S, ns, list, info, cnt, bid, nblk, lds,
+                                        reinterpret_cast<BlockRed*>(lds + 2 * 4096));
 }
 
 template <bool ONE>

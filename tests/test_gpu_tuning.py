@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 BOUNDS = [[64, 128, 512, 1024], [32, 64, 128, 512], [64, 128, 256, 1024], [32, 128, 512, 512],
-          [64, 64, 128, 512], [32, 32, 32, 32]]
+          [64, 64, 128, 512], [32, 32, 32, 32], [64, 128, 512, 2048], [32, 64, 256, 2048]]
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +65,7 @@ def test_bounds_in_a_fused_batch(sc, ctx):
 
 
 def test_invalid_bounds_rejected(sc, ctx):
-    for hi in ([16, 64, 128, 512], [64, 32, 128, 512], [64, 128, 1024, 1024], [64, 128, 512, 2048]):
+    for hi in ([16, 64, 128, 512], [64, 32, 128, 512], [64, 128, 1024, 1024], [64, 128, 512, 4096]):
         with pytest.raises(sc.SclapError):
             ctx.set_bin_bounds(hi)
     assert ctx.bin_bounds() == [64, 128, 512, 1024]
@@ -78,7 +78,7 @@ def test_autotune_keeps_admissible_bounds(sc):
         r = c.autotune(d, 300, rounds=2)
         print(r, flush=True)
         hi = r["bounds"]
-        assert 32 <= hi[0] <= 64 and hi[0] <= hi[1] <= 128 and hi[1] <= hi[2] <= 512 and hi[2] <= hi[3] <= 1024
+        assert 32 <= hi[0] <= 64 and hi[0] <= hi[1] <= 128 and hi[1] <= hi[2] <= 512 and hi[2] <= hi[3] <= 2048
         assert c.bin_bounds() == hi
         assert 0 < r["ms"] <= r["default_ms"]
         part, st = sc.partition(c, d, 16)
