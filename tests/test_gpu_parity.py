@@ -304,3 +304,32 @@ def test_empty_graph(sc, ctx):
         want_part, want = oracle.partition(gg, 4)
         assert np.array_equal(host(pp), want_part), gg.name
         assert st["cut"] == want["cut"] and st["rounds_r"] == want["rounds_r"], gg.name
+
+
+def many_hubs_graph(seed=12, n=40000, hubs=1100, samples=4600):
+    """`hubs` nodes of degree > 4096 joined to random leaves, plus random
+    leaf-leaf edges; symmetric CSR with ascending rows."""
+    rng = np.random.default_rng(seed)
+    u = np.concatenate([np.repeat(np.arange(hubs), samples), rng.integers(hubs, n, 60000)])
+    v = np.concatenate([rng.integers(hubs, n, hubs * samples), rng.integers(hubs, n, 60000)])
+    keep = u != v
+    key = np.unique(np.minimum(u, v)[keep].astype(np.int64) * n + np.maximum(u, v)[keep])
+    lo, hi = key // n, key % n
+    a, b = np.concatenate([lo, hi]), np.concatenate([hi, lo])
+    order = np.lexsort((b, a))
+    a, b = a[order], b[order]
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, a + 1, 1)
+    return graphgen.Graph(np.cumsum(rp), b.astype(np.int32))
+
+
+def test_many_hubs_over_many_rounds(sc, ctx):
+    """More than 1024 hubs (degree > 4096) clustered for 8 rounds: the hub
+    layout is scanned in several blocks of 1024 hubs, and from the fourth
+    round on each hub's label parts are sized by the pairs it staged two
+    rounds before; labels, moves and visits equal the oracle's."""
+    g = many_hubs_graph()
+    assert (np.diff(g.row_ptr)[:1100] > 4096).all()
+    before = ctx.path_counters()
+    assert_cluster_parity(sc, ctx, g, 300, 8)
+    assert ctx.path_counters()["hub_rounds"] - before["hub_rounds"] == 8
