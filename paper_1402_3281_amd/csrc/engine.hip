@@ -175,7 +175,7 @@ void ctx_release(Ctx* c, hipStream_t st) {
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
                     &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_mat,
-                    &c->binscr, &c->cutbuf, &c->tadm, &c->hub_keep, &c->trows, &c->part8, &c->lab8, &c->hub_dist};
+                    &c->binscr, &c->cutbuf, &c->tadm, &c->hub_keep, &c->trows, &c->part8, &c->lab8};
   c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
   (void)hipStreamSynchronize(st);
@@ -550,11 +550,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_slice.ensure((Nz + 1) * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_tab.ensure((Nz + 1) * sizeof(int64_t), st));
     SCLAP_TRY(c->hub_P.ensure(Nz * sizeof(uint32_t), st));
-    {
-      const void* before = c->hub_dist.p;
-      SCLAP_TRY(c->hub_dist.ensure(4 * Nz * sizeof(uint32_t), st));
-      if (c->hub_dist.p != before) c->hub_dist_valid[0] = c->hub_dist_valid[1] = false;  // no counts yet
-    }
     SCLAP_TRY(c->hub_maps.ensure(2 * map_cap * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_mat.ensure((size_t)std::max<int64_t>(hub_mat, 1) * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_gkeys.ensure((size_t)hub_stage * sizeof(int2), st));
@@ -607,10 +602,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     all_cluster = all_cluster && jobs[s]->stage == ST_COARSEN;
   }
   const bool reuse_bins = all_cluster && c->bin_sig_valid && sig == c->bin_sig && c->bin_cap_used == bin_cap;
-  // the parity of the slots' round numbers when they all agree, else -1
-  int round_parity = ns > 0 ? (int)(jobs[0]->round & 1) : -1;
-  for (int s = 1; s < ns; ++s)
-    if ((int)(jobs[s]->round & 1) != round_parity) round_parity = -1;
 
   if (c->profile) SCLAP_HIP(hipEventRecord(c->ev[kRateGroups + 1], st));
   c->path_ctr[0].fetch_add(1, std::memory_order_relaxed);
@@ -648,9 +639,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     hub.own = (int64_t*)c->hub_own.p;
     hub.best = (unsigned long long*)c->hub_best.p;
     hub.overflow = small + 10;
-    hub.hub_dist = (uint32_t*)c->hub_dist.p + (round_parity > 0 ? Nz : 0);
-    hub.hub_nc = (uint32_t*)c->hub_dist.p + 2 * Nz;
-    hub.hub_cap = (uint32_t*)c->hub_dist.p + 3 * Nz;
   }
   bool unit_weights = true;
   for (int s = 0; s < ns; ++s) unit_weights = unit_weights && c->pin_slots[s].ew == nullptr;
@@ -659,25 +647,15 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
   if (any_plain) {
     // (binned nodes of CONN_BUILD slots are rated here too, and again, with
     // the same result, from their new rows below)
-    // from the fourth clustering round of a level on, the hubs' label parts
-    // are sized by the pairs they staged two rounds before (a round of the
-    // same direction, over the same hubs: the bins are reused), when every
-    // slot is at a round of the same parity
-    if (!reuse_bins) c->hub_dist_valid[0] = c->hub_dist_valid[1] = false;
-    const bool hub_adapt =
-        hubs && reuse_bins && c->hub_keep_valid && round_parity >= 0 && c->hub_dist_valid[round_parity];
     SCLAP_TRY(launch_rate(S, ns, bins, binfo, bin_cap, meta, hub, N, hubs, unit_weights,
                           tiny_graph ? std::max<int64_t>(bin_max_deg, 64) : bin_max_deg, lo5, lo7, hubs_ident,
-                          reuse_bins && c->hub_keep_valid && !hub_adapt, hub_adapt, st,
+                          reuse_bins && c->hub_keep_valid, st,
                           c->profile ? c->ev : nullptr, &groups));
     c->hub_keep_valid = hubs;
-    if (round_parity >= 0) c->hub_dist_valid[round_parity] = hubs && all_cluster && !hubs_ident;
-    else c->hub_dist_valid[0] = c->hub_dist_valid[1] = false;
   } else {
     // every binned slot builds its block connections and is rated from them
     if (any_binned && hubs) SCLAP_TRY(launch_hub_prep(S, ns, bins, bin_cap, meta, hub, st));
     c->hub_keep_valid = false;
-    c->hub_dist_valid[0] = c->hub_dist_valid[1] = false;
     if (c->profile)
       for (int e = 0; e <= kRateGroups; ++e) SCLAP_HIP(hipEventRecord(c->ev[e], st));
   }

@@ -26,11 +26,6 @@ struct HubLayout {
   int64_t* own;           // hubs: own-label connection (kept 0)
   unsigned long long* best;  // hubs: best foreign candidate key (kept 0)
   uint32_t* overflow;     // 1
-  uint32_t* hub_dist;     // hubs: pairs the hub staged (summed by its parts) in this round, and before
-                          // prep resets it, two rounds before (one array per round parity)
-  uint32_t* hub_nc;       // hubs: chunks of each hub and ...
-  uint32_t* hub_cap;      // ... its label parts sized by its degree (written by a full prep, read by
-                          // an adapting one)
 };
 
 // Bins the rated nodes; also lists them all in `rated` (rated_cnt) and sets
@@ -58,13 +53,10 @@ constexpr int kMarkGroup = kRateGroups;
 // max_deg: no binned node has a larger degree (the launches of bins above
 // it are left out).  *groups (may be NULL): bit g set when launch group g
 // (the intervals between evs[g] and evs[g + 1]) ran a kernel.
-// hub_layout_kept: the hub layout of the previous round is reused as it is;
-// hub_adapt: it is laid out again with each hub's label parts sized by the
-// pairs it staged two rounds before (same hubs, clustering only).
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, int32_t lo5, int32_t lo7, bool hubs_ident, bool hub_layout_kept, bool hub_adapt,
-                hipStream_t st, hipEvent_t* evs, unsigned* groups);
+                int64_t max_deg, int32_t lo5, int32_t lo7, bool hubs_ident, bool hub_layout_kept, hipStream_t st,
+                hipEvent_t* evs, unsigned* groups);
 // Small contended sets resolved on the device (admission, then the admitted
 // weight added to each target's W); sets *big_flag if too large.
 int launch_contended_small(const DevSlot* S, int ns, const uint64_t* keys, const uint32_t* ccnt, int node_bits,

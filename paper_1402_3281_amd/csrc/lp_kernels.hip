@@ -1065,31 +1065,11 @@ __device__ __forceinline__ uint32_t hub_part_of(int32_t t, uint32_t P) {
   return (hash32((uint32_t)t) >> 19) & (P - 1);
 }
 
-// Label parts of a hub that staged `pairs` (label, sum) pairs two rounds
-// before in the same clustering (a round of the same direction, which admits
-// the same side of the labels): about kHubAdaptPairs per part, at most the
-// parts sized by its degree (cap) and at least cap / kHubAdaptFloor of them.
-// The pairs of a hub are at least its distinct labels, so the parts rarely
-// overfill; when one does, it is taken in several passes, and with at least
-// cap / kHubAdaptFloor parts the passes always suffice (any part count gives
-// the same result).
-constexpr uint32_t kHubAdaptPairs = 1024;
-constexpr uint32_t kHubAdaptFloor = 16;
-__device__ __forceinline__ uint32_t hub_parts_adapted(uint32_t pairs, uint32_t cap) {
-  uint32_t P = cap / kHubAdaptFloor > 1 ? cap / kHubAdaptFloor : 1;
-  while (P < cap && (uint64_t)P * kHubAdaptPairs < pairs) P <<= 1;
-  return P;
-}
-
 // One workgroup: per hub chunk, part and matrix offsets (exclusive scans).
-// adapt: the hubs are those of the previous rounds (same bins), whose chunk
-// map stands; only the label parts are laid out again, sized by the pairs
-// each hub staged in L.hub_dist two rounds before.  Every hub's staged-pair
-// count there is then reset for this round.
 template <bool ONE>
 __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S, int ns,
                                                    const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ cnt_ptr, HubLayout L, int adapt) {
+                                                   const uint32_t* __restrict__ cnt_ptr, HubLayout L) {
   constexpr int NW = 1024 / kWave;
   __shared__ uint32_t wc[NW], wp[NW];
   __shared__ int64_t wm[NW];
@@ -1108,21 +1088,12 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
     uint32_t nc = 0, np = 0;
     int64_t nm = 0;
     if (i < cnt) {
-      if (adapt) {
-        // the same hubs as the full prep that wrote their sizes
-        nc = L.hub_nc[i];
-        np = hub_parts_adapted(L.hub_dist[i], L.hub_cap[i]);
-      } else {
-        const int64_t u = list[i];
-        const DevSlot& sl = S[SLOT(u)];
-        const int64_t v = u - sl.nbase;
-        const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
-        nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
-        np = hub_parts(d, sl.nlabels);
-        L.hub_nc[i] = nc;
-        L.hub_cap[i] = np;
-      }
-      L.hub_dist[i] = 0;
+      const int64_t u = list[i];
+      const DevSlot& sl = S[SLOT(u)];
+      const int64_t v = u - sl.nbase;
+      const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
+      nc = (uint32_t)((d + kHubChunk - 1) / kHubChunk);
+      np = hub_parts(d, sl.nlabels);
       nm = (int64_t)nc * (np + 1);
       L.hub_P[i] = np;
     }
@@ -1156,8 +1127,7 @@ __global__ void __launch_bounds__(1024) k_hub_prep(const DevSlot* __restrict__ S
       L.part_off[i] = p0;
       L.mat_off[i] = m0;
       if ((int64_t)c0 + nc <= L.map_cap && (int64_t)p0 + np <= L.map_cap) {
-        if (!adapt)
-          for (uint32_t c = 0; c < nc; ++c) L.chunk_hub[c0 + c] = i;
+        for (uint32_t c = 0; c < nc; ++c) L.chunk_hub[c0 + c] = i;
         for (uint32_t p = 0; p < np; ++p) L.part_hub[p0 + p] = i;
       } else {
         *L.overflow = 1;
@@ -1512,7 +1482,6 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
     }
     if (threadIdx.x == 0) {
       if (best) atomicMax(&L.best[i], (unsigned long long)best);
-      if (len) atomicAdd(&L.hub_dist[i], len);
       L.part_total[g] = 0;
     }
     __syncthreads();
@@ -2836,8 +2805,8 @@ int launch_bin(const DevSlot* S, int ns, int64_t T, int32_t* bins, uint64_t* bin
 
 int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* binfo, int64_t bin_cap,
                 const uint32_t* bin_cnt, const HubLayout& hub, int64_t n_hint, bool hubs, bool unit_weights,
-                int64_t max_deg, int32_t lo5, int32_t lo7, bool hubs_ident, bool hub_layout_kept, bool hub_adapt,
-                hipStream_t st, hipEvent_t* evs, unsigned* groups) {
+                int64_t max_deg, int32_t lo5, int32_t lo7, bool hubs_ident, bool hub_layout_kept, hipStream_t st,
+                hipEvent_t* evs, unsigned* groups) {
   const unsigned G = grid_for(n_hint, 64, 2048);
   // bins 5-6 hold degrees above lo5, bin 7 degrees above lo7 (the smallest
   // such bounds over the slots)
@@ -2861,7 +2830,7 @@ int launch_rate(const DevSlot* S, int ns, const int32_t* bins, const uint64_t* b
     const int32_t* hb = bins + 8 * bin_cap;
     const uint32_t* hc = bin_cnt + 8;
     if (hub_layout_kept) hipLaunchKernelGGL(k_hub_reuse, dim3(1), dim3(1), 0, st, hub);
-    else LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub, hub_adapt ? 1 : 0);
+    else LAUNCH(k_hub_prep, 1, 1024, S, ns, hb, hc, hub);
     LAUNCH(k_hub_chunk, G, kHubChunkThreads, S, ns, hb, hub);
     if (!hubs_ident) {
       // (first clustering rounds stage no pairs: their chunks went to the hubs' best directly)
@@ -2915,7 +2884,7 @@ const uint32_t* bin_rated_offsets(void* scratch, int64_t T) {
 
 int launch_hub_prep(const DevSlot* S, int ns, const int32_t* bins, int64_t bin_cap, const uint32_t* bin_cnt,
                     const HubLayout& hub, hipStream_t st) {
-  LAUNCH(k_hub_prep, 1, 1024, S, ns, bins + 8 * bin_cap, bin_cnt + 8, hub, 0);
+  LAUNCH(k_hub_prep, 1, 1024, S, ns, bins + 8 * bin_cap, bin_cnt + 8, hub);
   SCLAP_HIP(hipGetLastError());
   return SCLAP_OK;
 }

@@ -325,9 +325,8 @@ def many_hubs_graph(seed=12, n=40000, hubs=1100, samples=4600):
 
 def test_many_hubs_over_many_rounds(sc, ctx):
     """More than 1024 hubs (degree > 4096) clustered for 8 rounds: the hub
-    layout is scanned in several blocks of 1024 hubs, and from the fourth
-    round on each hub's label parts are sized by the pairs it staged two
-    rounds before; labels, moves and visits equal the oracle's."""
+    layout is scanned in several blocks of 1024 hubs and kept over the
+    rounds; labels, moves and visits equal the oracle's."""
     g = many_hubs_graph()
     assert (np.diff(g.row_ptr)[:1100] > 4096).all()
     before = ctx.path_counters()
