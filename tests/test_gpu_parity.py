@@ -332,3 +332,11 @@ def test_many_hubs_over_many_rounds(sc, ctx):
     before = ctx.path_counters()
     assert_cluster_parity(sc, ctx, g, 300, 8)
     assert ctx.path_counters()["hub_rounds"] - before["hub_rounds"] == 8
+
+
+@pytest.mark.parametrize("k", [256, 257])
+def test_partition_cut_block_widths(sc, ctx, k):
+    """The partition's cut reads the blocks from a one-byte copy when k <= 256
+    and from the blocks themselves above: both equal the oracle."""
+    name, g = mid_graphs()[2]
+    assert_partition_parity(sc, ctx, g, k)
