@@ -125,12 +125,11 @@ struct Ctx {
   // scratch reused by every step
   Scratch bins, ckeys, ckeys2, tkey, wv, prefix, prim, hub_chunk, hub_tab, hub_own, hub_gkeys;
   Scratch step_ctr, small, slots_dev, ip_slots, hub_slice, hub_best, movers, binfo, hub_maps, binmeta;
-  Scratch hub_P, hub_ptot, hub_mat, binscr, cutbuf, tadm, hub_keep, trows, part8, lab8;
+  Scratch hub_P, hub_mat, binscr, cutbuf, tadm, hub_keep, trows, part8, lab8;
   // jobs and levels whose nodes the current bins hold (clustering rounds only)
   std::vector<std::pair<const void*, int>> bin_sig;
   bool bin_sig_valid = false;
   int64_t bin_cap_used = 0;
-  int64_t hub_parts_cap = 0;       // part counters allocated (kept 0 between rounds)
   bool hub_keep_valid = false;     // the hub layout buffers hold the last clustering round's layout
   // pinned host staging
   int64_t* pin = nullptr;

@@ -174,9 +174,8 @@ void ctx_release(Ctx* c, hipStream_t st) {
   Scratch* all[] = {&c->bins, &c->ckeys, &c->ckeys2, &c->tkey, &c->wv, &c->prefix, &c->prim, &c->hub_chunk,
                     &c->hub_tab, &c->hub_own, &c->hub_gkeys, &c->step_ctr, &c->small,
                     &c->slots_dev, &c->ip_slots, &c->hub_slice, &c->hub_best, &c->movers, &c->binfo,
-                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_ptot, &c->hub_mat,
+                    &c->hub_maps, &c->binmeta, &c->hub_P, &c->hub_mat,
                     &c->binscr, &c->cutbuf, &c->tadm, &c->hub_keep, &c->trows, &c->part8, &c->lab8};
-  c->hub_parts_cap = 0;
   for (Scratch* s : all) s->release(st);
   (void)hipStreamSynchronize(st);
   if (c->pin) (void)hipHostFree(c->pin);
@@ -553,15 +552,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_maps.ensure(2 * map_cap * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_mat.ensure((size_t)std::max<int64_t>(hub_mat, 1) * sizeof(uint32_t), st));
     SCLAP_TRY(c->hub_gkeys.ensure((size_t)hub_stage * sizeof(int2), st));
-    if (c->hub_parts_cap < hub_parts || !c->hub_ptot.p) {
-      // the capacity is only valid with its buffer: a failed allocation
-      // leaves hub_ptot empty, and the next round must not take the old
-      // capacity for a buffer that no longer exists
-      c->hub_parts_cap = 0;
-      SCLAP_TRY(c->hub_ptot.ensure((size_t)hub_parts * sizeof(uint32_t), st));
-      SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, (int64_t)(c->hub_ptot.bytes / sizeof(uint32_t)), 0, st));
-      c->hub_parts_cap = (int64_t)(c->hub_ptot.bytes / sizeof(uint32_t));
-    }
   }
   if (c->hub_own.bytes < Nz * sizeof(int64_t) || !c->hub_own.p) {
     SCLAP_TRY(c->hub_own.ensure(Nz * sizeof(int64_t), st));
@@ -630,7 +620,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     SCLAP_TRY(c->hub_keep.ensure(64, st));
     hub.totals = small + 11;
     hub.totals_kept = (uint32_t*)c->hub_keep.p;
-    hub.part_total = (uint32_t*)c->hub_ptot.p;
     hub.parts_cap = hub_parts;
     hub.mat = (uint32_t*)c->hub_mat.p;
     hub.mat_cap = hub_mat;
@@ -697,7 +686,6 @@ int lp_round(Ctx* c, std::vector<Job*>& jobs, hipStream_t st) {
     // a hub label part beyond its LDS table, a layout beyond its sizes, or a
     // hash table that filled up: the counters that are kept zero between
     // rounds may be left nonzero, so they are cleared before the error
-    if (c->hub_parts_cap > 0) SCLAP_TRY(fill_u32((uint32_t*)c->hub_ptot.p, c->hub_parts_cap, 0, st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_own.p, (int64_t)(c->hub_own.bytes / 8), 0, st));
     SCLAP_TRY(fill_i64((int64_t*)c->hub_best.p, (int64_t)(c->hub_best.bytes / 8), 0, st));
     (void)hipStreamSynchronize(st);

@@ -17,8 +17,7 @@ struct HubLayout {
   int64_t map_cap;
   uint32_t* totals;       // 2: chunks, parts
   uint32_t* totals_kept;  // 2: the same, kept between rounds (the layout is reused with the bins)
-  uint32_t* part_total;   // parts_cap: pairs of every part (kept 0)
-  int64_t parts_cap;
+  int64_t parts_cap;      // the most label parts a layout may hold
   uint32_t* mat;          // mat_cap: per chunk, the first staged pair of each part (P + 1)
   int64_t mat_cap;
   int2* stage;            // stage_cap: (label, weight sum) pairs, kHubChunk per chunk, grouped by part

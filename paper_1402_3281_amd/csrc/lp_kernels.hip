@@ -1046,11 +1046,11 @@ __global__ void __launch_bounds__(512) k_rate_large(const DevSlot* __restrict__ 
 //   prep     per hub: chunks of kHubChunk entries, label parts (a power of
 //            two, about kHubPartLabels distinct labels each), offsets
 //   chunk    per chunk: labels aggregated in an LDS table; the chunk's
-//            (label, sum) pairs are staged grouped by part (the part's first
-//            pair noted in the hub's chunk x part matrix), and every part's
-//            pair count is summed with one atomic per chunk
-//   part     per part: the part's pairs, read from every chunk of its hub,
-//            aggregated in LDS; the best eligible label of the part,
+//            (label, sum) pairs are staged grouped by part, each part's
+//            first pair noted in the hub's chunk x part matrix
+//   part     per part: the part's pairs, counted from the matrix and read
+//            from every chunk of its hub, aggregated in LDS; the best
+//            eligible label of the part,
 //            combined per hub with an integer maximum
 //   final    per hub: the own label against the best foreign one.
 // Every label of a hub falls in exactly one part, so the per-part sums are
@@ -1310,16 +1310,10 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
       if (threadIdx.x == NT - 1) loff[P] = run;
     }
     __syncthreads();
-    // chunk x part matrix: the part offsets of the staged pairs; each part's
-    // pair count
+    // chunk x part matrix: the part offsets of the staged pairs (a part's
+    // pairs in this chunk are the difference of two of them)
     uint32_t* mat_loff = L.mat + L.mat_off[i] + (int64_t)lc * (P + 1);
-    for (uint32_t p = threadIdx.x; p <= P; p += NT) {
-      mat_loff[p] = loff[p];
-      if (p < P) {
-        const uint32_t k = loff[p + 1] - loff[p];
-        if (k) atomicAdd(&L.part_total[L.part_off[i] + p], k);
-      }
-    }
+    for (uint32_t p = threadIdx.x; p <= P; p += NT) mat_loff[p] = loff[p];
     // staged pairs grouped by part; the used slots are cleared
     int2* stage = L.stage + (int64_t)c * kHubChunk;
     for (uint32_t k = threadIdx.x; k < nu; k += NT) {
@@ -1334,8 +1328,8 @@ __global__ void __launch_bounds__(kHubChunkThreads) k_hub_chunk(const DevSlot* _
   }
 }
 
-// Best eligible label of every part; the part's counter is reset.  The
-// part's pairs are read where its hub's chunks staged them: for hubs of up
+// Best eligible label of every part.  The part's pairs are read where its
+// hub's chunks staged them, and counted from the hub's chunk x part matrix: for hubs of up
 // to kHubFlat chunks, the workgroup's threads stride over the part's pairs
 // of all chunks in a row (each finds its chunk by binary search over the
 // prefix of the chunks' pair counts in LDS); larger hubs take a thread per
@@ -1356,6 +1350,7 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
   __shared__ uint32_t s_beg[kHubFlat];      // first pair of the part in each chunk's stage
   __shared__ uint32_t s_pre[kHubFlat + 1];  // exclusive prefix of the chunks' pair counts
   __shared__ uint32_t s_wsum[4];
+  __shared__ int64_t s_red[4];
   constexpr uint32_t NT = 256;
   if (*L.overflow) return;
   const uint32_t nparts = L.totals[1];
@@ -1369,7 +1364,6 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
     const int64_t cv = gld(sl.nw, v);
     const int64_t conn_own = L.own[i];
     const bool own_ok = own_allowed(sl, own);
-    const uint32_t len = L.part_total[g];
     const uint32_t P = L.hub_P[i];
     const uint32_t pp = g - L.part_off[i];
     const int64_t d = gld(sl.rp, v + 1) - gld(sl.rp, v);
@@ -1409,6 +1403,18 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
       }
       if (threadIdx.x == NT - 1) s_pre[nc] = run;
       __syncthreads();
+    }
+    // the part's pairs over all chunks of its hub
+    uint32_t len;
+    if (flat) {
+      len = s_pre[nc];
+    } else {
+      int64_t acc = 0;
+      for (uint32_t lc = threadIdx.x; lc < nc; lc += NT) {
+        const uint32_t* ml = mat + (int64_t)lc * (P + 1);
+        acc += ml[pp + 1] - ml[pp];
+      }
+      len = (uint32_t)block_reduce(acc, s_red, OpAdd64());
     }
     uint64_t best = 0;
     for (uint32_t Q = 1;; Q <<= 1) {
@@ -1482,7 +1488,6 @@ __global__ void __launch_bounds__(256) k_hub_part(const DevSlot* __restrict__ S,
     }
     if (threadIdx.x == 0) {
       if (best) atomicMax(&L.best[i], (unsigned long long)best);
-      L.part_total[g] = 0;
     }
     __syncthreads();
   }
