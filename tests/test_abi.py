@@ -59,9 +59,10 @@ def test_server_footprint_bounds():
     state with refinement's block connections, the per-node and per-entry
     scratch of the fused rounds (degree bins 9 x (4 + 8) B, hub rows 16 B,
     rated list and movers 12 B, contended keys and their buffers 36 B per
-    node; staged hub pairs 16 B x 1.5 per entry) and a contraction's
-    temporaries (key cache 8 B per entry and four 8 B arrays per undirected
-    edge)."""
+    node, byte copies of the blocks; staged hub pairs, bounded here by
+    16 B x 1.5 per entry; tile rows) and a contraction's temporaries (the
+    cross keys as emitted, room for every entry at 8 B, and four 8 B arrays
+    per undirected edge)."""
     import paper_1402_3281_amd as sc
 
     for n, m, k, ew, nwb in ((1 << 10, 16 << 10, 2, False, 0), (1 << 20, 32 << 20, 64, False, 0),
